@@ -1,0 +1,671 @@
+// =============================================================================
+// CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, sequential, FP64 reference for one time step of the Brownian
+// hard-disk method of Carter, Hitschfeld, Navarro and Soto, "GPU parallel
+// simulation algorithm of Brownian particles with excluded volume using
+// Delaunay triangulations" (arXiv:1703.02484).  Only the test-suite, the smoke
+// check and the benchmark's CPU-baseline leg may load this library; the GPU
+// library never does.  It shares no source with the GPU path.
+//
+// Build: g++ -std=c++17 -O2 -ffp-contract=off (no fast-math), single thread.
+//
+// Readings of the paper that this file adopts where the paper is silent,
+// ambiguous or garbled (each is restated where it is used):
+//   * hard walls with mirror reflection instead of the paper's periodic box;
+//   * translational noise amplitude sqrt(2 D dt) (mean-square displacement
+//     4 D t in 2D), the rotational rule of Sec. 7 already carries the 2;
+//   * general S x S strength matrix K[a][b] = strength on species a from b,
+//     which is mu_a alpha_b in the paper's two-charge model (Sec. 2.2);
+//   * overlap displacement along the unit vector (Sec. 2.3 equation), summed
+//     Jacobi-style over all overlapping Delaunay edges (Sec. 4.4, Algorithm 2),
+//     the per-particle sum truncated to length cap_frac * r_i (Sec. 4.4: the
+//     sigma/4 heuristic, half a radius), rounds repeated until no Delaunay
+//     edge overlaps (Sec. 4.4) with a round cap;
+//   * the triangulation is recomputed from scratch (Bowyer-Watson) whenever
+//     positions change, including after every overlap round: the Delaunay
+//     triangulation is unique in general position, so this is the plain
+//     definition that the GPU's flip rounds (Sec. 4.1, 4.3) reach faster;
+//   * the inverted-triangle predicate of Sec. 4.3 is evaluated for both
+//     orderings of the two opposite vertices (the printed formula tests the
+//     wrong triangle and contradicts its own figure).
+//
+// Functions with no independent pin say "parity unpinned" in their comment.
+// =============================================================================
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10, written from Salmon, Moraes, Dror and Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3" (SC'11).  The paper itself draws XORWOW numbers
+// from a closed library; a counter-based generator replaces it so that noise is
+// a pure function of (seed, step, particle id, stream).
+// ----------------------------------------------------------------------------
+struct Words4 { uint32_t w[4]; };
+
+Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+    const uint64_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;      // round multipliers
+    const uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;      // key schedule (Weyl) increments
+    for (int round = 0; round < 10; ++round) {
+        uint64_t pa = MA * (uint64_t)c0;
+        uint64_t pb = MB * (uint64_t)c2;
+        uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t n0 = hi_b ^ c1 ^ k0;
+        uint32_t n1 = lo_b;
+        uint32_t n2 = hi_a ^ c3 ^ k1;
+        uint32_t n3 = lo_a;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += WA; k1 += WB;
+    }
+    Words4 r;
+    r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+    return r;
+}
+
+// Two standard normals for (seed, step, id, stream) by Box and Muller (1958):
+// u1 in (0,1] from words 0,1 and u2 in [0,1) from words 2,3, 53 bits each.
+void normal_pair(uint64_t seed, int64_t step, uint32_t id, uint32_t stream, double &z0, double &z1) {
+    uint64_t st = (uint64_t)step;
+    Words4 w = philox4x32_10(id, (uint32_t)st, (uint32_t)(st >> 32), stream,
+                             (uint32_t)seed, (uint32_t)(seed >> 32));
+    uint64_t m1 = ((((uint64_t)w.w[0]) << 32) | w.w[1]) >> 11;
+    uint64_t m2 = ((((uint64_t)w.w[2]) << 32) | w.w[3]) >> 11;
+    double u1 = ((double)m1 + 1.0) * 0x1.0p-53;
+    double u2 = (double)m2 * 0x1.0p-53;
+    double rho = std::sqrt(-2.0 * std::log(u1));
+    double ang = 2.0 * M_PI * u2;
+    z0 = rho * std::cos(ang);
+    z1 = rho * std::sin(ang);
+}
+
+// ----------------------------------------------------------------------------
+// Geometric predicates, plain FP64 in translated form.
+// ----------------------------------------------------------------------------
+inline double orient2(double ax, double ay, double bx, double by, double cx, double cy) {
+    // twice the signed area of (a, b, c); > 0 when counter-clockwise
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+inline double incircle(double ax, double ay, double bx, double by, double cx, double cy, double dx, double dy) {
+    // > 0 when d lies strictly inside the circle through the CCW triangle (a, b, c)
+    double adx = ax - dx, ady = ay - dy;
+    double bdx = bx - dx, bdy = by - dy;
+    double cdx = cx - dx, cdy = cy - dy;
+    double alift = adx * adx + ady * ady;
+    double blift = bdx * bdx + bdy * bdy;
+    double clift = cdx * cdx + cdy * cdy;
+    return alift * (bdx * cdy - cdx * bdy) - blift * (adx * cdy - cdx * ady) + clift * (adx * bdy - bdx * ady);
+}
+
+// Sec. 4.3: is point p inside the closed triangle (v1, v2, v3)?  Barycentric
+// form: p - v1 = s (v2 - v1) + t (v3 - v1); inside when s, t >= 0 and s + t <= 1.
+// The comparisons are multiplied through by the signed doubled area so that
+// either orientation of the triangle is handled, as in the paper's two cases.
+bool point_in_closed_triangle(const double *v1, const double *v2, const double *v3, const double *p) {
+    double e0x = v2[0] - v1[0], e0y = v2[1] - v1[1];
+    double e1x = v3[0] - v1[0], e1y = v3[1] - v1[1];
+    double ex = p[0] - v1[0], ey = p[1] - v1[1];
+    double area = e0x * e1y - e0y * e1x;          // (v2 - v1) x (v3 - v1)
+    double s = ex * e1y - ey * e1x;               // (p - v1) x (v3 - v1)  = s * area
+    double t = e0x * ey - e0y * ex;               // (v2 - v1) x (p - v1)  = t * area
+    if (area < 0.0) return (s <= 0.0) && (t <= 0.0) && (s + t >= area);
+    return (s >= 0.0) && (t >= 0.0) && (s + t <= area);
+}
+
+// Sec. 4.3 flip criterion for edge (v1, v2) whose opposite vertices are v3 and
+// v4: flip when either opposite vertex lies in the closed triangle formed by
+// the edge and the other opposite vertex.
+bool inverted_edge_flip(const double *v1, const double *v2, const double *v3, const double *v4) {
+    return point_in_closed_triangle(v1, v2, v3, v4) || point_in_closed_triangle(v1, v2, v4, v3);
+}
+
+// ----------------------------------------------------------------------------
+// Delaunay triangulation by Bowyer-Watson insertion with an infinite vertex.
+// A ghost triangle (u, v, INF) stands for the outside of hull edge v -> u; a
+// point conflicts with it when it lies strictly outside that edge or on the
+// open edge itself.  A finite triangle conflicts when the point is strictly
+// inside its circumcircle.  Each insertion removes the connected set of
+// conflicting triangles and joins the new point to the cavity boundary.
+// ----------------------------------------------------------------------------
+const int INF = -1;
+
+struct Tri {
+    int v[3];    // CCW; at most one entry is INF
+    int nb[3];   // nb[k]: triangle across edge (v[k], v[(k+1)%3])
+    bool alive;
+};
+
+struct Delaunay {
+    const double *xy = nullptr;
+    int n = 0;
+    std::vector<Tri> tris;
+    std::vector<int> free_list;
+    int last = 0;
+
+    bool is_ghost(const Tri &t) const { return t.v[0] == INF || t.v[1] == INF || t.v[2] == INF; }
+    const double *P(int i) const { return xy + 2 * i; }
+
+    bool conflicts(int ti, const double *p) const {
+        const Tri &t = tris[ti];
+        if (!is_ghost(t)) {
+            const double *a = P(t.v[0]), *b = P(t.v[1]), *c = P(t.v[2]);
+            return incircle(a[0], a[1], b[0], b[1], c[0], c[1], p[0], p[1]) > 0.0;
+        }
+        int k = 0;
+        while (t.v[k] != INF) ++k;
+        int u = t.v[(k + 1) % 3], v = t.v[(k + 2) % 3];   // ghost reads (u, v, INF) after rotation
+        const double *pu = P(u), *pv = P(v);
+        double o = orient2(pu[0], pu[1], pv[0], pv[1], p[0], p[1]);
+        if (o > 0.0) return true;   // strictly outside hull edge v -> u
+        if (o < 0.0) return false;
+        // collinear with the hull edge: conflict only on the open segment
+        double dot = (p[0] - pu[0]) * (pv[0] - pu[0]) + (p[1] - pu[1]) * (pv[1] - pu[1]);
+        double len2 = (pv[0] - pu[0]) * (pv[0] - pu[0]) + (pv[1] - pu[1]) * (pv[1] - pu[1]);
+        return dot > 0.0 && dot < len2;
+    }
+
+    int new_tri(int a, int b, int c) {
+        Tri t;
+        t.v[0] = a; t.v[1] = b; t.v[2] = c;
+        t.nb[0] = t.nb[1] = t.nb[2] = -1;
+        t.alive = true;
+        if (!free_list.empty()) {
+            int id = free_list.back();
+            free_list.pop_back();
+            tris[id] = t;
+            return id;
+        }
+        tris.push_back(t);
+        return (int)tris.size() - 1;
+    }
+
+    // Walk from `last` towards p across edges that p lies strictly beyond.
+    int locate(const double *p) {
+        int ti = last;
+        if (!tris[ti].alive) {
+            for (ti = 0; ti < (int)tris.size() && !tris[ti].alive; ++ti) {}
+        }
+        if (is_ghost(tris[ti])) {
+            const Tri &g = tris[ti];
+            int k = 0;
+            while (g.v[k] != INF) ++k;
+            ti = g.nb[(k + 1) % 3];   // finite triangle across the ghost's hull edge
+        }
+        size_t guard = 0, limit = 4 * tris.size() + 16;
+        for (;;) {
+            const Tri &t = tris[ti];
+            if (is_ghost(t)) return ti;
+            int moved = -1;
+            for (int e = 0; e < 3; ++e) {
+                int k = (e + (int)(guard % 3)) % 3;
+                const double *a = P(t.v[k]), *b = P(t.v[(k + 1) % 3]);
+                if (orient2(a[0], a[1], b[0], b[1], p[0], p[1]) < 0.0) { moved = t.nb[k]; break; }
+            }
+            if (moved < 0) return ti;
+            ti = moved;
+            if (++guard > limit) return -1;
+        }
+    }
+
+    bool insert(int pi) {
+        const double *p = P(pi);
+        int start = locate(p);
+        if (start < 0) return false;
+        if (!conflicts(start, p)) {
+            // the located triangle contains p; if it does not conflict, p
+            // coincides with a vertex (excluded by the hard-disk input).
+            return false;
+        }
+        std::vector<int> cavity, stack;
+        cavity.reserve(16);
+        stack.push_back(start);
+        tris[start].alive = false;   // mark as taken into the cavity
+        while (!stack.empty()) {
+            int ti = stack.back();
+            stack.pop_back();
+            cavity.push_back(ti);
+            for (int k = 0; k < 3; ++k) {
+                int nb = tris[ti].nb[k];
+                if (nb >= 0 && tris[nb].alive && conflicts(nb, p)) {
+                    tris[nb].alive = false;
+                    stack.push_back(nb);
+                }
+            }
+        }
+        // boundary edges (u, v) of the cavity, each seen from its cavity triangle
+        struct BEdge { int u, v, outside; };
+        std::vector<BEdge> boundary;
+        for (int ti : cavity) {
+            for (int k = 0; k < 3; ++k) {
+                int nb = tris[ti].nb[k];
+                if (nb < 0 || tris[nb].alive) boundary.push_back({tris[ti].v[k], tris[ti].v[(k + 1) % 3], nb});
+            }
+        }
+        for (int ti : cavity) free_list.push_back(ti);
+        std::unordered_map<int, int> starts;   // boundary start vertex -> new triangle
+        std::vector<int> created;
+        created.reserve(boundary.size());
+        for (const BEdge &be : boundary) {
+            int t = new_tri(be.u, be.v, pi);
+            tris[t].nb[0] = be.outside;
+            if (be.outside >= 0) {
+                Tri &o = tris[be.outside];
+                for (int k = 0; k < 3; ++k)
+                    if (o.v[k] == be.v && o.v[(k + 1) % 3] == be.u) o.nb[k] = t;
+            }
+            starts[be.u] = t;
+            created.push_back(t);
+        }
+        for (int t : created) {
+            int v = tris[t].v[1];
+            int u = tris[t].v[0];
+            // edge (v, p) borders the new triangle starting at v
+            auto it = starts.find(v);
+            if (it == starts.end()) return false;
+            tris[t].nb[1] = it->second;
+            tris[it->second].nb[2] = t;
+            (void)u;
+        }
+        for (int t : created)
+            if (!is_ghost(tris[t])) { last = t; break; }
+        return true;
+    }
+
+    // Builds DT(xy).  Returns false when all points are collinear or the
+    // input has coincident points.
+    bool build(const double *pts, int npts) {
+        xy = pts;
+        n = npts;
+        tris.clear();
+        free_list.clear();
+        if (n < 3) return false;
+        int i0 = 0, i1 = 1, i2 = -1;
+        for (int k = 2; k < n; ++k) {
+            const double *a = P(i0), *b = P(i1), *c = P(k);
+            if (orient2(a[0], a[1], b[0], b[1], c[0], c[1]) != 0.0) { i2 = k; break; }
+        }
+        if (i2 < 0) return false;
+        {
+            const double *a = P(i0), *b = P(i1), *c = P(i2);
+            if (orient2(a[0], a[1], b[0], b[1], c[0], c[1]) < 0.0) std::swap(i1, i2);
+        }
+        int t0 = new_tri(i0, i1, i2);
+        int g0 = new_tri(i1, i0, INF);
+        int g1 = new_tri(i2, i1, INF);
+        int g2 = new_tri(i0, i2, INF);
+        // link by matching reversed edges
+        std::vector<int> all = {t0, g0, g1, g2};
+        for (int a : all)
+            for (int ka = 0; ka < 3; ++ka)
+                for (int b : all) {
+                    if (a == b) continue;
+                    for (int kb = 0; kb < 3; ++kb)
+                        if (tris[a].v[ka] == tris[b].v[(kb + 1) % 3] && tris[a].v[(ka + 1) % 3] == tris[b].v[kb])
+                            tris[a].nb[ka] = b;
+                }
+        last = t0;
+        for (int k = 0; k < n; ++k) {
+            if (k == i0 || k == i1 || k == i2) continue;
+            if (!insert(k)) return false;
+        }
+        return true;
+    }
+
+    void finite_triangles(std::vector<int> &out) const {
+        out.clear();
+        for (const Tri &t : tris)
+            if (t.alive && !is_ghost(t)) { out.push_back(t.v[0]); out.push_back(t.v[1]); out.push_back(t.v[2]); }
+    }
+
+    // unique finite edges (i < j)
+    void finite_edges(std::vector<std::pair<int, int>> &out) const {
+        out.clear();
+        for (const Tri &t : tris) {
+            if (!t.alive || is_ghost(t)) continue;
+            for (int k = 0; k < 3; ++k) {
+                int a = t.v[k], b = t.v[(k + 1) % 3];
+                int nbv = t.nb[k];
+                // each interior edge is seen twice; keep it from the side with a < b,
+                // hull edges (ghost neighbour) once
+                bool nb_ghost = nbv >= 0 && is_ghost(tris[nbv]);
+                if (a < b || nb_ghost) out.push_back({std::min(a, b), std::max(a, b)});
+            }
+        }
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
+    }
+};
+
+// ----------------------------------------------------------------------------
+// Pair forces, Sec. 2.2: F_i = sum_{j != i} K[s_i][s_j] g(d_ij) (r_i - r_j)/d_ij,
+// g(d) = d^-q (power law; q = 2 is the paper's long-range r/r^3, q = 6 its
+// short-range r/r^7) or g(d) = A exp(-d/lam)/d (screened), zero beyond an
+// inclusive cutoff when cutoff > 0 (Sec. 2.2 cutoff rule, no force shift).
+// Brute force over all ordered pairs; no neighbour list.
+// ----------------------------------------------------------------------------
+struct ForceModel {
+    int S = 1;
+    std::vector<double> K;     // S*S row-major
+    int kind = 0;              // 0 power, 1 screened
+    double q = 2.0, A = 1.0, lam = 1.0, cutoff = 0.0;
+};
+
+inline double pair_scale(const ForceModel &fm, double d) {
+    // returns g(d)/d so that the force is scale * (r_i - r_j)
+    if (fm.kind == 0) {
+        if (fm.q == 2.0) return 1.0 / (d * d * d);
+        return std::pow(d, -fm.q) / d;
+    }
+    return fm.A * std::exp(-d / fm.lam) / d / d;
+}
+
+void forces_subset(const ForceModel &fm, int n, const double *xy, const int *sp, const int *idx, int m,
+                   double *out) {
+    for (int a = 0; a < m; ++a) {
+        int i = idx ? idx[a] : a;
+        double fx = 0.0, fy = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+            double d = std::sqrt(dx * dx + dy * dy);
+            if (fm.cutoff > 0.0 && d > fm.cutoff) continue;
+            double k = fm.K[sp[i] * fm.S + sp[j]];
+            double s = k * pair_scale(fm, d);
+            fx += s * dx;
+            fy += s * dy;
+        }
+        out[2 * a] = fx;
+        out[2 * a + 1] = fy;
+    }
+}
+
+// Hard walls: mirror reflection about the shifted wall, then a safety clamp.
+inline double wall(double c, double r, double L) {
+    double lo = r, hi = L - r;
+    if (c < lo) c = 2.0 * lo - c;
+    if (c > hi) c = 2.0 * hi - c;
+    if (c < lo) c = lo;
+    if (c > hi) c = hi;
+    return c;
+}
+
+struct Stats {
+    int64_t steps = 0;
+    int64_t overlap_rounds_total = 0;
+    int64_t overlap_rounds_max = 0;
+    int64_t overlap_edges_total = 0;
+    int64_t cap_hits = 0;
+    int64_t reversals = 0;
+    int64_t noise_clamps = 0;
+};
+
+// One Jacobi overlap round over the given edges, Sec. 2.3 and Sec. 4.4:
+// every overlapping edge (d < r_i + r_j) moves both ends apart along the unit
+// vector by f (r_i + r_j - d); the summed move of each particle is truncated to
+// length cap_frac * r_i; walls are applied.  Returns the number of overlapping
+// edges found (0: nothing moved).
+int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac,
+                      const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits) {
+    std::vector<double> disp(2 * (size_t)n, 0.0);
+    std::vector<char> touched(n, 0);
+    int64_t count = 0;
+    for (const auto &e : edges) {
+        int i = e.first, j = e.second;
+        double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+        double d = std::sqrt(dx * dx + dy * dy);
+        double contact = rad[i] + rad[j];
+        if (!(d < contact)) continue;
+        ++count;
+        double s = f * (contact - d) / d;
+        disp[2 * i] += s * dx;
+        disp[2 * i + 1] += s * dy;
+        disp[2 * j] -= s * dx;
+        disp[2 * j + 1] -= s * dy;
+        touched[i] = touched[j] = 1;
+    }
+    if (count == 0) return 0;
+    for (int i = 0; i < n; ++i) {
+        if (!touched[i]) continue;
+        double ddx = disp[2 * i], ddy = disp[2 * i + 1];
+        double len = std::sqrt(ddx * ddx + ddy * ddy);
+        double cap = cap_frac * rad[i];
+        if (len > cap) {
+            double sc = cap / len;
+            ddx = ddx * sc;
+            ddy = ddy * sc;
+            if (cap_hits) ++*cap_hits;
+        }
+        xy[2 * i] = wall(xy[2 * i] + ddx, rad[i], L);
+        xy[2 * i + 1] = wall(xy[2 * i + 1] + ddy, rad[i], L);
+    }
+    return count;
+}
+
+struct Sim {
+    int n = 0;
+    std::vector<double> xy, rad, theta;
+    std::vector<int> sp;
+    ForceModel fm;
+    double L = 0, D = 0, dt = 0, v0 = 0, Dr = 0;
+    uint64_t seed = 0;
+    int64_t step = 0;
+    double f = 1.0, cap_frac = 0.5, clip = 3.0;
+    int max_rounds = 10000;
+    Stats st;
+    Delaunay dt_now;
+    std::vector<std::pair<int, int>> edges;
+    std::vector<double> forces;
+    int last_rounds = 0;
+
+    bool retriangulate() {
+        if (!dt_now.build(xy.data(), n)) return false;
+        dt_now.finite_edges(edges);
+        return true;
+    }
+
+    // One step, in the order of Algorithm 1 with the overlap loop of Sec. 4.4.
+    // Returns 0, -3 (round cap exceeded) or -4 (triangulation failed).
+    int advance() {
+        forces.assign(2 * (size_t)n, 0.0);
+        forces_subset(fm, n, xy.data(), sp.data(), nullptr, n, forces.data());
+        const double amp = std::sqrt(2.0 * D * dt);
+        const double amp_r = std::sqrt(2.0 * Dr * dt);
+        std::vector<double> nxy(2 * (size_t)n);
+        for (int i = 0; i < n; ++i) {
+            double zx, zy, nr, unused;
+            normal_pair(seed, step, (uint32_t)i, 0u, zx, zy);
+            if (zx > clip) { zx = clip; ++st.noise_clamps; }
+            if (zx < -clip) { zx = -clip; ++st.noise_clamps; }
+            if (zy > clip) { zy = clip; ++st.noise_clamps; }
+            if (zy < -clip) { zy = -clip; ++st.noise_clamps; }
+            normal_pair(seed, step, (uint32_t)i, 1u, nr, unused);
+            double th = theta[i];
+            double vx = forces[2 * i] + v0 * std::cos(th);
+            double vy = forces[2 * i + 1] + v0 * std::sin(th);
+            double x = xy[2 * i] + vx * dt + amp * zx;
+            double y = xy[2 * i + 1] + vy * dt + amp * zy;
+            nxy[2 * i] = wall(x, rad[i], L);
+            nxy[2 * i + 1] = wall(y, rad[i], L);
+            theta[i] = th + amp_r * nr;
+        }
+        // Sec. 4.3: an edge whose vector reversed means the pair passed through
+        // each other; counted (the paper discards the step, not done here).
+        for (const auto &e : edges) {
+            int i = e.first, j = e.second;
+            double ox = xy[2 * j] - xy[2 * i], oy = xy[2 * j + 1] - xy[2 * i + 1];
+            double mx = nxy[2 * j] - nxy[2 * i], my = nxy[2 * j + 1] - nxy[2 * i + 1];
+            if (ox * mx + oy * my < 0.0) ++st.reversals;
+        }
+        xy.swap(nxy);
+        if (!retriangulate()) return -4;
+        int rounds = 0;
+        for (;;) {
+            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, edges, &st.cap_hits);
+            if (cnt == 0) break;
+            ++rounds;
+            st.overlap_edges_total += cnt;
+            if (!retriangulate()) return -4;
+            if (rounds >= max_rounds) {
+                // still overlapping after the cap?
+                bool any = false;
+                for (const auto &e : edges) {
+                    int i = e.first, j = e.second;
+                    double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+                    if (std::sqrt(dx * dx + dy * dy) < rad[i] + rad[j]) { any = true; break; }
+                }
+                if (any) return -3;
+                break;
+            }
+        }
+        last_rounds = rounds;
+        st.overlap_rounds_total += rounds;
+        if (rounds > st.overlap_rounds_max) st.overlap_rounds_max = rounds;
+        ++st.steps;
+        ++step;
+        return 0;
+    }
+};
+
+}  // namespace
+
+// =============================================================================
+// C interface for the test-suite (ctypes).
+// =============================================================================
+extern "C" {
+
+void orc_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out) {
+    Words4 w = philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    for (int k = 0; k < 4; ++k) out[k] = w.w[k];
+}
+
+// Raw (unclamped) normal pairs for ids 0..n-1 of one (seed, step, stream).
+void orc_normals(int n, uint64_t seed, int64_t step, uint32_t stream, double *out) {
+    for (int i = 0; i < n; ++i) normal_pair(seed, step, (uint32_t)i, stream, out[2 * i], out[2 * i + 1]);
+}
+
+double orc_orient2(const double *a, const double *b, const double *c) {
+    return orient2(a[0], a[1], b[0], b[1], c[0], c[1]);
+}
+
+double orc_incircle(const double *a, const double *b, const double *c, const double *d) {
+    return incircle(a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]);
+}
+
+int orc_inverted_edge_flip(const double *v1, const double *v2, const double *v3, const double *v4) {
+    return inverted_edge_flip(v1, v2, v3, v4) ? 1 : 0;
+}
+
+int orc_point_in_closed_triangle(const double *v1, const double *v2, const double *v3, const double *p) {
+    return point_in_closed_triangle(v1, v2, v3, p) ? 1 : 0;
+}
+
+// Finite Delaunay triangles (CCW) of n points; tri_out holds 3*cap ints.
+// Returns the triangle count, or -1 on failure, -2 when cap is too small.
+int orc_delaunay(int n, const double *xy, int *tri_out, int cap) {
+    Delaunay d;
+    if (!d.build(xy, n)) return -1;
+    std::vector<int> t;
+    d.finite_triangles(t);
+    int nt = (int)(t.size() / 3);
+    if (nt > cap) return -2;
+    std::memcpy(tri_out, t.data(), t.size() * sizeof(int));
+    return nt;
+}
+
+// Forces for the particles listed in idx (m of them; idx NULL = all n).
+void orc_forces(int n, const double *xy, const int *sp, int S, const double *K, int kind, double q, double A,
+                double lam, double cutoff, const int *idx, int m, double *out) {
+    ForceModel fm;
+    fm.S = S;
+    fm.K.assign(K, K + S * S);
+    fm.kind = kind; fm.q = q; fm.A = A; fm.lam = lam; fm.cutoff = cutoff;
+    forces_subset(fm, n, xy, sp, idx, idx ? m : n, out);
+}
+
+double orc_wall(double c, double r, double L) { return wall(c, r, L); }
+
+// One overlap round over the current Delaunay edges of xy (in place).
+// Returns the number of overlapping edges, -4 if the triangulation failed.
+int64_t orc_overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac,
+                          int64_t *cap_hits) {
+    Delaunay d;
+    if (!d.build(xy, n)) return -4;
+    std::vector<std::pair<int, int>> e;
+    d.finite_edges(e);
+    return overlap_round(n, xy, rad, L, f, cap_frac, e, cap_hits);
+}
+
+// --- simulation handle -------------------------------------------------------
+void *orc_sim_new(int n, const double *xy, const double *rad, const int *sp, const double *theta, int S,
+                  const double *K, int kind, double q, double A, double lam, double cutoff, double L, double D,
+                  double dt, double v0, double Dr, uint64_t seed, int64_t step0, double f, double cap_frac,
+                  double clip, int max_rounds) {
+    Sim *s = new Sim();
+    s->n = n;
+    s->xy.assign(xy, xy + 2 * (size_t)n);
+    s->rad.assign(rad, rad + n);
+    s->sp.assign(sp, sp + n);
+    if (theta) s->theta.assign(theta, theta + n); else s->theta.assign(n, 0.0);
+    s->fm.S = S;
+    s->fm.K.assign(K, K + S * S);
+    s->fm.kind = kind; s->fm.q = q; s->fm.A = A; s->fm.lam = lam; s->fm.cutoff = cutoff;
+    s->L = L; s->D = D; s->dt = dt; s->v0 = v0; s->Dr = Dr;
+    s->seed = seed; s->step = step0;
+    s->f = f; s->cap_frac = cap_frac; s->clip = clip; s->max_rounds = max_rounds;
+    if (!s->retriangulate()) { delete s; return nullptr; }
+    return s;
+}
+
+int orc_sim_step(void *h, int64_t nsteps) {
+    Sim *s = (Sim *)h;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int rc = s->advance();
+        if (rc != 0) return rc;
+    }
+    return 0;
+}
+
+int orc_sim_last_rounds(void *h) { return ((Sim *)h)->last_rounds; }
+
+void orc_sim_get(void *h, double *xy, double *theta, int64_t *step, int64_t *stats7) {
+    Sim *s = (Sim *)h;
+    if (xy) std::memcpy(xy, s->xy.data(), s->xy.size() * sizeof(double));
+    if (theta) std::memcpy(theta, s->theta.data(), s->theta.size() * sizeof(double));
+    if (step) *step = s->step;
+    if (stats7) {
+        stats7[0] = s->st.steps;
+        stats7[1] = s->st.overlap_rounds_total;
+        stats7[2] = s->st.overlap_rounds_max;
+        stats7[3] = s->st.overlap_edges_total;
+        stats7[4] = s->st.cap_hits;
+        stats7[5] = s->st.reversals;
+        stats7[6] = s->st.noise_clamps;
+    }
+}
+
+// Forces at the current positions (the ones the next step will use).
+void orc_sim_forces(void *h, double *out) {
+    Sim *s = (Sim *)h;
+    forces_subset(s->fm, s->n, s->xy.data(), s->sp.data(), nullptr, s->n, out);
+}
+
+int orc_sim_triangles(void *h, int *tri_out, int cap) {
+    Sim *s = (Sim *)h;
+    std::vector<int> t;
+    s->dt_now.finite_triangles(t);
+    int nt = (int)(t.size() / 3);
+    if (nt > cap) return -2;
+    std::memcpy(tri_out, t.data(), t.size() * sizeof(int));
+    return nt;
+}
+
+void orc_sim_free(void *h) { delete (Sim *)h; }
+
+}  // extern "C"

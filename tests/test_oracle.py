@@ -1,0 +1,363 @@
+"""Pins for the CPU oracle: each test checks it against something other than
+itself (published values, closed forms, library routines, invariants, brute
+force).  No GPU needed."""
+import math
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+from scipy.spatial import ConvexHull, Delaunay as QhullDelaunay
+from scipy.special import erf
+
+import oracle
+from paper_1703_02484_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+
+
+def _tri_set(tris, names=None):
+    if names is None:
+        return {tuple(sorted(map(int, t))) for t in tris}
+    return {"".join(sorted(names[int(i)] for i in t)) for t in tris}
+
+
+# --------------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    for row in _rows("philox_kat.txt"):
+        vals = [int(v, 16) for v in row]
+        out = oracle.philox4x32_10(vals[0:4], vals[4:6])
+        assert [int(v) for v in out] == vals[6:10]
+
+
+def test_normals_statistics():
+    # 2^20 normals: mean 0, variance 1, band masses against erf (and the
+    # paper's printed 0.683 / 0.954 / 0.997); clamped variance and clamp rate
+    # against the closed forms of a normal truncated by clamping at +-3.
+    z = np.concatenate([oracle.normals(1 << 18, seed=7, step=s, stream=0).ravel() for s in range(2)])
+    assert abs(z.mean()) < 5e-3
+    assert abs(z.var() - 1.0) < 6e-3
+    for k, printed in _rows("normal_bands.txt"):
+        k = float(k)
+        frac = np.mean(np.abs(z) <= k)
+        assert abs(frac - erf(k / math.sqrt(2))) < 2e-3
+        assert abs(frac - float(printed)) < 2e-3
+    zc = np.clip(z, -3, 3)
+    p_out = 1 - erf(3 / math.sqrt(2))
+    phi3 = math.exp(-4.5) / math.sqrt(2 * math.pi)
+    var_clamped = (1 - p_out) - 2 * 3 * phi3 + 9 * p_out
+    assert abs(var_clamped - 0.9950072780) < 1e-9
+    assert abs(zc.var() - var_clamped) < 6e-3
+    assert abs(np.mean(np.abs(z) > 3) - p_out) < 4e-4
+
+
+def test_normals_keyed_by_id_step_stream():
+    a = oracle.normals(8, seed=1, step=5, stream=0)
+    b = oracle.normals(8, seed=1, step=5, stream=0)
+    assert np.array_equal(a, b)
+    for other in (oracle.normals(8, 2, 5, 0), oracle.normals(8, 1, 6, 0), oracle.normals(8, 1, 5, 1)):
+        assert not np.any(other == a)
+    # particle id enters the counter: row i of a longer call equals row i of a shorter one
+    c = oracle.normals(16, seed=1, step=5, stream=0)
+    assert np.array_equal(c[:8], a)
+
+
+# --------------------------------------------------------------------- forces
+def test_two_particle_closed_form():
+    xy = np.array([[10.0, 10.0], [13.0, 14.0]])  # d = 5
+    K = np.array([[0.3, -0.7], [0.11, 2.0]])
+    sp = np.array([0, 1])
+    f = oracle.forces(xy, sp, K, kind="power", q=2.0)
+    u = (xy[0] - xy[1]) / 5.0
+    np.testing.assert_allclose(f[0], K[0, 1] / 25.0 * u, rtol=1e-14)
+    np.testing.assert_allclose(f[1], -K[1, 0] / 25.0 * u, rtol=1e-14)
+    # the paper's short-range law r/r^7: magnitude d^-6
+    f6 = oracle.forces(xy, sp, K, kind="power", q=6.0)
+    np.testing.assert_allclose(f6[0], K[0, 1] / 5.0 ** 6 * u, rtol=1e-13)
+    # screened: A exp(-d/lam)/d
+    fs = oracle.forces(xy, sp, K, kind="screened", A=1.7, lam=0.5)
+    np.testing.assert_allclose(fs[0], K[0, 1] * 1.7 * math.exp(-10.0) / 5.0 * u, rtol=1e-13)
+
+
+def test_cutoff_inclusive():
+    xy = np.array([[0.0, 0.0], [2.5, 0.0], [0.0, 2.5000001]])
+    f = oracle.forces(xy, np.zeros(3, np.int32), np.array([[1.0]]), kind="screened", A=1.0, lam=0.5,
+                      cutoff=2.5)
+    g = math.exp(-5.0) / 2.5
+    # particle 0: pair with 1 at exactly the cutoff counts, pair with 2 does not
+    np.testing.assert_allclose(f[0], [-g, 0.0], rtol=1e-14)
+    assert f[2][0] == 0.0 and f[2][1] == 0.0
+
+
+def test_total_force_invariants():
+    rng = np.random.default_rng(3)
+    xy = synth.rsa(300, 60.0, 1.0, seed=4)
+    sp = rng.integers(0, 3, 300).astype(np.int32)
+    Ks = rng.normal(size=(3, 3))
+    Ks = Ks + Ks.T
+    f = oracle.forces(xy, sp, Ks)
+    assert np.abs(f.sum(0)).max() <= 1e-13 * np.abs(f).sum()
+    Kn = rng.normal(size=(3, 3))
+    f = oracle.forces(xy, sp, Kn)
+    # brute force: sum_i F_i = sum_{i<j} (K_{s_i s_j} - K_{s_j s_i}) (r_i - r_j)/d^3
+    tot = np.zeros(2)
+    for i in range(300):
+        d = xy[i] - xy[i + 1:]
+        r3 = np.sqrt((d * d).sum(1)) ** 3
+        w = Kn[sp[i], sp[i + 1:]] - Kn[sp[i + 1:], sp[i]]
+        tot += (w[:, None] * d / r3[:, None]).sum(0)
+    np.testing.assert_allclose(f.sum(0), tot, rtol=1e-10, atol=1e-13)
+    # linear in K
+    f2 = oracle.forces(xy, sp, 2.5 * Kn)
+    np.testing.assert_allclose(f2, 2.5 * f, rtol=1e-12, atol=1e-14 * np.abs(f).max())
+
+
+# --------------------------------------------------------------------- walls
+@pytest.mark.parametrize("c,expect", [(0.5, 1.5), (1.0, 1.0), (5.0, 5.0), (9.25, 8.75), (9.0, 9.0),
+                                      (-0.5, 2.5)])
+def test_wall_reflection(c, expect):
+    assert oracle.wall(c, 1.0, 10.0) == pytest.approx(expect, abs=0)
+
+
+def test_wall_clamp_after_double_cross():
+    # -20 reflects to 22 at the lower wall, to -4 at the upper one, then clamps to r
+    assert oracle.wall(-20.0, 1.0, 10.0) == 1.0
+    assert oracle.wall(30.0, 1.0, 10.0) == 1.0
+
+
+# --------------------------------------------------------------------- triangulation
+def _load_fig(name):
+    pts, moved, meshes = {}, {}, {}
+    for row in _rows(name):
+        if row[0] == "point":
+            pts[row[1]] = (float(row[2]), float(row[3]))
+        elif row[0] == "moved":
+            moved[row[1]] = (float(row[2]), float(row[3]))
+        else:
+            meshes[row[0]] = {"".join(sorted(t)) for t in row[1:]}
+    names = "".join(sorted(pts))
+    xy = np.array([pts[k] for k in names])
+    xy2 = xy.copy()
+    for k, v in moved.items():
+        xy2[names.index(k)] = v
+    return names, xy, xy2, meshes
+
+
+@pytest.mark.parametrize("n,phi,seed", [(40, 0.3, 1), (120, 0.5, 2), (200, 0.2, 3)])
+def test_delaunay_empty_circumcircle_bruteforce(n, phi, seed):
+    xy = synth.rsa(n, synth.box_side(n, phi), 1.0, seed)
+    tris = oracle.delaunay(xy)
+    for a, b, c in tris:
+        assert oracle.orient2(xy[a], xy[b], xy[c]) > 0
+        for p in range(n):
+            if p in (a, b, c):
+                continue
+            assert oracle.incircle(xy[a], xy[b], xy[c], xy[p]) <= 0.0
+    # Euler counts: triangles 2n-2-h, edges 3n-3-h (h hull vertices, from Qhull)
+    h = len(ConvexHull(xy).vertices)
+    assert len(tris) == 2 * n - 2 - h
+    edges = {tuple(sorted(e)) for t in tris for e in combinations(t.tolist(), 2)}
+    assert len(edges) == 3 * n - 3 - h
+
+
+@pytest.mark.parametrize("n,phi", [(1024, 0.3), (4096, 0.5), (20000, 0.4)])
+def test_delaunay_matches_qhull(n, phi):
+    xy = synth.rsa(n, synth.box_side(n, phi), 1.0, seed=n)
+    assert _tri_set(oracle.delaunay(xy)) == _tri_set(QhullDelaunay(xy).simplices)
+
+
+def test_fig5_panels_are_delaunay():
+    names, xy, xy2, meshes = _load_fig("fig5_inverted_tri1.txt")
+    assert _tri_set(oracle.delaunay(xy), names) == meshes["mesh_a"]
+    assert _tri_set(oracle.delaunay(xy2), names) == meshes["mesh_d"]
+
+
+def test_fig6_start_is_delaunay_final_panel_is_not():
+    names, xy, xy2, meshes = _load_fig("fig6_inverted_tri2.txt")
+    assert _tri_set(oracle.delaunay(xy), names) == meshes["mesh_a"]
+    dt2 = _tri_set(oracle.delaunay(xy2), names)
+    assert dt2 != meshes["mesh_d"]
+    assert dt2 == {"abe", "bef", "bcf", "cdf", "def"}
+
+
+# --------------------------------------------------------------------- inversion predicate
+def test_fig4_predicate():
+    p = {r[0]: (float(r[1]), float(r[2])) for r in _rows("fig4_barycentric.txt")}
+    assert not oracle.inverted_edge_flip(p["v1"], p["v2"], p["v3"], p["v4"])
+    assert oracle.inverted_edge_flip(p["v1"], p["v2"], p["v3"], p["v4_moved"])
+    # v4 moved into the triangle (v1, v2, v3), as the paper states
+    assert oracle.point_in_closed_triangle(p["v1"], p["v2"], p["v3"], p["v4_moved"])
+    # label independence: swapping the two opposite vertices gives the same answer
+    assert oracle.inverted_edge_flip(p["v1"], p["v2"], p["v4_moved"], p["v3"])
+
+
+def _edges_with_opposites(mesh):
+    out = {}
+    for t in mesh:
+        for e in combinations(t, 2):
+            key = "".join(sorted(e))
+            out.setdefault(key, []).append([v for v in t if v not in e][0])
+    return {k: v for k, v in out.items() if len(v) == 2}
+
+
+def test_fig5_predicate_selects_cd():
+    names, xy, xy2, meshes = _load_fig("fig5_inverted_tri1.txt")
+    P = {k: xy2[names.index(k)] for k in names}
+    fired = [e for e, (o1, o2) in _edges_with_opposites(meshes["mesh_a"]).items()
+             if oracle.inverted_edge_flip(P[e[0]], P[e[1]], P[o1], P[o2])]
+    assert fired == ["cd"]
+    # after flipping cd -> ab, the Lawson flip be -> cd: d inside circle (b, e, c)
+    b, c, d, e = P["b"], P["c"], P["d"], P["e"]
+    assert oracle.orient2(b, e, c) > 0
+    assert oracle.incircle(b, e, c, d) == pytest.approx(60.5, abs=1e-12)
+
+
+def test_fig6_predicate_fires_nowhere_then_on_ce():
+    names, xy, xy2, meshes = _load_fig("fig6_inverted_tri2.txt")
+    P = {k: xy2[names.index(k)] for k in names}
+    edges = _edges_with_opposites(meshes["mesh_a"])
+    assert not any(oracle.inverted_edge_flip(P[e[0]], P[e[1]], P[o1], P[o2]) for e, (o1, o2) in edges.items())
+    # the shaded triangle bef is inverted by the move
+    assert oracle.orient2(P["b"], P["e"], P["f"]) * oracle.orient2(xy[1], xy[4], xy[5]) < 0
+    edges_c = _edges_with_opposites(meshes["mesh_c"])
+    fired = [e for e, (o1, o2) in edges_c.items() if oracle.inverted_edge_flip(P[e[0]], P[e[1]], P[o1], P[o2])]
+    assert fired == ["ce"]
+
+
+# --------------------------------------------------------------------- overlap rounds
+@pytest.mark.parametrize("f,expect", [(1.0, "bounce"), (0.5, "contact")])
+def test_single_pair_round(f, expect):
+    xy = np.array([[10.0, 10.0], [11.5, 10.4], [30.0, 30.0], [10.0, 40.0]])
+    rad = np.ones(4)
+    d = math.hypot(1.5, 0.4)
+    out, cnt, hits = oracle.overlap_round(xy, rad, L=50.0, f=f, cap_frac=10.0)
+    assert cnt == 1 and hits == 0
+    d2 = math.hypot(*(out[1] - out[0]))
+    if expect == "bounce":
+        assert d2 == pytest.approx(2 * 2.0 - d, abs=1e-13)
+    else:
+        assert d2 == pytest.approx(2.0, abs=1e-13)
+    # direction kept, centre of mass conserved, far particles untouched
+    np.testing.assert_allclose((out[0] + out[1]) / 2, (xy[0] + xy[1]) / 2, atol=1e-13)
+    u0 = (xy[1] - xy[0]) / d
+    u1 = (out[1] - out[0]) / d2
+    np.testing.assert_allclose(u0, u1, atol=1e-13)
+    assert np.array_equal(out[2:], xy[2:])
+
+
+def test_cap_truncates_to_half_radius():
+    # two disks pressing the centre one from the same side (Sec. 4.4 instability figure)
+    xy = np.array([[20.0, 20.0], [18.6, 20.3], [18.6, 19.7], [40.0, 40.0]])
+    rad = np.ones(4)
+    out, cnt, hits = oracle.overlap_round(xy, rad, L=60.0, f=1.0, cap_frac=0.5)
+    assert cnt >= 2 and hits >= 1
+    assert math.hypot(*(out[0] - xy[0])) == pytest.approx(0.5, abs=1e-14)
+    # direction kept: the uncapped sum points along +x
+    assert out[0][1] == pytest.approx(20.0, abs=1e-14) and out[0][0] > 20.0
+
+
+def test_round_is_idempotent_without_overlaps():
+    xy = synth.rsa(500, synth.box_side(500, 0.5), 1.0, 9)
+    out, cnt, hits = oracle.overlap_round(xy, np.ones(500), L=synth.box_side(500, 0.5))
+    assert cnt == 0 and np.array_equal(out, xy)
+
+
+# --------------------------------------------------------------------- full step
+def _bruteforce_min_gap(xy, r=1.0):
+    from scipy.spatial import cKDTree
+    pairs = cKDTree(xy).query_pairs(2 * r - 1e-12)
+    return len(pairs)
+
+
+def test_free_diffusion_exact_displacement():
+    # K = 0, no walls touched, no overlaps possible (dilute): x(t) - x(0) = sqrt(2 D dt) sum of clamped noise
+    n, L = 64, 4000.0
+    g = np.linspace(500.0, 3500.0, 8)
+    xy = np.array([[a, b] for a in g for b in g])
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.zeros((1, 1)), L=L, D=0.7, dt=0.01,
+                           seed=11)
+    sim.step(20)
+    x1, _, step, st = sim.state()
+    amp = math.sqrt(2 * 0.7 * 0.01)
+    acc = np.zeros((n, 2))
+    for s in range(20):
+        acc += np.clip(oracle.normals(n, 11, s, 0), -3, 3)
+    np.testing.assert_allclose(x1 - xy, amp * acc, atol=1e-11)
+    assert step == 20 and st["overlap_rounds_total"] == 0
+
+
+def test_free_diffusion_msd():
+    n, L = 2000, 1e5
+    xy = synth.rsa(n, L, 1.0, seed=5)
+    D, dt, steps = 1.0, 1e-3, 50
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.zeros((1, 1)), L=L, D=D, dt=dt,
+                           seed=3)
+    sim.step(steps)
+    x1 = sim.state()[0]
+    msd = np.mean(np.sum((x1 - xy) ** 2, axis=1))
+    expect = 4 * D * dt * steps * 0.9950072780
+    assert abs(msd / expect - 1) < 0.07
+
+
+def test_abp_straight_line():
+    n = 16
+    xy = np.array([[200.0 + 40 * (i % 4), 200.0 + 40 * (i // 4)] for i in range(n)])
+    th = np.linspace(0, 2 * math.pi, n, endpoint=False)
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), L=1000.0, D=0.0,
+                           dt=0.05, v0=1.5, Dr=0.0, seed=1)
+    sim.step(40)
+    x1, th1, _, _ = sim.state()
+    np.testing.assert_allclose(x1 - xy, 1.5 * 2.0 * np.stack([np.cos(th), np.sin(th)], 1), atol=1e-12)
+    np.testing.assert_allclose(th1, th, atol=0)
+
+
+def test_rotational_diffusion_exact():
+    n = 8
+    xy = np.array([[100.0 + 30 * (i % 4), 100.0 + 37 * (i // 4)] for i in range(n)])
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), np.zeros(n), np.zeros((1, 1)), L=1000.0,
+                           D=0.0, dt=0.01, v0=0.0, Dr=2.0, seed=4)
+    sim.step(5)
+    th = sim.state()[1]
+    acc = sum(oracle.normals(n, 4, s, 1)[:, 0] for s in range(5))
+    np.testing.assert_allclose(th, math.sqrt(2 * 2.0 * 0.01) * acc, atol=1e-13)
+
+
+def test_steps_leave_no_overlap_and_delaunay():
+    # dense, strong noise: many overlap rounds; after every step no pair overlaps
+    # (brute force) and the stored triangulation equals Qhull's
+    n = 400
+    L = synth.box_side(n, 0.55 * 0.9)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0, dt=2e-3,
+                           seed=2)
+    rounds = 0
+    for _ in range(10):
+        sim.step(1)
+        rounds += sim.last_rounds()
+        x1 = sim.state()[0]
+        assert _bruteforce_min_gap(x1) == 0
+        assert _tri_set(sim.triangles()) == _tri_set(QhullDelaunay(x1).simplices)
+        assert np.all(x1 >= 1.0) and np.all(x1 <= L - 1.0)
+    assert rounds > 0
+    assert sim.state()[3]["noise_clamps"] >= 0
+
+
+def test_reversal_counter_fires_on_huge_step():
+    # two disks side by side, huge dt: the noise swaps them often; counter must see it
+    n = 30
+    xy = np.array([[50.0 + 2.2 * (i % 15), 50.0 + 2.3 * (i // 15)] for i in range(n)])
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.zeros((1, 1)), L=200.0, D=1.0,
+                           dt=4.0, seed=1)
+    sim.step(1)
+    assert sim.state()[3]["reversals"] > 0
+
+
+def test_box_side_matches_paper_abp_example():
+    vals = {r[0]: float(r[1]) for r in _rows("abp_box.txt")}
+    L = synth.box_side(int(vals["N"]), vals["phi"], vals["sigma"] / 2)
+    assert L == pytest.approx(vals["L"], abs=0.05)
