@@ -1,0 +1,198 @@
+/*
+ * bd.h -- C ABI of the MI355X Brownian hard-disk library.
+ *
+ * The library advances N hard disks in a square box with hard walls by the
+ * time step of Carter, Hitschfeld, Navarro and Soto, "GPU parallel simulation
+ * algorithm of Brownian particles with excluded volume using Delaunay
+ * triangulations" (arXiv:1703.02484), Algorithm 1: pair forces, an
+ * Euler-Maruyama move with Brownian noise (Sec. 2.2, 2.4), repair of the
+ * Delaunay triangulation by edge flips (Sec. 4.1, 4.3), and overlap
+ * correction over Delaunay edges (Sec. 2.3, 4.4, Algorithm 2).  The
+ * triangulation and all particle state stay resident in device memory.
+ *
+ * Conventions shared by every entry point:
+ *   - Host arrays are caller-owned.  Inputs are copied before the call
+ *     returns; outputs are written before it returns.
+ *   - Particle arrays are in caller order (the order given to bd_init).
+ *     Positions are interleaved (x0, y0, x1, y1, ...).
+ *   - Every call returns BD_OK (0) or a negative BD_ERR_* code; no C++
+ *     exception crosses this interface.  bd_strerror() names a code and
+ *     bd_last_error() gives the detail of the last failure on a handle.
+ *   - A handle is used by one host thread at a time.
+ */
+#ifndef BD_H
+#define BD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BD_MAX_SPECIES 8
+
+enum bd_error {
+    BD_OK = 0,
+    BD_ERR_INVALID_ARG = -1,     /* NULL pointer, n < 3, NaN or out-of-range parameter */
+    BD_ERR_BAD_INPUT = -2,       /* initial disks overlap or lie outside the walls */
+    BD_ERR_NO_CONVERGENCE = -3,  /* overlap rounds exceeded max_overlap_rounds */
+    BD_ERR_TRIANGULATION = -4,   /* the triangulation could not be built or repaired */
+    BD_ERR_DEVICE = -5,          /* a HIP runtime call failed */
+    BD_ERR_OOM = -6              /* device or pinned host allocation failed */
+};
+
+enum bd_force_kind {
+    BD_FORCE_POWER = 0,     /* g(d) = d^-q: q = 2 is the paper's long-range law r/r^3, q = 6 its r/r^7 */
+    BD_FORCE_SCREENED = 1   /* g(d) = A exp(-d / lambda) / d */
+};
+
+enum bd_precision {
+    BD_PREC_FP64 = 0,       /* forces computed and summed in FP64 */
+    BD_PREC_FP32 = 1        /* forces in FP32 from FP32 copies of the positions; everything else FP64 */
+};
+
+/*
+ * Pair force F_i = sum_{j != i} K[s_i][s_j] g(d_ij) (r_i - r_j) / d_ij
+ * (Sec. 2.2: the two-charge model mu_i alpha_k generalised to an S x S
+ * strength matrix; positive K repels).  With cutoff > 0 only pairs with
+ * d_ij <= cutoff contribute (Sec. 2.2 cutoff rule, no force shift).
+ */
+typedef struct bd_force_params {
+    int32_t kind;        /* bd_force_kind */
+    int32_t S;           /* number of species, 1..BD_MAX_SPECIES */
+    double q;            /* power-law exponent of g (kind POWER) */
+    double A;            /* screened amplitude (kind SCREENED) */
+    double lambda;       /* screening length (kind SCREENED) */
+    double cutoff;       /* <= 0: all pairs */
+    double skin;         /* neighbour-list skin for cutoff > 0 */
+    const double *K;     /* S*S row-major, K[a*S + b] acts on species a from species b; copied */
+} bd_force_params;
+
+/*
+ * Step parameters.  Positions advance by
+ *   x <- x + (F + v0 (cos th, sin th)) dt + sqrt(2 D dt) xi       (Sec. 2.2, Sec. 7)
+ *   th <- th + sqrt(2 Dr dt) n                                   (Sec. 7)
+ * with xi two standard normals clamped to [-noise_clip, noise_clip]
+ * (Sec. 2.4, truncation method) and n one standard normal, drawn from
+ * Philox4x32-10 keyed by (seed, step, particle id, stream).
+ */
+typedef struct bd_params {
+    double L;                    /* box [0, L]^2, hard walls */
+    double D;                    /* translational diffusion coefficient */
+    double dt;                   /* time step */
+    double v0;                   /* self-propulsion speed */
+    double Dr;                   /* rotational diffusion coefficient */
+    uint64_t seed;               /* noise key */
+    int64_t step0;               /* index of the first step (noise counter), for resume */
+    double overlap_factor;       /* Sec. 2.3: 1.0 moves each disk by the overlap ("bounce"), 0.5 to contact */
+    double cap_frac;             /* Sec. 4.4: summed correction truncated to cap_frac * r_i (0.5 = sigma/4) */
+    double noise_clip;           /* Sec. 2.4: clamp of each normal component (3.0) */
+    double contact_tol;          /* a pair overlaps when d < (r_i + r_j)(1 - contact_tol) (1e-9) */
+    int32_t max_overlap_rounds;  /* cap on overlap rounds per step (10000) */
+    int32_t max_flip_rounds;     /* cap on flip rounds per repair before the host rebuild (200) */
+    int32_t force_precision;     /* bd_precision */
+    int32_t reserved;            /* must be 0 */
+} bd_params;
+
+/* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
+typedef struct bd_stats {
+    int64_t steps;
+    int64_t overlap_rounds_total;   /* overlap-correction rounds that moved disks */
+    int64_t overlap_rounds_max;     /* most rounds in one step */
+    int64_t overlap_edges_total;    /* overlapping Delaunay edges corrected, summed over rounds */
+    int64_t cap_hits;               /* per-disk corrections truncated by the cap */
+    int64_t reversals;              /* Delaunay edges whose vector reversed in a move (Sec. 4.3) */
+    int64_t noise_clamps;           /* clamped normal components */
+    int64_t flips_total;            /* edge flips performed on the device */
+    int64_t inversion_flips;        /* of which decided by the inverted-triangle rule (Sec. 4.3) */
+    int64_t flip_rounds_total;      /* parallel flip rounds launched */
+    int64_t kinetic_repairs;        /* repairs redone on the device in sub-steps (multi-edge crossings) */
+    int64_t host_rebuilds;          /* repairs that fell back to a host triangulation */
+    int64_t reserved[4];
+} bd_stats;
+
+typedef struct bd_sim bd_sim;
+
+/* Name of an error code (static string). */
+const char *bd_strerror(int code);
+
+/* Detail of the last failure on sim (static per handle; never NULL; "" if none). */
+const char *bd_last_error(const bd_sim *sim);
+
+/* Fills p with the defaults named in the field comments; L must still be set. */
+void bd_params_default(bd_params *p);
+
+/*
+ * Creates a simulation of n >= 3 disks (Algorithm 1 initial state).
+ *   xy       2n doubles, centres; each must satisfy r_i <= x, y <= L - r_i
+ *   radii    n doubles > 0
+ *   species  n int32 in [0, S)
+ *   theta    n doubles (initial director angles) or NULL for zeros
+ * Disks may touch but not overlap (d_ij >= r_i + r_j), else BD_ERR_BAD_INPUT.
+ * Builds the Delaunay triangulation on the host once (Sec. 4.1) and uploads
+ * it; all later repairs run on the device.  Uses the calling thread's current
+ * HIP device and creates its own stream (see bd_set_stream).
+ * On success *out owns all device memory until bd_destroy.
+ */
+int bd_init(bd_sim **out, int32_t n, const double *xy, const double *radii, const int32_t *species,
+            const double *theta, const bd_force_params *fp, const bd_params *p);
+
+/*
+ * Advances nsteps >= 0 steps of Algorithm 1: forces, move, walls, flip repair
+ * of the triangulation, then overlap rounds (each followed by a repair) until
+ * no Delaunay edge overlaps.  On return the triangulation is the Delaunay
+ * triangulation of the current positions.  On error the state is that of the
+ * last completed step.
+ */
+int bd_step(bd_sim *sim, int64_t nsteps);
+
+/* Forces at the current positions in caller order, 2n doubles.  Does not advance time. */
+int bd_forces(bd_sim *sim, double *f_out);
+
+/*
+ * Copies the state out: xy_out (2n doubles, may be NULL), theta_out (n
+ * doubles, may be NULL), step_out (may be NULL), stats_out (may be NULL).
+ * Synchronises the library's stream.
+ */
+int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
+
+/*
+ * Finite triangles of the resident triangulation, counter-clockwise, caller
+ * ids: 3 int32 per triangle into tri_out (room for cap triangles; 2n is
+ * always enough), count into *ntri_out.  BD_ERR_INVALID_ARG if cap is short.
+ */
+int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out);
+
+/*
+ * Replaces the positions (2n doubles, caller order, inside the walls) and
+ * restores the Delaunay triangulation by the device flip repair (inverted-
+ * triangle flips, Sec. 4.3, with Lawson flips, Sec. 4.1).  When a disk crossed
+ * more than one edge, which the inverted-triangle rule cannot untangle
+ * (Sec. 4.3, two-flip figure), the repair restarts from the previous
+ * triangulation and replays the move in 2, 4, ... 64 equal sub-steps, each
+ * repaired by the same rule; only if that fails is the triangulation rebuilt
+ * on the host.  No overlap correction and no time advance.
+ */
+int bd_set_positions(bd_sim *sim, const double *xy);
+
+/* Runs later work on hip_stream (a hipStream_t; NULL = the library's own stream). */
+int bd_set_stream(bd_sim *sim, void *hip_stream);
+
+/*
+ * Per-kernel timing for measurement: with enable != 0 the library records HIP
+ * events on its stream around each launch of the all-pairs force kernel.
+ * bd_kernel_time() returns the summed milliseconds and launch count since
+ * timing was enabled (it synchronises the stream).
+ */
+int bd_enable_kernel_timing(bd_sim *sim, int enable);
+int bd_kernel_time(bd_sim *sim, double *force_ms, int64_t *force_launches);
+
+/* Frees everything; accepts NULL. */
+void bd_destroy(bd_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BD_H */

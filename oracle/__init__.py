@@ -60,13 +60,14 @@ def _load():
     lib.orc_forces.restype = None
     lib.orc_wall.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.orc_wall.restype = ctypes.c_double
-    lib.orc_overlap_round.argtypes = [ctypes.c_int, V, V, ctypes.c_double, ctypes.c_double, ctypes.c_double, V]
+    lib.orc_overlap_round.argtypes = [ctypes.c_int, V, V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, V]
     lib.orc_overlap_round.restype = ctypes.c_int64
     lib.orc_sim_new.argtypes = [ctypes.c_int, V, V, V, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, ctypes.c_int]
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.orc_sim_new.restype = V
     lib.orc_sim_step.argtypes = [V, ctypes.c_int64]
     lib.orc_sim_step.restype = ctypes.c_int
@@ -163,13 +164,13 @@ def wall(c: float, r: float, L: float) -> float:
     return _load().orc_wall(c, r, L)
 
 
-def overlap_round(xy: np.ndarray, radii, L: float, f: float = 1.0, cap_frac: float = 0.5):
+def overlap_round(xy: np.ndarray, radii, L: float, f: float = 1.0, cap_frac: float = 0.5, contact_tol: float = 1e-9):
     """One Jacobi round on the Delaunay edges of xy; returns (new_xy, n_overlapping_edges, cap_hits)."""
     lib = _load()
     out = np.ascontiguousarray(xy, dtype=np.float64).copy()
     rad = np.ascontiguousarray(radii, dtype=np.float64)
     hits = np.zeros(1, dtype=np.int64)
-    cnt = lib.orc_overlap_round(out.shape[0], _p(out), _p(rad), L, f, cap_frac, _p(hits))
+    cnt = lib.orc_overlap_round(out.shape[0], _p(out), _p(rad), L, f, cap_frac, contact_tol, _p(hits))
     if cnt < 0:
         raise RuntimeError("oracle triangulation failed")
     return out, int(cnt), int(hits[0])
@@ -184,7 +185,7 @@ class OracleSim:
 
     def __init__(self, xy, radii, species, theta, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0,
                  L=100.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0, step0=0, overlap_factor=1.0,
-                 cap_frac=0.5, noise_clip=3.0, max_overlap_rounds=10000):
+                 cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9, max_overlap_rounds=10000):
         lib = _load()
         self._lib = lib
         self.xy0 = np.ascontiguousarray(xy, dtype=np.float64)
@@ -197,7 +198,7 @@ class OracleSim:
         self._h = lib.orc_sim_new(self.n, _p(self.xy0), _p(self._rad), _p(self._sp), _p(self._th), S,
                                   _p(self._K), 0 if kind == "power" else 1, q, A, lam, cutoff, L, D, dt, v0, Dr,
                                   ctypes.c_uint64(seed), int(step0), overlap_factor, cap_frac, noise_clip,
-                                  int(max_overlap_rounds))
+                                  contact_tol, int(max_overlap_rounds))
         if not self._h:
             raise RuntimeError("oracle: initial triangulation failed")
 
@@ -205,7 +206,8 @@ class OracleSim:
     def from_workload(cls, w, **over):
         kw = dict(K=w.K, kind=w.kind, q=w.q, A=w.A, lam=w.lam, cutoff=w.cutoff, L=w.L, D=w.D, dt=w.dt,
                   v0=w.v0, Dr=w.Dr, seed=w.seed, step0=w.step0, overlap_factor=w.overlap_factor,
-                  cap_frac=w.cap_frac, noise_clip=w.noise_clip, max_overlap_rounds=w.max_overlap_rounds)
+                  cap_frac=w.cap_frac, noise_clip=w.noise_clip, contact_tol=w.contact_tol,
+                  max_overlap_rounds=w.max_overlap_rounds)
         kw.update(over)
         return cls(w.xy, w.radii, w.species, w.theta, **kw)
 

@@ -21,7 +21,10 @@
 //     Jacobi-style over all overlapping Delaunay edges (Sec. 4.4, Algorithm 2),
 //     the per-particle sum truncated to length cap_frac * r_i (Sec. 4.4: the
 //     sigma/4 heuristic, half a radius), rounds repeated until no Delaunay
-//     edge overlaps (Sec. 4.4) with a round cap;
+//     edge overlaps (Sec. 4.4) with a round cap; "overlapping" means
+//     d < (r_i + r_j)(1 - contact_tol): with the contact factor 1/2 a pair is
+//     moved exactly to contact and rounding may leave it an ulp short, which a
+//     bare strict test would keep correcting forever;
 //   * the triangulation is recomputed from scratch (Bowyer-Watson) whenever
 //     positions change, including after every overlap round: the Delaunay
 //     triangulation is unique in general position, so this is the plain
@@ -407,11 +410,13 @@ struct Stats {
 };
 
 // One Jacobi overlap round over the given edges, Sec. 2.3 and Sec. 4.4:
-// every overlapping edge (d < r_i + r_j) moves both ends apart along the unit
+// every overlapping edge (d < (r_i + r_j)(1 - tol)) moves both ends apart along the unit
 // vector by f (r_i + r_j - d); the summed move of each particle is truncated to
 // length cap_frac * r_i; walls are applied.  Returns the number of overlapping
 // edges found (0: nothing moved).
-int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac,
+inline bool overlapping(double d, double contact, double tol) { return d < contact * (1.0 - tol); }
+
+int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac, double tol,
                       const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits) {
     std::vector<double> disp(2 * (size_t)n, 0.0);
     std::vector<char> touched(n, 0);
@@ -421,7 +426,7 @@ int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, 
         double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
         double d = std::sqrt(dx * dx + dy * dy);
         double contact = rad[i] + rad[j];
-        if (!(d < contact)) continue;
+        if (!overlapping(d, contact, tol)) continue;
         ++count;
         double s = f * (contact - d) / d;
         disp[2 * i] += s * dx;
@@ -456,7 +461,7 @@ struct Sim {
     double L = 0, D = 0, dt = 0, v0 = 0, Dr = 0;
     uint64_t seed = 0;
     int64_t step = 0;
-    double f = 1.0, cap_frac = 0.5, clip = 3.0;
+    double f = 1.0, cap_frac = 0.5, clip = 3.0, tol = 1e-9;
     int max_rounds = 10000;
     Stats st;
     Delaunay dt_now;
@@ -507,7 +512,7 @@ struct Sim {
         if (!retriangulate()) return -4;
         int rounds = 0;
         for (;;) {
-            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, edges, &st.cap_hits);
+            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, edges, &st.cap_hits);
             if (cnt == 0) break;
             ++rounds;
             st.overlap_edges_total += cnt;
@@ -518,7 +523,7 @@ struct Sim {
                 for (const auto &e : edges) {
                     int i = e.first, j = e.second;
                     double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
-                    if (std::sqrt(dx * dx + dy * dy) < rad[i] + rad[j]) { any = true; break; }
+                    if (overlapping(std::sqrt(dx * dx + dy * dy), rad[i] + rad[j], tol)) { any = true; break; }
                 }
                 if (any) return -3;
                 break;
@@ -593,20 +598,20 @@ double orc_wall(double c, double r, double L) { return wall(c, r, L); }
 
 // One overlap round over the current Delaunay edges of xy (in place).
 // Returns the number of overlapping edges, -4 if the triangulation failed.
-int64_t orc_overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac,
+int64_t orc_overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac, double tol,
                           int64_t *cap_hits) {
     Delaunay d;
     if (!d.build(xy, n)) return -4;
     std::vector<std::pair<int, int>> e;
     d.finite_edges(e);
-    return overlap_round(n, xy, rad, L, f, cap_frac, e, cap_hits);
+    return overlap_round(n, xy, rad, L, f, cap_frac, tol, e, cap_hits);
 }
 
 // --- simulation handle -------------------------------------------------------
 void *orc_sim_new(int n, const double *xy, const double *rad, const int *sp, const double *theta, int S,
                   const double *K, int kind, double q, double A, double lam, double cutoff, double L, double D,
                   double dt, double v0, double Dr, uint64_t seed, int64_t step0, double f, double cap_frac,
-                  double clip, int max_rounds) {
+                  double clip, double tol, int max_rounds) {
     Sim *s = new Sim();
     s->n = n;
     s->xy.assign(xy, xy + 2 * (size_t)n);
@@ -618,7 +623,7 @@ void *orc_sim_new(int n, const double *xy, const double *rad, const int *sp, con
     s->fm.kind = kind; s->fm.q = q; s->fm.A = A; s->fm.lam = lam; s->fm.cutoff = cutoff;
     s->L = L; s->D = D; s->dt = dt; s->v0 = v0; s->Dr = Dr;
     s->seed = seed; s->step = step0;
-    s->f = f; s->cap_frac = cap_frac; s->clip = clip; s->max_rounds = max_rounds;
+    s->f = f; s->cap_frac = cap_frac; s->clip = clip; s->tol = tol; s->max_rounds = max_rounds;
     if (!s->retriangulate()) { delete s; return nullptr; }
     return s;
 }

@@ -1,0 +1,327 @@
+// Per-particle kernels of the time step: the all-pairs force (Sec. 2.2,
+// Sec. 4.1 "one thread per particle, no symmetry used"), the Euler-Maruyama
+// move with Brownian noise and self-propulsion (Sec. 2.2, 2.4, 7) and hard
+// walls.
+//
+// Force layout.  Particles are permuted once so that species are contiguous
+// ("sorted order").  The j range is cut into chunks that never straddle a
+// species boundary; workgroup (bx, c) accumulates, for its 256*P particles i,
+// the unweighted sum Phi_{i,c} = sum_{j in chunk c} (r_i - r_j)/d^3.  The
+// update kernel then forms F_i = sum_c K[s_i][spec(c)] Phi_{i,c} in FP64 in a
+// fixed chunk order (deterministic, no atomics).  Inside the j loop every lane
+// of the wavefront needs the same j, so j positions are wave-uniform loads
+// (scalar data cache) and the VALU only sees the pair arithmetic.
+#include <hip/hip_runtime.h>
+
+#include "bd_internal.h"
+#include "geom.h"
+
+namespace bd {
+namespace {
+
+constexpr int kForceBlock = 256;
+constexpr int kPerLane = 4;   // particles i per lane (register blocking)
+
+// ---------------------------------------------------------------- cast
+template <typename T2>
+__global__ void k_cast(int n, const double *__restrict__ x, const double *__restrict__ y,
+                       const int *__restrict__ sorted_id, T2 *__restrict__ pj) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int i = sorted_id[k];
+    T2 v;
+    v.x = x[i];
+    v.y = y[i];
+    pj[k] = v;
+}
+
+// ---------------------------------------------------------------- forces
+template <typename T>
+__device__ __forceinline__ T rsqrt_t(T v);
+template <>
+__device__ __forceinline__ float rsqrt_t<float>(float v) { return __builtin_amdgcn_rsqf(v); }
+template <>
+__device__ __forceinline__ double rsqrt_t<double>(double v) { return rsqrt(v); }
+
+template <typename T>
+__device__ __forceinline__ T self_floor();
+template <>
+__device__ __forceinline__ float self_floor<float>() { return 1e-20f; }
+template <>
+__device__ __forceinline__ double self_floor<double>() { return 1e-200; }
+
+// Inverse-square law (q = 2, all pairs): Phi += (r_i - r_j) / d^3.
+// SELF: the range may contain i itself; d^2 is floored so the self term is 0.
+template <typename T, typename T2, int P, bool SELF>
+__device__ __forceinline__ void pair_range_q2(const T2 *__restrict__ pj, int j0, int j1, const T (&xi)[P],
+                                              const T (&yi)[P], T (&ax)[P], T (&ay)[P]) {
+#pragma unroll 8
+    for (int j = j0; j < j1; ++j) {
+        const T2 q = pj[j];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T dx = xi[k] - q.x;
+            T dy = yi[k] - q.y;
+            T d2 = dx * dx + dy * dy;
+            if (SELF) d2 = d2 > self_floor<T>() ? d2 : self_floor<T>();
+            T inv = rsqrt_t<T>(d2);
+            T inv3 = inv * inv * inv;
+            ax[k] += dx * inv3;
+            ay[k] += dy * inv3;
+        }
+    }
+}
+
+// General law: power d^-q or screened A exp(-d/lam)/d, optional inclusive cutoff.
+struct LawArgs {
+    int kind;
+    double q, A, lam, cutoff;
+};
+
+template <typename T, typename T2, int P>
+__device__ __forceinline__ void pair_range_general(const T2 *__restrict__ pj, int j0, int j1, const T (&xi)[P],
+                                                   const T (&yi)[P], T (&ax)[P], T (&ay)[P], const LawArgs law) {
+    const T cut2 = law.cutoff > 0.0 ? (T)(law.cutoff * law.cutoff) : (T)0;
+    const T expo = (T)(-0.5 * (law.q + 1.0));
+    const T invlam = (T)(1.0 / law.lam);
+    const T A = (T)law.A;
+    for (int j = j0; j < j1; ++j) {
+        const T2 q = pj[j];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T dx = xi[k] - q.x;
+            T dy = yi[k] - q.y;
+            T d2 = dx * dx + dy * dy;
+            bool ok = d2 > (T)0 && (cut2 == (T)0 || d2 <= cut2);
+            T dd = ok ? d2 : (T)1;
+            T s;
+            if (law.kind == BD_FORCE_POWER) {
+                s = pow(dd, expo);
+            } else {
+                T d = sqrt(dd);
+                s = A * exp(-d * invlam) / dd;
+            }
+            s = ok ? s : (T)0;
+            ax[k] += dx * s;
+            ay[k] += dy * s;
+        }
+    }
+}
+
+template <typename T, typename T2, int P, bool FAST>
+__global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj, int n,
+                                                       const Chunk *__restrict__ chunks, T2 *__restrict__ part,
+                                                       LawArgs law) {
+    const Chunk cd = chunks[blockIdx.y];
+    const int ib = blockIdx.x * (kForceBlock * P);
+    T xi[P], yi[P], ax[P], ay[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        int i = ib + k * kForceBlock + threadIdx.x;
+        T2 v = pj[i < n ? i : n - 1];
+        xi[k] = v.x;
+        yi[k] = v.y;
+        ax[k] = (T)0;
+        ay[k] = (T)0;
+    }
+    if (FAST) {
+        // self range: the workgroup's own particles inside this chunk
+        int lo = cd.js > ib ? cd.js : ib;
+        int hi = cd.je < ib + kForceBlock * P ? cd.je : ib + kForceBlock * P;
+        if (lo < hi) {
+            pair_range_q2<T, T2, P, false>(pj, cd.js, lo, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, true>(pj, lo, hi, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false>(pj, hi, cd.je, xi, yi, ax, ay);
+        } else {
+            pair_range_q2<T, T2, P, false>(pj, cd.js, cd.je, xi, yi, ax, ay);
+        }
+    } else {
+        pair_range_general<T, T2, P>(pj, cd.js, cd.je, xi, yi, ax, ay, law);
+    }
+    T2 *out = part + (size_t)blockIdx.y * n;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        int i = ib + k * kForceBlock + threadIdx.x;
+        if (i < n) {
+            T2 v;
+            v.x = ax[k];
+            v.y = ay[k];
+            out[i] = v;
+        }
+    }
+}
+
+// F_i = sum_c K[s_i][spec(c)] Phi_{i,c}, FP64, fixed chunk order.
+template <typename T2>
+__device__ __forceinline__ void gather_force(const T2 *__restrict__ part, int n, int nchunks,
+                                             const Chunk *__restrict__ chunks, const double *__restrict__ K,
+                                             int S, int si, int k, double &fx, double &fy) {
+    fx = 0.0;
+    fy = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+        double w = K[si * S + chunks[c].spec];
+        T2 v = part[(size_t)c * n + k];
+        fx += w * (double)v.x;
+        fy += w * (double)v.y;
+    }
+}
+
+// ---------------------------------------------------------------- noise
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplies whose high halves are mixed with the other counter words and the
+// round key; the two key words advance by fixed Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        unsigned lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
+        unsigned lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Box-Muller (1958) on two 53-bit uniforms: u1 in (0, 1], u2 in [0, 1).
+__device__ __forceinline__ void box_muller(uint4 w, double &z0, double &z1) {
+#pragma clang fp contract(off)
+    unsigned long long m1 = ((((unsigned long long)w.x) << 32) | w.y) >> 11;
+    unsigned long long m2 = ((((unsigned long long)w.z) << 32) | w.w) >> 11;
+    double u1 = ((double)m1 + 1.0) * 0x1.0p-53;
+    double u2 = (double)m2 * 0x1.0p-53;
+    double rho = sqrt(-2.0 * log(u1));
+    double ang = 2.0 * M_PI * u2;
+    z0 = rho * cos(ang);
+    z1 = rho * sin(ang);
+}
+
+struct EmArgs {
+    int n, S, nchunks;
+    double dt, amp, amp_r, v0, L, clip;
+    uint64_t seed;
+    int64_t step;
+};
+
+// Fused Euler-Maruyama update: gather forces, draw noise (stream 0:
+// translation, stream 1: rotation), move, reflect at the walls, keep the
+// previous state for the reversal check and for error rollback.
+template <typename T2>
+__global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ part, const Chunk *__restrict__ chunks,
+                                            const double *__restrict__ K, const int *__restrict__ pos_of,
+                                            const int *__restrict__ sp, const double *__restrict__ rad,
+                                            double *__restrict__ x, double *__restrict__ y,
+                                            double *__restrict__ xo, double *__restrict__ yo,
+                                            double *__restrict__ th, double *__restrict__ tho,
+                                            unsigned long long *__restrict__ acc) {
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int clamps = 0;
+    if (i < a.n) {
+        double fx, fy;
+        gather_force<T2>(part, a.n, a.nchunks, chunks, K, a.S, sp[i], pos_of[i], fx, fy);
+        const unsigned slo = (unsigned)(unsigned long long)a.step;
+        const unsigned shi = (unsigned)((unsigned long long)a.step >> 32);
+        const uint2 key = make_uint2((unsigned)a.seed, (unsigned)(a.seed >> 32));
+        double zx, zy, nr, unused;
+        box_muller(philox10(make_uint4((unsigned)i, slo, shi, 0u), key), zx, zy);
+        box_muller(philox10(make_uint4((unsigned)i, slo, shi, 1u), key), nr, unused);
+        if (zx > a.clip) { zx = a.clip; ++clamps; }
+        if (zx < -a.clip) { zx = -a.clip; ++clamps; }
+        if (zy > a.clip) { zy = a.clip; ++clamps; }
+        if (zy < -a.clip) { zy = -a.clip; ++clamps; }
+        const double x0 = x[i], y0 = y[i], t0 = th[i], r = rad[i];
+        const double vx = fx + a.v0 * cos(t0);
+        const double vy = fy + a.v0 * sin(t0);
+        const double xn = x0 + vx * a.dt + a.amp * zx;
+        const double yn = y0 + vy * a.dt + a.amp * zy;
+        xo[i] = x0;
+        yo[i] = y0;
+        tho[i] = t0;
+        x[i] = bd_wall(xn, r, a.L);
+        y[i] = bd_wall(yn, r, a.L);
+        th[i] = t0 + a.amp_r * nr;
+    }
+    if (clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
+}
+
+template <typename T2>
+__global__ void k_reduce_forces(int n, int S, int nchunks, const T2 *__restrict__ part,
+                                const Chunk *__restrict__ chunks, const double *__restrict__ K,
+                                const int *__restrict__ pos_of, const int *__restrict__ sp,
+                                double *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double fx, fy;
+    gather_force<T2>(part, n, nchunks, chunks, K, S, sp[i], pos_of[i], fx, fy);
+    out[2 * i] = fx;
+    out[2 * i + 1] = fy;
+}
+
+inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+void launch_cast(Sim &s) {
+    const int nb = blocks_for(s.n, 256);
+    if (s.fp32)
+        hipLaunchKernelGGL(k_cast<float2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sorted_id,
+                           (float2 *)s.pj);
+    else
+        hipLaunchKernelGGL(k_cast<double2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sorted_id,
+                           (double2 *)s.pj);
+}
+
+void launch_force(Sim &s) {
+    LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
+    dim3 grid(blocks_for(s.n, kForceBlock * kPerLane), s.nchunks);
+    if (s.fp32) {
+        if (s.kind_fast)
+            hipLaunchKernelGGL((k_force<float, float2, kPerLane, true>), grid, dim3(kForceBlock), 0, s.stream,
+                               (const float2 *)s.pj, s.n, s.chunks, (float2 *)s.part, law);
+        else
+            hipLaunchKernelGGL((k_force<float, float2, kPerLane, false>), grid, dim3(kForceBlock), 0, s.stream,
+                               (const float2 *)s.pj, s.n, s.chunks, (float2 *)s.part, law);
+    } else {
+        if (s.kind_fast)
+            hipLaunchKernelGGL((k_force<double, double2, kPerLane, true>), grid, dim3(kForceBlock), 0, s.stream,
+                               (const double2 *)s.pj, s.n, s.chunks, (double2 *)s.part, law);
+        else
+            hipLaunchKernelGGL((k_force<double, double2, kPerLane, false>), grid, dim3(kForceBlock), 0, s.stream,
+                               (const double2 *)s.pj, s.n, s.chunks, (double2 *)s.part, law);
+    }
+}
+
+void launch_em(Sim &s) {
+    EmArgs a;
+    a.n = s.n;
+    a.S = s.S;
+    a.nchunks = s.nchunks;
+    a.dt = s.p.dt;
+    a.amp = std::sqrt(2.0 * s.p.D * s.p.dt);
+    a.amp_r = std::sqrt(2.0 * s.p.Dr * s.p.dt);
+    a.v0 = s.p.v0;
+    a.L = s.p.L;
+    a.clip = s.p.noise_clip;
+    a.seed = s.p.seed;
+    a.step = s.step;
+    const int nb = blocks_for(s.n, 256);
+    if (s.fp32)
+        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.chunks,
+                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc);
+    else
+        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.chunks,
+                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc);
+}
+
+void launch_reduce_forces(Sim &s) {
+    const int nb = blocks_for(s.n, 256);
+    if (s.fp32)
+        hipLaunchKernelGGL(k_reduce_forces<float2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S, s.nchunks,
+                           (const float2 *)s.part, s.chunks, s.Kd, s.pos_of, s.sp, s.fout);
+    else
+        hipLaunchKernelGGL(k_reduce_forces<double2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S, s.nchunks,
+                           (const double2 *)s.part, s.chunks, s.Kd, s.pos_of, s.sp, s.fout);
+}
+
+}  // namespace bd

@@ -99,6 +99,7 @@ class Workload:
     overlap_factor: float = 1.0
     cap_frac: float = 0.5
     noise_clip: float = 3.0
+    contact_tol: float = 1e-9   # overlap when d < (r_i + r_j)(1 - contact_tol)
     max_overlap_rounds: int = 10000
     steps: int = 100
     fp32_forces: bool = False

@@ -19,3 +19,12 @@ def gpu_available() -> bool:
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Prints the test id (flushed) before a GPU test starts, so a run that
+    dies on the device still names the case it was in."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield

@@ -1,0 +1,101 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol that
+include/bd.h declares, its struct layouts match the binding, and argument
+validation rejects bad input before any device call."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1703_02484_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = _declared()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(binding.EXPORTED)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(f"""
+#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu\\n", sizeof(bd_params), sizeof(bd_force_params), sizeof(bd_stats));
+  printf("%zu %zu %zu %zu\\n", offsetof(bd_params, seed), offsetof(bd_params, contact_tol),
+         offsetof(bd_params, max_overlap_rounds), offsetof(bd_params, force_precision));
+  printf("%zu %zu\\n", offsetof(bd_force_params, q), offsetof(bd_force_params, K));
+  printf("%zu %zu\\n", offsetof(bd_stats, kinetic_repairs), offsetof(bd_stats, host_rebuilds));
+  return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-o", str(exe), str(src)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    P, F, S = binding.Params, binding.ForceParams, binding.Stats
+    assert vals[0:3] == [ctypes.sizeof(P), ctypes.sizeof(F), ctypes.sizeof(S)]
+    assert vals[3:7] == [P.seed.offset, P.contact_tol.offset, P.max_overlap_rounds.offset,
+                         P.force_precision.offset]
+    assert vals[7:9] == [F.q.offset, F.K.offset]
+    assert vals[9:11] == [S.kinetic_repairs.offset, S.host_rebuilds.offset]
+
+
+def test_params_default():
+    lib = binding.load()
+    p = binding.Params()
+    lib.bd_params_default(ctypes.byref(p))
+    assert p.D == 1.0 and p.dt == 1e-4 and p.overlap_factor == 1.0 and p.cap_frac == 0.5
+    assert p.noise_clip == 3.0 and p.contact_tol == 1e-9 and p.max_overlap_rounds == 10000
+    assert lib.bd_strerror(-3) == b"BD_ERR_NO_CONVERGENCE"
+
+
+def _init(xy, radii=None, L=20.0, **kw):
+    xy = np.asarray(xy, dtype=np.float64)
+    n = xy.shape[0]
+    radii = np.ones(n) if radii is None else radii
+    return binding.Sim(xy, radii, np.zeros(n, np.int32), None, np.array([[1e-2]]), L=L, **kw)
+
+
+# These inputs are rejected by the host-side validation that runs before any
+# device call, so they need no GPU.
+def test_rejects_overlapping_input():
+    with pytest.raises(binding.BDError) as e:
+        _init([[5.0, 5.0], [6.5, 5.0], [10.0, 10.0]])
+    assert e.value.code == -2
+
+
+def test_rejects_disk_outside_walls():
+    with pytest.raises(binding.BDError) as e:
+        _init([[0.5, 5.0], [5.0, 5.0], [10.0, 10.0]])
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("kw", [dict(dt=float("nan")), dict(D=-1.0), dict(contact_tol=0.5),
+                                dict(cap_frac=0.0), dict(L=float("inf"))])
+def test_rejects_bad_parameters(kw):
+    with pytest.raises(binding.BDError) as e:
+        _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], **kw)
+    assert e.value.code == -1
+
+
+def test_rejects_too_few_disks():
+    with pytest.raises(binding.BDError) as e:
+        _init([[5.0, 5.0], [9.0, 5.0]])
+    assert e.value.code == -1

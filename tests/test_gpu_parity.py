@@ -1,0 +1,220 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Tolerances: positions |x_gpu - x_orc| / max(|x_orc|, 1) <= 1e-9 with FP64
+forces and <= 1e-4 with FP32 forces; the triangulation is compared exactly
+(same triangle set as the oracle's Delaunay triangulation).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial import Delaunay as QhullDelaunay
+
+import oracle
+from paper_1703_02484_amd import binding, synth
+from tests._checks import check_delaunay, count_overlaps, rel_err, tri_set
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _pair(w, **over):
+    return binding.Sim.from_workload(w, **over), oracle.OracleSim.from_workload(w, **over)
+
+
+def _force_scale(f):
+    return np.abs(f).max()
+
+
+# ------------------------------------------------------------------ forces
+def test_forces_fp64_c1():
+    w = synth.make("C1")
+    g = binding.Sim.from_workload(w)
+    fo = oracle.forces(w.xy, w.species, w.K)
+    fg = g.forces()
+    assert np.abs(fg - fo).max() <= 1e-12 * _force_scale(fo)
+
+
+@pytest.mark.parametrize("n", [3, 100, 1000, 4099])
+def test_forces_fp32_ragged(n):
+    w = synth.make("C2", n=n)
+    g = binding.Sim.from_workload(w)
+    fo = oracle.forces(w.xy, w.species, w.K)
+    fg = g.forces()
+    assert np.abs(fg - fo).max() <= 1e-4 * _force_scale(fo)
+
+
+def test_forces_fp64_general_power_and_screened():
+    w = synth.make("C1", n=777)
+    for kw in (dict(kind="power", q=6.0), dict(kind="screened", A=1.0, lam=0.5, cutoff=2.5)):
+        g = binding.Sim.from_workload(w, **kw)
+        fo = oracle.forces(w.xy, w.species, w.K, **kw)
+        fg = g.forces()
+        assert np.abs(fg - fo).max() <= 1e-11 * max(_force_scale(fo), 1e-300)
+
+
+def test_forces_full_size_c2_sampled():
+    w = synth.make("C2")
+    g = binding.Sim.from_workload(w)
+    fg = g.forces()
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(w.n, 512, replace=False))
+    fo = oracle.forces(w.xy, w.species, w.K, idx=idx)
+    scale = np.abs(fo).max()
+    assert np.abs(fg[idx] - fo).max() <= 1e-4 * scale
+
+
+# ------------------------------------------------------------------ triangulation
+def test_initial_triangulation_matches_oracle():
+    for w in (synth.make("C1"), synth.make("C2", n=5000), synth.make("C3", n=3000)):
+        g = binding.Sim.from_workload(w)
+        assert tri_set(g.triangles()) == tri_set(oracle.delaunay(w.xy))
+
+
+def _load_fig(name):
+    pts, moved = {}, {}
+    for ln in open(os.path.join(GOLDEN, name)):
+        f = ln.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "point":
+            pts[f[1]] = (float(f[2]), float(f[3]))
+        elif f[0] == "moved":
+            moved[f[1]] = (float(f[2]), float(f[3]))
+    names = "".join(sorted(pts))
+    xy = np.array([pts[k] for k in names]) + 5.0   # keep small disks inside the walls
+    xy2 = xy.copy()
+    for k, v in moved.items():
+        xy2[names.index(k)] = np.array(v) + 5.0
+    return names, xy, xy2
+
+
+def _small_sim(xy):
+    n = xy.shape[0]
+    return binding.Sim(xy, np.full(n, 0.1), np.zeros(n, np.int32), None, np.array([[0.0]]), L=30.0)
+
+
+def test_fig5_single_inversion_then_lawson():
+    names, xy, xy2 = _load_fig("fig5_inverted_tri1.txt")
+    g = _small_sim(xy)
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy))
+    g.set_positions(xy2)
+    st = g.state()[3]
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy2))
+    assert st["inversion_flips"] >= 1 and st["flips_total"] >= 2
+    assert st["kinetic_repairs"] == 0 and st["host_rebuilds"] == 0
+
+
+def test_fig6_two_edge_crossing_is_replayed_on_device():
+    names, xy, xy2 = _load_fig("fig6_inverted_tri2.txt")
+    g = _small_sim(xy)
+    g.set_positions(xy2)
+    st = g.state()[3]
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy2))
+    assert st["kinetic_repairs"] == 1 and st["host_rebuilds"] == 0
+
+
+# ------------------------------------------------------------------ trajectories
+def _run_parity(w, steps, tol, check_every=10, **over):
+    g, o = _pair(w, **over)
+    worst = 0.0
+    for s in range(steps):
+        g.step(1)
+        o.step(1)
+        if (s + 1) % check_every == 0 or s + 1 == steps:
+            xg, tg, sg, stg = g.state()
+            xo, to, so, sto = o.state()
+            worst = max(worst, rel_err(xg, xo))
+            assert worst <= tol, (s, worst)
+            assert np.abs(tg - to).max() <= max(tol, 1e-12)
+            assert sg == so
+            assert tri_set(g.triangles()) == tri_set(o.triangles()), s
+    stg, sto = g.state()[3], o.state()[3]
+    for k in ("overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "reversals", "noise_clamps"):
+        assert stg[k] == sto[k], (k, stg[k], sto[k])
+    assert stg["host_rebuilds"] == 0
+    return worst, stg
+
+
+def test_trajectory_c1_fp64_100_steps():
+    worst, st = _run_parity(synth.make("C1"), 100, 1e-9)
+    assert st["overlap_rounds_total"] > 0
+
+
+def test_trajectory_c2_fp32_reduced_100_steps():
+    worst, st = _run_parity(synth.make("C2", n=4096), 100, 1e-4)
+    assert st["flips_total"] > 0
+
+
+def test_trajectory_c5_contact_factor_fp64():
+    _run_parity(synth.make("C5", n=2048), 50, 1e-9)
+
+
+def test_trajectory_dense_multi_crossings():
+    # strong noise in a dense box: many inversions and multi-edge crossings
+    n = 600
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    w = synth.Workload("dense", xy, np.ones(n), np.zeros(n, np.int32), np.zeros(n), 1, np.array([[0.0]]), L=L,
+                       D=1.0, dt=2e-3, seed=2)
+    worst, st = _run_parity(w, 12, 1e-9, check_every=1)
+    assert st["kinetic_repairs"] > 0
+
+
+def test_full_size_c2_bench_configuration():
+    # the configuration the benchmark times: 3 steps, then properties at full size
+    w = synth.make("C2")
+    g = binding.Sim.from_workload(w)
+    g.step(3)
+    x, th, step, st = g.state()
+    assert step == 3
+    assert np.all(x >= 1.0) and np.all(x <= w.L - 1.0)
+    tris = g.triangles()
+    check_delaunay(x, tris)
+    assert tri_set(tris) == tri_set(QhullDelaunay(x).simplices)
+    assert count_overlaps(x) == 0
+    assert st["host_rebuilds"] == 0
+
+
+# ------------------------------------------------------------------ determinism, resume, errors
+def test_bitwise_run_to_run():
+    w = synth.make("C2", n=3000)
+    a = binding.Sim.from_workload(w)
+    b = binding.Sim.from_workload(w)
+    a.step(15)
+    b.step(15)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    assert tri_set(a.triangles()) == tri_set(b.triangles())
+
+
+def test_resume_from_state():
+    w = synth.make("C1", n=800)
+    a = binding.Sim.from_workload(w)
+    a.step(20)
+    full = a.state()[0]
+    b = binding.Sim.from_workload(w)
+    b.step(10)
+    xy, th, step, _ = b.state()
+    c = binding.Sim(xy, w.radii, w.species, th, w.K, L=w.L, D=w.D, dt=w.dt, seed=w.seed, step0=step)
+    c.step(10)
+    assert rel_err(c.state()[0], full) <= 1e-12
+
+
+def test_round_cap_reports_no_convergence_and_rolls_back():
+    n = 400
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    g = binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0, dt=2e-3, seed=2,
+                    max_overlap_rounds=1)
+    before = None
+    with pytest.raises(binding.BDError) as e:
+        for _ in range(20):
+            before = g.state()[0]
+            g.step(1)
+    assert e.value.code == -3
+    after, _, _, _ = g.state()
+    assert np.array_equal(after, before)
+    check_delaunay(after, g.triangles())
