@@ -158,11 +158,27 @@ int bd_forces(bd_sim *sim, double *f_out);
 int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
 
 /*
- * Finite triangles of the resident triangulation, counter-clockwise, caller
- * ids: 3 int32 per triangle into tri_out (room for cap triangles; 2n is
- * always enough), count into *ntri_out.  BD_ERR_INVALID_ARG if cap is short.
+ * Finite triangles of the resident triangulation, counter-clockwise: 3 int32
+ * per triangle into tri_out (room for cap triangles; 2 (n + m) is always
+ * enough), count into *ntri_out.  Ids 0..n-1 are disks in caller order; ids
+ * n..n+m-1 are the frame points of bd_get_frame.  BD_ERR_INVALID_ARG if cap
+ * is short.
  */
 int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out);
+
+/*
+ * The triangulated point set is the disks plus m fixed frame points outside
+ * the walls, which play the role of the paper's boundary-free periodic
+ * triangulation (Sec. 2.1) for a box with walls: they keep the triangles
+ * along the walls well shaped, and no frame point can lie in the diametral
+ * circle of an overlapping pair, so the closest overlapping pair stays a
+ * Delaunay edge.  Frame: four arcs at 2 r_max beyond the wall lines, one point
+ * per 2 r_max, bowed outwards by at most r_max / 2 (strictly convex), the
+ * bottom, right, top and left sides holding K, K+1, K+2, K+3 points with
+ * K = ceil((L + 4 r_max) / (2 r_max)).  *m_out receives m; with xy_out non-NULL
+ * (room for cap points) the 2m coordinates are written in vertex-id order.
+ */
+int bd_get_frame(bd_sim *sim, double *xy_out, int32_t cap, int32_t *m_out);
 
 /*
  * Replaces the positions (2n doubles, caller order, inside the walls) and

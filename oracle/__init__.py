@@ -8,6 +8,7 @@ library and the GPU library never imports it.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional, Sequence
@@ -79,6 +80,10 @@ def _load():
     lib.orc_sim_forces.restype = None
     lib.orc_sim_triangles.argtypes = [V, V, ctypes.c_int]
     lib.orc_sim_triangles.restype = ctypes.c_int
+    lib.orc_frame.argtypes = [ctypes.c_double, ctypes.c_double, V, ctypes.c_int]
+    lib.orc_frame.restype = ctypes.c_int
+    lib.orc_sim_frame_count.argtypes = [V]
+    lib.orc_sim_frame_count.restype = ctypes.c_int
     lib.orc_sim_free.argtypes = [V]
     lib.orc_sim_free.restype = None
     _lib = lib
@@ -139,6 +144,23 @@ def delaunay(xy: np.ndarray) -> np.ndarray:
     if nt < 0:
         raise RuntimeError(f"oracle delaunay failed ({nt})")
     return out[:nt].copy()
+
+
+def frame(L: float, rmax: float) -> np.ndarray:
+    """Fixed frame points outside the walls of [0, L]^2 (rows x, y)."""
+    lib = _load()
+    cap = int(4 * (math.ceil((L + 4 * rmax) / (2 * rmax)) + 4))
+    out = np.zeros((cap, 2), dtype=np.float64)
+    m = lib.orc_frame(float(L), float(rmax), _p(out), cap)
+    if m < 0:
+        raise RuntimeError("frame buffer too small")
+    return out[:m].copy()
+
+
+def delaunay_with_frame(xy: np.ndarray, L: float, rmax: float) -> np.ndarray:
+    """Delaunay triangles of the disks plus the wall frame (frame ids follow the disks)."""
+    pts = np.concatenate([np.asarray(xy, dtype=np.float64), frame(L, rmax)])
+    return delaunay(pts)
 
 
 def forces(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, idx=None) -> np.ndarray:
@@ -234,7 +256,7 @@ class OracleSim:
         return out
 
     def triangles(self) -> np.ndarray:
-        cap = 2 * self.n + 4
+        cap = 2 * (self.n + self._lib.orc_sim_frame_count(self._h)) + 4
         out = np.zeros((cap, 3), dtype=np.int32)
         nt = self._lib.orc_sim_triangles(self._h, _p(out), cap)
         return out[:nt].copy()

@@ -29,6 +29,13 @@
 //     positions change, including after every overlap round: the Delaunay
 //     triangulation is unique in general position, so this is the plain
 //     definition that the GPU's flip rounds (Sec. 4.1, 4.3) reach faster;
+//   * the triangulated point set is the disks plus a fixed frame of points
+//     outside the walls (see wall_frame): the paper triangulates a periodic
+//     box, which has no boundary; with walls, disks pressed against a wall are
+//     nearly collinear and the bare Delaunay triangulation degenerates into
+//     super-thin triangles along the walls, which the frame prevents.  No frame
+//     point lies in the diametral circle of an overlapping pair, so the
+//     closest overlapping pair is still a Delaunay edge;
 //   * the inverted-triangle predicate of Sec. 4.3 is evaluated for both
 //     orderings of the two opposite vertices (the printed formula tests the
 //     wrong triangle and contradicts its own figure).
@@ -399,6 +406,37 @@ inline double wall(double c, double r, double L) {
     return c;
 }
 
+// Frame of fixed points outside the walls of [0, L]^2: four arcs at
+// 2 rmax beyond the wall lines (bottom, right, top, left, counter-clockwise),
+// one point per 2 rmax along a side of length L + 4 rmax, pushed outwards by
+// (rmax / 2) 4u(1 - u) at relative position u so that all of them are strict
+// hull corners; side j holds K + j points, K = ceil((L + 4 rmax) / (2 rmax)),
+// and starts at its corner.
+void wall_frame(double L, double rmax, std::vector<double> &out) {
+    out.clear();
+    const double a = 2.0 * rmax;
+    const double span = L + 2.0 * a;
+    const double bow_max = 0.5 * rmax;
+    const int K = (int)std::ceil(span / (2.0 * rmax));
+    for (int side = 0; side < 4; ++side) {
+        const int count = K + side;
+        for (int k = 0; k < count; ++k) {
+            const double u = (double)k / (double)count;
+            const double bow = bow_max * (4.0 * u * (1.0 - u));
+            const double t = u * span;
+            double px = 0.0, py = 0.0;
+            switch (side) {
+                case 0: px = t - a; py = -a - bow; break;
+                case 1: px = L + a + bow; py = t - a; break;
+                case 2: px = L + a - t; py = L + a + bow; break;
+                default: px = -a - bow; py = L + a - t; break;
+            }
+            out.push_back(px);
+            out.push_back(py);
+        }
+    }
+}
+
 struct Stats {
     int64_t steps = 0;
     int64_t overlap_rounds_total = 0;
@@ -465,13 +503,21 @@ struct Sim {
     int max_rounds = 10000;
     Stats st;
     Delaunay dt_now;
-    std::vector<std::pair<int, int>> edges;
+    std::vector<double> frame;                 // 2m coordinates
+    std::vector<double> pts;                   // disks then frame, the triangulated set
+    std::vector<std::pair<int, int>> edges;    // Delaunay edges between two disks
     std::vector<double> forces;
     int last_rounds = 0;
 
     bool retriangulate() {
-        if (!dt_now.build(xy.data(), n)) return false;
-        dt_now.finite_edges(edges);
+        pts.assign(xy.begin(), xy.end());
+        pts.insert(pts.end(), frame.begin(), frame.end());
+        if (!dt_now.build(pts.data(), (int)(pts.size() / 2))) return false;
+        std::vector<std::pair<int, int>> all;
+        dt_now.finite_edges(all);
+        edges.clear();
+        for (const auto &e : all)
+            if (e.first < n && e.second < n) edges.push_back(e);
         return true;
     }
 
@@ -607,6 +653,16 @@ int64_t orc_overlap_round(int n, double *xy, const double *rad, double L, double
     return overlap_round(n, xy, rad, L, f, cap_frac, tol, e, cap_hits);
 }
 
+// Frame points (2 doubles each) into out (room for cap points); returns m or -2.
+int orc_frame(double L, double rmax, double *out, int cap) {
+    std::vector<double> f;
+    wall_frame(L, rmax, f);
+    int m = (int)(f.size() / 2);
+    if (m > cap) return -2;
+    std::memcpy(out, f.data(), f.size() * sizeof(double));
+    return m;
+}
+
 // --- simulation handle -------------------------------------------------------
 void *orc_sim_new(int n, const double *xy, const double *rad, const int *sp, const double *theta, int S,
                   const double *K, int kind, double q, double A, double lam, double cutoff, double L, double D,
@@ -624,6 +680,9 @@ void *orc_sim_new(int n, const double *xy, const double *rad, const int *sp, con
     s->L = L; s->D = D; s->dt = dt; s->v0 = v0; s->Dr = Dr;
     s->seed = seed; s->step = step0;
     s->f = f; s->cap_frac = cap_frac; s->clip = clip; s->tol = tol; s->max_rounds = max_rounds;
+    double rmax = 0.0;
+    for (int i = 0; i < n; ++i) rmax = std::max(rmax, rad[i]);
+    wall_frame(L, rmax, s->frame);
     if (!s->retriangulate()) { delete s; return nullptr; }
     return s;
 }
@@ -660,6 +719,8 @@ void orc_sim_forces(void *h, double *out) {
     Sim *s = (Sim *)h;
     forces_subset(s->fm, s->n, s->xy.data(), s->sp.data(), nullptr, s->n, out);
 }
+
+int orc_sim_frame_count(void *h) { return (int)(((Sim *)h)->frame.size() / 2); }
 
 int orc_sim_triangles(void *h, int *tri_out, int cap) {
     Sim *s = (Sim *)h;

@@ -20,7 +20,7 @@ BD_PREC_FP64 = 0
 BD_PREC_FP32 = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_step", "bd_forces",
-            "bd_get_state", "bd_get_triangulation", "bd_set_positions", "bd_set_stream",
+            "bd_get_state", "bd_get_triangulation", "bd_get_frame", "bd_set_positions", "bd_set_stream",
             "bd_enable_kernel_timing", "bd_kernel_time", "bd_destroy")
 
 
@@ -86,6 +86,8 @@ def load() -> ctypes.CDLL:
     lib.bd_get_state.restype = ctypes.c_int
     lib.bd_get_triangulation.argtypes = [V, V, ctypes.c_int32, P(ctypes.c_int32)]
     lib.bd_get_triangulation.restype = ctypes.c_int
+    lib.bd_get_frame.argtypes = [V, V, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.bd_get_frame.restype = ctypes.c_int
     lib.bd_set_positions.argtypes = [V, V]
     lib.bd_set_positions.restype = ctypes.c_int
     lib.bd_set_stream.argtypes = [V, V]
@@ -166,8 +168,17 @@ class Sim:
                     "bd_get_state")
         return xy, th, int(step.value), st.as_dict()
 
+    def frame(self) -> np.ndarray:
+        m = ctypes.c_int32()
+        self._check(self._lib.bd_get_frame(self._h, None, 0, ctypes.byref(m)), "bd_get_frame")
+        out = np.zeros((m.value, 2), dtype=np.float64)
+        self._check(self._lib.bd_get_frame(self._h, _ptr(out), m.value, ctypes.byref(m)), "bd_get_frame")
+        return out
+
     def triangles(self) -> np.ndarray:
-        cap = 2 * self.n + 4
+        m = ctypes.c_int32()
+        self._check(self._lib.bd_get_frame(self._h, None, 0, ctypes.byref(m)), "bd_get_frame")
+        cap = 2 * (self.n + m.value) + 4
         out = np.zeros((cap, 3), dtype=np.int32)
         nt = ctypes.c_int32()
         self._check(self._lib.bd_get_triangulation(self._h, _ptr(out), cap, ctypes.byref(nt)),

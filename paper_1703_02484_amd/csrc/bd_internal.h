@@ -40,11 +40,13 @@ struct Chunk {
 };
 
 struct Sim {
-    int n = 0;          // particles
+    int n = 0;          // particles (vertex ids 0..n-1)
+    int m = 0;          // fixed frame points outside the walls (vertex ids n..n+m-1)
+    int nv = 0;         // finite vertices n + m
     int S = 1;          // species
-    int T = 0;          // triangles incl. ghosts: 2n - 2
+    int T = 0;          // triangles incl. ghosts: 2 nv - 2
     int H = 0;          // half-edges: 3T
-    int inf = 0;        // infinite vertex id (= n)
+    int inf = 0;        // infinite vertex id (= nv)
     bd_params p{};
     bd_force_params fp{};
     std::vector<double> K;           // S*S
@@ -128,6 +130,9 @@ void launch_interp(Sim &s, int i, int k);            // x = xa + (i/k)(xb - xa);
 // arrays of 3(2n-2) entries.  Returns 0, or -1 when all points are collinear
 // or two coincide.
 int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_v, std::vector<int> &he_twin);
+
+// Fixed frame points closing the triangulation outside the walls of [0, L]^2.
+void frame_points(double L, double rmax, std::vector<double> &fx, std::vector<double> &fy);
 
 }  // namespace bd
 

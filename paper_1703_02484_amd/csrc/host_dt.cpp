@@ -9,6 +9,7 @@
 // (in-circle for finite quads, convexity for edges to the infinite vertex).
 // Output is the device half-edge layout: triangle t owns half-edges 3t..3t+2.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <numeric>
 #include <vector>
@@ -195,6 +196,46 @@ struct Mesh {
 };
 
 }  // namespace
+
+// The frame: four bowed arcs just outside the walls, at distance a = 2 rmax
+// beyond each wall line, one point every s = 2 rmax, bowed outwards by up to
+// rmax / 2 so that every frame point is a strict convex-hull corner; side j
+// (bottom, right, top, left, counter-clockwise) has K + j points so that no
+// two sides mirror each other.  Each side contributes its starting corner.
+void frame_points(double L, double rmax, std::vector<double> &fx, std::vector<double> &fy) {
+#pragma clang fp contract(off)
+    const double a = 2.0 * rmax;
+    const double s = 2.0 * rmax;
+    const double bow_max = 0.5 * rmax;
+    const double span = L + 2.0 * a;
+    const int K = (int)std::ceil(span / s);
+    fx.clear();
+    fy.clear();
+    for (int side = 0; side < 4; ++side) {
+        const int cnt = K + side;
+        for (int k = 0; k < cnt; ++k) {
+            const double u = (double)k / (double)cnt;
+            const double bow = bow_max * (4.0 * u * (1.0 - u));
+            const double t = u * span;
+            double px, py;
+            if (side == 0) {
+                px = t - a;
+                py = -a - bow;
+            } else if (side == 1) {
+                px = L + a + bow;
+                py = t - a;
+            } else if (side == 2) {
+                px = L + a - t;
+                py = L + a + bow;
+            } else {
+                px = -a - bow;
+                py = L + a - t;
+            }
+            fx.push_back(px);
+            fy.push_back(py);
+        }
+    }
+}
 
 int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_v, std::vector<int> &he_twin) {
     if (n < 3) return -1;

@@ -2,10 +2,12 @@
 // and 4.3) and overlap correction over Delaunay edges (Sec. 2.3, 4.4,
 // Algorithm 2).
 //
-// Triangulation layout (SoA, ghosts included, T = 2n - 2 triangles):
+// Triangulation layout (SoA, ghosts included).  Vertices are the n disks
+// (ids 0..n-1), the fixed frame points outside the walls (n..nv-1) and the
+// infinite vertex (nv); T = 2 nv - 2 triangles.
 //   he_v[h]     origin vertex of half-edge h; triangle t owns h = 3t..3t+2 CCW
 //   he_twin[h]  opposite half-edge
-//   vert_he[v]  one outgoing half-edge of vertex v (v = n is the infinite vertex)
+//   vert_he[v]  one outgoing half-edge of vertex v
 //
 // One flip round is three launches:
 //   eval   every candidate edge (all edges, or a worklist) applies the flip
@@ -79,7 +81,7 @@ Topo topo_of(Sim &s) {
 // Range guards: a corrupt triangulation must never turn into an out-of-bounds
 // access; it is reported through C_TOPO_ERR and repaired on the host.
 __device__ __forceinline__ bool bad_he(const Topo &t, int h) { return (unsigned)h >= (unsigned)(3 * t.T); }
-__device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v > (unsigned)t.n; }
+__device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v > (unsigned)t.inf; }
 __device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctr[C_TOPO_ERR], 1); }
 
 __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
@@ -101,7 +103,7 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
     const int a = t.he_v[h], b = t.he_v[bd_next(h)], c = t.he_v[bd_prev(h)];
     const int d = t.he_v[bd_prev(tw)];
     if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c) || bad_v(t, d)) return topo_err(t);
-    if (reversal && a != t.inf && b != t.inf) {
+    if (reversal && a < t.n && b < t.n) {
         // Sec. 4.3: the pair passed through each other if the edge vector reversed
         double ox = t.xo[b] - t.xo[a], oy = t.yo[b] - t.yo[a];
         double mx = t.x[b] - t.x[a], my = t.y[b] - t.y[a];
@@ -269,7 +271,7 @@ __global__ void k_ovl_detect(Topo t, int stamp, double keep) {
                 topo_err(t);
                 continue;
             }
-            if (a == t.inf || b == t.inf) continue;
+            if (a >= t.n || b >= t.n) continue;   // frame points and the infinite vertex never overlap
             double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
             double d = sqrt(dx * dx + dy * dy);
             if (d < (t.rad[a] + t.rad[b]) * keep) {
@@ -323,7 +325,7 @@ __global__ void k_ovl_gather(Topo t, int ntouched, double f, double cap_frac, do
     h = best;
     do {
         int w = t.he_v[bd_next(h)];
-        if (w != t.inf) {
+        if (w < t.n) {
             double dx = xv - t.x[w], dy = yv - t.y[w];
             double d = sqrt(dx * dx + dy * dy);
             double contact = rv + t.rad[w];

@@ -59,22 +59,22 @@ void read_counters(Sim &s) {
 }
 
 void upload_topology(Sim &s, const std::vector<int> &he_v, const std::vector<int> &he_twin) {
-    std::vector<int> vh(s.n + 1, -1);
+    std::vector<int> vh(s.nv + 1, -1);
     for (int h = 0; h < s.H; ++h) vh[he_v[h]] = h;
     check(hipMemcpyAsync(s.he_v, he_v.data(), sizeof(int) * s.H, hipMemcpyHostToDevice, s.stream), "he_v");
     check(hipMemcpyAsync(s.he_twin, he_twin.data(), sizeof(int) * s.H, hipMemcpyHostToDevice, s.stream), "twin");
-    check(hipMemcpyAsync(s.vert_he, vh.data(), sizeof(int) * (s.n + 1), hipMemcpyHostToDevice, s.stream), "vh");
+    check(hipMemcpyAsync(s.vert_he, vh.data(), sizeof(int) * (s.nv + 1), hipMemcpyHostToDevice, s.stream), "vh");
     check(hipStreamSynchronize(s.stream), "topology upload");
 }
 
 // Host rebuild of DT(current positions).  Returns BD_OK or BD_ERR_TRIANGULATION.
 int host_rebuild(Sim &s) {
-    std::vector<double> hx(s.n), hy(s.n);
-    check(hipMemcpyAsync(hx.data(), s.x, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "x");
-    check(hipMemcpyAsync(hy.data(), s.y, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "y");
+    std::vector<double> hx(s.nv), hy(s.nv);
+    check(hipMemcpyAsync(hx.data(), s.x, sizeof(double) * s.nv, hipMemcpyDeviceToHost, s.stream), "x");
+    check(hipMemcpyAsync(hy.data(), s.y, sizeof(double) * s.nv, hipMemcpyDeviceToHost, s.stream), "y");
     check(hipStreamSynchronize(s.stream), "rebuild download");
     std::vector<int> hv, ht;
-    if (host_delaunay(s.n, hx.data(), hy.data(), hv, ht) != 0) {
+    if (host_delaunay(s.nv, hx.data(), hy.data(), hv, ht) != 0) {
         s.last_error = "host Delaunay rebuild failed (collinear or coincident positions)";
         return BD_ERR_TRIANGULATION;
     }
@@ -110,7 +110,7 @@ bool flip_rounds(Sim &s, bool full, bool reversal, int count, bool *snap) {
             check(hipMemcpyAsync(s.snap_v, s.he_v, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream), "snap");
             check(hipMemcpyAsync(s.snap_twin, s.he_twin, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream),
                   "snap");
-            check(hipMemcpyAsync(s.snap_vh, s.vert_he, sizeof(int) * (s.n + 1), hipMemcpyDeviceToDevice, s.stream),
+            check(hipMemcpyAsync(s.snap_vh, s.vert_he, sizeof(int) * (s.nv + 1), hipMemcpyDeviceToDevice, s.stream),
                   "snap");
             *snap = true;
         }
@@ -164,7 +164,7 @@ int repair(Sim &s, bool full, bool reversal, int count, MoveFrom from, int ntouc
         check(hipMemcpyAsync(s.he_v, s.snap_v, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream), "restore");
         check(hipMemcpyAsync(s.he_twin, s.snap_twin, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream),
               "restore");
-        check(hipMemcpyAsync(s.vert_he, s.snap_vh, sizeof(int) * (s.n + 1), hipMemcpyDeviceToDevice, s.stream),
+        check(hipMemcpyAsync(s.vert_he, s.snap_vh, sizeof(int) * (s.nv + 1), hipMemcpyDeviceToDevice, s.stream),
               "restore");
         bool ok = true;
         for (int i = 1; i <= k && ok; ++i) {
@@ -346,11 +346,17 @@ int validate_args(int n, const double *xy, const double *radii, const int32_t *s
 
 int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_t *species, const double *theta,
               const bd_force_params *fp, const bd_params *p) {
+    double rmax = 0.0;
+    for (int i = 0; i < n; ++i) rmax = std::max(rmax, radii[i]);
+    std::vector<double> fx, fy;
+    frame_points(p->L, rmax, fx, fy);
     s.n = n;
+    s.m = (int)fx.size();
+    s.nv = n + s.m;
     s.S = fp->S;
-    s.T = 2 * n - 2;
+    s.T = 2 * s.nv - 2;
     s.H = 3 * s.T;
-    s.inf = n;
+    s.inf = s.nv;
     s.p = *p;
     s.fp = *fp;
     s.K.assign(fp->K, fp->K + fp->S * fp->S);
@@ -362,11 +368,18 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     check(hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking), "stream");
     s.stream = s.own_stream;
 
-    std::vector<double> hx(n), hy(n), hth(n, 0.0);
+    // finite vertices: the disks, then the frame, then one padding entry for the infinite vertex
+    const int nv = s.nv;
+    std::vector<double> hx(nv + 1, 0.0), hy(nv + 1, 0.0), hth(n, 0.0), hrad(nv + 1, 0.0);
     for (int i = 0; i < n; ++i) {
         hx[i] = xy[2 * i];
         hy[i] = xy[2 * i + 1];
+        hrad[i] = radii[i];
         if (theta) hth[i] = theta[i];
+    }
+    for (int k = 0; k < s.m; ++k) {
+        hx[n + k] = fx[k];
+        hy[n + k] = fy[k];
     }
     // species-sorted permutation (stable: ids ascending inside a species)
     std::vector<int> sorted(n), pos(n), block_start(s.S + 1, 0);
@@ -382,14 +395,13 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     }
     setup_chunks(s, block_start);
 
-    // one padding entry past the last particle stands for the infinite vertex
-    s.x = dalloc<double>(n + 1);
-    s.y = dalloc<double>(n + 1);
-    s.xo = dalloc<double>(n + 1);
-    s.yo = dalloc<double>(n + 1);
+    s.x = dalloc<double>(nv + 1);
+    s.y = dalloc<double>(nv + 1);
+    s.xo = dalloc<double>(nv + 1);
+    s.yo = dalloc<double>(nv + 1);
     s.th = dalloc<double>(n);
     s.tho = dalloc<double>(n);
-    s.rad = dalloc<double>(n + 1);
+    s.rad = dalloc<double>(nv + 1);
     s.sp = dalloc<int>(n);
     s.sorted_id = dalloc<int>(n);
     s.pos_of = dalloc<int>(n);
@@ -401,7 +413,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.fout = dalloc<double>(2 * (size_t)n);
     s.he_v = dalloc<int>(s.H);
     s.he_twin = dalloc<int>(s.H);
-    s.vert_he = dalloc<int>(n + 1);
+    s.vert_he = dalloc<int>(nv + 1);
     s.claim = dalloc<unsigned long long>(s.T);
     s.tri_stamp = dalloc<int>(s.T);
     s.moved = dalloc<int>(s.H);
@@ -416,7 +428,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.oldpos = dalloc<double2>(n);
     s.snap_v = dalloc<int>(s.H);
     s.snap_twin = dalloc<int>(s.H);
-    s.snap_vh = dalloc<int>(n + 1);
+    s.snap_vh = dalloc<int>(nv + 1);
     s.xa = dalloc<double>(n);
     s.ya = dalloc<double>(n);
     s.xb = dalloc<double>(n);
@@ -427,25 +439,19 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     if (hipHostMalloc((void **)&s.hacc, sizeof(unsigned long long) * N_ACC, hipHostMallocDefault) != hipSuccess)
         throw std::bad_alloc();
 
-    check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "x");
-    check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "y");
-    check(hipMemcpyAsync(s.xo, hx.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "xo");
-    check(hipMemcpyAsync(s.yo, hy.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "yo");
+    check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "x");
+    check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "y");
+    check(hipMemcpyAsync(s.xo, hx.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "xo");
+    check(hipMemcpyAsync(s.yo, hy.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "yo");
     check(hipMemcpyAsync(s.th, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "th");
     check(hipMemcpyAsync(s.tho, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "tho");
-    check(hipMemcpyAsync(s.rad, radii, sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "rad");
+    check(hipMemcpyAsync(s.rad, hrad.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "rad");
     check(hipMemcpyAsync(s.sp, species, sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sp");
     check(hipMemcpyAsync(s.sorted_id, sorted.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sorted");
     check(hipMemcpyAsync(s.pos_of, pos.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "pos");
     check(hipMemcpyAsync(s.chunks, s.chunks_h.data(), sizeof(Chunk) * s.nchunks, hipMemcpyHostToDevice, s.stream),
           "chunks");
     check(hipMemcpyAsync(s.Kd, s.K.data(), sizeof(double) * s.S * s.S, hipMemcpyHostToDevice, s.stream), "K");
-    const double pad = 0.0;
-    check(hipMemcpyAsync(s.x + n, &pad, sizeof(double), hipMemcpyHostToDevice, s.stream), "pad");
-    check(hipMemcpyAsync(s.y + n, &pad, sizeof(double), hipMemcpyHostToDevice, s.stream), "pad");
-    check(hipMemcpyAsync(s.xo + n, &pad, sizeof(double), hipMemcpyHostToDevice, s.stream), "pad");
-    check(hipMemcpyAsync(s.yo + n, &pad, sizeof(double), hipMemcpyHostToDevice, s.stream), "pad");
-    check(hipMemcpyAsync(s.rad + n, &pad, sizeof(double), hipMemcpyHostToDevice, s.stream), "pad");
     check(hipMemsetAsync(s.claim, 0, sizeof(unsigned long long) * s.T, s.stream), "claim");
     check(hipMemsetAsync(s.tri_stamp, 0, sizeof(int) * s.T, s.stream), "tri_stamp");
     check(hipMemsetAsync(s.edge_stamp, 0, sizeof(int) * s.H, s.stream), "edge_stamp");
@@ -454,8 +460,8 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     check(hipMemsetAsync(s.ctr, 0, sizeof(int) * N_CTR, s.stream), "ctr");
 
     std::vector<int> hv, ht;
-    if (host_delaunay(n, hx.data(), hy.data(), hv, ht) != 0) {
-        s.last_error = "initial Delaunay triangulation failed (collinear or coincident positions)";
+    if (host_delaunay(nv, hx.data(), hy.data(), hv, ht) != 0) {
+        s.last_error = "initial Delaunay triangulation failed (coincident positions)";
         return BD_ERR_TRIANGULATION;
     }
     upload_topology(s, hv, ht);
@@ -619,6 +625,28 @@ int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *nt
             ++cnt;
         }
         *ntri_out = cnt;
+        return (int)BD_OK;
+    });
+}
+
+int bd_get_frame(bd_sim *sim, double *xy_out, int32_t cap, int32_t *m_out) {
+    if (!sim || !m_out) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    *m_out = s.m;
+    if (!xy_out) return BD_OK;
+    if (cap < s.m) {
+        s.last_error = "frame buffer too small";
+        return BD_ERR_INVALID_ARG;
+    }
+    return bd::guarded(s, [&] {
+        std::vector<double> hx(s.m), hy(s.m);
+        bd::check(hipMemcpyAsync(hx.data(), s.x + s.n, sizeof(double) * s.m, hipMemcpyDeviceToHost, s.stream), "x");
+        bd::check(hipMemcpyAsync(hy.data(), s.y + s.n, sizeof(double) * s.m, hipMemcpyDeviceToHost, s.stream), "y");
+        bd::check(hipStreamSynchronize(s.stream), "sync");
+        for (int k = 0; k < s.m; ++k) {
+            xy_out[2 * k] = hx[k];
+            xy_out[2 * k + 1] = hy[k];
+        }
         return (int)BD_OK;
     });
 }

@@ -68,10 +68,19 @@ def test_forces_full_size_c2_sampled():
 
 
 # ------------------------------------------------------------------ triangulation
+def test_frame_matches_oracle():
+    for w in (synth.make("C1"), synth.make("C3", n=3000)):
+        g = binding.Sim.from_workload(w)
+        assert np.array_equal(g.frame(), oracle.frame(w.L, 1.0))
+
+
 def test_initial_triangulation_matches_oracle():
     for w in (synth.make("C1"), synth.make("C2", n=5000), synth.make("C3", n=3000)):
         g = binding.Sim.from_workload(w)
-        assert tri_set(g.triangles()) == tri_set(oracle.delaunay(w.xy))
+        assert tri_set(g.triangles()) == tri_set(oracle.delaunay_with_frame(w.xy, w.L, 1.0))
+
+
+FIG_L = 60.0
 
 
 def _load_fig(name):
@@ -85,25 +94,39 @@ def _load_fig(name):
         elif f[0] == "moved":
             moved[f[1]] = (float(f[2]), float(f[3]))
     names = "".join(sorted(pts))
-    xy = np.array([pts[k] for k in names]) + 5.0   # keep small disks inside the walls
+    # centred in a 60-box, far from the wall frame, so the figure's own
+    # triangles are Delaunay with the frame present
+    xy = np.array([pts[k] for k in names]) + 27.0
     xy2 = xy.copy()
     for k, v in moved.items():
-        xy2[names.index(k)] = np.array(v) + 5.0
+        xy2[names.index(k)] = np.array(v) + 27.0
     return names, xy, xy2
 
 
 def _small_sim(xy):
     n = xy.shape[0]
-    return binding.Sim(xy, np.full(n, 0.1), np.zeros(n, np.int32), None, np.array([[0.0]]), L=30.0)
+    return binding.Sim(xy, np.full(n, 0.1), np.zeros(n, np.int32), None, np.array([[0.0]]), L=FIG_L)
+
+
+def _fig_tris(g, names):
+    # triangles among the figure's own points
+    return {"".join(sorted(names[i] for i in t)) for t in g.triangles().tolist() if max(t) < len(names)}
+
+
+def _fig_dt(xy, names):
+    return {"".join(sorted(names[i] for i in t)) for t in oracle.delaunay_with_frame(xy, FIG_L, 0.1).tolist()
+            if max(t) < len(names)}
 
 
 def test_fig5_single_inversion_then_lawson():
     names, xy, xy2 = _load_fig("fig5_inverted_tri1.txt")
     g = _small_sim(xy)
-    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy))
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay_with_frame(xy, FIG_L, 0.1))
+    assert _fig_tris(g, names) == {"acd", "bcd", "bce", "bde"}      # panel (a)
     g.set_positions(xy2)
     st = g.state()[3]
-    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy2))
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay_with_frame(xy2, FIG_L, 0.1))
+    assert _fig_tris(g, names) == {"abc", "abd", "bcd", "cde"}      # panel (d)
     assert st["inversion_flips"] >= 1 and st["flips_total"] >= 2
     assert st["kinetic_repairs"] == 0 and st["host_rebuilds"] == 0
 
@@ -113,7 +136,8 @@ def test_fig6_two_edge_crossing_is_replayed_on_device():
     g = _small_sim(xy)
     g.set_positions(xy2)
     st = g.state()[3]
-    assert tri_set(g.triangles()) == tri_set(oracle.delaunay(xy2))
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay_with_frame(xy2, FIG_L, 0.1))
+    assert _fig_tris(g, names) == {"abe", "bef", "bcf", "cdf", "def"}
     assert st["kinetic_repairs"] == 1 and st["host_rebuilds"] == 0
 
 
@@ -153,15 +177,36 @@ def test_trajectory_c5_contact_factor_fp64():
     _run_parity(synth.make("C5", n=2048), 50, 1e-9)
 
 
-def test_trajectory_dense_multi_crossings():
-    # strong noise in a dense box: many inversions and multi-edge crossings
+def test_trajectory_dense_strong_noise():
+    # dense box, noise amplitude ~0.2 per step: many overlap rounds and cap truncations
     n = 600
     L = synth.box_side(n, 0.5)
     xy = synth.rsa(n, L, 1.0, seed=8)
     w = synth.Workload("dense", xy, np.ones(n), np.zeros(n, np.int32), np.zeros(n), 1, np.array([[0.0]]), L=L,
-                       D=1.0, dt=2e-3, seed=2)
+                       D=1.0, dt=2e-2, seed=2)
     worst, st = _run_parity(w, 12, 1e-9, check_every=1)
-    assert st["kinetic_repairs"] > 0
+    assert st["cap_hits"] > 0 and st["overlap_rounds_max"] >= 3
+
+
+def test_large_moves_repaired_on_device():
+    # in a dilute box, 2% of the disks jump 1.5-3 units: some cross more than
+    # one edge, which the device resolves by replaying the move in sub-steps
+    rng = np.random.default_rng(3)
+    n = 3000
+    L = synth.box_side(n, 0.15)
+    xy = synth.rsa(n, L, 1.0, seed=3)
+    g = binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L)
+    moved = xy.copy()
+    pick = rng.choice(n, n // 50, replace=False)
+    ang = rng.uniform(0, 2 * np.pi, pick.size)
+    rad = rng.uniform(1.5, 3.0, pick.size)
+    target = moved[pick] + np.column_stack([rad * np.cos(ang), rad * np.sin(ang)])
+    inside = np.all((target > 1.0) & (target < L - 1.0), axis=1)   # jumps leaving the box are skipped
+    moved[pick[inside]] = target[inside]
+    g.set_positions(moved)
+    st = g.state()[3]
+    assert tri_set(g.triangles()) == tri_set(oracle.delaunay_with_frame(moved, L, 1.0))
+    assert st["kinetic_repairs"] >= 1 and st["host_rebuilds"] == 0
 
 
 def test_full_size_c2_bench_configuration():
@@ -173,8 +218,9 @@ def test_full_size_c2_bench_configuration():
     assert step == 3
     assert np.all(x >= 1.0) and np.all(x <= w.L - 1.0)
     tris = g.triangles()
-    check_delaunay(x, tris)
-    assert tri_set(tris) == tri_set(QhullDelaunay(x).simplices)
+    pts = np.concatenate([x, g.frame()])
+    check_delaunay(pts, tris)
+    assert tri_set(tris) == tri_set(QhullDelaunay(pts).simplices)
     assert count_overlaps(x) == 0
     assert st["host_rebuilds"] == 0
 
@@ -217,4 +263,4 @@ def test_round_cap_reports_no_convergence_and_rolls_back():
     assert e.value.code == -3
     after, _, _, _ = g.state()
     assert np.array_equal(after, before)
-    check_delaunay(after, g.triangles())
+    check_delaunay(np.concatenate([after, g.frame()]), g.triangles())

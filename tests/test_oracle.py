@@ -327,9 +327,41 @@ def test_rotational_diffusion_exact():
     np.testing.assert_allclose(th, math.sqrt(2 * 2.0 * 0.01) * acc, atol=1e-13)
 
 
+def test_frame_is_strictly_convex_outside_the_walls():
+    for L, r in ((103.5534, 1.0), (30.0, 0.1), (717.4389, 1.0)):
+        f = oracle.frame(L, r)
+        K = math.ceil((L + 4 * r) / (2 * r))
+        assert len(f) == 4 * K + 6
+        # every frame point is a hull vertex (strictly convex chain)
+        assert len(ConvexHull(f).vertices) == len(f)
+        # at least 2 r beyond the wall lines, at most 2.5 r
+        dist = np.maximum(np.maximum(-f[:, 0], f[:, 0] - L), np.maximum(-f[:, 1], f[:, 1] - L))
+        assert dist.min() >= 2 * r - 1e-12 and dist.max() <= 2.5 * r + 1e-12
+        # consecutive points no farther apart than 2 r along a side (plus the bow)
+        gaps = np.hypot(*(np.roll(f, -1, 0) - f).T)
+        assert gaps.max() <= 2 * r * 1.01
+
+
+def test_frame_keeps_closest_overlapping_pair_delaunay():
+    # disks pressed into a corner and along a wall, with a few overlaps: the
+    # closest overlapping pair is an edge of DT(disks + frame)
+    rng = np.random.default_rng(5)
+    L = 40.0
+    for _ in range(50):
+        xy = np.column_stack([rng.uniform(1, 8, 12), rng.uniform(1, 1.3, 12)])
+        d = np.hypot(*(xy[:, None] - xy[None]).transpose(2, 0, 1))
+        np.fill_diagonal(d, np.inf)
+        i, j = np.unravel_index(np.argmin(d), d.shape)
+        if d[i, j] >= 2.0:
+            continue
+        tris = oracle.delaunay_with_frame(xy, L, 1.0)
+        edges = {tuple(sorted(e)) for t in tris.tolist() for e in combinations(t, 2)}
+        assert (min(i, j), max(i, j)) in edges
+
+
 def test_steps_leave_no_overlap_and_delaunay():
     # dense, strong noise: many overlap rounds; after every step no pair overlaps
-    # (brute force) and the stored triangulation equals Qhull's
+    # (brute force) and the stored triangulation equals Qhull's on disks + frame
     n = 400
     L = synth.box_side(n, 0.55 * 0.9)
     xy = synth.rsa(n, L, 1.0, seed=8)
@@ -341,7 +373,8 @@ def test_steps_leave_no_overlap_and_delaunay():
         rounds += sim.last_rounds()
         x1 = sim.state()[0]
         assert _bruteforce_min_gap(x1) == 0
-        assert _tri_set(sim.triangles()) == _tri_set(QhullDelaunay(x1).simplices)
+        pts = np.concatenate([x1, oracle.frame(L, 1.0)])
+        assert _tri_set(sim.triangles()) == _tri_set(QhullDelaunay(pts).simplices)
         assert np.all(x1 >= 1.0) and np.all(x1 <= L - 1.0)
     assert rounds > 0
     assert sim.state()[3]["noise_clamps"] >= 0
