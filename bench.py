@@ -30,6 +30,24 @@ PEAK_FP32_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FMA)
 PEAK_FP32_NONPACKED = 78.6     # 256 CU x 64 lanes x 2 flops x 2.4 GHz without packed FP32
 PEAK_FP64_TFLOPS = 78.6
 
+# HBM bytes per k_force launch on the default workload from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
+# 1 GiB copy; valid only for the kernel source it was measured on (sha1 below).
+MEASURED_TRAFFIC = {"sha1": "8bac9cffa81cb2ad39614b828de57ecf8b0b0d69", "workload": "C2", "n": 65536,
+                    "bytes_per_launch": 24767440.7}
+
+
+def measured_traffic(workload, n):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1703_02484_amd", "csrc", "k_particles.hip")
+    with open(src, "rb") as fh:
+        h = hashlib.sha1(fh.read()).hexdigest()
+    m = MEASURED_TRAFFIC
+    if h != m["sha1"] or workload != m["workload"] or n != m["n"]:
+        return None
+    return m["bytes_per_launch"]
+
 
 def cpu_baseline(w):
     import oracle
@@ -50,6 +68,8 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design note, "
@@ -65,6 +85,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read_per_dispatch": nbytes, "bytes_written_per_dispatch": nbytes,
+                                               "dispatches": 5}}), flush=True)
+        return
     w = synth.make(args.workload, n=args.n)
     sim = binding.Sim.from_workload(w)
     sim.step(args.warmup)
@@ -121,7 +151,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": measured_traffic(w.name, n),
+            "traffic_unit": "bytes per launch",
             "flops_per_launch": FLOPS_PER_PAIR * pairs,
             "avg_launch_ms": avg_force_s * 1e3,
             "launches": launches,
