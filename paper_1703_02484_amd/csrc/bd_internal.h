@@ -12,18 +12,31 @@
 
 namespace bd {
 
-// Device int32 counters (ctr[]) and uint64 accumulators (acc[]).
-enum Ctr {
-    C_CAND = 0,
-    C_WL_NEXT = 1,
-    C_TOUCHED = 2,
-    C_OVL_EDGES = 3,
-    C_INVALID = 4,
-    C_STAR_OVF = 5,
-    C_TOPO_ERR = 6,   // an index read from the triangulation was out of range
-    C_INVERTED = 7,   // evaluated quads holding an inverted or flat finite triangle
-    N_CTR = 16
+// Device control block (int32 ctl[]): flags and per-slot work counts.  A step
+// is enqueued as a budgeted sequence of rounds; every round uses its own count
+// slots, so no count is reset or read back between launches.
+constexpr int MAXR = 160;     // flip-round slots (even: worklists alternate by slot parity)
+constexpr int MAXREP = 48;    // repair slots
+constexpr int MAXO = 48;      // overlap-round slots
+enum Ctl {
+    K_HALT = 0,        // nonzero: stop; the host finishes the step
+    K_REASON = 1,      // HaltReason
+    K_STAGE = 2,       // repair slot (or overlap round) where the step halted
+    K_DONE = 3,        // the overlap loop found no overlapping edge
+    K_TOPO = 4,        // an index read from the triangulation was out of range
+    K_STAR = 5,        // a vertex star walk exceeded its bound
+    K_OVL_ROUNDS = 6,  // overlap rounds that moved disks in the budgeted sequence
+    K_LAST = 7,        // last round slot of the repair that halted
+    K_CAND = 8,                      // [MAXR] flip candidates of round slot j
+    K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
+    K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
+    K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
+    K_TOUCH = K_INV + MAXREP,        // [MAXO] disks queued by overlap round k
+    K_OVL = K_TOUCH + MAXO,          // [MAXO] overlapping edges found by overlap round k
+    N_CTL = K_OVL + MAXO
 };
+enum HaltReason { HALT_REPAIR_BUDGET = 1, HALT_INVALID = 2, HALT_TOPOLOGY = 3, HALT_OVERLAP_BUDGET = 4 };
+
 enum Acc {
     A_FLIPS = 0,
     A_INV_FLIPS = 1,
@@ -77,8 +90,7 @@ struct Sim {
     int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
     unsigned long long *claim = nullptr;
     int *tri_stamp = nullptr, *moved = nullptr, *edge_stamp = nullptr, *vstamp = nullptr;
-    int *wl[2] = {nullptr, nullptr};
-    int wl_cur = 0;
+    int *wl[2] = {nullptr, nullptr};   // worklists; round slot j reads wl[j & 1]
     int2 *cand = nullptr;
     int *cand_won = nullptr;
     int *touched = nullptr;
@@ -89,11 +101,13 @@ struct Sim {
     double *xa = nullptr, *ya = nullptr, *xb = nullptr, *yb = nullptr;
     int round_id = 0;                // flip-round stamp
     int vround = 0;                  // overlap-round stamp
-    // counters
-    int *ctr = nullptr;
+    // control block and accumulators
+    int *ctl = nullptr;
     unsigned long long *acc = nullptr;
-    int *hctr = nullptr;             // pinned mirror of ctr
+    int *hctl = nullptr;             // pinned mirror of ctl
     unsigned long long *hacc = nullptr;
+    // round budgets of the enqueued step (adapted to recent steps)
+    int budget_em_rounds = 5, budget_ovl_rounds = 4, budget_overlaps = 3;
 
     // host-side stats
     bd_stats st{};
@@ -111,19 +125,23 @@ void launch_cast(Sim &s);
 void launch_force(Sim &s);
 void launch_em(Sim &s);
 void launch_reduce_forces(Sim &s);
-// triangulation
-void launch_flip_eval_full(Sim &s, int round, bool reversal);
-void launch_flip_eval_list(Sim &s, int round, int count);
-void launch_flip_apply(Sim &s, int round, int ncand);
-void launch_flip_fix(Sim &s, int round, int ncand);
-void launch_validate(Sim &s);
-// overlap correction
-void launch_ovl_detect(Sim &s, int vstamp);
-void launch_ovl_gather(Sim &s, int ntouched);
-void launch_ovl_apply(Sim &s, int ntouched, int next_round);
+// triangulation (slot: round slot in ctl; rep: repair slot)
+void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal);
+void launch_flip_eval_list(Sim &s, int round, int slot);
+void launch_flip_apply(Sim &s, int round, int slot);
+void launch_flip_fix(Sim &s, int round, int slot);
+void launch_validate(Sim &s, int rep);
+void launch_repair_check(Sim &s, int rep, int last);
+void launch_snapshot(Sim &s);
+// overlap correction (k: overlap-round slot)
+void launch_ovl_detect(Sim &s, int vstamp, int k);
+void launch_ovl_check(Sim &s, int k);
+void launch_final_check(Sim &s, int k);
+void launch_ovl_gather(Sim &s, int k);
+void launch_ovl_apply(Sim &s, int k, int next_round, int slot);
 // kinetic fallback helpers
-void launch_scatter_oldpos(Sim &s, int ntouched);   // xa[v] = oldpos for touched v
-void launch_interp(Sim &s, int i, int k);            // x = xa + (i/k)(xb - xa); exactly xb when i == k
+void launch_scatter_oldpos(Sim &s, int k);            // xa[v] = old position for disks touched in round k
+void launch_interp(Sim &s, int i, int k);             // x = xa + (i/k)(xb - xa); exactly xb when i == k
 
 // ---- host triangulation (host_dt.cpp) --------------------------------------
 // Delaunay triangulation of (x[i], y[i]) with infinite vertex n, as half-edge

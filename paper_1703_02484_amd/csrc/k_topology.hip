@@ -25,6 +25,12 @@
 //          re-queues itself.
 // The globally lowest candidate always wins both claims, so every round with a
 // candidate makes progress.
+//
+// Control.  Work counts live in the device control block `ctl` in per-round
+// and per-overlap-round slots, so a whole step can be enqueued without the
+// host reading anything back: every kernel reads its count from `ctl` and
+// returns at once when the step has halted (an error or an exhausted budget,
+// left for the host to finish) or the overlap loop is done.
 #include <hip/hip_runtime.h>
 
 #include "bd_internal.h"
@@ -32,6 +38,8 @@
 
 namespace bd {
 namespace {
+
+constexpr int kMaxGrid = 512;
 
 struct Topo {
     int n, inf, T;
@@ -41,10 +49,10 @@ struct Topo {
     int *tri_stamp, *moved, *edge_stamp, *vstamp;
     int2 *cand;
     int *cand_won;
-    int *wl_in, *wl_out;
+    int *wl0, *wl1;
     int *touched;
     double2 *newpos, *oldpos;
-    int *ctr;
+    int *ctl;
     unsigned long long *acc;
 };
 
@@ -68,36 +76,58 @@ Topo topo_of(Sim &s) {
     t.vstamp = s.vstamp;
     t.cand = s.cand;
     t.cand_won = s.cand_won;
-    t.wl_in = s.wl[s.wl_cur];
-    t.wl_out = s.wl[s.wl_cur ^ 1];
+    t.wl0 = s.wl[0];
+    t.wl1 = s.wl[1];
     t.touched = s.touched;
     t.newpos = s.newpos;
     t.oldpos = s.oldpos;
-    t.ctr = s.ctr;
+    t.ctl = s.ctl;
     t.acc = s.acc;
     return t;
 }
 
+__device__ __forceinline__ bool stopped(const int *ctl) { return (ctl[K_HALT] | ctl[K_DONE]) != 0; }
+__device__ __forceinline__ int *wl_of(const Topo &t, int slot) { return (slot & 1) ? t.wl1 : t.wl0; }
+
 // Range guards: a corrupt triangulation must never turn into an out-of-bounds
-// access; it is reported through C_TOPO_ERR and repaired on the host.
+// access; it is reported through K_TOPO and repaired on the host.
 __device__ __forceinline__ bool bad_he(const Topo &t, int h) { return (unsigned)h >= (unsigned)(3 * t.T); }
 __device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v > (unsigned)t.inf; }
-__device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctr[C_TOPO_ERR], 1); }
+__device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctl[K_TOPO], 1); }
 
 __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
     return ((unsigned long long)(unsigned)round << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)e);
 }
 
-__device__ __forceinline__ void push_edge(const Topo &t, int e, int stamp) {
+// Appends edge e to the worklist of round slot `slot` once per stamp.
+__device__ __forceinline__ void push_edge(const Topo &t, int e, int stamp, int slot) {
     if (atomicExch(&t.edge_stamp[e], stamp) != stamp) {
-        int slot = atomicAdd(&t.ctr[C_WL_NEXT], 1);
-        t.wl_out[slot] = e;
+        int pos = atomicAdd(&t.ctl[K_WL + slot], 1);
+        wl_of(t, slot)[pos] = e;
     }
 }
 
+// Is d already a neighbour of the finite vertex c?  A flip of (a, b) into
+// (c, d) is only a flip if c-d is not an edge yet: on an embedded
+// triangulation that always holds, but on a folded one (several inverted
+// triangles around a disk that crossed more than one edge) the inverted-
+// triangle rule can ask for it, and performing it would glue a duplicate edge.
+// The star is read during evaluation, before any flip of the round.
+__device__ __forceinline__ bool adjacent(const Topo &t, int c, int d) {
+    const int h0 = t.vert_he[c];
+    if (bad_he(t, h0)) return true;
+    int h = h0, guard = 0;
+    do {
+        if (t.he_v[bd_next(h)] == d) return true;
+        h = t.he_twin[bd_prev(h)];
+        if (bad_he(t, h) || ++guard > 4096) return true;
+    } while (h != h0);
+    return false;
+}
+
 // Evaluates the canonical edge h (h < twin) and, if it must flip, registers
-// it as a candidate and claims its two triangles.
-__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, bool reversal) {
+// it as a candidate of round slot `slot` and claims its two triangles.
+__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, bool reversal) {
     if (bad_he(t, tw)) return topo_err(t);
     const int t1 = h / 3, t2 = tw / 3;
     const int a = t.he_v[h], b = t.he_v[bd_next(h)], c = t.he_v[bd_prev(h)];
@@ -111,159 +141,206 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
     }
     bool inverted = false;
     const int rule = bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, &inverted);
-    if (inverted) atomicAdd(&t.ctr[C_INVERTED], 1);
+    if (inverted) atomicAdd(&t.ctl[K_INVQ + slot], 1);
     if (rule == BD_NOFLIP) return;
-    int slot = atomicAdd(&t.ctr[C_CAND], 1);
-    t.cand[slot] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
+    if (c != t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
+        // blocked for now (c-d may disappear in this very round): look again next round
+        push_edge(t, h, round + 1, slot + 1 == MAXR ? 0 : slot + 1);
+        return;
+    }
+    int pos = atomicAdd(&t.ctl[K_CAND + slot], 1);
+    t.cand[pos] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
     const unsigned long long key = claim_key(round, h);
     atomicMax(&t.claim[t1], key);
     atomicMax(&t.claim[t2], key);
 }
 
-__global__ void k_flip_eval_full(Topo t, int round, int reversal) {
-    int tri = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tri >= t.T) return;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        int h = 3 * tri + k;
-        int tw = t.he_twin[h];
-        if (h < tw) eval_edge(t, h, tw, round, reversal != 0);
-    }
-}
-
-__global__ void k_flip_eval_list(Topo t, int round, int count) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= count) return;
-    int h = t.wl_in[idx];
-    if (bad_he(t, h)) return topo_err(t);
-    int tw = t.he_twin[h];
-    if (bad_he(t, tw)) return topo_err(t);
-    if (tw < h) {
-        int s = h;
-        h = tw;
-        tw = s;
-    }
-    eval_edge(t, h, tw, round, false);
-}
-
-__global__ void k_flip_apply(Topo t, int round, int ncand) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ncand) return;
-    const int2 cd = t.cand[idx];
-    const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
-    const unsigned long long key = claim_key(round, h);
-    const bool won = t.claim[t1] == key && t.claim[t2] == key;
-    t.cand_won[idx] = 0;
-    if (!won) return;
-    // the quad is owned by this thread: (a, b, c) = t1 from h, (b, a, d) = t2 from its twin
-    const int hb = bd_next(h), hc = bd_prev(h);
-    const int g = t.he_twin[h];
-    if (g / 3 != t2) return topo_err(t);
-    const int ga = bd_next(g), gd = bd_prev(g);
-    const int a = t.he_v[h], b = t.he_v[hb], c = t.he_v[hc], d = t.he_v[gd];
-    const int Thb = t.he_twin[hb], Thc = t.he_twin[hc], Tga = t.he_twin[ga], Tgd = t.he_twin[gd];
-    if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c) || bad_v(t, d) || bad_he(t, Thb) || bad_he(t, Thc) ||
-        bad_he(t, Tga) || bad_he(t, Tgd))
-        return topo_err(t);
-    const int s1 = 3 * t1, s2 = 3 * t2;
-    // new t1 = (c, a, d), new t2 = (d, b, c); the diagonal c-d is slot 2 of both
-    t.he_v[s1 + 0] = c;
-    t.he_v[s1 + 1] = a;
-    t.he_v[s1 + 2] = d;
-    t.he_v[s2 + 0] = d;
-    t.he_v[s2 + 1] = b;
-    t.he_v[s2 + 2] = c;
-    t.he_twin[s1 + 0] = Thc;   // c -> a, old neighbour index (fixed in k_flip_fix)
-    t.he_twin[s1 + 1] = Tga;   // a -> d
-    t.he_twin[s1 + 2] = s2 + 2;
-    t.he_twin[s2 + 0] = Tgd;   // d -> b
-    t.he_twin[s2 + 1] = Thb;   // b -> c
-    t.he_twin[s2 + 2] = s1 + 2;
-    t.moved[hc] = s1 + 0;
-    t.moved[ga] = s1 + 1;
-    t.moved[gd] = s2 + 0;
-    t.moved[hb] = s2 + 1;
-    t.tri_stamp[t1] = round;
-    t.tri_stamp[t2] = round;
-    // every flip rewrites the outgoing half-edge of all four vertices, so each
-    // entry stays valid whichever concurrent flip writes it last
-    t.vert_he[a] = s1 + 1;
-    t.vert_he[b] = s2 + 1;
-    t.vert_he[c] = s1 + 0;
-    t.vert_he[d] = s2 + 0;
-    t.cand_won[idx] = 1;
-    atomicAdd(&t.acc[A_FLIPS], 1ull);
-    if (cd.y & (int)0x80000000) atomicAdd(&t.acc[A_INV_FLIPS], 1ull);
-}
-
-__global__ void k_flip_fix(Topo t, int round, int ncand) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ncand) return;
-    const int2 cd = t.cand[idx];
-    const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
-    const int next = round + 1;
-    if (!t.cand_won[idx]) {
-        if (t.tri_stamp[t1] != round && t.tri_stamp[t2] != round) push_edge(t, h, next);
-        return;
-    }
-    const int outer[4] = {3 * t1 + 0, 3 * t1 + 1, 3 * t2 + 0, 3 * t2 + 1};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int nh = outer[k];
-        const int o = t.he_twin[nh];
-        if (bad_he(t, o)) {
-            topo_err(t);
-            continue;
-        }
-        int tw;
-        if (t.tri_stamp[o / 3] == round) {
-            tw = t.moved[o];
-            if (bad_he(t, tw)) {
-                topo_err(t);
-                continue;
-            }
-            t.he_twin[nh] = tw;
-        } else {
-            tw = o;
-            t.he_twin[o] = nh;
-        }
-        push_edge(t, nh < tw ? nh : tw, next);
-    }
-    const int d1 = 3 * t1 + 2, d2 = 3 * t2 + 2;
-    push_edge(t, d1 < d2 ? d1 : d2, next);
-}
-
-__global__ void k_validate(Topo t) {
-    int tri = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tri >= t.T) return;
-    int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
-    if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c)) {
-        atomicAdd(&t.ctr[C_INVALID], 1);
-        return topo_err(t);
-    }
-    if (a == t.inf || b == t.inf || c == t.inf) return;
-    if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctr[C_INVALID], 1);
-}
-
-// ---------------------------------------------------------------- overlaps
-// Detect: every finite Delaunay edge with d < r_i + r_j (Algorithm 2 test,
-// Sec. 2.3 contact distance generalised to r_i + r_j); both ends are queued
-// once per round.
-__device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp) {
-    if (atomicExch(&t.vstamp[v], stamp) != stamp) {
-        int slot = atomicAdd(&t.ctr[C_TOUCHED], 1);
-        t.touched[slot] = v;
-    }
-}
-
-__global__ void k_ovl_detect(Topo t, int stamp, double keep) {
-#pragma clang fp contract(off)
-    int tri = blockIdx.x * blockDim.x + threadIdx.x;
-    int found = 0;
-    if (tri < t.T) {
+__global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
+    if (stopped(t.ctl)) return;
+    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             int h = 3 * tri + k;
+            int tw = t.he_twin[h];
+            if (h < tw) eval_edge(t, h, tw, round, slot, reversal != 0);
+        }
+    }
+}
+
+__global__ void k_flip_eval_list(Topo t, int round, int slot) {
+    if (stopped(t.ctl)) return;
+    const int count = t.ctl[K_WL + slot];
+    const int *wl = wl_of(t, slot);
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
+        int h = wl[idx];
+        if (bad_he(t, h)) {
+            topo_err(t);
+            continue;
+        }
+        int tw = t.he_twin[h];
+        if (bad_he(t, tw)) {
+            topo_err(t);
+            continue;
+        }
+        if (tw < h) {
+            int s = h;
+            h = tw;
+            tw = s;
+        }
+        eval_edge(t, h, tw, round, slot, false);
+    }
+}
+
+__global__ void k_flip_apply(Topo t, int round, int slot) {
+    if (stopped(t.ctl)) return;
+    const int ncand = t.ctl[K_CAND + slot];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
+        const int2 cd = t.cand[idx];
+        const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
+        const unsigned long long key = claim_key(round, h);
+        const bool won = t.claim[t1] == key && t.claim[t2] == key;
+        t.cand_won[idx] = 0;
+        if (!won) continue;
+        // the quad is owned by this thread: (a, b, c) = t1 from h, (b, a, d) = t2 from its twin
+        const int hb = bd_next(h), hc = bd_prev(h);
+        const int g = t.he_twin[h];
+        if (g / 3 != t2) {
+            topo_err(t);
+            continue;
+        }
+        const int ga = bd_next(g), gd = bd_prev(g);
+        const int a = t.he_v[h], b = t.he_v[hb], c = t.he_v[hc], d = t.he_v[gd];
+        const int Thb = t.he_twin[hb], Thc = t.he_twin[hc], Tga = t.he_twin[ga], Tgd = t.he_twin[gd];
+        if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c) || bad_v(t, d) || bad_he(t, Thb) || bad_he(t, Thc) ||
+            bad_he(t, Tga) || bad_he(t, Tgd)) {
+            topo_err(t);
+            continue;
+        }
+        const int s1 = 3 * t1, s2 = 3 * t2;
+        // new t1 = (c, a, d), new t2 = (d, b, c); the diagonal c-d is slot 2 of both
+        t.he_v[s1 + 0] = c;
+        t.he_v[s1 + 1] = a;
+        t.he_v[s1 + 2] = d;
+        t.he_v[s2 + 0] = d;
+        t.he_v[s2 + 1] = b;
+        t.he_v[s2 + 2] = c;
+        t.he_twin[s1 + 0] = Thc;   // c -> a, old neighbour index (fixed in k_flip_fix)
+        t.he_twin[s1 + 1] = Tga;   // a -> d
+        t.he_twin[s1 + 2] = s2 + 2;
+        t.he_twin[s2 + 0] = Tgd;   // d -> b
+        t.he_twin[s2 + 1] = Thb;   // b -> c
+        t.he_twin[s2 + 2] = s1 + 2;
+        t.moved[hc] = s1 + 0;
+        t.moved[ga] = s1 + 1;
+        t.moved[gd] = s2 + 0;
+        t.moved[hb] = s2 + 1;
+        t.tri_stamp[t1] = round;
+        t.tri_stamp[t2] = round;
+        // every flip rewrites the outgoing half-edge of all four vertices, so each
+        // entry stays valid whichever concurrent flip writes it last
+        t.vert_he[a] = s1 + 1;
+        t.vert_he[b] = s2 + 1;
+        t.vert_he[c] = s1 + 0;
+        t.vert_he[d] = s2 + 0;
+        t.cand_won[idx] = 1;
+        atomicAdd(&t.acc[A_FLIPS], 1ull);
+        if (cd.y & (int)0x80000000) atomicAdd(&t.acc[A_INV_FLIPS], 1ull);
+    }
+}
+
+__global__ void k_flip_fix(Topo t, int round, int slot) {
+    if (stopped(t.ctl)) return;
+    const int ncand = t.ctl[K_CAND + slot];
+    const int next = round + 1;
+    const int nslot = slot + 1 == MAXR ? 0 : slot + 1;   // slots are used circularly
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
+        const int2 cd = t.cand[idx];
+        const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
+        if (!t.cand_won[idx]) {
+            if (t.tri_stamp[t1] != round && t.tri_stamp[t2] != round) push_edge(t, h, next, nslot);
+            continue;
+        }
+        const int outer[4] = {3 * t1 + 0, 3 * t1 + 1, 3 * t2 + 0, 3 * t2 + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int nh = outer[k];
+            const int o = t.he_twin[nh];
+            if (bad_he(t, o)) {
+                topo_err(t);
+                continue;
+            }
+            int tw;
+            if (t.tri_stamp[o / 3] == round) {
+                tw = t.moved[o];
+                if (bad_he(t, tw)) {
+                    topo_err(t);
+                    continue;
+                }
+                t.he_twin[nh] = tw;
+            } else {
+                tw = o;
+                t.he_twin[o] = nh;
+            }
+            push_edge(t, nh < tw ? nh : tw, next, nslot);
+        }
+        const int d1 = 3 * t1 + 2, d2 = 3 * t2 + 2;
+        push_edge(t, d1 < d2 ? d1 : d2, next, nslot);
+    }
+}
+
+// Counts finite triangles that are not positively oriented after repair `rep`.
+__global__ void k_validate(Topo t, int rep) {
+    if (stopped(t.ctl)) return;
+    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
+        int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
+        if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c)) {
+            atomicAdd(&t.ctl[K_INV + rep], 1);
+            topo_err(t);
+            continue;
+        }
+        if (a == t.inf || b == t.inf || c == t.inf) continue;
+        if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctl[K_INV + rep], 1);
+    }
+}
+
+// End of repair `rep` whose last round used slot `last`: halt the step when the
+// repair did not finish inside its round budget or left an invalid triangle.
+__global__ void k_repair_check(int *ctl, int rep, int last) {
+    if (stopped(ctl)) return;
+    int reason = 0;
+    if (ctl[K_TOPO] != 0)
+        reason = HALT_TOPOLOGY;
+    else if (ctl[K_CAND + last] != 0)
+        reason = HALT_REPAIR_BUDGET;
+    else if (ctl[K_INV + rep] != 0)
+        reason = HALT_INVALID;
+    if (reason) {
+        ctl[K_REASON] = reason;
+        ctl[K_STAGE] = rep;
+        ctl[K_LAST] = last;
+        ctl[K_HALT] = 1;
+    }
+}
+
+// ---------------------------------------------------------------- overlaps
+// Detect: every Delaunay edge between two disks with d < (r_i + r_j)(1 - tol)
+// (Algorithm 2 test, Sec. 2.3 contact distance); both ends are queued once
+// per round.
+__device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, int k) {
+    if (atomicExch(&t.vstamp[v], stamp) != stamp) {
+        int pos = atomicAdd(&t.ctl[K_TOUCH + k], 1);
+        t.touched[pos] = v;
+    }
+}
+
+__global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
+#pragma clang fp contract(off)
+    if (stopped(t.ctl)) return;
+    int found = 0;
+    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            int h = 3 * tri + e;
             int tw = t.he_twin[h];
             if (h > tw) continue;
             int a = t.he_v[h], b = t.he_v[bd_next(h)];
@@ -276,109 +353,158 @@ __global__ void k_ovl_detect(Topo t, int stamp, double keep) {
             double d = sqrt(dx * dx + dy * dy);
             if (d < (t.rad[a] + t.rad[b]) * keep) {
                 ++found;
-                mark_touched(t, a, stamp);
-                mark_touched(t, b, stamp);
+                mark_touched(t, a, stamp, k);
+                mark_touched(t, b, stamp, k);
             }
         }
     }
-    if (found) atomicAdd(&t.ctr[C_OVL_EDGES], found);
+    if (found) atomicAdd(&t.ctl[K_OVL + k], found);
 }
 
-// Gather: for a queued vertex, sum the Jacobi displacement over its star
+// Overlap round k found nothing: the overlap loop of this step is done.
+__global__ void k_ovl_check(int *ctl, int k) {
+    if (stopped(ctl)) return;
+    if (ctl[K_TOPO] != 0) {
+        ctl[K_REASON] = HALT_TOPOLOGY;
+        ctl[K_STAGE] = k;
+        ctl[K_HALT] = 1;
+        return;
+    }
+    if (ctl[K_OVL + k] == 0)
+        ctl[K_DONE] = 1;
+    else
+        ctl[K_OVL_ROUNDS] = k + 1;
+}
+
+// After the last budgeted round: overlaps remain, the host continues.
+__global__ void k_final_check(int *ctl, int k) {
+    if (stopped(ctl)) return;
+    ctl[K_REASON] = HALT_OVERLAP_BUDGET;
+    ctl[K_STAGE] = k;
+    ctl[K_HALT] = 1;
+}
+
+// Gather: for a queued disk, sum the Jacobi displacement over its star
 // (Sec. 2.3 displacement along the unit vector, factor f), starting at the
 // neighbour of smallest id so the summation order is independent of flip
 // history; truncate the sum to cap_frac * r (Sec. 4.4); reflect at the walls.
-__global__ void k_ovl_gather(Topo t, int ntouched, double f, double cap_frac, double L, double keep) {
+__global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double L, double keep) {
 #pragma clang fp contract(off)
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ntouched) return;
-    const int v = t.touched[idx];
-    const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
-    const int h0 = t.vert_he[v];
-    if (bad_he(t, h0)) {
-        topo_err(t);
+    if (stopped(t.ctl)) return;
+    const int ntouched = t.ctl[K_TOUCH + k];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
+        const int v = t.touched[idx];
+        const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
         t.newpos[idx] = make_double2(xv, yv);
-        return;
-    }
-    int best = h0, bestid = 0x7FFFFFFF;
-    int h = h0;
-    int guard = 0;
-    do {
-        int w = t.he_v[bd_next(h)];
-        if (bad_v(t, w)) {
+        const int h0 = t.vert_he[v];
+        if (bad_he(t, h0)) {
             topo_err(t);
-            t.newpos[idx] = make_double2(xv, yv);
-            return;
+            continue;
         }
-        if (w != t.inf && w < bestid) {
-            bestid = w;
-            best = h;
-        }
-        h = t.he_twin[bd_prev(h)];
-        if (bad_he(t, h) || ++guard > 4096) {
-            atomicAdd(&t.ctr[C_STAR_OVF], 1);
-            t.newpos[idx] = make_double2(xv, yv);
-            return;
-        }
-    } while (h != h0);
-    double sx = 0.0, sy = 0.0;
-    h = best;
-    do {
-        int w = t.he_v[bd_next(h)];
-        if (w < t.n) {
-            double dx = xv - t.x[w], dy = yv - t.y[w];
-            double d = sqrt(dx * dx + dy * dy);
-            double contact = rv + t.rad[w];
-            if (d < contact * keep) {
-                double s = f * (contact - d) / d;
-                sx += s * dx;
-                sy += s * dy;
+        int best = h0, bestid = 0x7FFFFFFF;
+        int h = h0;
+        int guard = 0;
+        bool broken = false;
+        do {
+            int w = t.he_v[bd_next(h)];
+            if (bad_v(t, w)) {
+                broken = true;
+                break;
             }
+            if (w != t.inf && w < bestid) {
+                bestid = w;
+                best = h;
+            }
+            h = t.he_twin[bd_prev(h)];
+            if (bad_he(t, h) || ++guard > 4096) {
+                broken = true;
+                break;
+            }
+        } while (h != h0);
+        if (broken) {
+            topo_err(t);
+            atomicAdd(&t.ctl[K_STAR], 1);
+            continue;
         }
-        h = t.he_twin[bd_prev(h)];
-    } while (h != best);
-    const double len = sqrt(sx * sx + sy * sy);
-    const double cap = cap_frac * rv;
-    if (len > cap) {
-        double sc = cap / len;
-        sx = sx * sc;
-        sy = sy * sc;
-        atomicAdd(&t.acc[A_CAP_HITS], 1ull);
+        double sx = 0.0, sy = 0.0;
+        h = best;
+        do {
+            int w = t.he_v[bd_next(h)];
+            if (w < t.n) {
+                double dx = xv - t.x[w], dy = yv - t.y[w];
+                double d = sqrt(dx * dx + dy * dy);
+                double contact = rv + t.rad[w];
+                if (d < contact * keep) {
+                    double s = f * (contact - d) / d;
+                    sx += s * dx;
+                    sy += s * dy;
+                }
+            }
+            h = t.he_twin[bd_prev(h)];
+        } while (h != best);
+        const double len = sqrt(sx * sx + sy * sy);
+        const double cap = cap_frac * rv;
+        if (len > cap) {
+            double sc = cap / len;
+            sx = sx * sc;
+            sy = sy * sc;
+            atomicAdd(&t.acc[A_CAP_HITS], 1ull);
+        }
+        t.newpos[idx] = make_double2(bd_wall(xv + sx, rv, L), bd_wall(yv + sy, rv, L));
     }
-    t.newpos[idx] = make_double2(bd_wall(xv + sx, rv, L), bd_wall(yv + sy, rv, L));
 }
 
-// Apply: write the new positions and queue every edge of the moved vertex's
-// triangles (incident edges and link edges) for the following flip repair.
-__global__ void k_ovl_apply(Topo t, int ntouched, int next_round) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ntouched) return;
-    const int v = t.touched[idx];
-    const double2 np = t.newpos[idx];
-    t.oldpos[idx] = make_double2(t.x[v], t.y[v]);
-    ((double *)t.x)[v] = np.x;
-    ((double *)t.y)[v] = np.y;
-    const int h0 = t.vert_he[v];
-    if (bad_he(t, h0)) return topo_err(t);
-    int h = h0, guard = 0;
-    do {
-        int tw = t.he_twin[h];
-        int l = bd_next(h);
-        int lt = t.he_twin[l];
-        if (bad_he(t, tw) || bad_he(t, lt)) return topo_err(t);
-        push_edge(t, h < tw ? h : tw, next_round);
-        push_edge(t, l < lt ? l : lt, next_round);
-        h = t.he_twin[bd_prev(h)];
-        if (bad_he(t, h)) return topo_err(t);
-    } while (h != h0 && ++guard < 4096);
+// Apply: write the new positions (keeping the old ones for a replay) and queue
+// every edge of the moved disk's triangles (incident and link edges) as the
+// worklist of round slot `slot`, the first round of the following repair.
+__global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
+    if (stopped(t.ctl)) return;
+    const int ntouched = t.ctl[K_TOUCH + k];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
+        const int v = t.touched[idx];
+        const double2 np = t.newpos[idx];
+        t.oldpos[idx] = make_double2(t.x[v], t.y[v]);
+        ((double *)t.x)[v] = np.x;
+        ((double *)t.y)[v] = np.y;
+        const int h0 = t.vert_he[v];
+        if (bad_he(t, h0)) {
+            topo_err(t);
+            continue;
+        }
+        int h = h0, guard = 0;
+        do {
+            int tw = t.he_twin[h];
+            int l = bd_next(h);
+            int lt = t.he_twin[l];
+            if (bad_he(t, tw) || bad_he(t, lt)) {
+                topo_err(t);
+                break;
+            }
+            push_edge(t, h < tw ? h : tw, next_round, slot);
+            push_edge(t, l < lt ? l : lt, next_round, slot);
+            h = t.he_twin[bd_prev(h)];
+            if (bad_he(t, h)) {
+                topo_err(t);
+                break;
+            }
+        } while (h != h0 && ++guard < 4096);
+    }
 }
 
-__global__ void k_scatter_oldpos(Topo t, int ntouched, double *xa, double *ya) {
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ntouched) return;
-    const int v = t.touched[idx];
-    xa[v] = t.oldpos[idx].x;
-    ya[v] = t.oldpos[idx].y;
+// Topology snapshot before a repair (skipped once the step has stopped, so the
+// snapshot of the failing repair survives).
+__global__ void k_copy_ints(int *dst, const int *src, int count, const int *ctl) {
+    if (stopped(ctl)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
+    const int ntouched = t.ctl[K_TOUCH + k];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
+        const int v = t.touched[idx];
+        xa[v] = t.oldpos[idx].x;
+        ya[v] = t.oldpos[idx].y;
+    }
 }
 
 __global__ void k_interp(int n, int i, int k, const double *xa, const double *ya, const double *xb,
@@ -396,65 +522,85 @@ __global__ void k_interp(int n, int i, int k, const double *xa, const double *ya
     }
 }
 
-inline int nb256(int n) { return (n + 255) / 256; }
+inline int grid_for(long items) {
+    long b = (items + 255) / 256;
+    if (b < 1) b = 1;
+    return (int)(b < kMaxGrid ? b : kMaxGrid);
+}
 
 }  // namespace
 
-void launch_flip_eval_full(Sim &s, int round, bool reversal) {
+void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_full, dim3(nb256(s.T)), dim3(256), 0, s.stream, t, round, reversal ? 1 : 0);
+    hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, round, slot,
+                       reversal ? 1 : 0);
 }
 
-void launch_flip_eval_list(Sim &s, int round, int count) {
-    if (count <= 0) return;
+void launch_flip_eval_list(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_list, dim3(nb256(count)), dim3(256), 0, s.stream, t, round, count);
+    hipLaunchKernelGGL(k_flip_eval_list, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
 }
 
-void launch_flip_apply(Sim &s, int round, int ncand) {
-    if (ncand <= 0) return;
+void launch_flip_apply(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_apply, dim3(nb256(ncand)), dim3(256), 0, s.stream, t, round, ncand);
+    hipLaunchKernelGGL(k_flip_apply, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
 }
 
-void launch_flip_fix(Sim &s, int round, int ncand) {
-    if (ncand <= 0) return;
+void launch_flip_fix(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_fix, dim3(nb256(ncand)), dim3(256), 0, s.stream, t, round, ncand);
+    hipLaunchKernelGGL(k_flip_fix, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
 }
 
-void launch_validate(Sim &s) {
+void launch_validate(Sim &s, int rep) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_validate, dim3(nb256(s.T)), dim3(256), 0, s.stream, t);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, rep);
 }
 
-void launch_ovl_detect(Sim &s, int vstamp) {
-    Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_detect, dim3(nb256(s.T)), dim3(256), 0, s.stream, t, vstamp, 1.0 - s.p.contact_tol);
+void launch_repair_check(Sim &s, int rep, int last) {
+    hipLaunchKernelGGL(k_repair_check, dim3(1), dim3(1), 0, s.stream, s.ctl, rep, last);
 }
 
-void launch_ovl_gather(Sim &s, int ntouched) {
-    if (ntouched <= 0) return;
+void launch_ovl_detect(Sim &s, int vstamp, int k) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_gather, dim3(nb256(ntouched)), dim3(256), 0, s.stream, t, ntouched,
-                       s.p.overlap_factor, s.p.cap_frac, s.p.L, 1.0 - s.p.contact_tol);
+    hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, vstamp,
+                       1.0 - s.p.contact_tol, k);
 }
 
-void launch_ovl_apply(Sim &s, int ntouched, int next_round) {
-    if (ntouched <= 0) return;
-    Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_apply, dim3(nb256(ntouched)), dim3(256), 0, s.stream, t, ntouched, next_round);
+void launch_ovl_check(Sim &s, int k) {
+    hipLaunchKernelGGL(k_ovl_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k);
 }
 
-void launch_scatter_oldpos(Sim &s, int ntouched) {
-    if (ntouched <= 0) return;
+void launch_final_check(Sim &s, int k) {
+    hipLaunchKernelGGL(k_final_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k);
+}
+
+void launch_ovl_gather(Sim &s, int k) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_scatter_oldpos, dim3(nb256(ntouched)), dim3(256), 0, s.stream, t, ntouched, s.xa, s.ya);
+    hipLaunchKernelGGL(k_ovl_gather, dim3(grid_for(s.n)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
+                       s.p.cap_frac, s.p.L, 1.0 - s.p.contact_tol);
+}
+
+void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n)), dim3(256), 0, s.stream, t, k, next_round, slot);
+}
+
+void launch_snapshot(Sim &s) {
+    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.H)), dim3(256), 0, s.stream, s.snap_v, s.he_v, s.H, s.ctl);
+    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.H)), dim3(256), 0, s.stream, s.snap_twin, s.he_twin, s.H,
+                       s.ctl);
+    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.nv + 1)), dim3(256), 0, s.stream, s.snap_vh, s.vert_he,
+                       s.nv + 1, s.ctl);
+}
+
+void launch_scatter_oldpos(Sim &s, int k) {
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_scatter_oldpos, dim3(grid_for(s.n)), dim3(256), 0, s.stream, t, k, s.xa, s.ya);
 }
 
 void launch_interp(Sim &s, int i, int k) {
-    hipLaunchKernelGGL(k_interp, dim3(nb256(s.n)), dim3(256), 0, s.stream, s.n, i, k, s.xa, s.ya, s.xb, s.yb, s.x,
-                       s.y);
+    hipLaunchKernelGGL(k_interp, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n, i, k, s.xa, s.ya, s.xb,
+                       s.yb, s.x, s.y);
 }
 
 }  // namespace bd

@@ -53,10 +53,13 @@ void fill_int(Sim &s, int *p, int count, int value) {
     hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, s.stream, p, count, value);
 }
 
-void read_counters(Sim &s) {
-    check(hipMemcpyAsync(s.hctr, s.ctr, sizeof(int) * N_CTR, hipMemcpyDeviceToHost, s.stream), "counter copy");
+void read_ctl(Sim &s) {
+    check(hipMemcpyAsync(s.hctl, s.ctl, sizeof(int) * N_CTL, hipMemcpyDeviceToHost, s.stream), "control copy");
     check(hipStreamSynchronize(s.stream), "stream sync");
 }
+
+// Zeroes one control entry (device work, ordered on the stream).
+void zero_ctl(Sim &s, int idx) { fill_int(s, s.ctl + idx, 1, 0); }
 
 void upload_topology(Sim &s, const std::vector<int> &he_v, const std::vector<int> &he_twin) {
     std::vector<int> vh(s.nv + 1, -1);
@@ -75,7 +78,7 @@ int host_rebuild(Sim &s) {
     check(hipStreamSynchronize(s.stream), "rebuild download");
     std::vector<int> hv, ht;
     if (host_delaunay(s.nv, hx.data(), hy.data(), hv, ht) != 0) {
-        s.last_error = "host Delaunay rebuild failed (collinear or coincident positions)";
+        s.last_error = "host Delaunay rebuild failed (coincident positions)";
         return BD_ERR_TRIANGULATION;
     }
     upload_topology(s, hv, ht);
@@ -83,72 +86,106 @@ int host_rebuild(Sim &s) {
     return BD_OK;
 }
 
-// Device flip rounds towards DT(x).  full: the first round scans every edge;
-// otherwise the worklist (count entries) seeds the repair.  When `snap` is
+// Slot cursor of one step: round slots, repair slots and overlap-round slots
+// are handed out in order and wrap around (the host zeroes a slot before it
+// reuses one).
+struct Cursor {
+    int slot = 0, rep = 0, oround = 0;
+    int take_slot() {
+        int v = slot;
+        slot = slot + 1 == MAXR ? 0 : slot + 1;
+        return v;
+    }
+    int take_rep() {
+        int v = rep;
+        rep = rep + 1 == MAXREP ? 0 : rep + 1;
+        return v;
+    }
+    int take_oround() {
+        int v = oround;
+        oround = oround + 1 == MAXO ? 0 : oround + 1;
+        return v;
+    }
+};
+
+inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
+
+// ------------------------------------------------------------------ budgeted sequence
+// Enqueues one repair of `rounds` flip rounds with no host read-back: a
+// topology snapshot, the rounds, the validation and the check that halts the
+// step when the budget was too small or a triangle stayed inverted.
+void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds) {
+    launch_snapshot(s);
+    const int rep = c.take_rep();
+    int last = -1;
+    for (int j = 0; j < rounds; ++j) {
+        const int r = ++s.round_id;
+        const int slot = c.take_slot();
+        if (j == 0 && full)
+            launch_flip_eval_full(s, r, slot, reversal);
+        else
+            launch_flip_eval_list(s, r, slot);
+        launch_flip_apply(s, r, slot);
+        launch_flip_fix(s, r, slot);
+        last = slot;
+    }
+    launch_validate(s, rep);
+    launch_repair_check(s, rep, last);
+}
+
+// ------------------------------------------------------------------ host-driven path
+// Flip rounds with one read-back per round (used to finish a step whose
+// budget ran out, for bd_set_positions and for the kinetic replay).  The
+// first round reads the worklist of slot c.slot unless `full`.  When `snap` is
 // given and the first evaluation meets an inverted triangle, the topology is
-// copied aside before any flip so the repair can be replayed.  Returns true
-// when the result is a valid triangulation with no edge left to flip.
-bool flip_rounds(Sim &s, bool full, bool reversal, int count, bool *snap) {
+// copied aside before any flip.  Returns true for a valid triangulation with
+// no edge left to flip.
+bool host_flip_rounds(Sim &s, Cursor &c, bool full, bool reversal, bool *snap) {
     if (snap) *snap = false;
     const int budget = s.p.max_flip_rounds > 0 ? s.p.max_flip_rounds : 200;
     bool done = false;
     for (int it = 0; it < budget; ++it) {
-        if (!full && count == 0) {
-            done = true;
-            break;
-        }
         const int r = ++s.round_id;
-        fill_int(s, s.ctr, N_CTR, 0);
+        const int slot = c.take_slot();
+        zero_ctl(s, K_CAND + slot);
+        zero_ctl(s, K_INVQ + slot);
+        zero_ctl(s, K_WL + next_slot(slot));
         if (full)
-            launch_flip_eval_full(s, r, reversal && it == 0);
+            launch_flip_eval_full(s, r, slot, reversal && it == 0);
         else
-            launch_flip_eval_list(s, r, count);
-        read_counters(s);
+            launch_flip_eval_list(s, r, slot);
+        read_ctl(s);
         ++s.st.flip_rounds_total;
-        if (s.hctr[C_TOPO_ERR] != 0) return false;
-        if (it == 0 && snap && s.hctr[C_INVERTED] > 0) {
-            check(hipMemcpyAsync(s.snap_v, s.he_v, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream), "snap");
-            check(hipMemcpyAsync(s.snap_twin, s.he_twin, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream),
-                  "snap");
-            check(hipMemcpyAsync(s.snap_vh, s.vert_he, sizeof(int) * (s.nv + 1), hipMemcpyDeviceToDevice, s.stream),
-                  "snap");
+        if (s.hctl[K_TOPO] != 0) return false;
+        if (it == 0 && snap && s.hctl[K_INVQ + slot] > 0) {
+            launch_snapshot(s);
             *snap = true;
         }
-        const int ncand = s.hctr[C_CAND];
-        if (ncand == 0) {
+        if (s.hctl[K_CAND + slot] == 0) {
             done = true;
+            c.slot = slot;   // reuse the empty slot
             break;
         }
-        launch_flip_apply(s, r, ncand);
-        launch_flip_fix(s, r, ncand);
-        read_counters(s);
-        if (s.hctr[C_TOPO_ERR] != 0) return false;
-        count = s.hctr[C_WL_NEXT];
-        s.wl_cur ^= 1;
+        launch_flip_apply(s, r, slot);
+        launch_flip_fix(s, r, slot);
         full = false;
     }
     if (!done) return false;
-    fill_int(s, s.ctr, N_CTR, 0);
-    launch_validate(s);
-    read_counters(s);
-    return s.hctr[C_INVALID] == 0;
+    const int rep = c.take_rep();
+    zero_ctl(s, K_INV + rep);
+    launch_validate(s, rep);
+    read_ctl(s);
+    return s.hctl[K_INV + rep] == 0 && s.hctl[K_TOPO] == 0;
 }
 
 // Where the positions before the move that is being repaired are kept.
 enum class MoveFrom { Previous, Touched };
 
-// Restores DT(x) after a move.  The paper's repair (inverted-triangle flips,
-// Sec. 4.3, and Lawson flips, Sec. 4.1) is tried first.  It cannot untangle a
-// disk that crossed more than one edge (Sec. 4.3, two-flip figure); then the
-// triangulation is restored from the snapshot and the same move is replayed
-// in k equal sub-steps (k = 2, 4, ..., 64), each repaired by the same rule,
-// ending exactly at the target positions.  The Delaunay triangulation of the
-// target is unique, so the path does not change the result.  A host rebuild
-// is the last resort.
-int repair(Sim &s, bool full, bool reversal, int count, MoveFrom from, int ntouched) {
-    bool snapped = false;
-    if (flip_rounds(s, full, reversal, count, &snapped)) return BD_OK;
-    if (!snapped) return host_rebuild(s);
+// Replays the move from the snapshot in k equal sub-steps (k = 2, 4, ..., 64),
+// each repaired by the Sec. 4.3 + Lawson rule, ending exactly at the target;
+// a host rebuild is the last resort.  The Delaunay triangulation of the
+// target is unique, so the path does not change the result.
+int kinetic_replay(Sim &s, Cursor &c, MoveFrom from, int oround) {
     const size_t bytes = sizeof(double) * s.n;
     check(hipMemcpyAsync(s.xb, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "xb");
     check(hipMemcpyAsync(s.yb, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "yb");
@@ -158,7 +195,7 @@ int repair(Sim &s, bool full, bool reversal, int count, MoveFrom from, int ntouc
     } else {
         check(hipMemcpyAsync(s.xa, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "xa");
         check(hipMemcpyAsync(s.ya, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "ya");
-        launch_scatter_oldpos(s, ntouched);
+        launch_scatter_oldpos(s, oround);
     }
     for (int k = 2; k <= 64; k *= 2) {
         check(hipMemcpyAsync(s.he_v, s.snap_v, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream), "restore");
@@ -169,7 +206,7 @@ int repair(Sim &s, bool full, bool reversal, int count, MoveFrom from, int ntouc
         bool ok = true;
         for (int i = 1; i <= k && ok; ++i) {
             launch_interp(s, i, k);
-            ok = flip_rounds(s, true, false, 0, nullptr);
+            ok = host_flip_rounds(s, c, true, false, nullptr);
         }
         if (ok) {
             ++s.st.kinetic_repairs;
@@ -181,10 +218,25 @@ int repair(Sim &s, bool full, bool reversal, int count, MoveFrom from, int ntouc
     return host_rebuild(s);
 }
 
+// Restores DT(x) after a move, host-driven: the paper's repair
+// (inverted-triangle flips, Sec. 4.3, and Lawson flips, Sec. 4.1) first; a
+// disk that crossed more than one edge (Sec. 4.3, two-flip figure) makes it
+// fail, and the move is replayed from the snapshot in sub-steps.
+int host_repair(Sim &s, Cursor &c, bool full, bool reversal, MoveFrom from, int oround) {
+    bool snapped = false;
+    if (host_flip_rounds(s, c, full, reversal, &snapped)) return BD_OK;
+    if (!snapped || s.hctl[K_TOPO] != 0) {
+        zero_ctl(s, K_TOPO);
+        return host_rebuild(s);
+    }
+    return kinetic_replay(s, c, from, oround);
+}
+
 void rollback(Sim &s) {
     check(hipMemcpyAsync(s.x, s.xo, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback x");
     check(hipMemcpyAsync(s.y, s.yo, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback y");
     check(hipMemcpyAsync(s.th, s.tho, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback th");
+    fill_int(s, s.ctl, N_CTL, 0);
     host_rebuild(s);
 }
 
@@ -203,52 +255,114 @@ void compute_forces(Sim &s) {
     }
 }
 
-int one_step(Sim &s) {
-    compute_forces(s);
-    launch_em(s);
-    int rc = repair(s, true, true, 0, MoveFrom::Previous, 0);
-    if (rc != BD_OK) {
-        rollback(s);
-        return rc;
-    }
-    int rounds = 0;
+// Host-driven overlap rounds from overlap round index `done_rounds` on; returns
+// BD_OK with *rounds_out updated, or an error code (state rolled back).
+int host_overlap_loop(Sim &s, Cursor &c, int &rounds) {
     const int max_rounds = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
     for (;;) {
-        const int stamp = ++s.vround;
-        fill_int(s, s.ctr, N_CTR, 0);
-        launch_ovl_detect(s, stamp);
-        read_counters(s);
-        if (s.hctr[C_TOPO_ERR] != 0) {
+        const int k = c.take_oround();
+        zero_ctl(s, K_TOUCH + k);
+        zero_ctl(s, K_OVL + k);
+        launch_ovl_detect(s, ++s.vround, k);
+        read_ctl(s);
+        if (s.hctl[K_TOPO] != 0) {
             s.last_error = "triangulation index out of range during overlap detection";
-            rollback(s);
             return BD_ERR_TRIANGULATION;
         }
-        const int nedges = s.hctr[C_OVL_EDGES];
-        const int ntouched = s.hctr[C_TOUCHED];
-        if (nedges == 0) break;
+        const int nedges = s.hctl[K_OVL + k];
+        if (nedges == 0) return BD_OK;
         if (rounds >= max_rounds) {
             s.last_error = "overlap correction did not converge within max_overlap_rounds";
-            rollback(s);
             return BD_ERR_NO_CONVERGENCE;
         }
         ++rounds;
         s.st.overlap_edges_total += nedges;
-        launch_ovl_gather(s, ntouched);
-        launch_ovl_apply(s, ntouched, s.round_id + 1);
-        read_counters(s);
-        if (s.hctr[C_STAR_OVF] != 0 || s.hctr[C_TOPO_ERR] != 0) {
-            s.last_error = "vertex star walk exceeded its bound (corrupt triangulation)";
+        launch_ovl_gather(s, k);
+        const int slot = c.slot;
+        zero_ctl(s, K_WL + slot);
+        launch_ovl_apply(s, k, s.round_id + 1, slot);
+        read_ctl(s);
+        if (s.hctl[K_STAR] != 0 || s.hctl[K_TOPO] != 0) {
+            s.last_error = "vertex star walk failed (corrupt triangulation)";
+            return BD_ERR_TRIANGULATION;
+        }
+        int rc = host_repair(s, c, false, false, MoveFrom::Touched, k);
+        if (rc != BD_OK) return rc;
+    }
+}
+
+// One step of Algorithm 1.  The whole step is enqueued as a budgeted sequence
+// (force, update, repair rounds, overlap rounds each with its repair) and the
+// control block is read back once; if a budget ran out or a repair failed,
+// the host finishes the step from exactly that point.
+int one_step(Sim &s) {
+    Cursor c;
+    fill_int(s, s.ctl, N_CTL, 0);
+    compute_forces(s);
+    launch_em(s);
+    enqueue_repair(s, c, true, true, s.budget_em_rounds);
+    std::vector<int> orounds;
+    for (int j = 0; j < s.budget_overlaps; ++j) {
+        const int k = c.take_oround();
+        orounds.push_back(k);
+        launch_ovl_detect(s, ++s.vround, k);
+        launch_ovl_check(s, k);
+        launch_ovl_gather(s, k);
+        launch_ovl_apply(s, k, s.round_id + 1, c.slot);
+        enqueue_repair(s, c, false, false, s.budget_ovl_rounds);
+    }
+    {
+        const int k = c.take_oround();
+        orounds.push_back(k);
+        launch_ovl_detect(s, ++s.vround, k);
+        launch_ovl_check(s, k);
+        launch_final_check(s, k);
+    }
+    read_ctl(s);
+    const int *h = s.hctl;
+    // bookkeeping of the budgeted part: overlap rounds that moved disks
+    int rounds = h[K_OVL_ROUNDS];
+    if (h[K_HALT]) {
+        if (h[K_REASON] == HALT_OVERLAP_BUDGET) rounds = s.budget_overlaps;
+        if (h[K_REASON] == HALT_REPAIR_BUDGET || h[K_REASON] == HALT_INVALID) rounds = h[K_STAGE];
+    }
+    for (int j = 0; j < rounds; ++j) s.st.overlap_edges_total += h[K_OVL + orounds[j]];
+    for (int j = 0; j < c.slot; ++j) s.st.flip_rounds_total += h[K_CAND + j] > 0 ? 1 : 0;
+    int rc = BD_OK;
+    if (h[K_HALT]) {
+        const int reason = h[K_REASON], stage = h[K_STAGE], last = h[K_LAST];
+        if (reason == HALT_TOPOLOGY) {
+            s.last_error = "triangulation index out of range";
             rollback(s);
             return BD_ERR_TRIANGULATION;
         }
-        const int wl = s.hctr[C_WL_NEXT];
-        s.wl_cur ^= 1;
-        rc = repair(s, false, false, wl, MoveFrom::Touched, ntouched);
+        // continue host-driven after the halting point
+        fill_int(s, s.ctl + K_HALT, 1, 0);
+        fill_int(s, s.ctl + K_DONE, 1, 0);
+        Cursor hc;
+        hc.slot = c.slot;
+        hc.rep = c.rep;
+        hc.oround = c.oround;
+        if (reason == HALT_REPAIR_BUDGET || reason == HALT_INVALID) {
+            // repair slot `stage`: 0 is the repair after the update, j >= 1 the one after overlap round j-1
+            const MoveFrom from = stage == 0 ? MoveFrom::Previous : MoveFrom::Touched;
+            const int k = stage == 0 ? 0 : orounds[stage - 1];
+            if (reason == HALT_REPAIR_BUDGET) {
+                hc.slot = next_slot(last);   // its worklist holds the edges still to evaluate
+                bool snapped = false;
+                if (!host_flip_rounds(s, hc, false, false, &snapped)) rc = kinetic_replay(s, hc, from, k);
+            } else {
+                rc = kinetic_replay(s, hc, from, k);
+            }
+        }
+        if (rc == BD_OK) rc = host_overlap_loop(s, hc, rounds);
         if (rc != BD_OK) {
             rollback(s);
             return rc;
         }
     }
+    // adapt the budgets to the rounds this step needed
+    s.budget_overlaps = std::max(2, std::min(8, rounds + 1));
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
@@ -278,10 +392,10 @@ void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.chunks, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he, s.claim, s.tri_stamp, s.moved,
                     s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won, s.touched, s.newpos, s.oldpos,
-                    s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctr, s.acc};
+                    s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl, s.acc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (s.hctr) (void)hipHostFree(s.hctr);
+    if (s.hctl) (void)hipHostFree(s.hctl);
     if (s.hacc) (void)hipHostFree(s.hacc);
     for (auto &e : s.ev) {
         (void)hipEventDestroy(e.first);
@@ -433,9 +547,9 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.ya = dalloc<double>(n);
     s.xb = dalloc<double>(n);
     s.yb = dalloc<double>(n);
-    s.ctr = dalloc<int>(N_CTR);
+    s.ctl = dalloc<int>(N_CTL);
     s.acc = dalloc<unsigned long long>(N_ACC);
-    if (hipHostMalloc((void **)&s.hctr, sizeof(int) * N_CTR, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+    if (hipHostMalloc((void **)&s.hctl, sizeof(int) * N_CTL, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
     if (hipHostMalloc((void **)&s.hacc, sizeof(unsigned long long) * N_ACC, hipHostMallocDefault) != hipSuccess)
         throw std::bad_alloc();
 
@@ -457,7 +571,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     check(hipMemsetAsync(s.edge_stamp, 0, sizeof(int) * s.H, s.stream), "edge_stamp");
     check(hipMemsetAsync(s.vstamp, 0, sizeof(int) * (n + 1), s.stream), "vstamp");
     check(hipMemsetAsync(s.acc, 0, sizeof(unsigned long long) * N_ACC, s.stream), "acc");
-    check(hipMemsetAsync(s.ctr, 0, sizeof(int) * N_CTR, s.stream), "ctr");
+    check(hipMemsetAsync(s.ctl, 0, sizeof(int) * N_CTL, s.stream), "ctl");
 
     std::vector<int> hv, ht;
     if (host_delaunay(nv, hx.data(), hy.data(), hv, ht) != 0) {
@@ -671,7 +785,9 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         bd::check(hipMemcpyAsync(s.yo, s.y, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "yo");
         bd::check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "x");
         bd::check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "y");
-        return bd::repair(s, true, false, 0, bd::MoveFrom::Previous, 0);
+        bd::fill_int(s, s.ctl, bd::N_CTL, 0);
+        bd::Cursor c;
+        return bd::host_repair(s, c, true, false, bd::MoveFrom::Previous, 0);
     });
 }
 
