@@ -39,7 +39,8 @@
 namespace bd {
 namespace {
 
-constexpr int kMaxGrid = 512;
+constexpr int kMaxGrid = 512;      // full scans over triangles
+constexpr int kListGrid = 128;     // worklist-driven launches (usually a few hundred items, often none)
 
 struct Topo {
     int n, inf, T;
@@ -99,12 +100,19 @@ __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
     return ((unsigned long long)(unsigned)round << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)e);
 }
 
-// Appends edge e to the worklist of round slot `slot` once per stamp.
+// Appends edge e to the worklist of round slot `slot` once per stamp.  The
+// lanes of a wavefront that push at the same time reserve their positions
+// with one atomic on the shared counter.
 __device__ __forceinline__ void push_edge(const Topo &t, int e, int stamp, int slot) {
-    if (atomicExch(&t.edge_stamp[e], stamp) != stamp) {
-        int pos = atomicAdd(&t.ctl[K_WL + slot], 1);
-        wl_of(t, slot)[pos] = e;
-    }
+    const bool fresh = atomicExch(&t.edge_stamp[e], stamp) != stamp;
+    const unsigned long long m = __ballot(fresh);
+    if (m == 0) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&t.ctl[K_WL + slot], __popcll(m));
+    base = __shfl(base, leader);
+    if (fresh) wl_of(t, slot)[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
 }
 
 // Is d already a neighbour of the finite vertex c?  A flip of (a, b) into
@@ -493,9 +501,14 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
 
 // Topology snapshot before a repair (skipped once the step has stopped, so the
 // snapshot of the failing repair survives).
-__global__ void k_copy_ints(int *dst, const int *src, int count, const int *ctl) {
-    if (stopped(ctl)) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) dst[i] = src[i];
+__global__ void k_snapshot(Topo t, int *snap_v, int *snap_twin, int *snap_vh, int nvh) {
+    if (stopped(t.ctl)) return;
+    const int H = 3 * t.T;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x) {
+        snap_v[i] = t.he_v[i];
+        snap_twin[i] = t.he_twin[i];
+        if (i < nvh) snap_vh[i] = t.vert_he[i];
+    }
 }
 
 __global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
@@ -522,10 +535,10 @@ __global__ void k_interp(int n, int i, int k, const double *xa, const double *ya
     }
 }
 
-inline int grid_for(long items) {
+inline int grid_for(long items, int cap = kMaxGrid) {
     long b = (items + 255) / 256;
     if (b < 1) b = 1;
-    return (int)(b < kMaxGrid ? b : kMaxGrid);
+    return (int)(b < cap ? b : cap);
 }
 
 }  // namespace
@@ -538,17 +551,17 @@ void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
 
 void launch_flip_eval_list(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_list, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_eval_list, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_apply(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_apply, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_apply, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_fix(Sim &s, int round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_fix, dim3(grid_for(s.H / 2)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_fix, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_validate(Sim &s, int rep) {
@@ -576,21 +589,19 @@ void launch_final_check(Sim &s, int k) {
 
 void launch_ovl_gather(Sim &s, int k) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_gather, dim3(grid_for(s.n)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
+    hipLaunchKernelGGL(k_ovl_gather, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
                        s.p.cap_frac, s.p.L, 1.0 - s.p.contact_tol);
 }
 
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n)), dim3(256), 0, s.stream, t, k, next_round, slot);
+    hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, next_round, slot);
 }
 
 void launch_snapshot(Sim &s) {
-    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.H)), dim3(256), 0, s.stream, s.snap_v, s.he_v, s.H, s.ctl);
-    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.H)), dim3(256), 0, s.stream, s.snap_twin, s.he_twin, s.H,
-                       s.ctl);
-    hipLaunchKernelGGL(k_copy_ints, dim3(grid_for(s.nv + 1)), dim3(256), 0, s.stream, s.snap_vh, s.vert_he,
-                       s.nv + 1, s.ctl);
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_snapshot, dim3(grid_for(s.H)), dim3(256), 0, s.stream, t, s.snap_v, s.snap_twin, s.snap_vh,
+                       s.nv + 1);
 }
 
 void launch_scatter_oldpos(Sim &s, int k) {

@@ -114,9 +114,10 @@ inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 // Enqueues one repair of `rounds` flip rounds with no host read-back: a
 // topology snapshot, the rounds, the validation and the check that halts the
 // step when the budget was too small or a triangle stayed inverted.
-void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds) {
+void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots) {
     launch_snapshot(s);
     const int rep = c.take_rep();
+    if (first_slots) first_slots->push_back(c.slot);
     int last = -1;
     for (int j = 0; j < rounds; ++j) {
         const int r = ++s.round_id;
@@ -300,7 +301,8 @@ int one_step(Sim &s) {
     fill_int(s, s.ctl, N_CTL, 0);
     compute_forces(s);
     launch_em(s);
-    enqueue_repair(s, c, true, true, s.budget_em_rounds);
+    std::vector<int> rep_first;   // first round slot of each enqueued repair
+    enqueue_repair(s, c, true, true, s.budget_em_rounds, &rep_first);
     std::vector<int> orounds;
     for (int j = 0; j < s.budget_overlaps; ++j) {
         const int k = c.take_oround();
@@ -309,7 +311,7 @@ int one_step(Sim &s) {
         launch_ovl_check(s, k);
         launch_ovl_gather(s, k);
         launch_ovl_apply(s, k, s.round_id + 1, c.slot);
-        enqueue_repair(s, c, false, false, s.budget_ovl_rounds);
+        enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first);
     }
     {
         const int k = c.take_oround();
@@ -361,7 +363,31 @@ int one_step(Sim &s) {
             return rc;
         }
     }
-    // adapt the budgets to the rounds this step needed
+    // adapt the budgets to the rounds this step needed: grow at once when a
+    // budget ran out, shrink by one when it was larger than needed
+    auto used_rounds = [&](int rep, int budget) {
+        for (int j = 0; j < budget; ++j)
+            if (h[K_CAND + rep_first[rep] + j] == 0) return j + 1;
+        return budget + 2;
+    };
+    auto adapt = [](int &budget, int used) {
+        if (used >= budget)
+            budget = std::min(8, used + 1);
+        else if (used + 1 < budget)
+            budget = std::max(2, budget - 1);
+    };
+    const int hreason = h[K_HALT] ? h[K_REASON] : 0;
+    // repair slot that stopped the budgeted sequence (none for an overlap budget halt)
+    const int halt_rep = (hreason == HALT_REPAIR_BUDGET || hreason == HALT_INVALID) ? h[K_STAGE] : 1 << 30;
+    if (halt_rep > 0)
+        adapt(s.budget_em_rounds, used_rounds(0, s.budget_em_rounds));
+    else if (hreason == HALT_REPAIR_BUDGET)
+        adapt(s.budget_em_rounds, s.budget_em_rounds + 2);
+    int ovl_used = 0;
+    for (int r = 1; r < (int)rep_first.size() && r <= rounds && r < halt_rep; ++r)
+        ovl_used = std::max(ovl_used, used_rounds(r, s.budget_ovl_rounds));
+    if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = s.budget_ovl_rounds + 2;
+    if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used);
     s.budget_overlaps = std::max(2, std::min(8, rounds + 1));
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
