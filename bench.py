@@ -49,6 +49,41 @@ def measured_traffic(workload, n):
     return m["bytes_per_launch"]
 
 
+def run_short_range(steps, warmup):
+    """Secondary measurement: the short-range Verlet workload (N = 1,048,576, phi = 0.5)."""
+    import torch
+
+    from paper_1703_02484_amd import binding, synth
+
+    w = synth.make("C3")
+    sim = binding.Sim.from_workload(w)
+    sim.step(warmup)
+    st0 = sim.state()[3]
+    sim.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.state()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    force_ms, launches = sim.kernel_time()
+    st1 = sim.state()[3]
+    d = {k: st1[k] - st0[k] for k in st1}
+    avg_s = force_ms / 1e3 / max(launches, 1)
+    # algorithmic bytes of k_force_nl per disk: own position 16, species 4, count 4,
+    # ~4 list entries x 4 (mean neighbours within cutoff + skin at phi = 0.5), force 16
+    bytes_per_disk = 16 + 4 + 4 + 4 * 4 + 16
+    gbs = bytes_per_disk * w.n / avg_s / 1e9
+    return {"workload": f"C3: N={w.n} screened A=1 lam=0.5 cutoff 2.5 skin 0.5, Verlet lists, FP64 pair forces, "
+                        f"phi=0.50, dt={w.dt}",
+            "value": w.n * steps / elapsed, "unit": "particle-steps/s", "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * elapsed / steps,
+            "force_nl_ms": avg_s * 1e3, "force_nl_gbs_algorithmic": gbs, "force_nl_frac_hbm": gbs / 8000.0,
+            "overlap_rounds_per_step": d["overlap_rounds_total"] / steps,
+            "flips_per_step": d["flips_total"] / steps, "verlet_rebuilds": d["verlet_rebuilds"],
+            "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"]}
+
+
 def cpu_baseline(w):
     import oracle
 
@@ -68,6 +103,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -160,6 +196,8 @@ def main():
             "frac_of_nonpacked": achieved / PEAK_FP32_NONPACKED if w.fp32_forces else None,
         },
     }
+    if not args.no_short_range and args.workload == "C2":
+        out["short_range"] = run_short_range(max(10, args.steps // 4), 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

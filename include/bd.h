@@ -65,7 +65,8 @@ typedef struct bd_force_params {
     double A;            /* screened amplitude (kind SCREENED) */
     double lambda;       /* screening length (kind SCREENED) */
     double cutoff;       /* <= 0: all pairs */
-    double skin;         /* neighbour-list skin for cutoff > 0 */
+    double skin;         /* cutoff > 0: Verlet lists hold pairs within cutoff + skin, rebuilt when a
+                            disk has moved more than skin / 2 since the last build */
     const double *K;     /* S*S row-major, K[a*S + b] acts on species a from species b; copied */
 } bd_force_params;
 
@@ -109,7 +110,8 @@ typedef struct bd_stats {
     int64_t flip_rounds_total;      /* parallel flip rounds launched */
     int64_t kinetic_repairs;        /* repairs redone on the device in sub-steps (multi-edge crossings) */
     int64_t host_rebuilds;          /* repairs that fell back to a host triangulation */
-    int64_t reserved[4];
+    int64_t verlet_rebuilds;        /* neighbour-list rebuilds (cutoff > 0) */
+    int64_t reserved[3];
 } bd_stats;
 
 typedef struct bd_sim bd_sim;

@@ -27,7 +27,9 @@ enum Ctl {
     K_STAR = 5,        // a vertex star walk exceeded its bound
     K_OVL_ROUNDS = 6,  // overlap rounds that moved disks in the budgeted sequence
     K_LAST = 7,        // last round slot of the repair that halted
-    K_CAND = 8,                      // [MAXR] flip candidates of round slot j
+    K_NL_REBUILD = 8,  // a disk moved more than skin/2 since the neighbour lists were built
+    K_NL_OVERFLOW = 9, // largest neighbour count when it exceeded the list capacity
+    K_CAND = 10,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -86,6 +88,16 @@ struct Sim {
     int iblock = 0;                  // i per workgroup in the force kernel
     double *Kd = nullptr;
     double *fout = nullptr;          // [2n] forces in caller order (bd_forces)
+    // short-range path: Verlet lists on a cell grid (cutoff > 0)
+    bool use_nl = false;
+    bool need_rebuild = true;
+    int nl_cap = 32, nl_nc = 1, nl_ncell = 1;
+    int *nl = nullptr, *nl_cnt = nullptr;
+    int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_items = nullptr;
+    double *xbuild = nullptr, *ybuild = nullptr;
+    double2 *fsr = nullptr;          // short-range forces, caller order
+    void *scan_tmp = nullptr;
+    size_t scan_bytes = 0;
     // triangulation (half-edge SoA, ghosts included)
     int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
     unsigned long long *claim = nullptr;
@@ -125,6 +137,11 @@ void launch_cast(Sim &s);
 void launch_force(Sim &s);
 void launch_em(Sim &s);
 void launch_reduce_forces(Sim &s);
+// short-range path (k_verlet.hip)
+size_t verlet_scan_bytes(int ncells);
+void launch_verlet_build(Sim &s);
+void launch_force_nl(Sim &s);
+void launch_skin_check(Sim &s);
 // triangulation (slot: round slot in ctl; rep: repair slot)
 void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal);
 void launch_flip_eval_list(Sim &s, int round, int slot);

@@ -213,13 +213,18 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
                                             double *__restrict__ x, double *__restrict__ y,
                                             double *__restrict__ xo, double *__restrict__ yo,
                                             double *__restrict__ th, double *__restrict__ tho,
-                                            unsigned long long *__restrict__ acc) {
+                                            unsigned long long *__restrict__ acc, const double2 *__restrict__ fdirect) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
     if (i < a.n) {
         double fx, fy;
-        gather_force<T2>(part, a.n, a.nchunks, chunks, K, a.S, sp[i], pos_of[i], fx, fy);
+        if (fdirect) {
+            fx = fdirect[i].x;
+            fy = fdirect[i].y;
+        } else {
+            gather_force<T2>(part, a.n, a.nchunks, chunks, K, a.S, sp[i], pos_of[i], fx, fy);
+        }
         const unsigned slo = (unsigned)(unsigned long long)a.step;
         const unsigned shi = (unsigned)((unsigned long long)a.step >> 32);
         const uint2 key = make_uint2((unsigned)a.seed, (unsigned)(a.seed >> 32));
@@ -308,10 +313,12 @@ void launch_em(Sim &s) {
     const int nb = blocks_for(s.n, 256);
     if (s.fp32)
         hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.chunks,
-                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc);
+                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc,
+                           s.use_nl ? s.fsr : nullptr);
     else
         hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.chunks,
-                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc);
+                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc,
+                           s.use_nl ? s.fsr : nullptr);
 }
 
 void launch_reduce_forces(Sim &s) {

@@ -238,21 +238,60 @@ void rollback(Sim &s) {
     check(hipMemcpyAsync(s.y, s.yo, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback y");
     check(hipMemcpyAsync(s.th, s.tho, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback th");
     fill_int(s, s.ctl, N_CTL, 0);
+    s.need_rebuild = true;
     host_rebuild(s);
 }
 
+// Rebuilds the Verlet lists from the current positions (one read-back to
+// check the list capacity; grows it once if a disk has too many neighbours).
+void verlet_rebuild(Sim &s) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        fill_int(s, s.cell_count, s.nl_ncell + 1, 0);
+        fill_int(s, s.cell_fill, s.nl_ncell, 0);
+        zero_ctl(s, K_NL_OVERFLOW);
+        launch_verlet_build(s);
+        read_ctl(s);
+        const int need = s.hctl[K_NL_OVERFLOW];
+        if (need == 0) {
+            ++s.st.verlet_rebuilds;
+            s.need_rebuild = false;
+            return;
+        }
+        if (need > 96 || s.nl_cap >= 96) throw DeviceError{hipErrorInvalidValue, "neighbour list capacity (96) exceeded"};
+        check(hipFree(s.nl), "free nl");
+        s.nl = nullptr;
+        s.nl_cap = 96;
+        s.nl = dalloc<int>((size_t)s.nl_cap * s.n);
+    }
+}
+
 void compute_forces(Sim &s) {
-    launch_cast(s);
+    if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
+    if (!s.use_nl) launch_cast(s);
+    hipEvent_t a = nullptr, b = nullptr;
     if (s.timing) {
-        hipEvent_t a, b;
         check(hipEventCreate(&a), "event");
         check(hipEventCreate(&b), "event");
         check(hipEventRecord(a, s.stream), "event record");
+    }
+    if (s.use_nl)
+        launch_force_nl(s);
+    else
         launch_force(s);
+    if (s.timing) {
         check(hipEventRecord(b, s.stream), "event record");
         s.ev.emplace_back(a, b);
-    } else {
-        launch_force(s);
+    }
+}
+
+// Skin test for the next step's lists (short-range path only).
+void skin_check(Sim &s, bool read_back) {
+    if (!s.use_nl) return;
+    zero_ctl(s, K_NL_REBUILD);
+    launch_skin_check(s);
+    if (read_back) {
+        read_ctl(s);
+        s.need_rebuild = s.hctl[K_NL_REBUILD] != 0;
     }
 }
 
@@ -320,8 +359,10 @@ int one_step(Sim &s) {
         launch_ovl_check(s, k);
         launch_final_check(s, k);
     }
+    skin_check(s, false);
     read_ctl(s);
     const int *h = s.hctl;
+    s.need_rebuild = s.use_nl && h[K_NL_REBUILD] != 0;
     // bookkeeping of the budgeted part: overlap rounds that moved disks
     int rounds = h[K_OVL_ROUNDS];
     if (h[K_HALT]) {
@@ -360,8 +401,10 @@ int one_step(Sim &s) {
         if (rc == BD_OK) rc = host_overlap_loop(s, hc, rounds);
         if (rc != BD_OK) {
             rollback(s);
+            s.need_rebuild = true;
             return rc;
         }
+        skin_check(s, true);   // positions moved after the budgeted sequence's test
     }
     // adapt the budgets to the rounds this step needed: grow at once when a
     // budget ran out, shrink by one when it was larger than needed
@@ -418,7 +461,9 @@ void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.chunks, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he, s.claim, s.tri_stamp, s.moved,
                     s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won, s.touched, s.newpos, s.oldpos,
-                    s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl, s.acc};
+                    s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl, s.acc, s.nl, s.nl_cnt,
+                    s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items, s.xbuild, s.ybuild, s.fsr,
+                    s.scan_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s.hctl) (void)hipHostFree(s.hctl);
@@ -444,6 +489,7 @@ int validate_args(int n, const double *xy, const double *radii, const int32_t *s
     if (!finite(fp->q) || !finite(fp->A) || !finite(fp->lambda) || !finite(fp->cutoff) || !finite(fp->skin))
         return err = "non-finite force parameter", BD_ERR_INVALID_ARG;
     if (fp->kind == BD_FORCE_SCREENED && !(fp->lambda > 0)) return err = "lambda must be > 0", BD_ERR_INVALID_ARG;
+    if (fp->cutoff > 0 && !(fp->skin >= 0)) return err = "skin must be >= 0", BD_ERR_INVALID_ARG;
     const double vals[] = {p->L, p->D, p->dt, p->v0, p->Dr, p->overlap_factor, p->cap_frac, p->noise_clip,
                            p->contact_tol};
     for (double v : vals)
@@ -504,6 +550,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.step = p->step0;
     s.fp32 = p->force_precision == BD_PREC_FP32;
     s.kind_fast = (fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)) ? 1 : 0;
+    s.use_nl = fp->cutoff > 0;
     check(hipGetDevice(&s.device), "hipGetDevice");
     check(hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking), "stream");
     s.stream = s.own_stream;
@@ -574,6 +621,23 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.xb = dalloc<double>(n);
     s.yb = dalloc<double>(n);
     s.ctl = dalloc<int>(N_CTL);
+    if (s.use_nl) {
+        const double rl = fp->cutoff + fp->skin;
+        s.nl_nc = std::max(1, std::min(46000, (int)std::floor(p->L / rl)));
+        s.nl_ncell = s.nl_nc * s.nl_nc;
+        s.cell_count = dalloc<int>(s.nl_ncell + 1);
+        s.cell_start = dalloc<int>(s.nl_ncell + 1);
+        s.cell_fill = dalloc<int>(s.nl_ncell);
+        s.cell_of = dalloc<int>(n);
+        s.cell_items = dalloc<int>(n);
+        s.nl = dalloc<int>((size_t)s.nl_cap * n);
+        s.nl_cnt = dalloc<int>(n);
+        s.xbuild = dalloc<double>(n);
+        s.ybuild = dalloc<double>(n);
+        s.fsr = dalloc<double2>(n);
+        s.scan_bytes = verlet_scan_bytes(s.nl_ncell);
+        s.scan_tmp = dalloc<char>(s.scan_bytes);
+    }
     s.acc = dalloc<unsigned long long>(N_ACC);
     if (hipHostMalloc((void **)&s.hctl, sizeof(int) * N_CTL, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
     if (hipHostMalloc((void **)&s.hacc, sizeof(unsigned long long) * N_ACC, hipHostMallocDefault) != hipSuccess)
@@ -605,6 +669,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
         return BD_ERR_TRIANGULATION;
     }
     upload_topology(s, hv, ht);
+    if (s.use_nl) verlet_rebuild(s);
     return BD_OK;
 }
 
@@ -702,9 +767,14 @@ int bd_forces(bd_sim *sim, double *f_out) {
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
         bd::compute_forces(s);
-        bd::launch_reduce_forces(s);
-        bd::check(hipMemcpyAsync(f_out, s.fout, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
-                  "forces copy");
+        if (s.use_nl) {
+            bd::check(hipMemcpyAsync(f_out, s.fsr, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
+                      "forces copy");
+        } else {
+            bd::launch_reduce_forces(s);
+            bd::check(hipMemcpyAsync(f_out, s.fout, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
+                      "forces copy");
+        }
         bd::check(hipStreamSynchronize(s.stream), "sync");
         return (int)BD_OK;
     });
@@ -812,6 +882,7 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         bd::check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "x");
         bd::check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "y");
         bd::fill_int(s, s.ctl, bd::N_CTL, 0);
+        s.need_rebuild = true;
         bd::Cursor c;
         return bd::host_repair(s, c, true, false, bd::MoveFrom::Previous, 0);
     });

@@ -264,3 +264,46 @@ def test_round_cap_reports_no_convergence_and_rolls_back():
     after, _, _, _ = g.state()
     assert np.array_equal(after, before)
     check_delaunay(np.concatenate([after, g.frame()]), g.triangles())
+
+
+# ------------------------------------------------------------------ short-range (Verlet) path
+@pytest.mark.parametrize("n", [50, 3000])
+def test_forces_verlet_screened(n):
+    w = synth.make("C3", n=n)
+    g = binding.Sim.from_workload(w)
+    fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=w.cutoff)
+    fg = g.forces()
+    assert np.abs(fg - fo).max() <= 1e-12 * max(_force_scale(fo), 1e-300)
+
+
+def test_forces_verlet_power_two_species():
+    # the paper's short-range law r/r^7 with a cutoff and a non-reciprocal 2x2 K
+    w = synth.make("C3", n=4000)
+    sp = (np.arange(w.n) % 2).astype(np.int32)
+    K = np.array([[1.0, -0.3], [0.2, 0.7]])
+    g = binding.Sim(w.xy, w.radii, sp, None, K, L=w.L, kind="power", q=6.0, cutoff=2.5, skin=0.5)
+    fo = oracle.forces(w.xy, sp, K, kind="power", q=6.0, cutoff=2.5)
+    assert np.abs(g.forces() - fo).max() <= 1e-12 * _force_scale(fo)
+
+
+def test_trajectory_c3_verlet_reduced():
+    worst, st = _run_parity(synth.make("C3", n=6000), 60, 1e-9)
+    assert st["verlet_rebuilds"] >= 2
+
+
+def test_full_size_c3_verlet():
+    # the short-range workload at full size (N = 1,048,576): sampled forces
+    # against the oracle, then 2 steps and the properties of the result
+    w = synth.make("C3")
+    g = binding.Sim.from_workload(w)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(w.n, 256, replace=False))
+    fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=w.cutoff, idx=idx)
+    fg = g.forces()
+    assert np.abs(fg[idx] - fo).max() <= 1e-12 * _force_scale(fo)
+    g.step(2)
+    x, th, step, st = g.state()
+    assert step == 2 and np.all(x >= 1.0) and np.all(x <= w.L - 1.0)
+    check_delaunay(np.concatenate([x, g.frame()]), g.triangles())
+    assert count_overlaps(x) == 0
+    assert st["host_rebuilds"] == 0
