@@ -82,6 +82,10 @@ def _load():
     lib.orc_sim_triangles.restype = ctypes.c_int
     lib.orc_frame.argtypes = [ctypes.c_double, ctypes.c_double, V, ctypes.c_int]
     lib.orc_frame.restype = ctypes.c_int
+    lib.orc_sim_set_tangent.argtypes = [V, V, V]
+    lib.orc_sim_set_tangent.restype = None
+    lib.orc_sim_get_tangent.argtypes = [V, V]
+    lib.orc_sim_get_tangent.restype = None
     lib.orc_sim_frame_count.argtypes = [V]
     lib.orc_sim_frame_count.restype = ctypes.c_int
     lib.orc_sim_free.argtypes = [V]
@@ -253,6 +257,17 @@ class OracleSim:
     def forces(self) -> np.ndarray:
         out = np.zeros((self.n, 2), dtype=np.float64)
         self._lib.orc_sim_forces(self._h, _p(out))
+        return out
+
+    def set_tangent(self, txy, tK=None):
+        """Carry forward-mode tangents from now on: txy (n, 2) for the positions, tK (S, S) for K."""
+        self._txy = np.ascontiguousarray(txy, dtype=np.float64).reshape(-1, 2)
+        self._tK = None if tK is None else np.ascontiguousarray(tK, dtype=np.float64)
+        self._lib.orc_sim_set_tangent(self._h, _p(self._txy), None if self._tK is None else _p(self._tK))
+
+    def tangent(self) -> np.ndarray:
+        out = np.zeros((self.n, 2), dtype=np.float64)
+        self._lib.orc_sim_get_tangent(self._h, _p(out))
         return out
 
     def triangles(self) -> np.ndarray:

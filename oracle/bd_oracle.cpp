@@ -396,6 +396,46 @@ void forces_subset(const ForceModel &fm, int n, const double *xy, const int *sp,
     }
 }
 
+// ----------------------------------------------------------------------------
+// Forward-mode derivatives (tangents) of one step.  Not part of the paper's
+// method: they define what its adjoint must compute.  The step is
+// differentiated as written, with every discrete decision held fixed -- the
+// overlapping edges of each correction round (the correction acts as a
+// projection onto the contact set of that round), the cap branch, the wall
+// branches, the cutoff -- so the tangent is that of the smooth map on the
+// current branch.  For the pair term u = r_i - r_j, d = |u|, s(d) = g(d)/d:
+//   d[K s(d) u] = K (s I + (s'(d)/d) u u^T) du + dK s u.
+// ----------------------------------------------------------------------------
+inline double pair_scale_slope(const ForceModel &fm, double d) {
+    // returns s'(d) / d for s = pair_scale
+    if (fm.kind == 0) return -(fm.q + 1.0) * std::pow(d, -fm.q - 3.0);
+    const double e = fm.A * std::exp(-d / fm.lam);
+    return e * (-1.0 / (fm.lam * d * d * d) - 2.0 / (d * d * d * d));
+}
+
+void force_tangent(const ForceModel &fm, int n, const double *xy, const int *sp, const double *txy,
+                   const double *tK, double *out) {
+    for (int i = 0; i < n; ++i) {
+        double fx = 0.0, fy = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double ux = xy[2 * i] - xy[2 * j], uy = xy[2 * i + 1] - xy[2 * j + 1];
+            double d = std::sqrt(ux * ux + uy * uy);
+            if (fm.cutoff > 0.0 && d > fm.cutoff) continue;
+            double dux = txy[2 * i] - txy[2 * j], duy = txy[2 * i + 1] - txy[2 * j + 1];
+            double k = fm.K[sp[i] * fm.S + sp[j]];
+            double tk = tK[sp[i] * fm.S + sp[j]];
+            double sc = pair_scale(fm, d);
+            double sl = pair_scale_slope(fm, d);
+            double ud = ux * dux + uy * duy;
+            fx += k * (sc * dux + sl * ux * ud) + tk * sc * ux;
+            fy += k * (sc * duy + sl * uy * ud) + tk * sc * uy;
+        }
+        out[2 * i] = fx;
+        out[2 * i + 1] = fy;
+    }
+}
+
 // Hard walls: mirror reflection about the shifted wall, then a safety clamp.
 inline double wall(double c, double r, double L) {
     double lo = r, hi = L - r;
@@ -404,6 +444,15 @@ inline double wall(double c, double r, double L) {
     if (c < lo) c = lo;
     if (c > hi) c = hi;
     return c;
+}
+
+// Derivative of wall() at c: -1 per reflection, 0 where the clamp acts.
+inline double wall_slope(double c, double r, double L) {
+    double lo = r, hi = L - r, sl = 1.0;
+    if (c < lo) { c = 2.0 * lo - c; sl = -sl; }
+    if (c > hi) { c = 2.0 * hi - c; sl = -sl; }
+    if (c < lo || c > hi) return 0.0;
+    return sl;
 }
 
 // Frame of fixed points outside the walls of [0, L]^2: four arcs at
@@ -454,9 +503,14 @@ struct Stats {
 // edges found (0: nothing moved).
 inline bool overlapping(double d, double contact, double tol) { return d < contact * (1.0 - tol); }
 
+// With txy non-NULL the tangent of the positions is carried through the round
+// (overlapping set, cap branch and wall branches fixed):
+//   d[f (sigma - d) u / d] = f ((sigma/d - 1) I - (sigma/d) n n^T) du,  n = u/d,
+//   d[c D/|D|] = (c/|D|)(I - e e^T) dD,  e = D/|D|  (when the cap acts).
 int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac, double tol,
-                      const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits) {
+                      const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits, double *txy = nullptr) {
     std::vector<double> disp(2 * (size_t)n, 0.0);
+    std::vector<double> tdisp(txy ? 2 * (size_t)n : 0, 0.0);
     std::vector<char> touched(n, 0);
     int64_t count = 0;
     for (const auto &e : edges) {
@@ -472,6 +526,17 @@ int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, 
         disp[2 * j] -= s * dx;
         disp[2 * j + 1] -= s * dy;
         touched[i] = touched[j] = 1;
+        if (txy) {
+            double nx = dx / d, ny = dy / d;
+            double dux = txy[2 * i] - txy[2 * j], duy = txy[2 * i + 1] - txy[2 * j + 1];
+            double a = contact / d, nd = nx * dux + ny * duy;
+            double ax = f * ((a - 1.0) * dux - a * nx * nd);
+            double ay = f * ((a - 1.0) * duy - a * ny * nd);
+            tdisp[2 * i] += ax;
+            tdisp[2 * i + 1] += ay;
+            tdisp[2 * j] -= ax;
+            tdisp[2 * j + 1] -= ay;
+        }
     }
     if (count == 0) return 0;
     for (int i = 0; i < n; ++i) {
@@ -479,11 +544,21 @@ int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, 
         double ddx = disp[2 * i], ddy = disp[2 * i + 1];
         double len = std::sqrt(ddx * ddx + ddy * ddy);
         double cap = cap_frac * rad[i];
+        double tdx = txy ? tdisp[2 * i] : 0.0, tdy = txy ? tdisp[2 * i + 1] : 0.0;
         if (len > cap) {
             double sc = cap / len;
+            if (txy) {
+                double ex = ddx / len, ey = ddy / len, et = ex * tdx + ey * tdy;
+                tdx = sc * (tdx - ex * et);
+                tdy = sc * (tdy - ey * et);
+            }
             ddx = ddx * sc;
             ddy = ddy * sc;
             if (cap_hits) ++*cap_hits;
+        }
+        if (txy) {
+            txy[2 * i] = wall_slope(xy[2 * i] + ddx, rad[i], L) * (txy[2 * i] + tdx);
+            txy[2 * i + 1] = wall_slope(xy[2 * i + 1] + ddy, rad[i], L) * (txy[2 * i + 1] + tdy);
         }
         xy[2 * i] = wall(xy[2 * i] + ddx, rad[i], L);
         xy[2 * i + 1] = wall(xy[2 * i + 1] + ddy, rad[i], L);
@@ -508,6 +583,9 @@ struct Sim {
     std::vector<std::pair<int, int>> edges;    // Delaunay edges between two disks
     std::vector<double> forces;
     int last_rounds = 0;
+    // forward-mode tangents (off unless set): positions and strength matrix
+    bool tan_on = false;
+    std::vector<double> txy, tK, tforce;
 
     bool retriangulate() {
         pts.assign(xy.begin(), xy.end());
@@ -526,6 +604,10 @@ struct Sim {
     int advance() {
         forces.assign(2 * (size_t)n, 0.0);
         forces_subset(fm, n, xy.data(), sp.data(), nullptr, n, forces.data());
+        if (tan_on) {
+            tforce.assign(2 * (size_t)n, 0.0);
+            force_tangent(fm, n, xy.data(), sp.data(), txy.data(), tK.data(), tforce.data());
+        }
         const double amp = std::sqrt(2.0 * D * dt);
         const double amp_r = std::sqrt(2.0 * Dr * dt);
         std::vector<double> nxy(2 * (size_t)n);
@@ -544,6 +626,10 @@ struct Sim {
             double y = xy[2 * i + 1] + vy * dt + amp * zy;
             nxy[2 * i] = wall(x, rad[i], L);
             nxy[2 * i + 1] = wall(y, rad[i], L);
+            if (tan_on) {
+                txy[2 * i] = wall_slope(x, rad[i], L) * (txy[2 * i] + dt * tforce[2 * i]);
+                txy[2 * i + 1] = wall_slope(y, rad[i], L) * (txy[2 * i + 1] + dt * tforce[2 * i + 1]);
+            }
             theta[i] = th + amp_r * nr;
         }
         // Sec. 4.3: an edge whose vector reversed means the pair passed through
@@ -558,7 +644,8 @@ struct Sim {
         if (!retriangulate()) return -4;
         int rounds = 0;
         for (;;) {
-            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, edges, &st.cap_hits);
+            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, edges, &st.cap_hits,
+                                        tan_on ? txy.data() : nullptr);
             if (cnt == 0) break;
             ++rounds;
             st.overlap_edges_total += cnt;
@@ -718,6 +805,23 @@ void orc_sim_get(void *h, double *xy, double *theta, int64_t *step, int64_t *sta
 void orc_sim_forces(void *h, double *out) {
     Sim *s = (Sim *)h;
     forces_subset(s->fm, s->n, s->xy.data(), s->sp.data(), nullptr, s->n, out);
+}
+
+// Starts carrying forward-mode tangents: txy (2n) of the positions and tK
+// (S*S, may be NULL for zero) of the strength matrix.
+void orc_sim_set_tangent(void *h, const double *txy, const double *tK) {
+    Sim *s = (Sim *)h;
+    s->tan_on = true;
+    s->txy.assign(txy, txy + 2 * (size_t)s->n);
+    if (tK)
+        s->tK.assign(tK, tK + s->fm.S * s->fm.S);
+    else
+        s->tK.assign(s->fm.S * s->fm.S, 0.0);
+}
+
+void orc_sim_get_tangent(void *h, double *out) {
+    Sim *s = (Sim *)h;
+    if (s->tan_on) std::memcpy(out, s->txy.data(), s->txy.size() * sizeof(double));
 }
 
 int orc_sim_frame_count(void *h) { return (int)(((Sim *)h)->frame.size() / 2); }

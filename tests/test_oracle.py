@@ -394,3 +394,129 @@ def test_box_side_matches_paper_abp_example():
     vals = {r[0]: float(r[1]) for r in _rows("abp_box.txt")}
     L = synth.box_side(int(vals["N"]), vals["phi"], vals["sigma"] / 2)
     assert L == pytest.approx(vals["L"], abs=0.05)
+
+
+# ------------------------------------------------------------------ forward-mode tangents
+# The oracle's tangents (held-fixed branches: overlapping set, cap, walls) are
+# pinned against central finite differences of its own forward map and against
+# closed forms derived from the geometry of one or two disks.
+def _tan_sim(xy, K, species=None, **kw):
+    xy = np.asarray(xy, dtype=np.float64)
+    n = xy.shape[0]
+    sp = np.zeros(n, np.int32) if species is None else species
+    return oracle.OracleSim(xy, np.ones(n), sp, kw.pop("theta", None), np.asarray(K, dtype=np.float64), **kw)
+
+
+def test_tangent_matches_central_differences():
+    w = synth.make("C5", n=200)
+    kw = dict(L=w.L, D=1.0, dt=1e-4, seed=3, overlap_factor=0.5)
+    rng = np.random.default_rng(0)
+    v = rng.normal(size=(w.n, 2))
+    tK = rng.normal(size=(2, 2)) * 1e-2
+    o = _tan_sim(w.xy, w.K, w.species, **kw)
+    o.set_tangent(v, tK)
+    o.step(5)
+    jvp = o.tangent()
+    assert o.state()[3]["overlap_edges_total"] > 0
+    h = 1e-7
+    xp = _tan_sim(w.xy + h * v, w.K + h * tK, w.species, **kw)
+    xm = _tan_sim(w.xy - h * v, w.K - h * tK, w.species, **kw)
+    xp.step(5)
+    xm.step(5)
+    fd = (xp.state()[0] - xm.state()[0]) / (2 * h)
+    assert np.abs(jvp - fd).max() <= 1e-6 * np.abs(jvp).max()
+
+
+def test_tangent_two_disk_radial_and_angular_closed_form():
+    # two disks, K = k, no noise: the separation r keeps its direction and its
+    # length follows d' = d + 2 k dt / d^2, so a radial perturbation scales by
+    # 1 - 4 k dt / d^3 and a perpendicular one (a rotation) by d'/d
+    k, dt = 0.7, 0.05
+    xy = np.array([[40.0, 50.0], [43.0, 50.0], [80.0, 80.0]])
+    d = 3.0
+    for pert, expect in (((1.0, 0.0), 1.0 - 4 * k * dt / d ** 3), ((0.0, 1.0), (d + 2 * k * dt / d ** 2) / d)):
+        o = _tan_sim(xy, [[k]], L=100.0, D=0.0, dt=dt)
+        v = np.zeros((3, 2))
+        v[1] = pert
+        o.set_tangent(v)
+        o.step(1)
+        t = o.tangent()
+        # the third disk is far: its own tangent and its pull are tiny but nonzero
+        assert t[1] - t[0] == pytest.approx(np.array(pert) * expect, abs=1e-5)
+
+
+def test_tangent_strength_closed_form():
+    # dK = 1 on the pair: d(separation)/dk = 2 dt / d^2 along the separation
+    dt = 0.05
+    xy = np.array([[40.0, 50.0], [43.0, 50.0], [90.0, 90.0]])
+    o = _tan_sim(xy, [[0.3]], L=100.0, D=0.0, dt=dt)
+    o.set_tangent(np.zeros((3, 2)), np.array([[1.0]]))
+    o.step(1)
+    t = o.tangent()
+    assert (t[1] - t[0])[0] == pytest.approx(2 * dt / 9.0, rel=1e-3)
+
+
+def test_tangent_identity_without_interactions():
+    # K = 0, dilute, away from the walls: every step is a translation by noise
+    n = 50
+    L = 400.0
+    xy = synth.rsa(n, 100.0, 1.0, seed=4) + 150.0
+    o = _tan_sim(xy, [[0.0]], L=L, D=1.0, dt=1e-3, seed=9)
+    v = np.random.default_rng(1).normal(size=(n, 2))
+    o.set_tangent(v)
+    o.step(20)
+    assert o.state()[3]["overlap_edges_total"] == 0
+    assert np.array_equal(o.tangent(), v)
+
+
+@pytest.mark.parametrize("f", [0.5, 1.0])
+def test_tangent_contact_projection_and_bounce(f):
+    # one overlapping pair, no force, no noise.  Contact (f = 1/2): the new
+    # separation is exactly sigma, so its tangent along the normal vanishes;
+    # bounce (f = 1): it is 2 sigma - d, so the normal tangent flips sign.  The
+    # moves are equal and opposite, so the sum of the two tangents is kept.
+    xy = np.array([[50.0, 50.0], [51.9, 50.3], [90.0, 90.0]])
+    o = _tan_sim(xy, [[0.0]], L=100.0, D=0.0, dt=1e-3, overlap_factor=f)
+    v = np.random.default_rng(2).normal(size=(3, 2))
+    o.set_tangent(v)
+    o.step(1)
+    t = o.tangent()
+    assert o.state()[3]["overlap_edges_total"] == 1
+    u = xy[0] - xy[1]
+    nrm = u / np.linalg.norm(u)
+    dn0 = nrm @ (v[0] - v[1])
+    x1 = o.state()[0]
+    nrm1 = (x1[0] - x1[1]) / np.linalg.norm(x1[0] - x1[1])
+    assert np.allclose(nrm, nrm1)
+    assert nrm @ (t[0] - t[1]) == pytest.approx(0.0 if f == 0.5 else -dn0, abs=1e-12)
+    assert t[0] + t[1] == pytest.approx(v[0] + v[1], abs=1e-12)
+
+
+def test_tangent_capped_move_keeps_normal_tangent():
+    # deep overlap: the move is truncated to half a radius along the normal, a
+    # length that no longer depends on d, so the normal tangent passes unchanged
+    xy = np.array([[50.0, 50.0], [50.8, 50.1], [90.0, 90.0]])
+    o = _tan_sim(xy, [[0.0]], L=100.0, D=0.0, dt=1e-3, max_overlap_rounds=1)
+    v = np.random.default_rng(3).normal(size=(3, 2))
+    o.set_tangent(v)
+    try:
+        o.step(1)
+    except RuntimeError:
+        pass
+    t = o.tangent()
+    assert o.state()[3]["cap_hits"] >= 2
+    u = xy[0] - xy[1]
+    nrm = u / np.linalg.norm(u)
+    assert nrm @ (t[0] - t[1]) == pytest.approx(nrm @ (v[0] - v[1]), abs=1e-12)
+
+
+def test_tangent_wall_reflection_negates():
+    # a self-propelled disk driven through the left wall is reflected: the x
+    # tangent changes sign, the y tangent is kept
+    xy = np.array([[1.01, 50.0], [50.0, 50.0], [80.0, 20.0]])
+    o = _tan_sim(xy, [[0.0]], L=100.0, D=0.0, dt=0.02, v0=1.0, theta=np.array([np.pi, 0.0, 0.0]))
+    o.set_tangent(np.array([[0.3, -0.7], [0.0, 0.0], [0.0, 0.0]]))
+    o.step(1)
+    x1 = o.state()[0]
+    assert x1[0, 0] == pytest.approx(1.01, abs=1e-9)
+    assert o.tangent()[0] == pytest.approx(np.array([-0.3, -0.7]), abs=1e-15)
