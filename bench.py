@@ -84,6 +84,61 @@ def run_short_range(steps, warmup):
             "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"]}
 
 
+def run_batched(steps, warmup, loop_steps):
+    """Batched systems (256 replicas, N_r log-uniform in [2048, 32768], FP64) in one handle, against a loop
+    that steps one handle per system with the same tiling (identical arithmetic, so equal accuracy)."""
+    import torch
+
+    from paper_1703_02484_amd import binding, synth
+
+    ws = synth.make_batch(256)
+    ntot = sum(w.n for w in ws)
+    pairs = sum(w.n * (w.n - 1) for w in ws)
+    b = binding.Sim.from_workloads(ws)
+    cfg = b.force_config()
+    b.step(warmup)
+    st0 = b.state()[3]
+    b.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.state()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    force_ms, launches = b.kernel_time()
+    st1 = b.state()[3]
+    b.close()
+    avg_s = force_ms / 1e3 / max(launches, 1)
+    tflops = FLOPS_PER_PAIR * pairs / avg_s / 1e12
+    out = {"workload": f"C4: {len(ws)} systems, N_r log-uniform in [2048, 32768] (sum {ntot}), phi_r ~ U[0.2, 0.5], "
+                       f"FP64 all-pairs inverse-square K=1e-2, dt=1e-4, seed_r=r",
+           "value": ntot * steps / elapsed, "unit": "particle-steps/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": 1e3 * elapsed / steps, "pair_interactions_per_s": pairs / avg_s,
+           "force_ms": avg_s * 1e3, "force_tflops": tflops, "force_frac_fp64": tflops / PEAK_FP64_TFLOPS,
+           "force_config": cfg,
+           "overlap_rounds_per_step": (st1["overlap_rounds_total"] - st0["overlap_rounds_total"]) / steps,
+           "host_rebuilds": st1["host_rebuilds"]}
+    # the same systems, one handle each, stepped one after another
+    singles = [binding.Sim.from_workload(w, force_chunk=cfg["chunk"]) for w in ws]
+    for s in singles:
+        s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(loop_steps):
+        for s in singles:
+            s.step(1)
+    for s in singles:
+        s.state()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for s in singles:
+        s.close()
+    out["per_system_loop"] = {"value": ntot * loop_steps / el, "unit": "particle-steps/s", "steps": loop_steps,
+                              "ms_per_step": 1e3 * el / loop_steps}
+    out["speedup_vs_loop"] = out["value"] / out["per_system_loop"]["value"]
+    return out
+
+
 def cpu_baseline(w):
     import oracle
 
@@ -104,6 +159,7 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the secondary 256-system batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -144,6 +200,7 @@ def main():
     elapsed = time.perf_counter() - t0
     force_ms, launches = sim.kernel_time()
     st1 = sim.state()[3]
+    fcfg = sim.force_config()
 
     n = w.n
     ms_per_step = 1e3 * elapsed / args.steps
@@ -181,7 +238,8 @@ def main():
             "host_rebuilds": d["host_rebuilds"],
         },
         "roofline": {
-            "kernel": "all-pairs force (k_force)",
+            "kernel": "all-pairs force (" + ("k_force_queue" if fcfg["persistent"] else "k_force") + ")",
+            "force_config": fcfg,
             "bound": "alu",
             "achieved": achieved,
             "peak": peak,
@@ -198,6 +256,8 @@ def main():
     }
     if not args.no_short_range and args.workload == "C2":
         out["short_range"] = run_short_range(max(10, args.steps // 4), 5)
+    if not args.no_batched and args.workload == "C2":
+        out["batched"] = run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -93,7 +93,9 @@ typedef struct bd_params {
     int32_t max_overlap_rounds;  /* cap on overlap rounds per step (10000) */
     int32_t max_flip_rounds;     /* cap on flip rounds per repair before the host rebuild (200) */
     int32_t force_precision;     /* bd_precision */
-    int32_t reserved;            /* must be 0 */
+    int32_t force_chunk;         /* all-pairs force: j per chunk (64..65536); 0 lets the library choose,
+                                    by timing the candidate tilings once per workload shape when the pair
+                                    count is large (see bd_get_force_config) */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
@@ -139,6 +141,47 @@ void bd_params_default(bd_params *p);
  */
 int bd_init(bd_sim **out, int32_t n, const double *xy, const double *radii, const int32_t *species,
             const double *theta, const bd_force_params *fp, const bd_params *p);
+
+/*
+ * Creates R >= 1 independent systems advanced together (batched replicas; not
+ * in the paper: each system on its own follows Algorithm 1 exactly as a
+ * handle from bd_init would).  System r holds n_per[r] >= 3 disks in a box
+ * [0, L_per[r]]^2 with noise key seed_per[r]; the arrays xy (2 per disk),
+ * radii, species and theta (or NULL) hold the systems one after another
+ * (disk offsets are the prefix sums of n_per).  p->L and p->seed are ignored;
+ * every other field of p and fp applies to all systems.  Noise is keyed by
+ * (seed_per[r], step, index of the disk inside its system), so a system's
+ * trajectory does not depend on the others; forces act only inside a system.
+ * The all-pairs force of all systems is one launch over a tile list ordered
+ * longest first.  Short-range forces (fp->cutoff > 0) need R == 1.
+ * bd_step, bd_forces, bd_get_state, bd_set_positions, bd_get_frame and
+ * bd_get_triangulation then act on the concatenation; bd_batch_layout gives
+ * the offsets.
+ */
+int bd_batch_init(bd_sim **out, int32_t R, const int32_t *n_per, const double *xy, const double *radii,
+                  const int32_t *species, const double *theta, const double *L_per, const uint64_t *seed_per,
+                  const bd_force_params *fp, const bd_params *p);
+
+/*
+ * Layout of the systems of a handle: *R_out systems; disk_off[r] (R+1
+ * entries, may be NULL) is the first disk of system r in caller order and
+ * frame_off[r] (R+1 entries, may be NULL) the first frame point of system r
+ * in bd_get_frame order.  Triangulation ids: disk i is i, frame point k is
+ * n + k with n = disk_off[R].
+ */
+int bd_batch_layout(bd_sim *sim, int32_t *R_out, int32_t *disk_off, int32_t *frame_off);
+
+/* Tiling of the all-pairs force kernel in use (measurement and reproducibility). */
+typedef struct bd_force_config {
+    int32_t chunk;        /* j per chunk (results depend on it at rounding level) */
+    int32_t per_lane;     /* i per lane; a tile holds 256 * per_lane particles i */
+    int32_t persistent;   /* 1: fixed grid taking tiles from a queue; 0: one workgroup per tile */
+    int32_t tiles;        /* tiles per force evaluation */
+    int32_t grid;         /* workgroups launched per force evaluation */
+    int32_t tuned;        /* 1: chosen by timing, 2: taken from the tuning cache, 0: fixed rule */
+    double tuned_ms;      /* force time of the chosen tiling when timed, else 0 */
+} bd_force_config;
+int bd_get_force_config(bd_sim *sim, bd_force_config *out);
 
 /*
  * Advances nsteps >= 0 steps of Algorithm 1: forces, move, walls, flip repair

@@ -19,9 +19,9 @@ BD_FORCE_SCREENED = 1
 BD_PREC_FP64 = 0
 BD_PREC_FP32 = 1
 
-EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_step", "bd_forces",
-            "bd_get_state", "bd_get_triangulation", "bd_get_frame", "bd_set_positions", "bd_set_stream",
-            "bd_enable_kernel_timing", "bd_kernel_time", "bd_destroy")
+EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
+            "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
+            "bd_set_positions", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_destroy")
 
 
 class ForceParams(ctypes.Structure):
@@ -37,7 +37,16 @@ class Params(ctypes.Structure):
                 ("noise_clip", ctypes.c_double), ("contact_tol", ctypes.c_double),
                 ("max_overlap_rounds", ctypes.c_int32),
                 ("max_flip_rounds", ctypes.c_int32), ("force_precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("force_chunk", ctypes.c_int32)]
+
+
+class ForceConfig(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("per_lane", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("grid", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 STAT_NAMES = ("steps", "overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "cap_hits",
@@ -78,6 +87,12 @@ def load() -> ctypes.CDLL:
     lib.bd_params_default.restype = None
     lib.bd_init.argtypes = [P(V), ctypes.c_int32, V, V, V, V, P(ForceParams), P(Params)]
     lib.bd_init.restype = ctypes.c_int
+    lib.bd_batch_init.argtypes = [P(V), ctypes.c_int32, V, V, V, V, V, V, V, P(ForceParams), P(Params)]
+    lib.bd_batch_init.restype = ctypes.c_int
+    lib.bd_batch_layout.argtypes = [V, P(ctypes.c_int32), V, V]
+    lib.bd_batch_layout.restype = ctypes.c_int
+    lib.bd_get_force_config.argtypes = [V, P(ForceConfig)]
+    lib.bd_get_force_config.restype = ctypes.c_int
     lib.bd_step.argtypes = [V, ctypes.c_int64]
     lib.bd_step.restype = ctypes.c_int
     lib.bd_forces.argtypes = [V, V]
@@ -106,36 +121,77 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
+def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, step0, overlap_factor, cap_frac,
+            noise_clip, contact_tol, max_overlap_rounds, max_flip_rounds, fp32, force_chunk):
+    Km = np.ascontiguousarray(K, dtype=np.float64)
+    fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
+                     skin, _ptr(Km))
+    p = Params()
+    lib.bd_params_default(ctypes.byref(p))
+    p.L, p.D, p.dt, p.v0, p.Dr = L, D, dt, v0, Dr
+    p.seed, p.step0 = seed & (2**64 - 1), step0
+    p.overlap_factor, p.cap_frac, p.noise_clip = overlap_factor, cap_frac, noise_clip
+    p.contact_tol = contact_tol
+    p.max_overlap_rounds, p.max_flip_rounds = max_overlap_rounds, max_flip_rounds
+    p.force_precision = BD_PREC_FP32 if fp32 else BD_PREC_FP64
+    p.force_chunk = force_chunk
+    return fp, p, Km
+
+
+_DEFAULTS = dict(kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, skin=0.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0,
+                 step0=0, overlap_factor=1.0, cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9,
+                 max_overlap_rounds=10000, max_flip_rounds=200, fp32=False, force_chunk=0)
+
+
 class Sim:
     """One simulation handle (``bd_sim``) living on the current HIP device."""
 
-    def __init__(self, xy, radii, species, theta, K, *, L, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0,
-                 skin=0.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0, step0=0, overlap_factor=1.0, cap_frac=0.5,
-                 noise_clip=3.0, contact_tol=1e-9, max_overlap_rounds=10000, max_flip_rounds=200, fp32=False):
+    def __init__(self, xy, radii, species, theta, K, *, L, **kw):
         lib = load()
         self._lib = lib
+        opts = dict(_DEFAULTS)
+        opts.update(kw)
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         self.n = xy.shape[0]
         rad = np.ascontiguousarray(radii, dtype=np.float64)
         sp = np.ascontiguousarray(species, dtype=np.int32)
         th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
-        Km = np.ascontiguousarray(K, dtype=np.float64)
-        fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
-                         skin, _ptr(Km))
-        p = Params()
-        lib.bd_params_default(ctypes.byref(p))
-        p.L, p.D, p.dt, p.v0, p.Dr = L, D, dt, v0, Dr
-        p.seed, p.step0 = seed & (2**64 - 1), step0
-        p.overlap_factor, p.cap_frac, p.noise_clip = overlap_factor, cap_frac, noise_clip
-        p.contact_tol = contact_tol
-        p.max_overlap_rounds, p.max_flip_rounds = max_overlap_rounds, max_flip_rounds
-        p.force_precision = BD_PREC_FP32 if fp32 else BD_PREC_FP64
+        fp, p, _keep = _params(lib, L=L, K=K, **opts)
         h = ctypes.c_void_p()
         rc = lib.bd_init(ctypes.byref(h), self.n, _ptr(xy), _ptr(rad), _ptr(sp), None if th is None else _ptr(th),
                          ctypes.byref(fp), ctypes.byref(p))
         if rc != 0:
             raise BDError(rc, f"bd_init failed: {lib.bd_strerror(rc).decode()}")
         self._h = h
+
+    @classmethod
+    def batch(cls, xys, radii, species, thetas, Ls, seeds, K, **kw):
+        """R independent systems in one handle (``bd_batch_init``); lists hold one entry per system."""
+        self = cls.__new__(cls)
+        lib = load()
+        self._lib = lib
+        opts = dict(_DEFAULTS)
+        opts.update(kw)
+        R = len(xys)
+        n_per = np.array([len(np.asarray(a).reshape(-1, 2)) for a in xys], dtype=np.int32)
+        xy = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1, 2) for a in xys]))
+        rad = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64) for a in radii]))
+        sp = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.int32) for a in species]))
+        th = None
+        if thetas is not None:
+            th = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64) for a in thetas]))
+        L_per = np.ascontiguousarray(Ls, dtype=np.float64)
+        seed_per = np.ascontiguousarray([int(v) & (2**64 - 1) for v in seeds], dtype=np.uint64)
+        self.n = int(n_per.sum())
+        fp, p, _keep = _params(lib, L=float(L_per[0]), K=K, **opts)
+        h = ctypes.c_void_p()
+        rc = lib.bd_batch_init(ctypes.byref(h), R, _ptr(n_per), _ptr(xy), _ptr(rad), _ptr(sp),
+                               None if th is None else _ptr(th), _ptr(L_per), _ptr(seed_per), ctypes.byref(fp),
+                               ctypes.byref(p))
+        if rc != 0:
+            raise BDError(rc, f"bd_batch_init failed: {lib.bd_strerror(rc).decode()}")
+        self._h = h
+        return self
 
     @classmethod
     def from_workload(cls, w, **over):
@@ -145,6 +201,33 @@ class Sim:
                   max_overlap_rounds=w.max_overlap_rounds, fp32=w.fp32_forces)
         kw.update(over)
         return cls(w.xy, w.radii, w.species, w.theta, w.K, **kw)
+
+    @classmethod
+    def from_workloads(cls, ws, **over):
+        """Batch of workloads that share force and step parameters (box sides and seeds per system)."""
+        w = ws[0]
+        kw = dict(kind=w.kind, q=w.q, A=w.A, lam=w.lam, cutoff=w.cutoff, skin=w.skin, D=w.D, dt=w.dt, v0=w.v0,
+                  Dr=w.Dr, step0=w.step0, overlap_factor=w.overlap_factor, cap_frac=w.cap_frac,
+                  noise_clip=w.noise_clip, contact_tol=w.contact_tol, max_overlap_rounds=w.max_overlap_rounds,
+                  fp32=w.fp32_forces)
+        kw.update(over)
+        return cls.batch([v.xy for v in ws], [v.radii for v in ws], [v.species for v in ws],
+                         [v.theta for v in ws] if all(v.theta is not None for v in ws) else None,
+                         [v.L for v in ws], [v.seed for v in ws], w.K, **kw)
+
+    def layout(self):
+        """(R, disk_off[R+1], frame_off[R+1]) of ``bd_batch_layout``."""
+        R = ctypes.c_int32()
+        self._check(self._lib.bd_batch_layout(self._h, ctypes.byref(R), None, None), "bd_batch_layout")
+        d = np.zeros(R.value + 1, dtype=np.int32)
+        f = np.zeros(R.value + 1, dtype=np.int32)
+        self._check(self._lib.bd_batch_layout(self._h, ctypes.byref(R), _ptr(d), _ptr(f)), "bd_batch_layout")
+        return R.value, d, f
+
+    def force_config(self):
+        c = ForceConfig()
+        self._check(self._lib.bd_get_force_config(self._h, ctypes.byref(c)), "bd_get_force_config")
+        return c.as_dict()
 
     def _check(self, rc: int, what: str):
         if rc != 0:

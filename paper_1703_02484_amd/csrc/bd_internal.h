@@ -29,7 +29,8 @@ enum Ctl {
     K_LAST = 7,        // last round slot of the repair that halted
     K_NL_REBUILD = 8,  // a disk moved more than skin/2 since the neighbour lists were built
     K_NL_OVERFLOW = 9, // largest neighbour count when it exceeded the list capacity
-    K_CAND = 10,                     // [MAXR] flip candidates of round slot j
+    K_FQUEUE = 10,     // next tile of the persistent all-pairs force launch
+    K_CAND = 11,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -49,19 +50,39 @@ enum Acc {
     N_ACC = 8
 };
 
-// One chunk of the all-pairs j loop: sorted j range [js, je) of species spec.
-struct Chunk {
-    int js, je, spec, pad;
+// One workgroup of the all-pairs force: sorted i range [i0, i1) (at most
+// 256 * per_lane) against the sorted j range [js, je) of one species of the same
+// system; partial sums go to part[pbase + i].
+struct Tile {
+    int i0, i1, js, je;
+    long long pbase;
+    long long work;   // (i1 - i0) * (je - js), for ordering
+};
+
+// Per-system constants read by the update kernel.
+struct RepInfo {
+    int off, n;            // disks [off, off + n) in caller order and in sorted order
+    int nch, cfirst;       // chunks of this system and the first one's index in chunk_spec
+    long long poff;        // partial sums of chunk c, sorted index k: part[poff + c n + (k - off)]
+    double L;              // box side
+    unsigned long long seed;
 };
 
 struct Sim {
-    int n = 0;          // particles (vertex ids 0..n-1)
+    int R = 1;          // independent systems held by this handle
+    int n = 0;          // particles of all systems (vertex ids 0..n-1)
     int m = 0;          // fixed frame points outside the walls (vertex ids n..n+m-1)
     int nv = 0;         // finite vertices n + m
     int S = 1;          // species
     int T = 0;          // triangles incl. ghosts: 2 nv - 2
     int H = 0;          // half-edges: 3T
-    int inf = 0;        // infinite vertex id (= nv)
+    int inf = 0;        // first infinite vertex id (= nv); system r has nv + r
+    std::vector<int> off_h, foff_h, toff_h;   // per system: first disk, first frame point (rel. n), first triangle
+    std::vector<double> L_h;
+    std::vector<unsigned long long> seed_h;
+    RepInfo *reps = nullptr;
+    int *rep_of = nullptr;           // system of each disk
+    double *Lr = nullptr;            // box side of each system
     bd_params p{};
     bd_force_params fp{};
     std::vector<double> K;           // S*S
@@ -82,10 +103,17 @@ struct Sim {
     int *pos_of = nullptr;           // caller id -> sorted index
     void *pj = nullptr;              // float2 / double2 [n], sorted order
     void *part = nullptr;            // [nchunks][n] float2 / double2 partial sums
-    std::vector<Chunk> chunks_h;
-    Chunk *chunks = nullptr;
-    int nchunks = 0;
-    int iblock = 0;                  // i per workgroup in the force kernel
+    Tile *tiles = nullptr;           // force tiles, longest first
+    int ntiles = 0;
+    int *chunk_spec = nullptr;       // species of each chunk
+    long long part_cap = 0;          // elements allocated for part
+    int chunk_len = 0;               // j per chunk (last chunk of a species may be shorter)
+    int per_lane = 4;                // i per lane: a tile holds 256 * per_lane particles
+    int persistent = 0;              // 1: fixed grid pulling tiles from a queue
+    int force_grid = 0;              // workgroups of the persistent launch
+    int tuned = 0;                   // 1: tiling chosen by timing, 2: from the tuning cache, 0: fixed rule
+    double tuned_ms = 0.0;           // force time of the chosen configuration when tuned, else 0
+    std::vector<int> bstart_h;       // per system, per species: first sorted index (R x (S+1))
     double *Kd = nullptr;
     double *fout = nullptr;          // [2n] forces in caller order (bd_forces)
     // short-range path: Verlet lists on a cell grid (cutoff > 0)
@@ -135,6 +163,7 @@ struct Sim {
 // ---- kernel launchers (k_*.hip) ------------------------------------------
 void launch_cast(Sim &s);
 void launch_force(Sim &s);
+int force_max_grid(Sim &s, int per_lane);            // resident workgroups of the persistent launch
 void launch_em(Sim &s);
 void launch_reduce_forces(Sim &s);
 // short-range path (k_verlet.hip)

@@ -55,7 +55,8 @@ BD_HD bool bd_in_closed_tri(double v1x, double v1y, double v2x, double v2y, doub
 enum { BD_NOFLIP = 0, BD_FLIP_LAWSON = 1, BD_FLIP_INVERSION = 2 };
 
 // Flip decision for the edge a -> b shared by triangles (a, b, c) and
-// (b, a, d), any of a, b, c, d possibly the infinite vertex.
+// (b, a, d), any of a, b, c, d possibly an infinite vertex (ids >= inf; a
+// batch of independent triangulations has one infinite vertex each).
 //   * Finite quad with an inverted (or flat) triangle: flip when one
 //     opposite vertex lies in the closed triangle formed by the edge and the
 //     other opposite vertex (Sec. 4.3, evaluated for both orderings).
@@ -70,14 +71,14 @@ enum { BD_NOFLIP = 0, BD_FLIP_LAWSON = 1, BD_FLIP_INVERSION = 2 };
 BD_HD int bd_flip_rule(int a, int b, int c, int d, int inf, const double *x, const double *y,
                        bool allow_inversion, bool *inverted = nullptr) {
     if (inverted) *inverted = false;
-    if (b == inf) return bd_orient(x[d], y[d], x[a], y[a], x[c], y[c]) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
-    if (a == inf) return bd_orient(x[c], y[c], x[b], y[b], x[d], y[d]) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
-    if (c == inf) {
+    if (b >= inf) return bd_orient(x[d], y[d], x[a], y[a], x[c], y[c]) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
+    if (a >= inf) return bd_orient(x[c], y[c], x[b], y[b], x[d], y[d]) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
+    if (c >= inf) {
         bool bad = bd_orient(x[b], y[b], x[a], y[a], x[d], y[d]) < 0.0;
         if (inverted) *inverted = bad;
         return bad ? BD_FLIP_INVERSION : BD_NOFLIP;
     }
-    if (d == inf) {
+    if (d >= inf) {
         bool bad = bd_orient(x[a], y[a], x[b], y[b], x[c], y[c]) < 0.0;
         if (inverted) *inverted = bad;
         return bad ? BD_FLIP_INVERSION : BD_NOFLIP;

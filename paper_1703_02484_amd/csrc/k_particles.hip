@@ -3,14 +3,17 @@
 // move with Brownian noise and self-propulsion (Sec. 2.2, 2.4, 7) and hard
 // walls.
 //
-// Force layout.  Particles are permuted once so that species are contiguous
-// ("sorted order").  The j range is cut into chunks that never straddle a
-// species boundary; workgroup (bx, c) accumulates, for its 256*P particles i,
-// the unweighted sum Phi_{i,c} = sum_{j in chunk c} (r_i - r_j)/d^3.  The
-// update kernel then forms F_i = sum_c K[s_i][spec(c)] Phi_{i,c} in FP64 in a
-// fixed chunk order (deterministic, no atomics).  Inside the j loop every lane
-// of the wavefront needs the same j, so j positions are wave-uniform loads
-// (scalar data cache) and the VALU only sees the pair arithmetic.
+// Force layout.  Inside each system the particles are permuted once so that
+// species are contiguous ("sorted order").  A system's j range is cut into
+// chunks that never straddle a species boundary; one workgroup handles one
+// tile (a block of 256*P particles i of one system against one chunk of the
+// same system) and writes the unweighted sum
+// Phi_{i,c} = sum_{j in chunk c} (r_i - r_j)/d^3.  Tiles of all systems form one
+// launch, longest first.  The update kernel then forms
+// F_i = sum_c K[s_i][spec(c)] Phi_{i,c} in FP64 in a fixed chunk order
+// (deterministic, no atomics).  Inside the j loop every lane of the wavefront
+// needs the same j, so j positions are wave-uniform loads (scalar data cache)
+// and the VALU only sees the pair arithmetic.
 #include <hip/hip_runtime.h>
 
 #include "bd_internal.h"
@@ -109,16 +112,14 @@ __device__ __forceinline__ void pair_range_general(const T2 *__restrict__ pj, in
 }
 
 template <typename T, typename T2, int P, bool FAST>
-__global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj, int n,
-                                                       const Chunk *__restrict__ chunks, T2 *__restrict__ part,
-                                                       LawArgs law) {
-    const Chunk cd = chunks[blockIdx.y];
-    const int ib = blockIdx.x * (kForceBlock * P);
+__device__ __forceinline__ void force_tile(const T2 *__restrict__ pj, const Tile &tl, T2 *__restrict__ part,
+                                           const LawArgs &law) {
+    const int ib = tl.i0;
     T xi[P], yi[P], ax[P], ay[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         int i = ib + k * kForceBlock + threadIdx.x;
-        T2 v = pj[i < n ? i : n - 1];
+        T2 v = pj[i < tl.i1 ? i : tl.i1 - 1];
         xi[k] = v.x;
         yi[k] = v.y;
         ax[k] = (T)0;
@@ -126,41 +127,69 @@ __global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj
     }
     if (FAST) {
         // self range: the workgroup's own particles inside this chunk
-        int lo = cd.js > ib ? cd.js : ib;
-        int hi = cd.je < ib + kForceBlock * P ? cd.je : ib + kForceBlock * P;
+        int lo = tl.js > ib ? tl.js : ib;
+        int hi = tl.je < tl.i1 ? tl.je : tl.i1;
         if (lo < hi) {
-            pair_range_q2<T, T2, P, false>(pj, cd.js, lo, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false>(pj, tl.js, lo, xi, yi, ax, ay);
             pair_range_q2<T, T2, P, true>(pj, lo, hi, xi, yi, ax, ay);
-            pair_range_q2<T, T2, P, false>(pj, hi, cd.je, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false>(pj, hi, tl.je, xi, yi, ax, ay);
         } else {
-            pair_range_q2<T, T2, P, false>(pj, cd.js, cd.je, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false>(pj, tl.js, tl.je, xi, yi, ax, ay);
         }
     } else {
-        pair_range_general<T, T2, P>(pj, cd.js, cd.je, xi, yi, ax, ay, law);
+        pair_range_general<T, T2, P>(pj, tl.js, tl.je, xi, yi, ax, ay, law);
     }
-    T2 *out = part + (size_t)blockIdx.y * n;
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         int i = ib + k * kForceBlock + threadIdx.x;
-        if (i < n) {
+        if (i < tl.i1) {
             T2 v;
             v.x = ax[k];
             v.y = ay[k];
-            out[i] = v;
+            part[tl.pbase + i] = v;
         }
     }
 }
 
-// F_i = sum_c K[s_i][spec(c)] Phi_{i,c}, FP64, fixed chunk order.
+// One workgroup per tile.
+template <typename T, typename T2, int P, bool FAST>
+__global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj, const Tile *__restrict__ tiles,
+                                                       T2 *__restrict__ part, LawArgs law) {
+    force_tile<T, T2, P, FAST>(pj, tiles[blockIdx.x], part, law);
+}
+
+// Persistent form: a grid sized to the resident workgroups takes tiles from
+// a queue (tile list longest first) until it is empty.  The queue counter is
+// zeroed before the launch; every workgroup leaves once the counter passes
+// the number of tiles.
+template <typename T, typename T2, int P, bool FAST>
+__global__ __launch_bounds__(kForceBlock) void k_force_queue(const T2 *__restrict__ pj,
+                                                             const Tile *__restrict__ tiles, int ntiles,
+                                                             T2 *__restrict__ part, LawArgs law,
+                                                             int *__restrict__ queue) {
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int t = next;
+        __syncthreads();
+        if (t >= ntiles) return;
+        force_tile<T, T2, P, FAST>(pj, tiles[t], part, law);
+    }
+}
+
+// F_i = sum_c K[s_i][spec(c)] Phi_{i,c} over the chunks of i's system, FP64,
+// fixed chunk order; k is i's sorted index.
 template <typename T2>
-__device__ __forceinline__ void gather_force(const T2 *__restrict__ part, int n, int nchunks,
-                                             const Chunk *__restrict__ chunks, const double *__restrict__ K,
+__device__ __forceinline__ void gather_force(const T2 *__restrict__ part, const RepInfo &ri,
+                                             const int *__restrict__ chunk_spec, const double *__restrict__ K,
                                              int S, int si, int k, double &fx, double &fy) {
     fx = 0.0;
     fy = 0.0;
-    for (int c = 0; c < nchunks; ++c) {
-        double w = K[si * S + chunks[c].spec];
-        T2 v = part[(size_t)c * n + k];
+    const long long row = ri.poff + (k - ri.off);
+    for (int c = 0; c < ri.nch; ++c) {
+        double w = K[si * S + chunk_spec[ri.cfirst + c]];
+        T2 v = part[row + (long long)c * ri.n];
         fx += w * (double)v.x;
         fy += w * (double)v.y;
     }
@@ -197,9 +226,8 @@ __device__ __forceinline__ void box_muller(uint4 w, double &z0, double &z1) {
 }
 
 struct EmArgs {
-    int n, S, nchunks;
-    double dt, amp, amp_r, v0, L, clip;
-    uint64_t seed;
+    int n, S;
+    double dt, amp, amp_r, v0, clip;
     int64_t step;
 };
 
@@ -207,7 +235,8 @@ struct EmArgs {
 // translation, stream 1: rotation), move, reflect at the walls, keep the
 // previous state for the reversal check and for error rollback.
 template <typename T2>
-__global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ part, const Chunk *__restrict__ chunks,
+__global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ part, const RepInfo *__restrict__ reps,
+                                            const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
                                             const double *__restrict__ K, const int *__restrict__ pos_of,
                                             const int *__restrict__ sp, const double *__restrict__ rad,
                                             double *__restrict__ x, double *__restrict__ y,
@@ -218,19 +247,22 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
     if (i < a.n) {
+        const RepInfo ri = reps[rep_of[i]];
         double fx, fy;
         if (fdirect) {
             fx = fdirect[i].x;
             fy = fdirect[i].y;
         } else {
-            gather_force<T2>(part, a.n, a.nchunks, chunks, K, a.S, sp[i], pos_of[i], fx, fy);
+            gather_force<T2>(part, ri, chunk_spec, K, a.S, sp[i], pos_of[i], fx, fy);
         }
+        // noise keyed by the system's seed and the particle's id inside its system
+        const unsigned id = (unsigned)(i - ri.off);
         const unsigned slo = (unsigned)(unsigned long long)a.step;
         const unsigned shi = (unsigned)((unsigned long long)a.step >> 32);
-        const uint2 key = make_uint2((unsigned)a.seed, (unsigned)(a.seed >> 32));
+        const uint2 key = make_uint2((unsigned)ri.seed, (unsigned)(ri.seed >> 32));
         double zx, zy, nr, unused;
-        box_muller(philox10(make_uint4((unsigned)i, slo, shi, 0u), key), zx, zy);
-        box_muller(philox10(make_uint4((unsigned)i, slo, shi, 1u), key), nr, unused);
+        box_muller(philox10(make_uint4(id, slo, shi, 0u), key), zx, zy);
+        box_muller(philox10(make_uint4(id, slo, shi, 1u), key), nr, unused);
         if (zx > a.clip) { zx = a.clip; ++clamps; }
         if (zx < -a.clip) { zx = -a.clip; ++clamps; }
         if (zy > a.clip) { zy = a.clip; ++clamps; }
@@ -243,27 +275,31 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
         xo[i] = x0;
         yo[i] = y0;
         tho[i] = t0;
-        x[i] = bd_wall(xn, r, a.L);
-        y[i] = bd_wall(yn, r, a.L);
+        x[i] = bd_wall(xn, r, ri.L);
+        y[i] = bd_wall(yn, r, ri.L);
         th[i] = t0 + a.amp_r * nr;
     }
     if (clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
 }
 
 template <typename T2>
-__global__ void k_reduce_forces(int n, int S, int nchunks, const T2 *__restrict__ part,
-                                const Chunk *__restrict__ chunks, const double *__restrict__ K,
-                                const int *__restrict__ pos_of, const int *__restrict__ sp,
-                                double *__restrict__ out) {
+__global__ void k_reduce_forces(int n, int S, const T2 *__restrict__ part, const RepInfo *__restrict__ reps,
+                                const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
+                                const double *__restrict__ K, const int *__restrict__ pos_of,
+                                const int *__restrict__ sp, double *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double fx, fy;
-    gather_force<T2>(part, n, nchunks, chunks, K, S, sp[i], pos_of[i], fx, fy);
+    gather_force<T2>(part, reps[rep_of[i]], chunk_spec, K, S, sp[i], pos_of[i], fx, fy);
     out[2 * i] = fx;
     out[2 * i + 1] = fy;
 }
 
 inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
+
+__global__ void k_zero_one(int *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
 
 }  // namespace
 
@@ -277,58 +313,103 @@ void launch_cast(Sim &s) {
                            (double2 *)s.pj);
 }
 
+namespace {
+
+template <typename T, typename T2, int P, bool FAST>
+void launch_force_t(Sim &s, const LawArgs &law) {
+    if (s.persistent) {
+        hipLaunchKernelGGL((k_force_queue<T, T2, P, FAST>), dim3(s.force_grid), dim3(kForceBlock), 0, s.stream,
+                           (const T2 *)s.pj, s.tiles, s.ntiles, (T2 *)s.part, law, s.ctl + K_FQUEUE);
+    } else {
+        hipLaunchKernelGGL((k_force<T, T2, P, FAST>), dim3(s.ntiles), dim3(kForceBlock), 0, s.stream,
+                           (const T2 *)s.pj, s.tiles, (T2 *)s.part, law);
+    }
+}
+
+template <typename T, typename T2, int P>
+void launch_force_p(Sim &s, const LawArgs &law) {
+    if (s.kind_fast)
+        launch_force_t<T, T2, P, true>(s, law);
+    else
+        launch_force_t<T, T2, P, false>(s, law);
+}
+
+template <typename T, typename T2, int P, bool FAST>
+int max_grid_t() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force_queue<T, T2, P, FAST>, kForceBlock, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+template <typename T, typename T2, int P>
+int max_grid_p(bool fast) {
+    return fast ? max_grid_t<T, T2, P, true>() : max_grid_t<T, T2, P, false>();
+}
+
+}  // namespace
+
+// Tiles of 256 * per_lane particles; per_lane is 2 or 4.
 void launch_force(Sim &s) {
     LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
-    dim3 grid(blocks_for(s.n, kForceBlock * kPerLane), s.nchunks);
+    if (s.persistent) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);
     if (s.fp32) {
-        if (s.kind_fast)
-            hipLaunchKernelGGL((k_force<float, float2, kPerLane, true>), grid, dim3(kForceBlock), 0, s.stream,
-                               (const float2 *)s.pj, s.n, s.chunks, (float2 *)s.part, law);
+        if (s.per_lane == 2)
+            launch_force_p<float, float2, 2>(s, law);
         else
-            hipLaunchKernelGGL((k_force<float, float2, kPerLane, false>), grid, dim3(kForceBlock), 0, s.stream,
-                               (const float2 *)s.pj, s.n, s.chunks, (float2 *)s.part, law);
+            launch_force_p<float, float2, 4>(s, law);
     } else {
-        if (s.kind_fast)
-            hipLaunchKernelGGL((k_force<double, double2, kPerLane, true>), grid, dim3(kForceBlock), 0, s.stream,
-                               (const double2 *)s.pj, s.n, s.chunks, (double2 *)s.part, law);
+        if (s.per_lane == 2)
+            launch_force_p<double, double2, 2>(s, law);
         else
-            hipLaunchKernelGGL((k_force<double, double2, kPerLane, false>), grid, dim3(kForceBlock), 0, s.stream,
-                               (const double2 *)s.pj, s.n, s.chunks, (double2 *)s.part, law);
+            launch_force_p<double, double2, 4>(s, law);
     }
+}
+
+int force_max_grid(Sim &s, int per_lane) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s.device) != hipSuccess || cus < 1)
+        cus = 256;
+    const bool fast = s.kind_fast != 0;
+    int per_cu;
+    if (s.fp32)
+        per_cu = per_lane == 2 ? max_grid_p<float, float2, 2>(fast) : max_grid_p<float, float2, 4>(fast);
+    else
+        per_cu = per_lane == 2 ? max_grid_p<double, double2, 2>(fast) : max_grid_p<double, double2, 4>(fast);
+    return cus * per_cu;
 }
 
 void launch_em(Sim &s) {
     EmArgs a;
     a.n = s.n;
     a.S = s.S;
-    a.nchunks = s.nchunks;
     a.dt = s.p.dt;
     a.amp = std::sqrt(2.0 * s.p.D * s.p.dt);
     a.amp_r = std::sqrt(2.0 * s.p.Dr * s.p.dt);
     a.v0 = s.p.v0;
-    a.L = s.p.L;
     a.clip = s.p.noise_clip;
-    a.seed = s.p.seed;
     a.step = s.step;
     const int nb = blocks_for(s.n, 256);
     if (s.fp32)
-        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.chunks,
-                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc,
-                           s.use_nl ? s.fsr : nullptr);
+        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.reps,
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
+                           s.acc, s.use_nl ? s.fsr : nullptr);
     else
-        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.chunks,
-                           s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc,
-                           s.use_nl ? s.fsr : nullptr);
+        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.reps,
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
+                           s.acc, s.use_nl ? s.fsr : nullptr);
 }
 
 void launch_reduce_forces(Sim &s) {
     const int nb = blocks_for(s.n, 256);
     if (s.fp32)
-        hipLaunchKernelGGL(k_reduce_forces<float2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S, s.nchunks,
-                           (const float2 *)s.part, s.chunks, s.Kd, s.pos_of, s.sp, s.fout);
+        hipLaunchKernelGGL(k_reduce_forces<float2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S,
+                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.fout);
     else
-        hipLaunchKernelGGL(k_reduce_forces<double2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S, s.nchunks,
-                           (const double2 *)s.part, s.chunks, s.Kd, s.pos_of, s.sp, s.fout);
+        hipLaunchKernelGGL(k_reduce_forces<double2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.S,
+                           (const double2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.fout);
 }
 
 }  // namespace bd

@@ -2,9 +2,11 @@
 // and 4.3) and overlap correction over Delaunay edges (Sec. 2.3, 4.4,
 // Algorithm 2).
 //
-// Triangulation layout (SoA, ghosts included).  Vertices are the n disks
-// (ids 0..n-1), the fixed frame points outside the walls (n..nv-1) and the
-// infinite vertex (nv); T = 2 nv - 2 triangles.
+// Triangulation layout (SoA, ghosts included).  A handle holds R independent
+// systems (R = 1 for one system).  Vertex ids: the disks of all systems
+// (0..n-1, system by system), their fixed frame points outside the walls
+// (n..nv-1), then one infinite vertex per system (nv..nv+R-1); system r has
+// 2 nv_r - 2 triangles and no edge between two systems.
 //   he_v[h]     origin vertex of half-edge h; triangle t owns h = 3t..3t+2 CCW
 //   he_twin[h]  opposite half-edge
 //   vert_he[v]  one outgoing half-edge of vertex v
@@ -43,7 +45,9 @@ constexpr int kMaxGrid = 512;      // full scans over triangles
 constexpr int kListGrid = 128;     // worklist-driven launches (usually a few hundred items, often none)
 
 struct Topo {
-    int n, inf, T;
+    int n, inf, nvert, T;   // disks, first infinite-vertex id, all vertex ids, triangles
+    const int *rep_of;      // replica of each disk
+    const double *Lr;       // box side of each replica
     const double *x, *y, *xo, *yo, *rad;
     int *he_v, *he_twin, *vert_he;
     unsigned long long *claim;
@@ -61,6 +65,9 @@ Topo topo_of(Sim &s) {
     Topo t;
     t.n = s.n;
     t.inf = s.inf;
+    t.nvert = s.inf + s.R;
+    t.rep_of = s.rep_of;
+    t.Lr = s.Lr;
     t.T = s.T;
     t.x = s.x;
     t.y = s.y;
@@ -93,7 +100,7 @@ __device__ __forceinline__ int *wl_of(const Topo &t, int slot) { return (slot & 
 // Range guards: a corrupt triangulation must never turn into an out-of-bounds
 // access; it is reported through K_TOPO and repaired on the host.
 __device__ __forceinline__ bool bad_he(const Topo &t, int h) { return (unsigned)h >= (unsigned)(3 * t.T); }
-__device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v > (unsigned)t.inf; }
+__device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v >= (unsigned)t.nvert; }
 __device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctl[K_TOPO], 1); }
 
 __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
@@ -151,7 +158,7 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
     const int rule = bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, &inverted);
     if (inverted) atomicAdd(&t.ctl[K_INVQ + slot], 1);
     if (rule == BD_NOFLIP) return;
-    if (c != t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
+    if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
         // blocked for now (c-d may disappear in this very round): look again next round
         push_edge(t, h, round + 1, slot + 1 == MAXR ? 0 : slot + 1);
         return;
@@ -306,7 +313,7 @@ __global__ void k_validate(Topo t, int rep) {
             topo_err(t);
             continue;
         }
-        if (a == t.inf || b == t.inf || c == t.inf) continue;
+        if (a >= t.inf || b >= t.inf || c >= t.inf) continue;
         if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctl[K_INV + rep], 1);
     }
 }
@@ -396,13 +403,14 @@ __global__ void k_final_check(int *ctl, int k) {
 // (Sec. 2.3 displacement along the unit vector, factor f), starting at the
 // neighbour of smallest id so the summation order is independent of flip
 // history; truncate the sum to cap_frac * r (Sec. 4.4); reflect at the walls.
-__global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double L, double keep) {
+__global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double keep) {
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
     const int ntouched = t.ctl[K_TOUCH + k];
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
         const int v = t.touched[idx];
         const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
+        const double L = t.Lr[t.rep_of[v]];
         t.newpos[idx] = make_double2(xv, yv);
         const int h0 = t.vert_he[v];
         if (bad_he(t, h0)) {
@@ -419,7 +427,7 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double L,
                 broken = true;
                 break;
             }
-            if (w != t.inf && w < bestid) {
+            if (w < t.inf && w < bestid) {
                 bestid = w;
                 best = h;
             }
@@ -590,7 +598,7 @@ void launch_final_check(Sim &s, int k) {
 void launch_ovl_gather(Sim &s, int k) {
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_gather, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
-                       s.p.cap_frac, s.p.L, 1.0 - s.p.contact_tol);
+                       s.p.cap_frac, 1.0 - s.p.contact_tol);
 }
 
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
@@ -601,7 +609,7 @@ void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
 void launch_snapshot(Sim &s) {
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_snapshot, dim3(grid_for(s.H)), dim3(256), 0, s.stream, t, s.snap_v, s.snap_twin, s.snap_vh,
-                       s.nv + 1);
+                       s.nv + s.R);
 }
 
 void launch_scatter_oldpos(Sim &s, int k) {

@@ -145,7 +145,7 @@ size_t verlet_scan_bytes(int ncells) {
 // Rebuilds the lists from the current positions.  The caller zeroed
 // cell_count, cell_fill and the overflow flag.
 void launch_verlet_build(Sim &s) {
-    const double inv_cell = (double)s.nl_nc / s.p.L;
+    const double inv_cell = (double)s.nl_nc / s.L_h[0];
     hipLaunchKernelGGL(k_cell_count, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell, s.nl_nc,
                        s.cell_of, s.cell_count);
     size_t bytes = s.scan_bytes;

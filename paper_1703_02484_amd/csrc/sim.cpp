@@ -12,12 +12,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "bd_internal.h"
@@ -62,12 +66,57 @@ void read_ctl(Sim &s) {
 void zero_ctl(Sim &s, int idx) { fill_int(s, s.ctl + idx, 1, 0); }
 
 void upload_topology(Sim &s, const std::vector<int> &he_v, const std::vector<int> &he_twin) {
-    std::vector<int> vh(s.nv + 1, -1);
+    std::vector<int> vh(s.nv + s.R, -1);
     for (int h = 0; h < s.H; ++h) vh[he_v[h]] = h;
     check(hipMemcpyAsync(s.he_v, he_v.data(), sizeof(int) * s.H, hipMemcpyHostToDevice, s.stream), "he_v");
     check(hipMemcpyAsync(s.he_twin, he_twin.data(), sizeof(int) * s.H, hipMemcpyHostToDevice, s.stream), "twin");
-    check(hipMemcpyAsync(s.vert_he, vh.data(), sizeof(int) * (s.nv + 1), hipMemcpyHostToDevice, s.stream), "vh");
+    check(hipMemcpyAsync(s.vert_he, vh.data(), sizeof(int) * (s.nv + s.R), hipMemcpyHostToDevice, s.stream), "vh");
     check(hipStreamSynchronize(s.stream), "topology upload");
+}
+
+// Delaunay triangulation of every system from host positions (global vertex
+// ids: disks, then frame points, then the infinite vertices).  System r owns
+// triangles [toff_r, toff_{r+1}); systems are independent, so they are
+// triangulated in parallel.  Returns 0, or -1 if one of them failed.
+int host_dt_all(Sim &s, const double *hx, const double *hy, std::vector<int> &hv, std::vector<int> &ht) {
+    hv.assign(s.H, -1);
+    ht.assign(s.H, -1);
+    std::atomic<int> next{0}, failed{0};
+    auto work = [&] {
+        std::vector<double> lx, ly;
+        std::vector<int> lv, lt;
+        for (int r = next++; r < s.R; r = next++) {
+            const int d0 = s.off_h[r], nr = s.off_h[r + 1] - d0;
+            const int f0 = s.n + s.foff_h[r], mr = s.foff_h[r + 1] - s.foff_h[r];
+            const int vr = nr + mr;
+            lx.resize(vr);
+            ly.resize(vr);
+            for (int i = 0; i < nr; ++i) {
+                lx[i] = hx[d0 + i];
+                ly[i] = hy[d0 + i];
+            }
+            for (int k = 0; k < mr; ++k) {
+                lx[nr + k] = hx[f0 + k];
+                ly[nr + k] = hy[f0 + k];
+            }
+            const int hb = 3 * s.toff_h[r], hr = 3 * (s.toff_h[r + 1] - s.toff_h[r]);
+            if (host_delaunay(vr, lx.data(), ly.data(), lv, lt) != 0 || (int)lv.size() != hr) {
+                failed = 1;
+                continue;
+            }
+            for (int h = 0; h < hr; ++h) {
+                const int v = lv[h];
+                hv[hb + h] = v < nr ? d0 + v : (v < vr ? f0 + (v - nr) : s.inf + r);
+                ht[hb + h] = hb + lt[h];
+            }
+        }
+    };
+    const int nth = std::max(1, std::min({s.R, 16, (int)std::thread::hardware_concurrency()}));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    return failed ? -1 : 0;
 }
 
 // Host rebuild of DT(current positions).  Returns BD_OK or BD_ERR_TRIANGULATION.
@@ -77,7 +126,7 @@ int host_rebuild(Sim &s) {
     check(hipMemcpyAsync(hy.data(), s.y, sizeof(double) * s.nv, hipMemcpyDeviceToHost, s.stream), "y");
     check(hipStreamSynchronize(s.stream), "rebuild download");
     std::vector<int> hv, ht;
-    if (host_delaunay(s.nv, hx.data(), hy.data(), hv, ht) != 0) {
+    if (host_dt_all(s, hx.data(), hy.data(), hv, ht) != 0) {
         s.last_error = "host Delaunay rebuild failed (coincident positions)";
         return BD_ERR_TRIANGULATION;
     }
@@ -202,7 +251,7 @@ int kinetic_replay(Sim &s, Cursor &c, MoveFrom from, int oround) {
         check(hipMemcpyAsync(s.he_v, s.snap_v, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream), "restore");
         check(hipMemcpyAsync(s.he_twin, s.snap_twin, sizeof(int) * s.H, hipMemcpyDeviceToDevice, s.stream),
               "restore");
-        check(hipMemcpyAsync(s.vert_he, s.snap_vh, sizeof(int) * (s.nv + 1), hipMemcpyDeviceToDevice, s.stream),
+        check(hipMemcpyAsync(s.vert_he, s.snap_vh, sizeof(int) * (s.nv + s.R), hipMemcpyDeviceToDevice, s.stream),
               "restore");
         bool ok = true;
         for (int i = 1; i <= k && ok; ++i) {
@@ -439,31 +488,276 @@ int one_step(Sim &s) {
     return BD_OK;
 }
 
-void setup_chunks(Sim &s, const std::vector<int> &block_start) {
-    const int per_block = 256 * 4;
-    const int nib = (s.n + per_block - 1) / per_block;
-    const int target_blocks = 2048;
-    int want = std::max(1, (target_blocks + nib - 1) / nib);
-    s.chunks_h.clear();
-    for (int b = 0; b < s.S; ++b) {
-        const int js = block_start[b], je = block_start[b + 1], cnt = je - js;
-        if (cnt <= 0) continue;
-        int nc = (int)std::llround((double)want * cnt / s.n);
-        nc = std::max(1, std::min(nc, std::max(1, cnt / 64)));
-        int len = (cnt + nc - 1) / nc;
-        len = (len + 7) / 8 * 8;
-        for (int j = js; j < je; j += len) s.chunks_h.push_back(Chunk{j, std::min(je, j + len), b, 0});
+// ------------------------------------------------------------------ force tiling
+// Chunks of one species range [js, je): nc = round(cnt / chunk) equal parts,
+// lengths rounded up to a multiple of 8.  Depends only on the range and the
+// chunk length, so a system is cut the same way alone or in a batch.
+void cut_species(int js, int je, int chunk, std::vector<int2> &out) {
+    const int cnt = je - js;
+    if (cnt <= 0) return;
+    int nc = std::max(1, (int)std::llround((double)cnt / chunk));
+    int len = (cnt + nc - 1) / nc;
+    len = (len + 7) / 8 * 8;
+    for (int j = js; j < je; j += len) out.push_back(make_int2(j, std::min(je, j + len)));
+}
+
+struct Tiling {
+    std::vector<Tile> tiles;
+    std::vector<int> chunk_spec;
+    std::vector<RepInfo> reps;
+    long long part_len = 0;
+};
+
+Tiling make_tiling(const Sim &s, int chunk, int per_lane) {
+    Tiling t;
+    t.reps.resize(s.R);
+    const int ib_len = 256 * per_lane;
+    std::vector<int2> ch;
+    for (int r = 0; r < s.R; ++r) {
+        RepInfo &ri = t.reps[r];
+        ri.off = s.off_h[r];
+        ri.n = s.off_h[r + 1] - s.off_h[r];
+        ri.cfirst = (int)t.chunk_spec.size();
+        ri.poff = t.part_len;
+        ri.L = s.L_h[r];
+        ri.seed = s.seed_h[r];
+        int nch = 0;
+        for (int b = 0; b < s.S; ++b) {
+            ch.clear();
+            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], chunk, ch);
+            for (const int2 &c : ch) {
+                t.chunk_spec.push_back(b);
+                for (int i0 = ri.off; i0 < ri.off + ri.n; i0 += ib_len) {
+                    Tile tl;
+                    tl.i0 = i0;
+                    tl.i1 = std::min(ri.off + ri.n, i0 + ib_len);
+                    tl.js = c.x;
+                    tl.je = c.y;
+                    tl.pbase = ri.poff + (long long)nch * ri.n - ri.off;
+                    tl.work = (long long)(tl.i1 - tl.i0) * (tl.je - tl.js);
+                    t.tiles.push_back(tl);
+                }
+                ++nch;
+            }
+        }
+        ri.nch = nch;
+        t.part_len += (long long)nch * ri.n;
     }
-    s.nchunks = (int)s.chunks_h.size();
+    std::stable_sort(t.tiles.begin(), t.tiles.end(), [](const Tile &a, const Tile &b) { return a.work > b.work; });
+    return t;
+}
+
+void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persistent) {
+    check(hipMemcpyAsync(s.tiles, t.tiles.data(), sizeof(Tile) * t.tiles.size(), hipMemcpyHostToDevice, s.stream),
+          "tiles");
+    check(hipMemcpyAsync(s.chunk_spec, t.chunk_spec.data(), sizeof(int) * t.chunk_spec.size(), hipMemcpyHostToDevice,
+                         s.stream),
+          "chunk_spec");
+    check(hipMemcpyAsync(s.reps, t.reps.data(), sizeof(RepInfo) * s.R, hipMemcpyHostToDevice, s.stream), "reps");
+    check(hipStreamSynchronize(s.stream), "tiling upload");
+    s.ntiles = (int)t.tiles.size();
+    s.chunk_len = chunk;
+    s.per_lane = per_lane;
+    s.persistent = persistent;
+    s.force_grid = persistent ? std::min(s.ntiles, force_max_grid(s, per_lane)) : s.ntiles;
+}
+
+// Fixed rule: the smallest power-of-two chunk (>= 64) that keeps the launch
+// at or below 2048 tiles.
+int default_chunk(const Sim &s) {
+    for (int c = 64;; c *= 2) {
+        if (c >= 65536) return 65536;
+        if ((long long)make_tiling(s, c, 4).tiles.size() <= 2048) return c;
+    }
+}
+
+// ------------------------------------------------------------------ autotuner
+// Candidate tilings (chunk length x i per lane x launch form) are timed on
+// the handle's own positions; the fastest is kept.  Choices are cached per
+// workload shape for the process, and in the JSON file named by the
+// environment variable BD_TUNE_CACHE when it is set, so that handles of the
+// same shape cut their sums the same way.
+struct TuneChoice {
+    int chunk, per_lane, persistent;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_file_read = false;
+
+std::string tune_key(const Sim &s) {
+    unsigned long long h = 1469598103934665603ull;   // FNV-1a over the system shapes
+    auto mix = [&](unsigned long long v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int r = 0; r < s.R; ++r)
+        for (int b = 0; b <= s.S; ++b) mix((unsigned long long)(s.bstart_h[r * (s.S + 1) + b] - s.off_h[r]));
+    hipDeviceProp_t prop;
+    std::string arch = hipGetDeviceProperties(&prop, s.device) == hipSuccess ? prop.gcnArchName : "unknown";
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|%s|%s|S%d|R%d|n%d|%016llx", arch.c_str(), s.fp32 ? "fp32" : "fp64",
+                  s.kind_fast ? "q2" : "general", s.S, s.R, s.n, h);
+    return buf;
+}
+
+void read_tune_file() {
+    g_tune_file_read = true;
+    const char *path = std::getenv("BD_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[300];
+        TuneChoice c;
+        if (std::sscanf(line, " \"%299[^\"]\": [%d, %d, %d, %lf]", key, &c.chunk, &c.per_lane, &c.persistent, &c.ms) ==
+            5)
+            g_tune[key] = c;
+    }
+    std::fclose(f);
+}
+
+void write_tune_file() {
+    const char *path = std::getenv("BD_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto &e : g_tune)
+        std::fprintf(f, "  \"%s\": [%d, %d, %d, %.6f]%s\n", e.first.c_str(), e.second.chunk, e.second.per_lane,
+                     e.second.persistent, e.second.ms, ++k < g_tune.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+double time_force(Sim &s, int reps) {
+    hipEvent_t a, b;
+    check(hipEventCreate(&a), "event");
+    check(hipEventCreate(&b), "event");
+    launch_force(s);   // warm-up
+    float best = 1e30f;
+    for (int k = 0; k < reps; ++k) {
+        check(hipEventRecord(a, s.stream), "event");
+        launch_force(s);
+        check(hipEventRecord(b, s.stream), "event");
+        check(hipEventSynchronize(b), "event sync");
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, a, b), "elapsed");
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return best;
+}
+
+// Allocates tiles / part for the largest of the given tilings.
+void alloc_force_buffers(Sim &s, long long max_tiles, long long max_part) {
+    const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
+    if (s.tiles) check(hipFree(s.tiles), "free tiles");
+    if (s.part) check(hipFree(s.part), "free part");
+    s.tiles = nullptr;
+    s.part = nullptr;
+    s.tiles = dalloc<Tile>((size_t)max_tiles);
+    s.part = dalloc<char>(vec * (size_t)max_part);
+    s.part_cap = max_part;
+}
+
+void setup_force(Sim &s) {
+    const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
+    s.reps = dalloc<RepInfo>(s.R);
+    long long max_chunks = 0;
+    for (int r = 0; r < s.R; ++r) max_chunks += (s.off_h[r + 1] - s.off_h[r]) / 8 + s.S;
+    s.chunk_spec = dalloc<int>((size_t)max_chunks);
+    if (s.use_nl) {   // short-range path: the all-pairs buffers stay minimal
+        Tiling t = make_tiling(s, 65536, 4);
+        alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+        upload_tiling(s, t, 65536, 4, 0);
+        return;
+    }
+    if (s.p.force_chunk > 0) {
+        Tiling t = make_tiling(s, s.p.force_chunk, 4);
+        alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+        upload_tiling(s, t, s.p.force_chunk, 4, 0);
+        return;
+    }
+    long double pairs = 0;
+    for (int r = 0; r < s.R; ++r) pairs += (long double)(s.off_h[r + 1] - s.off_h[r]) * (s.off_h[r + 1] - s.off_h[r]);
+    const int dchunk = default_chunk(s);
+    if (pairs < (long double)(1 << 26)) {
+        Tiling t = make_tiling(s, dchunk, 4);
+        alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+        upload_tiling(s, t, dchunk, 4, 0);
+        return;
+    }
+    const std::string key = tune_key(s);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_file_read) read_tune_file();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            const TuneChoice c = it->second;
+            Tiling t = make_tiling(s, c.chunk, c.per_lane);
+            alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+            upload_tiling(s, t, c.chunk, c.per_lane, c.persistent);
+            s.tuned = 2;
+            s.tuned_ms = c.ms;
+            return;
+        }
+    }
+    // candidates: chunk lengths around the fixed rule, both tile heights, both launch forms
+    std::vector<int> chunks;
+    for (int c = std::max(256, dchunk / 8); c <= std::min(65536, dchunk * 4); c *= 2) chunks.push_back(c);
+    const long long part_limit = (2ll << 30) / (long long)vec;
+    long long max_tiles = 0, max_part = 0;
+    std::vector<std::pair<int, int>> cands;   // (chunk, per_lane)
+    for (int c : chunks)
+        for (int pl : {2, 4}) {
+            Tiling t = make_tiling(s, c, pl);
+            if (t.part_len > part_limit) continue;
+            cands.emplace_back(c, pl);
+            max_tiles = std::max(max_tiles, (long long)t.tiles.size());
+            max_part = std::max(max_part, t.part_len);
+        }
+    if (cands.empty()) {
+        Tiling t = make_tiling(s, dchunk, 4);
+        alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+        upload_tiling(s, t, dchunk, 4, 0);
+        return;
+    }
+    alloc_force_buffers(s, max_tiles, max_part);
+    launch_cast(s);
+    TuneChoice best{0, 0, 0, 1e30};
+    for (const auto &cp : cands) {
+        Tiling t = make_tiling(s, cp.first, cp.second);
+        for (int pers = 0; pers <= 1; ++pers) {
+            upload_tiling(s, t, cp.first, cp.second, pers);
+            const double ms = time_force(s, 3);
+            if (ms < best.ms) best = TuneChoice{cp.first, cp.second, pers, ms};
+        }
+    }
+    Tiling t = make_tiling(s, best.chunk, best.per_lane);
+    alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+    upload_tiling(s, t, best.chunk, best.per_lane, best.persistent);
+    s.tuned = 1;
+    s.tuned_ms = best.ms;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    write_tune_file();
 }
 
 void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sorted_id, s.pos_of, s.pj, s.part,
-                    s.chunks, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he, s.claim, s.tri_stamp, s.moved,
-                    s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won, s.touched, s.newpos, s.oldpos,
-                    s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl, s.acc, s.nl, s.nl_cnt,
-                    s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items, s.xbuild, s.ybuild, s.fsr,
-                    s.scan_tmp};
+                    s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
+                    s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
+                    s.touched, s.newpos, s.oldpos, s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
+                    s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
+                    s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s.hctl) (void)hipHostFree(s.hctl);
@@ -478,10 +772,9 @@ void free_all(Sim &s) {
 
 bool finite(double v) { return std::isfinite(v); }
 
-int validate_args(int n, const double *xy, const double *radii, const int32_t *species, const double *theta,
-                  const bd_force_params *fp, const bd_params *p, std::string &err) {
-    if (!xy || !radii || !species || !fp || !p) return err = "NULL argument", BD_ERR_INVALID_ARG;
-    if (n < 3) return err = "n must be at least 3", BD_ERR_INVALID_ARG;
+// Parameters shared by all systems of a handle (L is checked per system).
+int validate_params(const bd_force_params *fp, const bd_params *p, std::string &err) {
+    if (!fp || !p) return err = "NULL argument", BD_ERR_INVALID_ARG;
     if (fp->S < 1 || fp->S > BD_MAX_SPECIES || !fp->K) return err = "S out of range or K NULL", BD_ERR_INVALID_ARG;
     if (fp->kind != BD_FORCE_POWER && fp->kind != BD_FORCE_SCREENED) return err = "unknown force kind", BD_ERR_INVALID_ARG;
     for (int k = 0; k < fp->S * fp->S; ++k)
@@ -490,29 +783,37 @@ int validate_args(int n, const double *xy, const double *radii, const int32_t *s
         return err = "non-finite force parameter", BD_ERR_INVALID_ARG;
     if (fp->kind == BD_FORCE_SCREENED && !(fp->lambda > 0)) return err = "lambda must be > 0", BD_ERR_INVALID_ARG;
     if (fp->cutoff > 0 && !(fp->skin >= 0)) return err = "skin must be >= 0", BD_ERR_INVALID_ARG;
-    const double vals[] = {p->L, p->D, p->dt, p->v0, p->Dr, p->overlap_factor, p->cap_frac, p->noise_clip,
-                           p->contact_tol};
+    const double vals[] = {p->D, p->dt, p->v0, p->Dr, p->overlap_factor, p->cap_frac, p->noise_clip, p->contact_tol};
     for (double v : vals)
         if (!finite(v)) return err = "non-finite step parameter", BD_ERR_INVALID_ARG;
-    if (!(p->L > 0) || p->D < 0 || !(p->dt > 0) || p->Dr < 0 || !(p->overlap_factor > 0) || !(p->cap_frac > 0) ||
+    if (p->D < 0 || !(p->dt > 0) || p->Dr < 0 || !(p->overlap_factor > 0) || !(p->cap_frac > 0) ||
         !(p->noise_clip > 0) || p->contact_tol < 0 || p->contact_tol > 1e-3)
         return err = "step parameter out of range", BD_ERR_INVALID_ARG;
     if (p->force_precision != BD_PREC_FP32 && p->force_precision != BD_PREC_FP64)
         return err = "unknown force precision", BD_ERR_INVALID_ARG;
-    if (p->reserved != 0) return err = "reserved field must be 0", BD_ERR_INVALID_ARG;
+    if (p->force_chunk != 0 && (p->force_chunk < 64 || p->force_chunk > 65536))
+        return err = "force_chunk must be 0 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    return BD_OK;
+}
+
+// One system: radii, species, positions inside [r, L - r], no overlap.
+int validate_system(int n, const double *xy, const double *radii, const int32_t *species, const double *theta,
+                    double L, int S, std::string &err) {
+    if (n < 3) return err = "n must be at least 3", BD_ERR_INVALID_ARG;
+    if (!finite(L) || !(L > 0)) return err = "box side must be finite and > 0", BD_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) {
         double r = radii[i], x = xy[2 * i], y = xy[2 * i + 1];
         if (!finite(r) || !(r > 0) || !finite(x) || !finite(y)) return err = "bad radius or position", BD_ERR_INVALID_ARG;
-        if (species[i] < 0 || species[i] >= fp->S) return err = "species out of range", BD_ERR_INVALID_ARG;
+        if (species[i] < 0 || species[i] >= S) return err = "species out of range", BD_ERR_INVALID_ARG;
         if (theta && !finite(theta[i])) return err = "non-finite theta", BD_ERR_INVALID_ARG;
-        if (x < r || x > p->L - r || y < r || y > p->L - r) return err = "disk outside the walls", BD_ERR_BAD_INPUT;
+        if (x < r || x > L - r || y < r || y > L - r) return err = "disk outside the walls", BD_ERR_BAD_INPUT;
     }
     // overlap check on a cell grid (cell side >= the largest contact distance)
     double rmax = 0;
     for (int i = 0; i < n; ++i) rmax = std::max(rmax, radii[i]);
     const double cell = 2 * rmax;
-    long nc = std::max(1L, std::min(32768L, (long)std::floor(p->L / cell)));
-    const double inv = nc / p->L;
+    long nc = std::max(1L, std::min(32768L, (long)std::floor(L / cell)));
+    const double inv = nc / L;
     std::vector<int> head((size_t)nc * nc, -1), nxt(n, -1);
     auto cidx = [&](double v) { long c = (long)(v * inv); return c < 0 ? 0 : (c >= nc ? nc - 1 : c); };
     for (int i = 0; i < n; ++i) {
@@ -530,17 +831,58 @@ int validate_args(int n, const double *xy, const double *radii, const int32_t *s
     return BD_OK;
 }
 
-int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_t *species, const double *theta,
-              const bd_force_params *fp, const bd_params *p) {
-    double rmax = 0.0;
-    for (int i = 0; i < n; ++i) rmax = std::max(rmax, radii[i]);
-    std::vector<double> fx, fy;
-    frame_points(p->L, rmax, fx, fy);
+int validate_batch(int R, const int32_t *n_per, const double *xy, const double *radii, const int32_t *species,
+                   const double *theta, const double *L_per, const bd_force_params *fp, const bd_params *p,
+                   std::string &err) {
+    if (R < 1 || !n_per || !xy || !radii || !species || !L_per) return err = "NULL argument or R < 1", BD_ERR_INVALID_ARG;
+    int rc = validate_params(fp, p, err);
+    if (rc != BD_OK) return rc;
+    if (R > 1 && fp->cutoff > 0) return err = "short-range forces need one system per handle", BD_ERR_INVALID_ARG;
+    long long total = 0;
+    for (int r = 0; r < R; ++r) {
+        if (n_per[r] < 3) return err = "every system needs at least 3 disks", BD_ERR_INVALID_ARG;
+        total += n_per[r];
+    }
+    if (total > (1ll << 28)) return err = "too many disks in one handle", BD_ERR_INVALID_ARG;
+    long long off = 0;
+    for (int r = 0; r < R; ++r) {
+        rc = validate_system(n_per[r], xy + 2 * off, radii + off, species + off, theta ? theta + off : nullptr,
+                             L_per[r], fp->S, err);
+        if (rc != BD_OK) {
+            if (R > 1) err = "system " + std::to_string(r) + ": " + err;
+            return rc;
+        }
+        off += n_per[r];
+    }
+    return BD_OK;
+}
+
+int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const double *radii, const int32_t *species,
+              const double *theta, const double *L_per, const uint64_t *seed_per, const bd_force_params *fp,
+              const bd_params *p) {
+    s.R = R;
+    s.off_h.assign(R + 1, 0);
+    for (int r = 0; r < R; ++r) s.off_h[r + 1] = s.off_h[r] + n_per[r];
+    const int n = s.off_h[R];
+    s.L_h.assign(L_per, L_per + R);
+    s.seed_h.assign(seed_per, seed_per + R);
+    // frame points of every system
+    std::vector<std::vector<double>> fxs(R), fys(R);
+    s.foff_h.assign(R + 1, 0);
+    for (int r = 0; r < R; ++r) {
+        double rmax = 0.0;
+        for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) rmax = std::max(rmax, radii[i]);
+        frame_points(L_per[r], rmax, fxs[r], fys[r]);
+        s.foff_h[r + 1] = s.foff_h[r] + (int)fxs[r].size();
+    }
     s.n = n;
-    s.m = (int)fx.size();
+    s.m = s.foff_h[R];
     s.nv = n + s.m;
     s.S = fp->S;
-    s.T = 2 * s.nv - 2;
+    s.toff_h.assign(R + 1, 0);
+    for (int r = 0; r < R; ++r)
+        s.toff_h[r + 1] = s.toff_h[r] + 2 * (s.off_h[r + 1] - s.off_h[r] + s.foff_h[r + 1] - s.foff_h[r]) - 2;
+    s.T = s.toff_h[R];
     s.H = 3 * s.T;
     s.inf = s.nv;
     s.p = *p;
@@ -555,52 +897,59 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     check(hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking), "stream");
     s.stream = s.own_stream;
 
-    // finite vertices: the disks, then the frame, then one padding entry for the infinite vertex
-    const int nv = s.nv;
-    std::vector<double> hx(nv + 1, 0.0), hy(nv + 1, 0.0), hth(n, 0.0), hrad(nv + 1, 0.0);
+    // finite vertices: the disks, then the frames, then one padding entry per infinite vertex
+    const int nv = s.nv, nva = nv + R;
+    std::vector<double> hx(nva, 0.0), hy(nva, 0.0), hth(n, 0.0), hrad(nva, 0.0);
+    std::vector<int> hrep(n);
     for (int i = 0; i < n; ++i) {
         hx[i] = xy[2 * i];
         hy[i] = xy[2 * i + 1];
         hrad[i] = radii[i];
         if (theta) hth[i] = theta[i];
     }
-    for (int k = 0; k < s.m; ++k) {
-        hx[n + k] = fx[k];
-        hy[n + k] = fy[k];
+    for (int r = 0; r < R; ++r) {
+        for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) hrep[i] = r;
+        for (int k = 0; k < (int)fxs[r].size(); ++k) {
+            hx[n + s.foff_h[r] + k] = fxs[r][k];
+            hy[n + s.foff_h[r] + k] = fys[r][k];
+        }
     }
-    // species-sorted permutation (stable: ids ascending inside a species)
-    std::vector<int> sorted(n), pos(n), block_start(s.S + 1, 0);
-    for (int i = 0; i < n; ++i) ++block_start[species[i] + 1];
-    for (int b = 0; b < s.S; ++b) block_start[b + 1] += block_start[b];
-    {
-        std::vector<int> fillp(block_start.begin(), block_start.end() - 1);
-        for (int i = 0; i < n; ++i) {
+    // species-sorted permutation inside each system (stable: ids ascending inside a species)
+    std::vector<int> sorted(n), pos(n);
+    s.bstart_h.assign((size_t)R * (s.S + 1), 0);
+    for (int r = 0; r < R; ++r) {
+        int *bs = &s.bstart_h[(size_t)r * (s.S + 1)];
+        std::vector<int> cnt(s.S + 1, 0);
+        for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) ++cnt[species[i] + 1];
+        bs[0] = s.off_h[r];
+        for (int b = 0; b < s.S; ++b) bs[b + 1] = bs[b] + cnt[b + 1];
+        std::vector<int> fillp(bs, bs + s.S);
+        for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) {
             int k = fillp[species[i]]++;
             sorted[k] = i;
             pos[i] = k;
         }
     }
-    setup_chunks(s, block_start);
 
-    s.x = dalloc<double>(nv + 1);
-    s.y = dalloc<double>(nv + 1);
-    s.xo = dalloc<double>(nv + 1);
-    s.yo = dalloc<double>(nv + 1);
+    s.x = dalloc<double>(nva);
+    s.y = dalloc<double>(nva);
+    s.xo = dalloc<double>(nva);
+    s.yo = dalloc<double>(nva);
     s.th = dalloc<double>(n);
     s.tho = dalloc<double>(n);
-    s.rad = dalloc<double>(nv + 1);
+    s.rad = dalloc<double>(nva);
     s.sp = dalloc<int>(n);
+    s.rep_of = dalloc<int>(n);
+    s.Lr = dalloc<double>(R);
     s.sorted_id = dalloc<int>(n);
     s.pos_of = dalloc<int>(n);
     const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
     s.pj = dalloc<char>(vec * n);
-    s.part = dalloc<char>(vec * n * (size_t)s.nchunks);
-    s.chunks = dalloc<Chunk>(s.nchunks);
     s.Kd = dalloc<double>(s.S * s.S);
     s.fout = dalloc<double>(2 * (size_t)n);
     s.he_v = dalloc<int>(s.H);
     s.he_twin = dalloc<int>(s.H);
-    s.vert_he = dalloc<int>(nv + 1);
+    s.vert_he = dalloc<int>(nva);
     s.claim = dalloc<unsigned long long>(s.T);
     s.tri_stamp = dalloc<int>(s.T);
     s.moved = dalloc<int>(s.H);
@@ -615,7 +964,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.oldpos = dalloc<double2>(n);
     s.snap_v = dalloc<int>(s.H);
     s.snap_twin = dalloc<int>(s.H);
-    s.snap_vh = dalloc<int>(nv + 1);
+    s.snap_vh = dalloc<int>(nva);
     s.xa = dalloc<double>(n);
     s.ya = dalloc<double>(n);
     s.xb = dalloc<double>(n);
@@ -623,7 +972,7 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     s.ctl = dalloc<int>(N_CTL);
     if (s.use_nl) {
         const double rl = fp->cutoff + fp->skin;
-        s.nl_nc = std::max(1, std::min(46000, (int)std::floor(p->L / rl)));
+        s.nl_nc = std::max(1, std::min(46000, (int)std::floor(L_per[0] / rl)));
         s.nl_ncell = s.nl_nc * s.nl_nc;
         s.cell_count = dalloc<int>(s.nl_ncell + 1);
         s.cell_start = dalloc<int>(s.nl_ncell + 1);
@@ -643,18 +992,18 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     if (hipHostMalloc((void **)&s.hacc, sizeof(unsigned long long) * N_ACC, hipHostMallocDefault) != hipSuccess)
         throw std::bad_alloc();
 
-    check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "x");
-    check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "y");
-    check(hipMemcpyAsync(s.xo, hx.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "xo");
-    check(hipMemcpyAsync(s.yo, hy.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "yo");
+    check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "x");
+    check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "y");
+    check(hipMemcpyAsync(s.xo, hx.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "xo");
+    check(hipMemcpyAsync(s.yo, hy.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "yo");
     check(hipMemcpyAsync(s.th, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "th");
     check(hipMemcpyAsync(s.tho, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "tho");
-    check(hipMemcpyAsync(s.rad, hrad.data(), sizeof(double) * (nv + 1), hipMemcpyHostToDevice, s.stream), "rad");
+    check(hipMemcpyAsync(s.rad, hrad.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "rad");
     check(hipMemcpyAsync(s.sp, species, sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sp");
+    check(hipMemcpyAsync(s.rep_of, hrep.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "rep_of");
+    check(hipMemcpyAsync(s.Lr, L_per, sizeof(double) * R, hipMemcpyHostToDevice, s.stream), "Lr");
     check(hipMemcpyAsync(s.sorted_id, sorted.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sorted");
     check(hipMemcpyAsync(s.pos_of, pos.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "pos");
-    check(hipMemcpyAsync(s.chunks, s.chunks_h.data(), sizeof(Chunk) * s.nchunks, hipMemcpyHostToDevice, s.stream),
-          "chunks");
     check(hipMemcpyAsync(s.Kd, s.K.data(), sizeof(double) * s.S * s.S, hipMemcpyHostToDevice, s.stream), "K");
     check(hipMemsetAsync(s.claim, 0, sizeof(unsigned long long) * s.T, s.stream), "claim");
     check(hipMemsetAsync(s.tri_stamp, 0, sizeof(int) * s.T, s.stream), "tri_stamp");
@@ -662,9 +1011,12 @@ int init_impl(Sim &s, int n, const double *xy, const double *radii, const int32_
     check(hipMemsetAsync(s.vstamp, 0, sizeof(int) * (n + 1), s.stream), "vstamp");
     check(hipMemsetAsync(s.acc, 0, sizeof(unsigned long long) * N_ACC, s.stream), "acc");
     check(hipMemsetAsync(s.ctl, 0, sizeof(int) * N_CTL, s.stream), "ctl");
+    check(hipStreamSynchronize(s.stream), "init upload");
+
+    setup_force(s);
 
     std::vector<int> hv, ht;
-    if (host_delaunay(nv, hx.data(), hy.data(), hv, ht) != 0) {
+    if (host_dt_all(s, hx.data(), hy.data(), hv, ht) != 0) {
         s.last_error = "initial Delaunay triangulation failed (coincident positions)";
         return BD_ERR_TRIANGULATION;
     }
@@ -727,26 +1079,67 @@ void bd_params_default(bd_params *p) {
     p->force_precision = BD_PREC_FP64;
 }
 
-int bd_init(bd_sim **out, int32_t n, const double *xy, const double *radii, const int32_t *species,
-            const double *theta, const bd_force_params *fp, const bd_params *p) {
+int bd_batch_init(bd_sim **out, int32_t R, const int32_t *n_per, const double *xy, const double *radii,
+                  const int32_t *species, const double *theta, const double *L_per, const uint64_t *seed_per,
+                  const bd_force_params *fp, const bd_params *p) {
     if (!out) return BD_ERR_INVALID_ARG;
     *out = nullptr;
     std::string err;
-    int rc = bd::validate_args(n, xy, radii, species, theta, fp, p, err);
+    int rc = bd::validate_batch(R, n_per, xy, radii, species, theta, L_per, fp, p, err);
+    if (rc == BD_OK && !seed_per) rc = BD_ERR_INVALID_ARG, err = "NULL seed_per";
     if (rc != BD_OK) {
-        std::fprintf(stderr, "bd_init: %s\n", err.c_str());
+        std::fprintf(stderr, "bd_batch_init: %s\n", err.c_str());
         return rc;
     }
     bd_sim *h = new (std::nothrow) bd_sim();
     if (!h) return BD_ERR_OOM;
-    rc = bd::guarded(h->s, [&] { return bd::init_impl(h->s, n, xy, radii, species, theta, fp, p); });
+    rc = bd::guarded(h->s, [&] {
+        return bd::init_impl(h->s, R, n_per, xy, radii, species, theta, L_per, seed_per, fp, p);
+    });
     if (rc != BD_OK) {
-        std::fprintf(stderr, "bd_init: %s\n", h->s.last_error.c_str());
+        std::fprintf(stderr, "bd_batch_init: %s\n", h->s.last_error.c_str());
         bd::free_all(h->s);
         delete h;
         return rc;
     }
     *out = h;
+    return BD_OK;
+}
+
+int bd_init(bd_sim **out, int32_t n, const double *xy, const double *radii, const int32_t *species,
+            const double *theta, const bd_force_params *fp, const bd_params *p) {
+    if (!out) return BD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!p) {
+        std::fprintf(stderr, "bd_init: NULL argument\n");
+        return BD_ERR_INVALID_ARG;
+    }
+    const double L = p->L;
+    const uint64_t seed = p->seed;
+    return bd_batch_init(out, 1, &n, xy, radii, species, theta, &L, &seed, fp, p);
+}
+
+int bd_batch_layout(bd_sim *sim, int32_t *R_out, int32_t *disk_off, int32_t *frame_off) {
+    if (!sim) return BD_ERR_INVALID_ARG;
+    const Sim &s = sim->s;
+    if (R_out) *R_out = s.R;
+    for (int r = 0; r <= s.R; ++r) {
+        if (disk_off) disk_off[r] = s.off_h[r];
+        if (frame_off) frame_off[r] = s.foff_h[r];
+    }
+    return BD_OK;
+}
+
+int bd_get_force_config(bd_sim *sim, bd_force_config *out) {
+    if (!sim || !out) return BD_ERR_INVALID_ARG;
+    const Sim &s = sim->s;
+    out->chunk = s.chunk_len;
+    out->per_lane = s.per_lane;
+    out->persistent = s.persistent;
+    out->tiles = s.ntiles;
+    out->grid = s.force_grid;
+    out->tuned = s.tuned;
+    out->tuned_ms = s.tuned_ms;
     return BD_OK;
 }
 
@@ -824,7 +1217,7 @@ int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *nt
         int cnt = 0;
         for (int t = 0; t < s.T; ++t) {
             int a = hv[3 * t], b = hv[3 * t + 1], c = hv[3 * t + 2];
-            if (a == s.inf || b == s.inf || c == s.inf) continue;
+            if (a >= s.inf || b >= s.inf || c >= s.inf) continue;
             if (cnt >= cap) {
                 s.last_error = "triangle buffer too small";
                 return (int)BD_ERR_INVALID_ARG;
@@ -868,13 +1261,16 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         std::vector<double> hx(s.n), hy(s.n), hr(s.n);
         bd::check(hipMemcpyAsync(hr.data(), s.rad, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "rad");
         bd::check(hipStreamSynchronize(s.stream), "sync");
-        for (int i = 0; i < s.n; ++i) {
-            hx[i] = xy[2 * i];
-            hy[i] = xy[2 * i + 1];
-            if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || hx[i] < hr[i] || hx[i] > s.p.L - hr[i] ||
-                hy[i] < hr[i] || hy[i] > s.p.L - hr[i]) {
-                s.last_error = "position outside the walls or not finite";
-                return (int)BD_ERR_BAD_INPUT;
+        for (int r = 0; r < s.R; ++r) {
+            const double L = s.L_h[r];
+            for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) {
+                hx[i] = xy[2 * i];
+                hy[i] = xy[2 * i + 1];
+                if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || hx[i] < hr[i] || hx[i] > L - hr[i] ||
+                    hy[i] < hr[i] || hy[i] > L - hr[i]) {
+                    s.last_error = "position outside the walls or not finite";
+                    return (int)BD_ERR_BAD_INPUT;
+                }
             }
         }
         bd::check(hipMemcpyAsync(s.xo, s.x, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "xo");

@@ -173,3 +173,23 @@ def batch_sizes(R: int = 256, seed: int = 0, lo: int = 2048, hi: int = 32768) ->
 def batch_phis(R: int = 256, seed: int = 0) -> List[float]:
     rng = np.random.Generator(np.random.PCG64(seed + 0xF1C4))
     return [float(v) for v in rng.uniform(0.2, 0.5, size=R)]
+
+
+def make_batch(R: int = 256, seed: int = 0, lo: int = 2048, hi: int = 32768,
+               steps: Optional[int] = None) -> List[Workload]:
+    """Batched workload C4: R independent systems of the C1 kind (FP64, S=1, K=1e-2, all pairs).
+
+    System r has N_r = floor(exp(U[ln lo, ln hi])) disks of radius 1 at area fraction phi_r ~ U[0.2, 0.5],
+    placed by random sequential insertion, and noise key seed_r = r.
+    """
+    sizes = batch_sizes(R, seed, lo, hi)
+    phis = batch_phis(R, seed)
+    out = []
+    for r in range(R):
+        n, phi = sizes[r], phis[r]
+        L = box_side(n, phi, 1.0)
+        xy = rsa(n, L, 1.0, seed * 1000003 + r)
+        out.append(Workload("C4", xy, np.ones(n), np.zeros(n, np.int32), np.zeros(n), 1, np.array([[1e-2]]),
+                            L=L, D=1.0, dt=1e-4, seed=r, steps=500 if steps is None else steps,
+                            fp32_forces=False, extra={"phi": phi, "replica": r}))
+    return out

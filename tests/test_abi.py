@@ -43,6 +43,8 @@ int main(void) {{
          offsetof(bd_params, max_overlap_rounds), offsetof(bd_params, force_precision));
   printf("%zu %zu\\n", offsetof(bd_force_params, q), offsetof(bd_force_params, K));
   printf("%zu %zu\\n", offsetof(bd_stats, kinetic_repairs), offsetof(bd_stats, host_rebuilds));
+  printf("%zu %zu %zu\\n", offsetof(bd_params, force_chunk), sizeof(bd_force_config),
+         offsetof(bd_force_config, tuned_ms));
   return 0;
 }}
 """)
@@ -55,6 +57,8 @@ int main(void) {{
                          P.force_precision.offset]
     assert vals[7:9] == [F.q.offset, F.K.offset]
     assert vals[9:11] == [S.kinetic_repairs.offset, S.host_rebuilds.offset]
+    C = binding.ForceConfig
+    assert vals[11:14] == [P.force_chunk.offset, ctypes.sizeof(C), C.tuned_ms.offset]
 
 
 def test_params_default():
@@ -99,3 +103,51 @@ def test_rejects_too_few_disks():
     with pytest.raises(binding.BDError) as e:
         _init([[5.0, 5.0], [9.0, 5.0]])
     assert e.value.code == -1
+
+
+def test_rejects_bad_force_chunk():
+    with pytest.raises(binding.BDError) as e:
+        _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], force_chunk=12)
+    assert e.value.code == -1
+
+
+def _batch(systems, Ls, **kw):
+    return binding.Sim.batch([np.asarray(x, dtype=np.float64) for x in systems], [np.ones(len(x)) for x in systems],
+                             [np.zeros(len(x), np.int32) for x in systems], None, Ls, list(range(len(systems))),
+                             np.array([[1e-2]]), **kw)
+
+
+GOOD = [[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]]
+
+
+def test_batch_rejects_bad_system():
+    # the second system overlaps; the first is fine
+    with pytest.raises(binding.BDError) as e:
+        _batch([GOOD, [[5.0, 5.0], [6.0, 5.0], [10.0, 10.0]]], [20.0, 20.0])
+    assert e.value.code == -2
+    # disk outside the walls of its own (smaller) box
+    with pytest.raises(binding.BDError) as e:
+        _batch([GOOD, [[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]]], [20.0, 11.0])
+    assert e.value.code == -2
+    with pytest.raises(binding.BDError) as e:
+        _batch([GOOD, GOOD[:2]], [20.0, 20.0])
+    assert e.value.code == -1
+    with pytest.raises(binding.BDError) as e:
+        _batch([GOOD, GOOD], [20.0, float("nan")])
+    assert e.value.code == -1
+
+
+def test_batch_rejects_short_range_with_several_systems():
+    with pytest.raises(binding.BDError) as e:
+        _batch([GOOD, GOOD], [20.0, 20.0], kind="screened", cutoff=2.5, skin=0.5)
+    assert e.value.code == -1
+
+
+def test_batch_rejects_empty():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    fp = binding.ForceParams(0, 1, 2.0, 1.0, 0.5, 0.0, 0.0, None)
+    p = binding.Params()
+    lib.bd_params_default(ctypes.byref(p))
+    assert lib.bd_batch_init(ctypes.byref(h), 0, None, None, None, None, None, None, None, ctypes.byref(fp),
+                             ctypes.byref(p)) == -1
