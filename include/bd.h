@@ -249,6 +249,34 @@ int bd_set_stream(bd_sim *sim, void *hip_stream);
 int bd_enable_kernel_timing(bd_sim *sim, int enable);
 int bd_kernel_time(bd_sim *sim, double *force_ms, int64_t *force_launches);
 
+/*
+ * Adjoint of the step (not in the paper): gradients of a scalar loss of the
+ * positions after nsteps steps with respect to the positions before them and
+ * to the strength matrix K.  The step is differentiated as written with every
+ * discrete choice of the forward pass held fixed: the overlapping partners of
+ * each correction round (the correction acts as a projection onto that
+ * round's contact set, Sec. 2.3 displacement and Sec. 4.4 Jacobi sum and
+ * cap), the cap branch, the wall branches.  Noise and director angles do not
+ * depend on the positions.  All-pairs inverse-square force only (kind POWER,
+ * q = 2, no cutoff); BD_ERR_INVALID_ARG otherwise.
+ *
+ * bd_adjoint_begin advances nsteps >= 1 steps exactly like bd_step while
+ * keeping a device copy of the state every checkpoint_every >= 1 steps; the
+ * handle is then at the final step (read it with bd_get_state).
+ *
+ * bd_adjoint_backward takes grad_xy = dL/dx at the final step (2n doubles,
+ * caller order) and writes grad_xy0 = dL/dx at the first step through the
+ * dynamics (2n doubles, may be NULL) and grad_K = dL/dK (S*S doubles,
+ * row-major, may be NULL).  It replays each segment between checkpoints
+ * from its checkpoint (recomputation instead of storing every step), records
+ * what the reverse sweep needs, and sweeps it backwards; the handle is left
+ * at the final step with its counters unchanged.  It may be called again
+ * with another grad_xy.  Device memory: one checkpoint per segment plus the
+ * positions of one segment.
+ */
+int bd_adjoint_begin(bd_sim *sim, int64_t nsteps, int32_t checkpoint_every);
+int bd_adjoint_backward(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K);
+
 /* Frees everything; accepts NULL. */
 void bd_destroy(bd_sim *sim);
 

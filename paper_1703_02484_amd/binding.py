@@ -21,7 +21,8 @@ BD_PREC_FP32 = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
-            "bd_set_positions", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_destroy")
+            "bd_set_positions", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_adjoint_begin",
+            "bd_adjoint_backward", "bd_destroy")
 
 
 class ForceParams(ctypes.Structure):
@@ -111,6 +112,10 @@ def load() -> ctypes.CDLL:
     lib.bd_enable_kernel_timing.restype = ctypes.c_int
     lib.bd_kernel_time.argtypes = [V, P(ctypes.c_double), P(ctypes.c_int64)]
     lib.bd_kernel_time.restype = ctypes.c_int
+    lib.bd_adjoint_begin.argtypes = [V, ctypes.c_int64, ctypes.c_int32]
+    lib.bd_adjoint_begin.restype = ctypes.c_int
+    lib.bd_adjoint_backward.argtypes = [V, V, V, V]
+    lib.bd_adjoint_backward.restype = ctypes.c_int
     lib.bd_destroy.argtypes = [V]
     lib.bd_destroy.restype = None
     _lib = lib
@@ -157,6 +162,7 @@ class Sim:
         sp = np.ascontiguousarray(species, dtype=np.int32)
         th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
         fp, p, _keep = _params(lib, L=L, K=K, **opts)
+        self._S = int(fp.S)
         h = ctypes.c_void_p()
         rc = lib.bd_init(ctypes.byref(h), self.n, _ptr(xy), _ptr(rad), _ptr(sp), None if th is None else _ptr(th),
                          ctypes.byref(fp), ctypes.byref(p))
@@ -184,6 +190,7 @@ class Sim:
         seed_per = np.ascontiguousarray([int(v) & (2**64 - 1) for v in seeds], dtype=np.uint64)
         self.n = int(n_per.sum())
         fp, p, _keep = _params(lib, L=float(L_per[0]), K=K, **opts)
+        self._S = int(fp.S)
         h = ctypes.c_void_p()
         rc = lib.bd_batch_init(ctypes.byref(h), R, _ptr(n_per), _ptr(xy), _ptr(rad), _ptr(sp),
                                None if th is None else _ptr(th), _ptr(L_per), _ptr(seed_per), ctypes.byref(fp),
@@ -283,6 +290,19 @@ class Sim:
         cnt = ctypes.c_int64()
         self._check(self._lib.bd_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(cnt)), "bd_kernel_time")
         return float(ms.value), int(cnt.value)
+
+    def adjoint_begin(self, nsteps: int, checkpoint_every: int):
+        """Advance nsteps steps keeping checkpoints for ``adjoint_backward``."""
+        self._check(self._lib.bd_adjoint_begin(self._h, int(nsteps), int(checkpoint_every)), "bd_adjoint_begin")
+
+    def adjoint_backward(self, grad_xy):
+        """dL/dx at the first step and dL/dK from dL/dx at the last step of ``adjoint_begin``."""
+        g = np.ascontiguousarray(grad_xy, dtype=np.float64).reshape(-1, 2)
+        g0 = np.zeros((self.n, 2), dtype=np.float64)
+        S = self._S
+        gK = np.zeros((S, S), dtype=np.float64)
+        self._check(self._lib.bd_adjoint_backward(self._h, _ptr(g), _ptr(g0), _ptr(gK)), "bd_adjoint_backward")
+        return g0, gK
 
     def close(self):
         if getattr(self, "_h", None):

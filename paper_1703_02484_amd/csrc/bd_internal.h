@@ -30,7 +30,10 @@ enum Ctl {
     K_NL_REBUILD = 8,  // a disk moved more than skin/2 since the neighbour lists were built
     K_NL_OVERFLOW = 9, // largest neighbour count when it exceeded the list capacity
     K_FQUEUE = 10,     // next tile of the persistent all-pairs force launch
-    K_CAND = 11,                     // [MAXR] flip candidates of round slot j
+    K_TAPE_ENT = 11,   // adjoint tape: entries recorded by the overlap rounds of this step
+    K_TAPE_DIR = 12,   // adjoint tape: overlap rounds recorded in this step
+    K_TAPE_OVF = 13,   // adjoint tape: 1 = capacity exceeded, 2 = a disk had more than MAXACT partners
+    K_CAND = 14,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -57,6 +60,55 @@ struct Tile {
     int i0, i1, js, je;
     long long pbase;
     long long work;   // (i1 - i0) * (je - js), for ordering
+};
+
+constexpr int MAXACT = 16;    // overlapping partners recorded per disk and round (adjoint tape)
+
+// Tape of one replayed segment of steps for the adjoint sweep: the positions
+// before every step, the wall slopes of every move, and for every overlap
+// round the disks it moved with their positions before the round, their
+// uncapped Jacobi sums, wall slopes and overlapping partners.
+struct Tape {
+    bool on = false;
+    int step_idx = 0;                      // step inside the segment being recorded
+    int ent_base = 0, dir_base = 0;        // entries / rounds recorded before this step
+    int cap_steps = 0, cap_ent = 0, cap_dir = 0;
+    double *px = nullptr, *py = nullptr;   // [cap_steps][n]
+    signed char *emwf = nullptr;           // [cap_steps][2n]
+    int *ev = nullptr;                     // [cap_ent] disk of each entry
+    double2 *eold = nullptr;               // [cap_ent] position before the round
+    double2 *edisp = nullptr;              // [cap_ent] uncapped Jacobi sum
+    signed char *ewf = nullptr;            // [2 cap_ent] wall slopes of the round's move
+    int *ecnt = nullptr;                   // [cap_ent] overlapping partners
+    int *enb = nullptr;                    // [cap_ent][MAXACT] their ids, in summation order
+    int2 *dir = nullptr;                   // [cap_dir] (first entry, count) of each round
+    std::vector<int> step_dir_end;         // rounds recorded up to the end of each step
+};
+
+// Device copy of the state at one step (adjoint checkpoints).
+struct Checkpoint {
+    double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr, *th = nullptr, *tho = nullptr;
+    int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
+    int64_t step = 0;
+    bd_stats st{};
+    unsigned long long acc[8] = {};
+    int budgets[3] = {0, 0, 0};
+};
+
+struct AdjState {
+    bool ready = false;                    // a forward pass with checkpoints has been run
+    int64_t t0 = 0, nsteps = 0;
+    int every = 0;
+    std::vector<Checkpoint> ck;            // at t0, t0 + every, ..., then the final state
+    Tape tape;
+    double2 *lam = nullptr, *nu = nullptr; // adjoint of the positions; round scratch
+    double *bx = nullptr, *by = nullptr;   // positions before a round, by disk id
+    double4 *pj4 = nullptr;                // sorted (x, y, lambda) of one step
+    double2 *gpart = nullptr;              // [part_cap] per-chunk adjoint force contributions
+    double *dk_rows = nullptr;             // [n][S] one step's dL/dK row of each particle
+    double *dk_blk = nullptr;              // [blocks][S*S] partial sums of dL/dK
+    double *dk = nullptr;                  // [S*S]
+    int dk_blocks = 0;
 };
 
 // Per-system constants read by the update kernel.
@@ -98,6 +150,7 @@ struct Sim {
     double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr;
     double *th = nullptr, *tho = nullptr, *rad = nullptr;
     int *sp = nullptr;
+    int *sp_sorted = nullptr;        // species in sorted order
     // force stage
     int *sorted_id = nullptr;        // sorted index -> caller id (species-sorted)
     int *pos_of = nullptr;           // caller id -> sorted index
@@ -149,6 +202,8 @@ struct Sim {
     // round budgets of the enqueued step (adapted to recent steps)
     int budget_em_rounds = 5, budget_ovl_rounds = 4, budget_overlaps = 3;
 
+    AdjState adj;
+
     // host-side stats
     bd_stats st{};
     std::string last_error;
@@ -188,6 +243,11 @@ void launch_ovl_apply(Sim &s, int k, int next_round, int slot);
 // kinetic fallback helpers
 void launch_scatter_oldpos(Sim &s, int k);            // xa[v] = old position for disks touched in round k
 void launch_interp(Sim &s, int i, int k);             // x = xa + (i/k)(xb - xa); exactly xb when i == k
+
+// adjoint sweep (k_adjoint.hip)
+void launch_adj_round(Sim &s, int first_entry, int count);     // one recorded overlap round, reversed
+void launch_adj_step(Sim &s, int t);                           // move of recorded step t, reversed
+void launch_adj_dk_final(Sim &s);
 
 // ---- host triangulation (host_dt.cpp) --------------------------------------
 // Delaunay triangulation of (x[i], y[i]) with infinite vertex n, as half-edge

@@ -107,6 +107,22 @@ BD_HD double bd_wall(double c, double r, double L) {
     return c;
 }
 
+// Slope of bd_wall at c: -1 per reflection, 0 where the clamp acts.
+BD_HD signed char bd_wall_slope(double c, double r, double L) {
+#pragma clang fp contract(off)
+    const double lo = r, hi = L - r;
+    signed char sl = 1;
+    if (c < lo) {
+        c = 2.0 * lo - c;
+        sl = -sl;
+    }
+    if (c > hi) {
+        c = 2.0 * hi - c;
+        sl = -sl;
+    }
+    return (c < lo || c > hi) ? (signed char)0 : sl;
+}
+
 // Half-edges of triangle t are 3t, 3t+1, 3t+2 in counter-clockwise order.
 BD_HD int bd_next(int h) { return (h % 3 == 2) ? h - 2 : h + 1; }
 BD_HD int bd_prev(int h) { return (h % 3 == 0) ? h + 2 : h - 1; }

@@ -242,7 +242,8 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
                                             double *__restrict__ x, double *__restrict__ y,
                                             double *__restrict__ xo, double *__restrict__ yo,
                                             double *__restrict__ th, double *__restrict__ tho,
-                                            unsigned long long *__restrict__ acc, const double2 *__restrict__ fdirect) {
+                                            unsigned long long *__restrict__ acc, const double2 *__restrict__ fdirect,
+                                            signed char *__restrict__ wf) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
@@ -277,6 +278,10 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
         tho[i] = t0;
         x[i] = bd_wall(xn, r, ri.L);
         y[i] = bd_wall(yn, r, ri.L);
+        if (wf) {   // adjoint tape: wall slopes of this move
+            wf[2 * (size_t)i] = bd_wall_slope(xn, r, ri.L);
+            wf[2 * (size_t)i + 1] = bd_wall_slope(yn, r, ri.L);
+        }
         th[i] = t0 + a.amp_r * nr;
     }
     if (clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
@@ -392,14 +397,16 @@ void launch_em(Sim &s) {
     a.clip = s.p.noise_clip;
     a.step = s.step;
     const int nb = blocks_for(s.n, 256);
+    const Tape &tp = s.adj.tape;
+    signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
     if (s.fp32)
         hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
-                           s.acc, s.use_nl ? s.fsr : nullptr);
+                           s.acc, s.use_nl ? s.fsr : nullptr, wf);
     else
         hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
-                           s.acc, s.use_nl ? s.fsr : nullptr);
+                           s.acc, s.use_nl ? s.fsr : nullptr, wf);
 }
 
 void launch_reduce_forces(Sim &s) {

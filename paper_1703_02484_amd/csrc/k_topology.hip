@@ -59,6 +59,12 @@ struct Topo {
     double2 *newpos, *oldpos;
     int *ctl;
     unsigned long long *acc;
+    // adjoint tape (null unless a segment is being recorded)
+    int *tev, *tecnt, *tenb;
+    double2 *teold, *tedisp;
+    signed char *tewf;
+    int2 *tdir;
+    int tent_base, tdir_base, tcap_ent, tcap_dir;
 };
 
 Topo topo_of(Sim &s) {
@@ -91,6 +97,19 @@ Topo topo_of(Sim &s) {
     t.oldpos = s.oldpos;
     t.ctl = s.ctl;
     t.acc = s.acc;
+    const Tape &tp = s.adj.tape;
+    const bool rec = tp.on;
+    t.tev = rec ? tp.ev : nullptr;
+    t.tecnt = tp.ecnt;
+    t.tenb = tp.enb;
+    t.teold = tp.eold;
+    t.tedisp = tp.edisp;
+    t.tewf = tp.ewf;
+    t.tdir = tp.dir;
+    t.tent_base = tp.ent_base;
+    t.tdir_base = tp.dir_base;
+    t.tcap_ent = tp.cap_ent;
+    t.tcap_dir = tp.cap_dir;
     return t;
 }
 
@@ -442,6 +461,12 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
             atomicAdd(&t.ctl[K_STAR], 1);
             continue;
         }
+        // adjoint tape: entry of this disk in this round
+        const bool rec = t.tev != nullptr;
+        const int e = rec ? t.tent_base + t.ctl[K_TAPE_ENT] + idx : 0;
+        const bool room = rec && e < t.tcap_ent;
+        if (rec && !room) atomicOr(&t.ctl[K_TAPE_OVF], 1);
+        int na = 0;
         double sx = 0.0, sy = 0.0;
         h = best;
         do {
@@ -454,10 +479,19 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
                     double s = f * (contact - d) / d;
                     sx += s * dx;
                     sy += s * dy;
+                    if (room && na < MAXACT) t.tenb[(size_t)e * MAXACT + na] = w;
+                    ++na;
                 }
             }
             h = t.he_twin[bd_prev(h)];
         } while (h != best);
+        if (room) {
+            if (na > MAXACT) atomicOr(&t.ctl[K_TAPE_OVF], 2);
+            t.tev[e] = v;
+            t.tecnt[e] = na < MAXACT ? na : MAXACT;
+            t.teold[e] = make_double2(xv, yv);
+            t.tedisp[e] = make_double2(sx, sy);
+        }
         const double len = sqrt(sx * sx + sy * sy);
         const double cap = cap_frac * rv;
         if (len > cap) {
@@ -465,6 +499,10 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
             sx = sx * sc;
             sy = sy * sc;
             atomicAdd(&t.acc[A_CAP_HITS], 1ull);
+        }
+        if (room) {
+            t.tewf[2 * (size_t)e] = bd_wall_slope(xv + sx, rv, L);
+            t.tewf[2 * (size_t)e + 1] = bd_wall_slope(yv + sy, rv, L);
         }
         t.newpos[idx] = make_double2(bd_wall(xv + sx, rv, L), bd_wall(yv + sy, rv, L));
     }
@@ -476,6 +514,16 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
 __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
     if (stopped(t.ctl)) return;
     const int ntouched = t.ctl[K_TOUCH + k];
+    if (t.tev != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        // adjoint tape: close the round's entries (written by the gather)
+        const int di = t.tdir_base + t.ctl[K_TAPE_DIR];
+        if (di < t.tcap_dir)
+            t.tdir[di] = make_int2(t.tent_base + t.ctl[K_TAPE_ENT], ntouched);
+        else
+            atomicOr(&t.ctl[K_TAPE_OVF], 1);
+        t.ctl[K_TAPE_ENT] += ntouched;
+        t.ctl[K_TAPE_DIR] += 1;
+    }
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
         const int v = t.touched[idx];
         const double2 np = t.newpos[idx];

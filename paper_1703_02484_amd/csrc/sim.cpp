@@ -387,6 +387,12 @@ int host_overlap_loop(Sim &s, Cursor &c, int &rounds) {
 int one_step(Sim &s) {
     Cursor c;
     fill_int(s, s.ctl, N_CTL, 0);
+    if (s.adj.tape.on) {   // adjoint tape: positions before the step
+        const Tape &tp = s.adj.tape;
+        const size_t off = (size_t)tp.step_idx * s.n, bytes = sizeof(double) * s.n;
+        check(hipMemcpyAsync(tp.px + off, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "tape x");
+        check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
+    }
     compute_forces(s);
     launch_em(s);
     std::vector<int> rep_first;   // first round slot of each enqueued repair
@@ -751,8 +757,11 @@ void setup_force(Sim &s) {
     write_tune_file();
 }
 
+void adj_free(Sim &s);
+
 void free_all(Sim &s) {
-    void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sorted_id, s.pos_of, s.pj, s.part,
+    adj_free(s);
+    void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
                     s.touched, s.newpos, s.oldpos, s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
@@ -939,6 +948,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.tho = dalloc<double>(n);
     s.rad = dalloc<double>(nva);
     s.sp = dalloc<int>(n);
+    s.sp_sorted = dalloc<int>(n);
     s.rep_of = dalloc<int>(n);
     s.Lr = dalloc<double>(R);
     s.sorted_id = dalloc<int>(n);
@@ -1000,6 +1010,9 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     check(hipMemcpyAsync(s.tho, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "tho");
     check(hipMemcpyAsync(s.rad, hrad.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "rad");
     check(hipMemcpyAsync(s.sp, species, sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sp");
+    std::vector<int> sps(n);
+    for (int k = 0; k < n; ++k) sps[k] = species[sorted[k]];
+    check(hipMemcpyAsync(s.sp_sorted, sps.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sp_sorted");
     check(hipMemcpyAsync(s.rep_of, hrep.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "rep_of");
     check(hipMemcpyAsync(s.Lr, L_per, sizeof(double) * R, hipMemcpyHostToDevice, s.stream), "Lr");
     check(hipMemcpyAsync(s.sorted_id, sorted.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sorted");
@@ -1023,6 +1036,222 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     upload_topology(s, hv, ht);
     if (s.use_nl) verlet_rebuild(s);
     return BD_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+void ck_alloc(Sim &s, Checkpoint &c) {
+    c.x = dalloc<double>(s.n);
+    c.y = dalloc<double>(s.n);
+    c.xo = dalloc<double>(s.n);
+    c.yo = dalloc<double>(s.n);
+    c.th = dalloc<double>(s.n);
+    c.tho = dalloc<double>(s.n);
+    c.he_v = dalloc<int>(s.H);
+    c.he_twin = dalloc<int>(s.H);
+    c.vert_he = dalloc<int>(s.nv + s.R);
+}
+
+void ck_free(Checkpoint &c) {
+    void *ptrs[] = {c.x, c.y, c.xo, c.yo, c.th, c.tho, c.he_v, c.he_twin, c.vert_he};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    c = Checkpoint();
+}
+
+void d2d(Sim &s, void *dst, const void *src, size_t bytes) {
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s.stream), "checkpoint copy");
+}
+
+void ck_save(Sim &s, Checkpoint &c) {
+    const size_t dn = sizeof(double) * s.n;
+    d2d(s, c.x, s.x, dn);
+    d2d(s, c.y, s.y, dn);
+    d2d(s, c.xo, s.xo, dn);
+    d2d(s, c.yo, s.yo, dn);
+    d2d(s, c.th, s.th, dn);
+    d2d(s, c.tho, s.tho, dn);
+    d2d(s, c.he_v, s.he_v, sizeof(int) * s.H);
+    d2d(s, c.he_twin, s.he_twin, sizeof(int) * s.H);
+    d2d(s, c.vert_he, s.vert_he, sizeof(int) * (s.nv + s.R));
+    check(hipMemcpyAsync(c.acc, s.acc, sizeof(unsigned long long) * N_ACC, hipMemcpyDeviceToHost, s.stream), "acc");
+    check(hipStreamSynchronize(s.stream), "checkpoint");
+    c.step = s.step;
+    c.st = s.st;
+    c.budgets[0] = s.budget_em_rounds;
+    c.budgets[1] = s.budget_ovl_rounds;
+    c.budgets[2] = s.budget_overlaps;
+}
+
+void ck_restore(Sim &s, const Checkpoint &c) {
+    const size_t dn = sizeof(double) * s.n;
+    d2d(s, s.x, c.x, dn);
+    d2d(s, s.y, c.y, dn);
+    d2d(s, s.xo, c.xo, dn);
+    d2d(s, s.yo, c.yo, dn);
+    d2d(s, s.th, c.th, dn);
+    d2d(s, s.tho, c.tho, dn);
+    d2d(s, s.he_v, c.he_v, sizeof(int) * s.H);
+    d2d(s, s.he_twin, c.he_twin, sizeof(int) * s.H);
+    d2d(s, s.vert_he, c.vert_he, sizeof(int) * (s.nv + s.R));
+    check(hipMemcpyAsync(s.acc, c.acc, sizeof(unsigned long long) * N_ACC, hipMemcpyHostToDevice, s.stream), "acc");
+    fill_int(s, s.ctl, N_CTL, 0);
+    check(hipStreamSynchronize(s.stream), "restore");
+    s.step = c.step;
+    s.st = c.st;
+    s.budget_em_rounds = c.budgets[0];
+    s.budget_ovl_rounds = c.budgets[1];
+    s.budget_overlaps = c.budgets[2];
+}
+
+void tape_free(Tape &tp) {
+    void *ptrs[] = {tp.px, tp.py, tp.emwf, tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    tp = Tape();
+}
+
+void tape_alloc_rounds(Tape &tp, int cap_ent, int cap_dir) {
+    void *ptrs[] = {tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir};
+    for (void *p : ptrs)
+        if (p) check(hipFree(p), "tape free");
+    tp.cap_ent = cap_ent;
+    tp.cap_dir = cap_dir;
+    tp.ev = dalloc<int>(cap_ent);
+    tp.eold = dalloc<double2>(cap_ent);
+    tp.edisp = dalloc<double2>(cap_ent);
+    tp.ewf = dalloc<signed char>(2 * (size_t)cap_ent);
+    tp.ecnt = dalloc<int>(cap_ent);
+    tp.enb = dalloc<int>((size_t)cap_ent * MAXACT);
+    tp.dir = dalloc<int2>(cap_dir);
+}
+
+void adj_free(Sim &s) {
+    AdjState &a = s.adj;
+    for (auto &c : a.ck) ck_free(c);
+    tape_free(a.tape);
+    void *ptrs[] = {a.lam, a.nu, a.bx, a.by, a.pj4, a.gpart, a.dk_rows, a.dk_blk, a.dk};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    a = AdjState();
+}
+
+int adjoint_begin(Sim &s, int64_t nsteps, int every) {
+    if (!s.kind_fast || s.use_nl) {
+        s.last_error = "the adjoint covers the all-pairs inverse-square force only";
+        return BD_ERR_INVALID_ARG;
+    }
+    adj_free(s);
+    AdjState &a = s.adj;
+    a.t0 = s.step;
+    a.nsteps = nsteps;
+    a.every = every;
+    const int nseg = (int)((nsteps + every - 1) / every);
+    a.ck.resize(nseg + 1);
+    for (auto &c : a.ck) ck_alloc(s, c);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        if (t % every == 0) ck_save(s, a.ck[t / every]);
+        int rc = one_step(s);
+        if (rc != BD_OK) {
+            adj_free(s);
+            return rc;
+        }
+    }
+    ck_save(s, a.ck[nseg]);
+    const int n = s.n;
+    a.lam = dalloc<double2>(n);
+    a.nu = dalloc<double2>(n);
+    a.bx = dalloc<double>(n);
+    a.by = dalloc<double>(n);
+    a.pj4 = dalloc<double4>(n);
+    a.gpart = dalloc<double2>((size_t)s.part_cap);
+    a.dk_blocks = (n + 255) / 256;
+    a.dk_rows = dalloc<double>((size_t)n * s.S);
+    a.dk_blk = dalloc<double>((size_t)a.dk_blocks * s.S * s.S);
+    a.dk = dalloc<double>(s.S * s.S);
+    Tape &tp = a.tape;
+    tp.cap_steps = every;
+    tp.px = dalloc<double>((size_t)every * n);
+    tp.py = dalloc<double>((size_t)every * n);
+    tp.emwf = dalloc<signed char>((size_t)every * 2 * n);
+    tape_alloc_rounds(tp, std::max(4096, 2 * n), std::max(256, 64 * every));
+    a.ready = true;
+    return BD_OK;
+}
+
+// Replays segment `seg` from its checkpoint with the tape on.  Returns BD_OK,
+// or an error (state left at the segment's end).
+int record_segment(Sim &s, int seg, int len) {
+    AdjState &a = s.adj;
+    Tape &tp = a.tape;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        ck_restore(s, a.ck[seg]);
+        tp.on = true;
+        tp.ent_base = 0;
+        tp.dir_base = 0;
+        tp.step_dir_end.assign(len, 0);
+        bool grow = false;
+        for (int t = 0; t < len; ++t) {
+            tp.step_idx = t;
+            int rc = one_step(s);
+            if (rc != BD_OK) {
+                tp.on = false;
+                return rc;
+            }
+            read_ctl(s);
+            const int *h = s.hctl;
+            if (h[K_TAPE_OVF] & 2) {
+                tp.on = false;
+                s.last_error = "a disk overlapped more partners in one round than the adjoint tape records";
+                return BD_ERR_INVALID_ARG;
+            }
+            if (h[K_TAPE_OVF]) grow = true;
+            tp.ent_base += h[K_TAPE_ENT];
+            tp.dir_base += h[K_TAPE_DIR];
+            tp.step_dir_end[t] = tp.dir_base;
+        }
+        tp.on = false;
+        if (!grow) return BD_OK;
+        tape_alloc_rounds(tp, std::max(tp.cap_ent, 2 * tp.ent_base), std::max(tp.cap_dir, 2 * tp.dir_base));
+    }
+    s.last_error = "adjoint tape could not be sized";
+    return BD_ERR_DEVICE;
+}
+
+int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK) {
+    AdjState &a = s.adj;
+    if (!a.ready) {
+        s.last_error = "bd_adjoint_begin has not been run";
+        return BD_ERR_INVALID_ARG;
+    }
+    Tape &tp = a.tape;
+    const int nseg = (int)a.ck.size() - 1;
+    check(hipMemcpyAsync(a.lam, gT, sizeof(double2) * s.n, hipMemcpyHostToDevice, s.stream), "lambda");
+    check(hipMemsetAsync(a.dk_blk, 0, sizeof(double) * a.dk_blocks * s.S * s.S, s.stream), "dk");
+    int rc = BD_OK;
+    std::vector<int2> dir;
+    for (int seg = nseg - 1; seg >= 0 && rc == BD_OK; --seg) {
+        const int len = (int)std::min<int64_t>(a.every, a.nsteps - (int64_t)seg * a.every);
+        rc = record_segment(s, seg, len);
+        if (rc != BD_OK) break;
+        dir.resize(tp.dir_base);
+        if (tp.dir_base > 0)
+            check(hipMemcpyAsync(dir.data(), tp.dir, sizeof(int2) * tp.dir_base, hipMemcpyDeviceToHost, s.stream),
+                  "tape directory");
+        check(hipStreamSynchronize(s.stream), "sync");
+        for (int t = len - 1; t >= 0; --t) {
+            const int r0 = t == 0 ? 0 : tp.step_dir_end[t - 1], r1 = tp.step_dir_end[t];
+            for (int r = r1 - 1; r >= r0; --r) launch_adj_round(s, dir[r].x, dir[r].y);
+            launch_adj_step(s, t);
+        }
+    }
+    if (rc == BD_OK) {
+        launch_adj_dk_final(s);
+        if (g0) check(hipMemcpyAsync(g0, a.lam, sizeof(double2) * s.n, hipMemcpyDeviceToHost, s.stream), "grad x0");
+        if (gK) check(hipMemcpyAsync(gK, a.dk, sizeof(double) * s.S * s.S, hipMemcpyDeviceToHost, s.stream), "grad K");
+        check(hipStreamSynchronize(s.stream), "sync");
+    }
+    ck_restore(s, a.ck[nseg]);   // back to the end of the forward pass
+    return rc;
 }
 
 const char *err_name(int code) {
@@ -1117,6 +1346,18 @@ int bd_init(bd_sim **out, int32_t n, const double *xy, const double *radii, cons
     const double L = p->L;
     const uint64_t seed = p->seed;
     return bd_batch_init(out, 1, &n, xy, radii, species, theta, &L, &seed, fp, p);
+}
+
+int bd_adjoint_begin(bd_sim *sim, int64_t nsteps, int32_t checkpoint_every) {
+    if (!sim || nsteps < 1 || checkpoint_every < 1) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] { return bd::adjoint_begin(s, nsteps, checkpoint_every); });
+}
+
+int bd_adjoint_backward(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K) {
+    if (!sim || !grad_xy) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] { return bd::adjoint_backward(s, grad_xy, grad_xy0, grad_K); });
 }
 
 int bd_batch_layout(bd_sim *sim, int32_t *R_out, int32_t *disk_off, int32_t *frame_off) {

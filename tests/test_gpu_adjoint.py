@@ -1,0 +1,165 @@
+"""Adjoint sweep (``bd_adjoint_begin`` / ``bd_adjoint_backward``) against the
+oracle's forward-mode tangents, against finite differences of the device's
+own forward map, and through ``torch.autograd``.
+
+Reverse and forward mode must agree: for any cotangent lambda_T and tangent
+(v, w), <dL/dx0, v> + <dL/dK, w> with L = <lambda_T, x_T> equals
+<lambda_T, JVP(v, w)>.  Tolerance 1e-10 relative (FP64, same trajectory).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1703_02484_amd import autograd as bdad
+from paper_1703_02484_amd import binding, synth
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _vjp_vs_jvp(w, steps, every, seed=1):
+    g = binding.Sim.from_workload(w)
+    g.adjoint_begin(steps, every)
+    o = oracle.OracleSim.from_workload(w)
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(w.n, 2))
+    tK = rng.normal(size=w.K.shape)
+    o.set_tangent(v, tK)
+    o.step(steps)
+    assert np.abs(g.state()[0] - o.state()[0]).max() <= 1e-9 * w.L
+    lamT = rng.normal(size=(w.n, 2))
+    g0, gK = g.adjoint_backward(lamT)
+    lhs = np.sum(g0 * v) + np.sum(gK * tK)
+    rhs = np.sum(lamT * o.tangent())
+    return lhs, rhs, o.state()[3]
+
+
+def test_vjp_matches_oracle_jvp_c5_reduced():
+    lhs, rhs, st = _vjp_vs_jvp(synth.make("C5", n=1024), 12, 5)
+    assert st["overlap_edges_total"] > 0
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_vjp_matches_oracle_jvp_dense_strong_noise():
+    # many overlap rounds per step, capped moves, wall contacts
+    n = 500
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    sp = (np.arange(n) % 2).astype(np.int32)
+    w = synth.Workload("dense", xy, np.ones(n), sp, np.zeros(n), 2, np.array([[0.05, -0.02], [0.03, 0.04]]), L=L,
+                       D=1.0, dt=2e-2, seed=2)
+    lhs, rhs, st = _vjp_vs_jvp(w, 6, 4)
+    assert st["cap_hits"] > 0 and st["overlap_rounds_max"] >= 2
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_dL_dK_matches_oracle_per_entry():
+    w = synth.make("C5", n=512)
+    steps = 10
+    g = binding.Sim.from_workload(w)
+    g.adjoint_begin(steps, 4)
+    xT = g.state()[0]
+    s0 = w.species == 0
+    lamT = np.zeros_like(xT)
+    lamT[s0] = 2.0 * (xT[s0] - w.xy[s0]) / s0.sum()
+    _, gK = g.adjoint_backward(lamT)
+    ref = np.zeros((2, 2))
+    for a in range(2):
+        for b in range(2):
+            o = oracle.OracleSim.from_workload(w)
+            e = np.zeros((2, 2))
+            e[a, b] = 1.0
+            o.set_tangent(np.zeros((w.n, 2)), e)
+            o.step(steps)
+            ref[a, b] = np.sum(lamT * o.tangent())
+    assert np.abs(gK - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    w = synth.make("C5", n=800)
+    lamT = np.random.default_rng(4).normal(size=(w.n, 2))
+    res = []
+    for every in (1, 4, 12):
+        g = binding.Sim.from_workload(w)
+        g.adjoint_begin(12, every)
+        res.append(g.adjoint_backward(lamT))
+    for g0, gK in res[1:]:
+        assert np.array_equal(g0, res[0][0]) and np.array_equal(gK, res[0][1])
+
+
+def test_backward_leaves_state_and_counters():
+    w = synth.make("C5", n=600)
+    g = binding.Sim.from_workload(w)
+    g.adjoint_begin(7, 3)
+    before = g.state()
+    g.adjoint_backward(np.ones((w.n, 2)))
+    after = g.state()
+    assert np.array_equal(before[0], after[0]) and before[2] == after[2] and before[3] == after[3]
+    g.step(2)   # stepping on from the final state still works
+    assert g.state()[2] == 9
+
+
+def _loss(w, x):
+    s0 = w.species == 0
+    d = x[s0] - w.xy[s0]
+    return float(np.sum(d * d) / s0.sum())
+
+
+def test_full_size_c5_against_finite_differences():
+    # N = 16,384, 50 steps, checkpoints every 10; dL/dK against central
+    # differences (h = 1e-6) of the device forward map
+    w = synth.make("C5")
+    steps = 50
+    g = binding.Sim.from_workload(w)
+    g.adjoint_begin(steps, 10)
+    xT = g.state()[0]
+    s0 = w.species == 0
+    lamT = np.zeros_like(xT)
+    lamT[s0] = 2.0 * (xT[s0] - w.xy[s0]) / s0.sum()
+    g0, gK = g.adjoint_backward(lamT)
+    h = 1e-6
+
+    def L_of(K=None, x0=None):
+        s = binding.Sim(w.xy if x0 is None else x0, w.radii, w.species, w.theta, w.K if K is None else K, L=w.L,
+                        D=w.D, dt=w.dt, seed=w.seed, overlap_factor=w.overlap_factor)
+        s.step(steps)
+        return _loss(w, s.state()[0])
+
+    fd = np.zeros((2, 2))
+    for a in range(2):
+        for b in range(2):
+            e = np.zeros((2, 2))
+            e[a, b] = h
+            fd[a, b] = (L_of(K=w.K + e) - L_of(K=w.K - e)) / (2 * h)
+    assert np.abs(gK - fd).max() <= 1e-5 * np.abs(fd).max()
+    # initial positions along a random direction (the loss also holds x0 directly)
+    v = np.random.default_rng(6).normal(size=(w.n, 2)) * 1e-2
+    direct = -np.sum(lamT[s0] * v[s0])
+    fdx = (L_of(x0=w.xy + h * v) - L_of(x0=w.xy - h * v)) / (2 * h)
+    assert np.sum(g0 * v) + direct == pytest.approx(fdx, rel=1e-5)
+
+
+def test_autograd_function_matches_adjoint_and_gradcheck():
+    w = synth.make("C5", n=96)
+    spec = bdad.RolloutSpec.from_workload(w)
+    K = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
+    x0 = torch.tensor(w.xy, dtype=torch.float64, requires_grad=True)
+    xT = bdad.rollout(K, x0, spec, 6, 3)
+    loss = bdad.msd_loss(xT, x0, w.species)
+    loss.backward()
+    # the same gradient from the ABI directly (chain part) plus the direct term of x0
+    g = binding.Sim.from_workload(w)
+    g.adjoint_begin(6, 3)
+    xTn = g.state()[0]
+    s0 = w.species == 0
+    lamT = np.zeros_like(xTn)
+    lamT[s0] = 2.0 * (xTn[s0] - w.xy[s0]) / s0.sum()
+    g0, gK = g.adjoint_backward(lamT)
+    g0[s0] -= lamT[s0]
+    assert np.allclose(K.grad.numpy(), gK, rtol=1e-12, atol=0)
+    assert np.allclose(x0.grad.numpy(), g0, rtol=1e-12, atol=1e-15)
+    # finite-difference check of the autograd wrapper on a few inputs
+    Kc = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda k: bdad.rollout(k, x0.detach(), spec, 4, 2)[:8], (Kc,), eps=1e-6,
+                                    atol=1e-6, rtol=1e-4)
