@@ -237,6 +237,15 @@ int bd_get_frame(bd_sim *sim, double *xy_out, int32_t cap, int32_t *m_out);
  */
 int bd_set_positions(bd_sim *sim, const double *xy);
 
+/*
+ * Graph mode (enable != 0; off after bd_init): each step's device work is
+ * replayed from HIP graphs captured on first use (one set per round-budget
+ * setting) instead of being launched kernel by kernel; the step counter and
+ * the round stamps are read from device memory, so replays need no new
+ * arguments.  Results are identical to the launch-by-launch mode.
+ */
+int bd_set_graph_mode(bd_sim *sim, int enable);
+
 /* Runs later work on hip_stream (a hipStream_t; NULL = the library's own stream). */
 int bd_set_stream(bd_sim *sim, void *hip_stream);
 

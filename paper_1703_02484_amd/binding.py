@@ -21,7 +21,7 @@ BD_PREC_FP32 = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
-            "bd_set_positions", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_adjoint_begin",
+            "bd_set_positions", "bd_set_graph_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_adjoint_begin",
             "bd_adjoint_backward", "bd_destroy")
 
 
@@ -106,6 +106,8 @@ def load() -> ctypes.CDLL:
     lib.bd_get_frame.restype = ctypes.c_int
     lib.bd_set_positions.argtypes = [V, V]
     lib.bd_set_positions.restype = ctypes.c_int
+    lib.bd_set_graph_mode.argtypes = [V, ctypes.c_int]
+    lib.bd_set_graph_mode.restype = ctypes.c_int
     lib.bd_set_stream.argtypes = [V, V]
     lib.bd_set_stream.restype = ctypes.c_int
     lib.bd_enable_kernel_timing.argtypes = [V, ctypes.c_int]
@@ -278,6 +280,9 @@ class Sim:
     def set_positions(self, xy):
         a = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         self._check(self._lib.bd_set_positions(self._h, _ptr(a)), "bd_set_positions")
+
+    def set_graph_mode(self, on: bool = True):
+        self._check(self._lib.bd_set_graph_mode(self._h, 1 if on else 0), "bd_set_graph_mode")
 
     def set_stream(self, stream_handle: Optional[int]):
         self._check(self._lib.bd_set_stream(self._h, stream_handle), "bd_set_stream")

@@ -62,6 +62,14 @@ struct Tile {
     long long work;   // (i1 - i0) * (je - js), for ordering
 };
 
+// Per-step values that kernels read from device memory, so that a captured
+// step can be replayed: the noise counter and the bases of the flip-round and
+// overlap-round stamps (kernels receive stamps relative to these bases).
+struct StepBase {
+    long long step;
+    int rbase, vbase;
+};
+
 constexpr int MAXACT = 16;    // overlapping partners recorded per disk and round (adjoint tape)
 
 // Tape of one replayed segment of steps for the adjoint sweep: the positions
@@ -192,8 +200,20 @@ struct Sim {
     // repair fallback: topology snapshot and the move it must replay
     int *snap_v = nullptr, *snap_twin = nullptr, *snap_vh = nullptr;
     double *xa = nullptr, *ya = nullptr, *xb = nullptr, *yb = nullptr;
-    int round_id = 0;                // flip-round stamp
-    int vround = 0;                  // overlap-round stamp
+    int round_id = 0;                // flip-round stamp (absolute)
+    int vround = 0;                  // overlap-round stamp (absolute)
+    StepBase *dbase = nullptr;       // device copy of the bases below
+    StepBase *hbase = nullptr;       // pinned staging for it
+    int rbase = 0, vbase = 0;        // bases currently on the device; launches pass stamp - base
+    // captured steps (one graph triple per round-budget setting)
+    bool use_graph = false;
+    struct StepGraph {
+        hipGraphExec_t pre = nullptr, force = nullptr, post = nullptr;
+        int r_used = 0, v_used = 0;
+        int c_slot = 0, c_rep = 0, c_oround = 0;
+        std::vector<int> orounds, rep_first;
+    };
+    std::vector<std::pair<long long, StepGraph>> graphs;
     // control block and accumulators
     int *ctl = nullptr;
     unsigned long long *acc = nullptr;

@@ -228,14 +228,13 @@ __device__ __forceinline__ void box_muller(uint4 w, double &z0, double &z1) {
 struct EmArgs {
     int n, S;
     double dt, amp, amp_r, v0, clip;
-    int64_t step;
 };
 
 // Fused Euler-Maruyama update: gather forces, draw noise (stream 0:
 // translation, stream 1: rotation), move, reflect at the walls, keep the
 // previous state for the reversal check and for error rollback.
 template <typename T2>
-__global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ part, const RepInfo *__restrict__ reps,
+__global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict__ base, const T2 *__restrict__ part, const RepInfo *__restrict__ reps,
                                             const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
                                             const double *__restrict__ K, const int *__restrict__ pos_of,
                                             const int *__restrict__ sp, const double *__restrict__ rad,
@@ -258,8 +257,9 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const T2 *__restrict__ par
         }
         // noise keyed by the system's seed and the particle's id inside its system
         const unsigned id = (unsigned)(i - ri.off);
-        const unsigned slo = (unsigned)(unsigned long long)a.step;
-        const unsigned shi = (unsigned)((unsigned long long)a.step >> 32);
+        const unsigned long long step = (unsigned long long)base->step;
+        const unsigned slo = (unsigned)step;
+        const unsigned shi = (unsigned)(step >> 32);
         const uint2 key = make_uint2((unsigned)ri.seed, (unsigned)(ri.seed >> 32));
         double zx, zy, nr, unused;
         box_muller(philox10(make_uint4(id, slo, shi, 0u), key), zx, zy);
@@ -395,16 +395,15 @@ void launch_em(Sim &s) {
     a.amp_r = std::sqrt(2.0 * s.p.Dr * s.p.dt);
     a.v0 = s.p.v0;
     a.clip = s.p.noise_clip;
-    a.step = s.step;
     const int nb = blocks_for(s.n, 256);
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
     if (s.fp32)
-        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const float2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, s.dbase, (const float2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
     else
-        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const double2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, s.dbase, (const double2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
 }

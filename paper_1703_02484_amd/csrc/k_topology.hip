@@ -59,6 +59,7 @@ struct Topo {
     double2 *newpos, *oldpos;
     int *ctl;
     unsigned long long *acc;
+    const StepBase *base;   // stamps passed to kernels are relative to base->rbase / base->vbase
     // adjoint tape (null unless a segment is being recorded)
     int *tev, *tecnt, *tenb;
     double2 *teold, *tedisp;
@@ -97,6 +98,7 @@ Topo topo_of(Sim &s) {
     t.oldpos = s.oldpos;
     t.ctl = s.ctl;
     t.acc = s.acc;
+    t.base = s.dbase;
     const Tape &tp = s.adj.tape;
     const bool rec = tp.on;
     t.tev = rec ? tp.ev : nullptr;
@@ -191,6 +193,7 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
 
 __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
     if (stopped(t.ctl)) return;
+    round += t.base->rbase;
     for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -203,6 +206,7 @@ __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
 
 __global__ void k_flip_eval_list(Topo t, int round, int slot) {
     if (stopped(t.ctl)) return;
+    round += t.base->rbase;
     const int count = t.ctl[K_WL + slot];
     const int *wl = wl_of(t, slot);
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
@@ -226,6 +230,7 @@ __global__ void k_flip_eval_list(Topo t, int round, int slot) {
 }
 
 __global__ void k_flip_apply(Topo t, int round, int slot) {
+    round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
@@ -283,6 +288,7 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
 }
 
 __global__ void k_flip_fix(Topo t, int round, int slot) {
+    round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
     const int next = round + 1;
@@ -370,6 +376,7 @@ __device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, in
 __global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
+    stamp += t.base->vbase;
     int found = 0;
     for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
 #pragma unroll
@@ -513,6 +520,7 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
 // worklist of round slot `slot`, the first round of the following repair.
 __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
     if (stopped(t.ctl)) return;
+    next_round += t.base->rbase;
     const int ntouched = t.ctl[K_TOUCH + k];
     if (t.tev != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
         // adjoint tape: close the round's entries (written by the gather)
@@ -600,22 +608,26 @@ inline int grid_for(long items, int cap = kMaxGrid) {
 }  // namespace
 
 void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
+    round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, round, slot,
                        reversal ? 1 : 0);
 }
 
 void launch_flip_eval_list(Sim &s, int round, int slot) {
+    round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_flip_eval_list, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_apply(Sim &s, int round, int slot) {
+    round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_flip_apply, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_fix(Sim &s, int round, int slot) {
+    round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_flip_fix, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
 }
@@ -630,6 +642,7 @@ void launch_repair_check(Sim &s, int rep, int last) {
 }
 
 void launch_ovl_detect(Sim &s, int vstamp, int k) {
+    vstamp -= s.vbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, vstamp,
                        1.0 - s.p.contact_tol, k);
@@ -650,6 +663,7 @@ void launch_ovl_gather(Sim &s, int k) {
 }
 
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
+    next_round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, next_round, slot);
 }

@@ -291,6 +291,15 @@ void rollback(Sim &s) {
     host_rebuild(s);
 }
 
+void drop_graphs(Sim &s) {
+    for (auto &e : s.graphs) {
+        if (e.second.pre) (void)hipGraphExecDestroy(e.second.pre);
+        if (e.second.force) (void)hipGraphExecDestroy(e.second.force);
+        if (e.second.post) (void)hipGraphExecDestroy(e.second.post);
+    }
+    s.graphs.clear();
+}
+
 // Rebuilds the Verlet lists from the current positions (one read-back to
 // check the list capacity; grows it once if a disk has too many neighbours).
 void verlet_rebuild(Sim &s) {
@@ -309,28 +318,23 @@ void verlet_rebuild(Sim &s) {
         if (need > 96 || s.nl_cap >= 96) throw DeviceError{hipErrorInvalidValue, "neighbour list capacity (96) exceeded"};
         check(hipFree(s.nl), "free nl");
         s.nl = nullptr;
+        drop_graphs(s);   // captured steps hold the old list pointer
         s.nl_cap = 96;
         s.nl = dalloc<int>((size_t)s.nl_cap * s.n);
     }
 }
 
+void timed(Sim &s, const std::function<void()> &work);
+
 void compute_forces(Sim &s) {
     if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
     if (!s.use_nl) launch_cast(s);
-    hipEvent_t a = nullptr, b = nullptr;
-    if (s.timing) {
-        check(hipEventCreate(&a), "event");
-        check(hipEventCreate(&b), "event");
-        check(hipEventRecord(a, s.stream), "event record");
-    }
-    if (s.use_nl)
-        launch_force_nl(s);
-    else
-        launch_force(s);
-    if (s.timing) {
-        check(hipEventRecord(b, s.stream), "event record");
-        s.ev.emplace_back(a, b);
-    }
+    timed(s, [&] {
+        if (s.use_nl)
+            launch_force_nl(s);
+        else
+            launch_force(s);
+    });
 }
 
 // Skin test for the next step's lists (short-range path only).
@@ -380,24 +384,21 @@ int host_overlap_loop(Sim &s, Cursor &c, int &rounds) {
     }
 }
 
-// One step of Algorithm 1.  The whole step is enqueued as a budgeted sequence
-// (force, update, repair rounds, overlap rounds each with its repair) and the
-// control block is read back once; if a budget ran out or a repair failed,
-// the host finishes the step from exactly that point.
-int one_step(Sim &s) {
-    Cursor c;
-    fill_int(s, s.ctl, N_CTL, 0);
-    if (s.adj.tape.on) {   // adjoint tape: positions before the step
-        const Tape &tp = s.adj.tape;
-        const size_t off = (size_t)tp.step_idx * s.n, bytes = sizeof(double) * s.n;
-        check(hipMemcpyAsync(tp.px + off, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "tape x");
-        check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
-    }
-    compute_forces(s);
-    launch_em(s);
-    std::vector<int> rep_first;   // first round slot of each enqueued repair
+// Puts the step counter and the stamp bases of the coming step in device
+// memory (stream-ordered); later launches pass stamps relative to them.
+void write_base(Sim &s) {
+    s.hbase->step = s.step;
+    s.hbase->rbase = s.round_id;
+    s.hbase->vbase = s.vround;
+    check(hipMemcpyAsync(s.dbase, s.hbase, sizeof(StepBase), hipMemcpyHostToDevice, s.stream), "step base");
+    s.rbase = s.round_id;
+    s.vbase = s.vround;
+}
+
+// The budgeted part of a step after the update: repair rounds, then overlap
+// rounds each with its repair, the final overlap check, the skin test.
+void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
     enqueue_repair(s, c, true, true, s.budget_em_rounds, &rep_first);
-    std::vector<int> orounds;
     for (int j = 0; j < s.budget_overlaps; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);
@@ -415,6 +416,105 @@ int one_step(Sim &s) {
         launch_final_check(s, k);
     }
     skin_check(s, false);
+}
+
+hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    check(hipStreamBeginCapture(s.stream, hipStreamCaptureModeRelaxed), "begin capture");
+    enqueue();
+    check(hipStreamEndCapture(s.stream, &g), "end capture");
+    hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check(rc, "graph instantiate");
+    return e;
+}
+
+// The captured step for the current round budgets (captured on first use):
+// [clear counters, cast] [force] [update, budgeted rounds, checks].  Stamps
+// inside are relative to the bases of the step being replayed.
+Sim::StepGraph &step_graph(Sim &s) {
+    const long long key = ((long long)s.budget_em_rounds << 32) | ((long long)s.budget_ovl_rounds << 16) |
+                          (long long)s.budget_overlaps;
+    for (auto &e : s.graphs)
+        if (e.first == key) return e.second;
+    Sim::StepGraph g;
+    const int r0 = s.round_id, v0 = s.vround;
+    g.pre = capture(s, [&] {
+        fill_int(s, s.ctl, N_CTL, 0);
+        if (!s.use_nl) launch_cast(s);
+    });
+    g.force = capture(s, [&] {
+        if (s.use_nl)
+            launch_force_nl(s);
+        else
+            launch_force(s);
+    });
+    Cursor c;
+    g.post = capture(s, [&] {
+        launch_em(s);
+        enqueue_rounds(s, c, g.orounds, g.rep_first);
+    });
+    g.r_used = s.round_id - r0;
+    g.v_used = s.vround - v0;
+    g.c_slot = c.slot;
+    g.c_rep = c.rep;
+    g.c_oround = c.oround;
+    s.round_id = r0;   // capturing ran nothing
+    s.vround = v0;
+    s.graphs.emplace_back(key, std::move(g));
+    return s.graphs.back().second;
+}
+
+void timed(Sim &s, const std::function<void()> &work) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (s.timing) {
+        check(hipEventCreate(&a), "event");
+        check(hipEventCreate(&b), "event");
+        check(hipEventRecord(a, s.stream), "event record");
+    }
+    work();
+    if (s.timing) {
+        check(hipEventRecord(b, s.stream), "event record");
+        s.ev.emplace_back(a, b);
+    }
+}
+
+// One step of Algorithm 1.  The whole step is enqueued as a budgeted sequence
+// (force, update, repair rounds, overlap rounds each with its repair) -- as
+// three captured graphs in graph mode -- and the control block is read back
+// once; if a budget ran out or a repair failed, the host finishes the step
+// from exactly that point.
+int one_step(Sim &s) {
+    Cursor c;
+    std::vector<int> rep_first;   // first round slot of each enqueued repair
+    std::vector<int> orounds;
+    write_base(s);
+    if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
+    if (s.use_graph && !s.adj.tape.on) {
+        Sim::StepGraph &g = step_graph(s);
+        check(hipGraphLaunch(g.pre, s.stream), "graph launch");
+        timed(s, [&] { check(hipGraphLaunch(g.force, s.stream), "graph launch"); });
+        check(hipGraphLaunch(g.post, s.stream), "graph launch");
+        s.round_id += g.r_used;
+        s.vround += g.v_used;
+        c.slot = g.c_slot;
+        c.rep = g.c_rep;
+        c.oround = g.c_oround;
+        orounds = g.orounds;
+        rep_first = g.rep_first;
+    } else {
+        fill_int(s, s.ctl, N_CTL, 0);
+        if (s.adj.tape.on) {   // adjoint tape: positions before the step
+            const Tape &tp = s.adj.tape;
+            const size_t off = (size_t)tp.step_idx * s.n, bytes = sizeof(double) * s.n;
+            check(hipMemcpyAsync(tp.px + off, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "tape x");
+            check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
+        }
+        compute_forces(s);
+        launch_em(s);
+        enqueue_rounds(s, c, orounds, rep_first);
+    }
     read_ctl(s);
     const int *h = s.hctl;
     s.need_rebuild = s.use_nl && h[K_NL_REBUILD] != 0;
@@ -769,6 +869,9 @@ void free_all(Sim &s) {
                     s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    drop_graphs(s);
+    if (s.dbase) (void)hipFree(s.dbase);
+    if (s.hbase) (void)hipHostFree(s.hbase);
     if (s.hctl) (void)hipHostFree(s.hctl);
     if (s.hacc) (void)hipHostFree(s.hacc);
     for (auto &e : s.ev) {
@@ -980,6 +1083,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.xb = dalloc<double>(n);
     s.yb = dalloc<double>(n);
     s.ctl = dalloc<int>(N_CTL);
+    s.dbase = dalloc<StepBase>(1);
+    if (hipHostMalloc((void **)&s.hbase, sizeof(StepBase), hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
     if (s.use_nl) {
         const double rl = fp->cutoff + fp->skin;
         s.nl_nc = std::max(1, std::min(46000, (int)std::floor(L_per[0] / rl)));
@@ -1025,6 +1130,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     check(hipMemsetAsync(s.acc, 0, sizeof(unsigned long long) * N_ACC, s.stream), "acc");
     check(hipMemsetAsync(s.ctl, 0, sizeof(int) * N_CTL, s.stream), "ctl");
     check(hipStreamSynchronize(s.stream), "init upload");
+    write_base(s);
 
     setup_force(s);
 
@@ -1522,6 +1628,16 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         s.need_rebuild = true;
         bd::Cursor c;
         return bd::host_repair(s, c, true, false, bd::MoveFrom::Previous, 0);
+    });
+}
+
+int bd_set_graph_mode(bd_sim *sim, int enable) {
+    if (!sim) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] {
+        bd::check(hipStreamSynchronize(s.stream), "sync");
+        s.use_graph = enable != 0;
+        return (int)BD_OK;
     });
 }
 

@@ -1,0 +1,83 @@
+"""Graph mode (``bd_set_graph_mode``): each step replayed from captured HIP
+graphs must give exactly the results of launching the same kernels one by one
+-- positions, angles, the triangulation and every counter -- including steps
+whose round budget runs out and are finished by the host, neighbour-list
+rebuilds, batches, and an adjoint pass whose replays run launch by launch."""
+import numpy as np
+import pytest
+
+from paper_1703_02484_amd import binding, synth
+from tests._checks import tri_set
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _same(a, b):
+    xa, ta, sa, sta = a.state()
+    xb, tb, sb, stb = b.state()
+    assert np.array_equal(xa, xb) and np.array_equal(ta, tb) and sa == sb
+    assert sta == stb
+    assert tri_set(a.triangles()) == tri_set(b.triangles())
+
+
+def _pair(make):
+    a, b = make(), make()
+    b.set_graph_mode(True)
+    return a, b
+
+
+@pytest.mark.parametrize("chunk", [1, 5])
+def test_graph_equals_eager_c2_reduced(chunk):
+    w = synth.make("C2", n=3000)
+    a, b = _pair(lambda: binding.Sim.from_workload(w))
+    for _ in range(20 // chunk):
+        a.step(chunk)
+        b.step(chunk)
+    _same(a, b)
+
+
+def test_graph_equals_eager_with_halts_and_continuations():
+    # dense box and strong noise: budgets run out, the host finishes steps,
+    # budgets adapt (several captured settings)
+    n = 600
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    mk = lambda: binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0,
+                             dt=2e-2, seed=2)
+    a, b = _pair(mk)
+    for _ in range(12):
+        a.step(1)
+        b.step(1)
+        _same(a, b)
+    assert b.state()[3]["overlap_rounds_max"] >= 3
+
+
+def test_graph_equals_eager_verlet():
+    w = synth.make("C3", n=6000)
+    a, b = _pair(lambda: binding.Sim.from_workload(w))
+    a.step(40)
+    b.step(40)
+    _same(a, b)
+    assert b.state()[3]["verlet_rebuilds"] >= 2
+
+
+def test_graph_equals_eager_batch():
+    ws = synth.make_batch(4, seed=3, lo=200, hi=1500)
+    a, b = _pair(lambda: binding.Sim.from_workloads(ws))
+    a.step(15)
+    b.step(15)
+    _same(a, b)
+
+
+def test_graph_forward_gives_same_gradients():
+    w = synth.make("C5", n=700)
+    lamT = np.random.default_rng(2).normal(size=(w.n, 2))
+    out = []
+    for graph in (False, True):
+        g = binding.Sim.from_workload(w)
+        g.set_graph_mode(graph)
+        g.adjoint_begin(9, 4)
+        out.append((g.state()[0], *g.adjoint_backward(lamT)))
+    for u, v in zip(out[0], out[1]):
+        assert np.array_equal(u, v)
