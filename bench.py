@@ -57,6 +57,7 @@ def run_short_range(steps, warmup):
 
     w = synth.make("C3")
     sim = binding.Sim.from_workload(w)
+    sim.set_graph_mode(True)
     sim.step(warmup)
     st0 = sim.state()[3]
     sim.enable_kernel_timing(True)
@@ -95,6 +96,7 @@ def run_batched(steps, warmup, loop_steps):
     ntot = sum(w.n for w in ws)
     pairs = sum(w.n * (w.n - 1) for w in ws)
     b = binding.Sim.from_workloads(ws)
+    b.set_graph_mode(True)
     cfg = b.force_config()
     b.step(warmup)
     st0 = b.state()[3]
@@ -121,6 +123,7 @@ def run_batched(steps, warmup, loop_steps):
     # the same systems, one handle each, stepped one after another
     singles = [binding.Sim.from_workload(w, force_chunk=cfg["chunk"]) for w in ws]
     for s in singles:
+        s.set_graph_mode(True)
         s.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,6 +140,48 @@ def run_batched(steps, warmup, loop_steps):
                               "ms_per_step": 1e3 * el / loop_steps}
     out["speedup_vs_loop"] = out["value"] / out["per_system_loop"]["value"]
     return out
+
+
+def run_adjoint():
+    """Gradient of the species-0 mean squared displacement after 50 steps (N = 16,384, FP64, contact factor 1/2)
+    with respect to K and the initial positions: forward with checkpoints every 10 steps, then the adjoint sweep."""
+    import numpy as np
+    import torch
+
+    from paper_1703_02484_amd import binding, synth
+
+    w = synth.make("C5")
+    warm = binding.Sim.from_workload(w)
+    warm.adjoint_begin(10, 10)
+    warm.adjoint_backward(np.zeros((w.n, 2)))
+    warm.close()
+    plain = binding.Sim.from_workload(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.step(50)
+    plain.state()
+    t_plain = time.perf_counter() - t0
+    plain.close()
+    g = binding.Sim.from_workload(w)
+    t0 = time.perf_counter()
+    g.adjoint_begin(50, 10)
+    xT = g.state()[0]
+    t_fwd = time.perf_counter() - t0
+    s0 = w.species == 0
+    lamT = np.zeros_like(xT)
+    lamT[s0] = 2.0 * (xT[s0] - w.xy[s0]) / s0.sum()
+    t0 = time.perf_counter()
+    g.adjoint_backward(lamT)
+    t_bwd = time.perf_counter() - t0
+    st = g.state()[3]
+    g.close()
+    pairs = w.n * (w.n - 1)
+    return {"workload": f"C5: N={w.n}, S=2, K=1e-2, FP64 all pairs, contact factor 1/2, 50 steps, checkpoints every 10, "
+                        f"loss = MSD of species 0",
+            "forward_plain_s": t_plain, "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd,
+            "backward_over_forward": t_bwd / t_plain,
+            "backward_pair_interactions_per_s": 2 * 50 * pairs / t_bwd,
+            "adjoint_flops_per_pair": 28, "overlap_rounds_forward": st["overlap_rounds_total"]}
 
 
 def cpu_baseline(w):
@@ -158,8 +203,12 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernel by kernel instead of replaying graphs")
     ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the secondary 256-system batched measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the secondary gradient measurement")
+    ap.add_argument("--only", choices=["short_range", "batched", "adjoint"], default=None,
+                    help="run one secondary measurement alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -187,8 +236,22 @@ def main():
         print(json.dumps({"copy_calibration": {"bytes_read_per_dispatch": nbytes, "bytes_written_per_dispatch": nbytes,
                                                "dispatches": 5}}), flush=True)
         return
+    if args.only:
+        fn = {"short_range": lambda: run_short_range(max(10, args.steps // 4), 5),
+              "batched": lambda: run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100)),
+              "adjoint": run_adjoint}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
     w = synth.make(args.workload, n=args.n)
     sim = binding.Sim.from_workload(w)
+    # the same steps launched kernel by kernel, for comparison with the graph replay timed below
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(max(1, args.steps // 4))
+    sim.state()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 4)
+    sim.set_graph_mode(not args.no_graph)
     sim.step(args.warmup)
     st0 = sim.state()[3]
     sim.enable_kernel_timing(True)
@@ -231,6 +294,8 @@ def main():
             "pair_interactions_per_s": pairs / avg_force_s,
             "force_ms_per_step": force_ms / max(launches, 1),
             "other_ms_per_step": ms_per_step - force_ms / max(launches, 1),
+            "graph_mode": not args.no_graph,
+            "eager_ms_per_step": eager_ms,
             "overlap_rounds_per_step": d["overlap_rounds_total"] / args.steps,
             "flips_per_step": d["flips_total"] / args.steps,
             "flip_rounds_per_step": d["flip_rounds_total"] / args.steps,
@@ -258,6 +323,8 @@ def main():
         out["short_range"] = run_short_range(max(10, args.steps // 4), 5)
     if not args.no_batched and args.workload == "C2":
         out["batched"] = run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100))
+    if not args.no_adjoint and args.workload == "C2":
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -109,7 +109,7 @@ typedef struct bd_stats {
     int64_t noise_clamps;           /* clamped normal components */
     int64_t flips_total;            /* edge flips performed on the device */
     int64_t inversion_flips;        /* of which decided by the inverted-triangle rule (Sec. 4.3) */
-    int64_t flip_rounds_total;      /* parallel flip rounds launched */
+    int64_t flip_rounds_total;      /* parallel flip rounds that flipped at least one edge */
     int64_t kinetic_repairs;        /* repairs redone on the device in sub-steps (multi-edge crossings) */
     int64_t host_rebuilds;          /* repairs that fell back to a host triangulation */
     int64_t verlet_rebuilds;        /* neighbour-list rebuilds (cutoff > 0) */

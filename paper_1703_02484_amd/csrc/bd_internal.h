@@ -65,10 +65,16 @@ struct Tile {
 // Per-step values that kernels read from device memory, so that a captured
 // step can be replayed: the noise counter and the bases of the flip-round and
 // overlap-round stamps (kernels receive stamps relative to these bases).
+// In graph mode several steps are queued at once: a step that halts (or
+// needs new neighbour lists) sets `stop`, and the steps queued after it do
+// nothing, so the host finishes that step and resumes exactly there.
 struct StepBase {
     long long step;
     int rbase, vbase;
+    int stop;        // 0 run; 1 the step batch_idx halted; 2 lists must be rebuilt first
+    int batch_idx;   // steps of the current batch completed on the device
 };
+constexpr int kRing = 64;      // most steps queued at once in graph mode
 
 constexpr int MAXACT = 16;    // overlapping partners recorded per disk and round (adjoint tape)
 
@@ -214,6 +220,8 @@ struct Sim {
         std::vector<int> orounds, rep_first;
     };
     std::vector<std::pair<long long, StepGraph>> graphs;
+    int *ring = nullptr;             // [kRing][N_CTL] control block of each queued step
+    int *hring = nullptr;            // pinned mirror
     // control block and accumulators
     int *ctl = nullptr;
     unsigned long long *acc = nullptr;
@@ -237,6 +245,8 @@ struct Sim {
 
 // ---- kernel launchers (k_*.hip) ------------------------------------------
 void launch_cast(Sim &s);
+void launch_step_begin(Sim &s);                       // clear the control block unless the batch stopped
+void launch_step_end(Sim &s, int r_used, int v_used); // record the control block, advance or stop
 void launch_force(Sim &s);
 int force_max_grid(Sim &s, int per_lane);            // resident workgroups of the persistent launch
 void launch_em(Sim &s);

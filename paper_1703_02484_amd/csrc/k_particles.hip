@@ -28,9 +28,9 @@ constexpr int kPerLane = 4;   // particles i per lane (register blocking)
 // ---------------------------------------------------------------- cast
 template <typename T2>
 __global__ void k_cast(int n, const double *__restrict__ x, const double *__restrict__ y,
-                       const int *__restrict__ sorted_id, T2 *__restrict__ pj) {
+                       const int *__restrict__ sorted_id, T2 *__restrict__ pj, const StepBase *__restrict__ base) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k >= n || base->stop) return;
     int i = sorted_id[k];
     T2 v;
     v.x = x[i];
@@ -154,7 +154,9 @@ __device__ __forceinline__ void force_tile(const T2 *__restrict__ pj, const Tile
 // One workgroup per tile.
 template <typename T, typename T2, int P, bool FAST>
 __global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj, const Tile *__restrict__ tiles,
-                                                       T2 *__restrict__ part, LawArgs law) {
+                                                       T2 *__restrict__ part, LawArgs law,
+                                                       const StepBase *__restrict__ base) {
+    if (base->stop) return;
     force_tile<T, T2, P, FAST>(pj, tiles[blockIdx.x], part, law);
 }
 
@@ -166,8 +168,10 @@ template <typename T, typename T2, int P, bool FAST>
 __global__ __launch_bounds__(kForceBlock) void k_force_queue(const T2 *__restrict__ pj,
                                                              const Tile *__restrict__ tiles, int ntiles,
                                                              T2 *__restrict__ part, LawArgs law,
-                                                             int *__restrict__ queue) {
+                                                             int *__restrict__ queue,
+                                                             const StepBase *__restrict__ base) {
     __shared__ int next;
+    if (base->stop) return;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(queue, 1);
         __syncthreads();
@@ -246,6 +250,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
+    if (base->stop) return;
     if (i < a.n) {
         const RepInfo ri = reps[rep_of[i]];
         double fx, fy;
@@ -306,16 +311,56 @@ __global__ void k_zero_one(int *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
+__global__ void k_step_begin(int *__restrict__ ctl, const StepBase *__restrict__ base) {
+    if (base->stop) return;   // keep the halted step's control block for the host
+    for (int i = threadIdx.x; i < N_CTL; i += blockDim.x) ctl[i] = 0;
+}
+
+// End of a queued step: record its control block in the ring (this kernel),
+// then either advance the step counter and the stamp bases, or stop the
+// batch when the step halted (the host finishes it) or needs new neighbour
+// lists (k_step_advance).
+__global__ void k_step_record(const int *__restrict__ ctl, const StepBase *__restrict__ base,
+                              int *__restrict__ ring) {
+    if (base->stop) return;
+    const int idx = base->batch_idx;
+    for (int i = threadIdx.x; i < N_CTL; i += blockDim.x) ring[(size_t)idx * N_CTL + i] = ctl[i];
+}
+
+__global__ void k_step_advance(const int *__restrict__ ctl, StepBase *__restrict__ base, int r_used, int v_used) {
+    if (threadIdx.x != 0 || base->stop) return;
+    if (ctl[K_HALT]) {
+        base->stop = 1;
+        return;
+    }
+    const int idx = base->batch_idx;
+    base->step += 1;
+    base->rbase += r_used;
+    base->vbase += v_used;
+    base->batch_idx = idx + 1;
+    if (ctl[K_NL_REBUILD] || idx + 1 >= kRing) base->stop = 2;
+}
+
 }  // namespace
+
+void launch_step_begin(Sim &s) {
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s.stream, s.ctl, (const StepBase *)s.dbase);
+}
+
+void launch_step_end(Sim &s, int r_used, int v_used) {
+    hipLaunchKernelGGL(k_step_record, dim3(1), dim3(256), 0, s.stream, (const int *)s.ctl,
+                       (const StepBase *)s.dbase, s.ring);
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s.stream, (const int *)s.ctl, s.dbase, r_used, v_used);
+}
 
 void launch_cast(Sim &s) {
     const int nb = blocks_for(s.n, 256);
     if (s.fp32)
         hipLaunchKernelGGL(k_cast<float2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sorted_id,
-                           (float2 *)s.pj);
+                           (float2 *)s.pj, (const StepBase *)s.dbase);
     else
         hipLaunchKernelGGL(k_cast<double2>, dim3(nb), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sorted_id,
-                           (double2 *)s.pj);
+                           (double2 *)s.pj, (const StepBase *)s.dbase);
 }
 
 namespace {
@@ -324,10 +369,10 @@ template <typename T, typename T2, int P, bool FAST>
 void launch_force_t(Sim &s, const LawArgs &law) {
     if (s.persistent) {
         hipLaunchKernelGGL((k_force_queue<T, T2, P, FAST>), dim3(s.force_grid), dim3(kForceBlock), 0, s.stream,
-                           (const T2 *)s.pj, s.tiles, s.ntiles, (T2 *)s.part, law, s.ctl + K_FQUEUE);
+                           (const T2 *)s.pj, s.tiles, s.ntiles, (T2 *)s.part, law, s.ctl + K_FQUEUE, s.dbase);
     } else {
         hipLaunchKernelGGL((k_force<T, T2, P, FAST>), dim3(s.ntiles), dim3(kForceBlock), 0, s.stream,
-                           (const T2 *)s.pj, s.tiles, (T2 *)s.part, law);
+                           (const T2 *)s.pj, s.tiles, (T2 *)s.part, law, s.dbase);
     }
 }
 
@@ -399,11 +444,11 @@ void launch_em(Sim &s) {
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
     if (s.fp32)
-        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, s.dbase, (const float2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, (const float2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
     else
-        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, s.dbase, (const double2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, (const double2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
 }

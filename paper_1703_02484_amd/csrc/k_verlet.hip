@@ -92,10 +92,10 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
                                                   const int *__restrict__ sp, const double *__restrict__ K, int S,
                                                   int kind, double q, double A, double lam, double rc,
                                                   const int *__restrict__ nl, const int *__restrict__ nl_cnt,
-                                                  double2 *__restrict__ f) {
+                                                  double2 *__restrict__ f, const StepBase *__restrict__ base) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || base->stop) return;
     const double xi = x[i], yi = y[i];
     const int si = sp[i];
     const int m = nl_cnt[i];
@@ -165,7 +165,8 @@ void launch_verlet_build(Sim &s) {
 
 void launch_force_nl(Sim &s) {
     hipLaunchKernelGGL(k_force_nl, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sp, s.Kd, s.S,
-                       s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff, s.nl, s.nl_cnt, s.fsr);
+                       s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff, s.nl, s.nl_cnt, s.fsr,
+                       (const StepBase *)s.dbase);
 }
 
 void launch_skin_check(Sim &s) {

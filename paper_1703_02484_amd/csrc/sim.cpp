@@ -205,7 +205,7 @@ bool host_flip_rounds(Sim &s, Cursor &c, bool full, bool reversal, bool *snap) {
         else
             launch_flip_eval_list(s, r, slot);
         read_ctl(s);
-        ++s.st.flip_rounds_total;
+        if (s.hctl[K_CAND + slot] > 0) ++s.st.flip_rounds_total;   // rounds that found an edge to flip
         if (s.hctl[K_TOPO] != 0) return false;
         if (it == 0 && snap && s.hctl[K_INVQ + slot] > 0) {
             launch_snapshot(s);
@@ -390,6 +390,8 @@ void write_base(Sim &s) {
     s.hbase->step = s.step;
     s.hbase->rbase = s.round_id;
     s.hbase->vbase = s.vround;
+    s.hbase->stop = 0;
+    s.hbase->batch_idx = 0;
     check(hipMemcpyAsync(s.dbase, s.hbase, sizeof(StepBase), hipMemcpyHostToDevice, s.stream), "step base");
     s.rbase = s.round_id;
     s.vbase = s.vround;
@@ -441,7 +443,7 @@ Sim::StepGraph &step_graph(Sim &s) {
     Sim::StepGraph g;
     const int r0 = s.round_id, v0 = s.vround;
     g.pre = capture(s, [&] {
-        fill_int(s, s.ctl, N_CTL, 0);
+        launch_step_begin(s);
         if (!s.use_nl) launch_cast(s);
     });
     g.force = capture(s, [&] {
@@ -454,6 +456,7 @@ Sim::StepGraph &step_graph(Sim &s) {
     g.post = capture(s, [&] {
         launch_em(s);
         enqueue_rounds(s, c, g.orounds, g.rep_first);
+        launch_step_end(s, s.round_id - r0, s.vround - v0);
     });
     g.r_used = s.round_id - r0;
     g.v_used = s.vround - v0;
@@ -480,48 +483,106 @@ void timed(Sim &s, const std::function<void()> &work) {
     }
 }
 
-// One step of Algorithm 1.  The whole step is enqueued as a budgeted sequence
-// (force, update, repair rounds, overlap rounds each with its repair) -- as
-// three captured graphs in graph mode -- and the control block is read back
-// once; if a budget ran out or a repair failed, the host finishes the step
-// from exactly that point.
-int one_step(Sim &s) {
+struct StepPlan {
     Cursor c;
-    std::vector<int> rep_first;   // first round slot of each enqueued repair
-    std::vector<int> orounds;
+    std::vector<int> orounds, rep_first;   // overlap-round slot and first round slot of each repair
+    int em_rounds = 0, ovl_rounds = 0, overlaps = 0;   // round budgets the step ran with
+};
+
+int finish_step(Sim &s, const int *h_in, const StepPlan &plan);
+
+// One step of Algorithm 1 launched kernel by kernel: the whole step is
+// enqueued as a budgeted sequence (force, update, repair rounds, overlap
+// rounds each with its repair) and the control block is read back once; if a
+// budget ran out or a repair failed, the host finishes the step from exactly
+// that point.
+int one_step(Sim &s) {
+    StepPlan plan;
     write_base(s);
     if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
-    if (s.use_graph && !s.adj.tape.on) {
-        Sim::StepGraph &g = step_graph(s);
-        check(hipGraphLaunch(g.pre, s.stream), "graph launch");
-        timed(s, [&] { check(hipGraphLaunch(g.force, s.stream), "graph launch"); });
-        check(hipGraphLaunch(g.post, s.stream), "graph launch");
-        s.round_id += g.r_used;
-        s.vround += g.v_used;
-        c.slot = g.c_slot;
-        c.rep = g.c_rep;
-        c.oround = g.c_oround;
-        orounds = g.orounds;
-        rep_first = g.rep_first;
-    } else {
-        fill_int(s, s.ctl, N_CTL, 0);
-        if (s.adj.tape.on) {   // adjoint tape: positions before the step
-            const Tape &tp = s.adj.tape;
-            const size_t off = (size_t)tp.step_idx * s.n, bytes = sizeof(double) * s.n;
-            check(hipMemcpyAsync(tp.px + off, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "tape x");
-            check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
-        }
-        compute_forces(s);
-        launch_em(s);
-        enqueue_rounds(s, c, orounds, rep_first);
+    fill_int(s, s.ctl, N_CTL, 0);
+    if (s.adj.tape.on) {   // adjoint tape: positions before the step
+        const Tape &tp = s.adj.tape;
+        const size_t off = (size_t)tp.step_idx * s.n, bytes = sizeof(double) * s.n;
+        check(hipMemcpyAsync(tp.px + off, s.x, bytes, hipMemcpyDeviceToDevice, s.stream), "tape x");
+        check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
     }
+    compute_forces(s);
+    launch_em(s);
+    plan.em_rounds = s.budget_em_rounds;
+    plan.ovl_rounds = s.budget_ovl_rounds;
+    plan.overlaps = s.budget_overlaps;
+    enqueue_rounds(s, plan.c, plan.orounds, plan.rep_first);
     read_ctl(s);
-    const int *h = s.hctl;
+    return finish_step(s, s.hctl, plan);
+}
+
+// Graph mode: up to kRing steps are queued as graph replays; each records its
+// control block and the first one that halts (or needs new neighbour lists)
+// stops the rest.  The host then does the per-step bookkeeping in order,
+// finishes a halted step exactly where it stopped, and queues the remainder.
+int run_graph_steps(Sim &s, int64_t nsteps) {
+    while (nsteps > 0) {
+        if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
+        Sim::StepGraph &g = step_graph(s);
+        const int m = (int)std::min<int64_t>(nsteps, kRing);
+        write_base(s);
+        for (int k = 0; k < m; ++k) {
+            check(hipGraphLaunch(g.pre, s.stream), "graph launch");
+            timed(s, [&] { check(hipGraphLaunch(g.force, s.stream), "graph launch"); });
+            check(hipGraphLaunch(g.post, s.stream), "graph launch");
+        }
+        StepBase hb;
+        check(hipMemcpyAsync(&s.hbase->step, &s.dbase->step, sizeof(StepBase), hipMemcpyDeviceToHost, s.stream),
+              "step base");
+        check(hipStreamSynchronize(s.stream), "sync");
+        hb = *s.hbase;
+        const int done = hb.batch_idx;
+        const int nrec = done + (hb.stop == 1 ? 1 : 0);
+        check(hipMemcpyAsync(s.hring, s.ring, sizeof(int) * N_CTL * nrec, hipMemcpyDeviceToHost, s.stream), "ring");
+        check(hipStreamSynchronize(s.stream), "sync");
+        StepPlan plan;
+        plan.em_rounds = s.budget_em_rounds;
+        plan.ovl_rounds = s.budget_ovl_rounds;
+        plan.overlaps = s.budget_overlaps;
+        plan.c.slot = g.c_slot;
+        plan.c.rep = g.c_rep;
+        plan.c.oround = g.c_oround;
+        plan.orounds = g.orounds;
+        plan.rep_first = g.rep_first;
+        const int r_used = g.r_used, v_used = g.v_used;   // g may move when budgets change below
+        for (int j = 0; j < nrec; ++j) {
+            // the device's stamp bases for this step, for any host-driven continuation
+            s.rbase = s.round_id;
+            s.vbase = s.vround;
+            s.round_id += r_used;
+            s.vround += v_used;
+            int rc = finish_step(s, s.hring + (size_t)j * N_CTL, plan);
+            if (rc != BD_OK) {
+                write_base(s);
+                return rc;
+            }
+        }
+        nsteps -= nrec;
+        write_base(s);   // clears the stop flag for later work on this handle
+    }
+    return BD_OK;
+}
+
+// Host side of a step whose budgeted part has run: bookkeeping, the
+// continuation of a halted step, budget adaptation.  h_in is the step's
+// control block as read back.
+int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
+    const std::vector<int> hv(h_in, h_in + N_CTL);
+    const int *h = hv.data();
+    const Cursor &c = plan.c;
+    const std::vector<int> &orounds = plan.orounds;
+    const std::vector<int> &rep_first = plan.rep_first;
     s.need_rebuild = s.use_nl && h[K_NL_REBUILD] != 0;
     // bookkeeping of the budgeted part: overlap rounds that moved disks
     int rounds = h[K_OVL_ROUNDS];
     if (h[K_HALT]) {
-        if (h[K_REASON] == HALT_OVERLAP_BUDGET) rounds = s.budget_overlaps;
+        if (h[K_REASON] == HALT_OVERLAP_BUDGET) rounds = plan.overlaps;
         if (h[K_REASON] == HALT_REPAIR_BUDGET || h[K_REASON] == HALT_INVALID) rounds = h[K_STAGE];
     }
     for (int j = 0; j < rounds; ++j) s.st.overlap_edges_total += h[K_OVL + orounds[j]];
@@ -577,14 +638,16 @@ int one_step(Sim &s) {
     const int hreason = h[K_HALT] ? h[K_REASON] : 0;
     // repair slot that stopped the budgeted sequence (none for an overlap budget halt)
     const int halt_rep = (hreason == HALT_REPAIR_BUDGET || hreason == HALT_INVALID) ? h[K_STAGE] : 1 << 30;
+    s.budget_em_rounds = plan.em_rounds;
+    s.budget_ovl_rounds = plan.ovl_rounds;
     if (halt_rep > 0)
-        adapt(s.budget_em_rounds, used_rounds(0, s.budget_em_rounds));
+        adapt(s.budget_em_rounds, used_rounds(0, plan.em_rounds));
     else if (hreason == HALT_REPAIR_BUDGET)
-        adapt(s.budget_em_rounds, s.budget_em_rounds + 2);
+        adapt(s.budget_em_rounds, plan.em_rounds + 2);
     int ovl_used = 0;
     for (int r = 1; r < (int)rep_first.size() && r <= rounds && r < halt_rep; ++r)
-        ovl_used = std::max(ovl_used, used_rounds(r, s.budget_ovl_rounds));
-    if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = s.budget_ovl_rounds + 2;
+        ovl_used = std::max(ovl_used, used_rounds(r, plan.ovl_rounds));
+    if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = plan.ovl_rounds + 2;
     if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used);
     s.budget_overlaps = std::max(2, std::min(8, rounds + 1));
     s.st.overlap_rounds_total += rounds;
@@ -871,6 +934,8 @@ void free_all(Sim &s) {
         if (p) (void)hipFree(p);
     drop_graphs(s);
     if (s.dbase) (void)hipFree(s.dbase);
+    if (s.ring) (void)hipFree(s.ring);
+    if (s.hring) (void)hipHostFree(s.hring);
     if (s.hbase) (void)hipHostFree(s.hbase);
     if (s.hctl) (void)hipHostFree(s.hctl);
     if (s.hacc) (void)hipHostFree(s.hacc);
@@ -1084,6 +1149,9 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.yb = dalloc<double>(n);
     s.ctl = dalloc<int>(N_CTL);
     s.dbase = dalloc<StepBase>(1);
+    s.ring = dalloc<int>((size_t)kRing * N_CTL);
+    if (hipHostMalloc((void **)&s.hring, sizeof(int) * kRing * N_CTL, hipHostMallocDefault) != hipSuccess)
+        throw std::bad_alloc();
     if (hipHostMalloc((void **)&s.hbase, sizeof(StepBase), hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
     if (s.use_nl) {
         const double rl = fp->cutoff + fp->skin;
@@ -1494,6 +1562,7 @@ int bd_step(bd_sim *sim, int64_t nsteps) {
     if (!sim || nsteps < 0) return BD_ERR_INVALID_ARG;
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
+        if (s.use_graph) return bd::run_graph_steps(s, nsteps);
         for (int64_t k = 0; k < nsteps; ++k) {
             int rc = bd::one_step(s);
             if (rc != BD_OK) return rc;

@@ -100,9 +100,9 @@ def test_backward_leaves_state_and_counters():
     assert g.state()[2] == 9
 
 
-def _loss(w, x):
+def _loss(w, x, x0=None):
     s0 = w.species == 0
-    d = x[s0] - w.xy[s0]
+    d = x[s0] - (w.xy if x0 is None else x0)[s0]
     return float(np.sum(d * d) / s0.sum())
 
 
@@ -127,7 +127,7 @@ def test_full_size_c5_against_finite_differences():
         s = binding.Sim(w.xy if x0 is None else x0, w.radii, w.species, w.theta, w.K if K is None else K, L=w.L,
                         D=w.D, dt=w.dt, seed=w.seed, overlap_factor=w.overlap_factor)
         s.step(steps)
-        return _loss(w, s.state()[0])
+        return _loss(w, s.state()[0], x0)
 
     v = np.random.default_rng(6).normal(size=(w.n, 2)) * 1e-2
     gv = np.sum(g0 * v) - np.sum(lamT[s0] * v[s0])   # the loss also holds x0 directly
