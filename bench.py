@@ -120,6 +120,22 @@ def run_batched(steps, warmup, loop_steps):
            "force_config": cfg,
            "overlap_rounds_per_step": (st1["overlap_rounds_total"] - st0["overlap_rounds_total"]) / steps,
            "host_rebuilds": st1["host_rebuilds"]}
+    # the same batch with FP32 pair sums (positions and predicates stay FP64)
+    b32 = binding.Sim.from_workloads(ws, fp32=True)
+    b32.set_graph_mode(True)
+    b32.step(warmup)
+    b32.enable_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b32.step(steps)
+    b32.state()
+    el32 = time.perf_counter() - t0
+    f32_ms, f32_launches = b32.kernel_time()
+    out["fp32"] = {"value": ntot * steps / el32, "unit": "particle-steps/s", "ms_per_step": 1e3 * el32 / steps,
+                   "force_ms": f32_ms / max(f32_launches, 1),
+                   "force_tflops": FLOPS_PER_PAIR * pairs / (f32_ms / 1e3 / max(f32_launches, 1)) / 1e12,
+                   "force_config": b32.force_config()}
+    b32.close()
     # the same systems, one handle each, stepped one after another
     singles = [binding.Sim.from_workload(w, force_chunk=cfg["chunk"]) for w in ws]
     for s in singles:

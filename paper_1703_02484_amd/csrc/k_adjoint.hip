@@ -169,7 +169,11 @@ __device__ __forceinline__ void adj_range(const double4 *__restrict__ pj4, int j
             if (SELF && j == ib + k * kAdjBlock + (int)threadIdx.x) continue;
             const double ux = xi[k] - q.x, uy = yi[k] - q.y;
             const double d2 = ux * ux + uy * uy;
-            const double inv = rsqrt(d2);
+            // d^-1 from the hardware estimate y0, corrected with e = 1 - d2 y0^2:
+            // y0 (1 - e)^-1/2 ~ y0 (1 + e/2 + 3/8 e^2), relative error O(e^3)
+            const double y0 = __builtin_amdgcn_rsq(d2);
+            const double e = fma(-d2, y0 * y0, 1.0);
+            const double inv = y0 * fma(fma(0.375, e, 0.5), e, 1.0);
             const double inv2 = inv * inv;
             const double inv3 = inv2 * inv;
             const double c5 = 3.0 * inv3 * inv2;

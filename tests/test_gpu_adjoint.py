@@ -166,3 +166,34 @@ def test_autograd_function_matches_adjoint_and_gradcheck():
     Kc = torch.tensor(w.K, dtype=torch.float64, requires_grad=True)
     assert torch.autograd.gradcheck(lambda k: bdad.rollout(k, x0.detach(), spec, 4, 2)[:8], (Kc,), eps=1e-6,
                                     atol=1e-6, rtol=1e-4)
+
+
+def test_single_segment_and_single_step():
+    # checkpoint interval longer than the run, and a one-step run
+    w = synth.make("C5", n=300)
+    for steps, every in ((5, 50), (1, 1)):
+        lhs, rhs, _ = _vjp_vs_jvp(w, steps, every, seed=steps)
+        assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_adjoint_of_a_batch_sums_dK_over_systems():
+    ws = synth.make_batch(3, seed=5, lo=150, hi=600)
+    for w in ws:
+        w.K = np.array([[0.02]])
+    b = binding.Sim.from_workloads(ws)
+    b.adjoint_begin(6, 4)
+    _, doff, _ = b.layout()
+    lamT = np.random.default_rng(9).normal(size=(b.n, 2))
+    g0, gK = b.adjoint_backward(lamT)
+    rng = np.random.default_rng(10)
+    total = 0.0
+    tot_lhs = 0.0
+    for r, w in enumerate(ws):
+        o = oracle.OracleSim.from_workload(w, K=np.array([[0.02]]))
+        v = rng.normal(size=(w.n, 2))
+        o.set_tangent(v, np.array([[1.0]]))
+        o.step(6)
+        total += np.sum(lamT[doff[r]:doff[r + 1]] * o.tangent())
+        tot_lhs += np.sum(g0[doff[r]:doff[r + 1]] * v)
+    tot_lhs += gK[0, 0]
+    assert abs(tot_lhs - total) <= 1e-10 * abs(total)

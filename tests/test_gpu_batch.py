@@ -192,3 +192,33 @@ def test_same_shape_handles_share_tiling():
     a.step(5)
     b.step(5)
     assert np.array_equal(a.state()[0], b.state()[0])
+
+
+def test_batch_of_one_equals_plain_handle():
+    w = synth.make("C1", n=700)
+    a = binding.Sim.from_workload(w)
+    b = binding.Sim.from_workloads([w])
+    a.step(12)
+    b.step(12)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    assert tri_set(a.triangles()) == tri_set(b.triangles())
+    assert a.force_config() == b.force_config()
+
+
+def test_batch_of_tiny_systems():
+    # three disks per system (the smallest allowed), boxes of different sides
+    xs, Ls = [], []
+    for r in range(6):
+        L = 8.0 + r
+        xs.append(synth.rsa(3, L, 1.0, seed=100 + r))
+        Ls.append(L)
+    K = np.array([[1e-2]])
+    kw = dict(dt=1e-3)
+    b = binding.Sim.batch(xs, [np.ones(3)] * 6, [np.zeros(3, np.int32)] * 6, None, Ls, list(range(6)), K, **kw)
+    b.step(20)
+    xb = b.state()[0]
+    _, doff, _ = b.layout()
+    for r in range(6):
+        o = oracle.OracleSim(xs[r], np.ones(3), np.zeros(3, np.int32), None, K, L=Ls[r], seed=r, **kw)
+        o.step(20)
+        assert rel_err(xb[doff[r]:doff[r + 1]], o.state()[0]) <= 1e-9, r
