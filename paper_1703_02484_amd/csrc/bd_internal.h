@@ -33,7 +33,9 @@ enum Ctl {
     K_TAPE_ENT = 11,   // adjoint tape: entries recorded by the overlap rounds of this step
     K_TAPE_DIR = 12,   // adjoint tape: overlap rounds recorded in this step
     K_TAPE_OVF = 13,   // adjoint tape: 1 = capacity exceeded, 2 = a disk had more than MAXACT partners
-    K_CAND = 14,                     // [MAXR] flip candidates of round slot j
+    K_FL_N = 14,       // edges flipped since the last overlap detection (list length)
+    K_FL_EPOCH = 15,   // stamp of the last overlap detection (dedupes that list)
+    K_CAND = 16,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -200,7 +202,10 @@ struct Sim {
     int *wl[2] = {nullptr, nullptr};   // worklists; round slot j reads wl[j & 1]
     int2 *cand = nullptr;
     int *cand_won = nullptr;
-    int *touched = nullptr;
+    int *touched = nullptr;          // [2][n] disks queued by an overlap round, by round parity
+    int *det_stamp = nullptr;        // [H] edge tested by the current local overlap detection
+    int *fl_stamp = nullptr;         // [H] edge recorded in the flipped list in the current epoch
+    int *fl = nullptr;               // [H/2 + 64] edges flipped since the last overlap detection
     double2 *newpos = nullptr;
     double2 *oldpos = nullptr;       // positions of touched disks before an overlap round
     // repair fallback: topology snapshot and the move it must replay
@@ -266,7 +271,9 @@ void launch_repair_check(Sim &s, int rep, int last);
 void launch_snapshot(Sim &s);
 // overlap correction (k: overlap-round slot)
 void launch_ovl_detect(Sim &s, int vstamp, int k);
-void launch_ovl_check(Sim &s, int k);
+// detection after round kprev: only edges at disks moved by round kprev and edges flipped since
+void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev);
+void launch_ovl_check(Sim &s, int k, int vstamp);
 void launch_final_check(Sim &s, int k);
 void launch_ovl_gather(Sim &s, int k);
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot);

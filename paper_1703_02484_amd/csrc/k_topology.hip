@@ -55,7 +55,8 @@ struct Topo {
     int2 *cand;
     int *cand_won;
     int *wl0, *wl1;
-    int *touched;
+    int *touched;           // [2][n], by overlap-round parity
+    int *det_stamp, *fl_stamp, *fl;
     double2 *newpos, *oldpos;
     int *ctl;
     unsigned long long *acc;
@@ -94,6 +95,9 @@ Topo topo_of(Sim &s) {
     t.wl0 = s.wl[0];
     t.wl1 = s.wl[1];
     t.touched = s.touched;
+    t.det_stamp = s.det_stamp;
+    t.fl_stamp = s.fl_stamp;
+    t.fl = s.fl;
     t.newpos = s.newpos;
     t.oldpos = s.oldpos;
     t.ctl = s.ctl;
@@ -116,6 +120,8 @@ Topo topo_of(Sim &s) {
 }
 
 __device__ __forceinline__ bool stopped(const int *ctl) { return (ctl[K_HALT] | ctl[K_DONE]) != 0; }
+// Disks queued by overlap round k (two buffers, so a round can read the previous round's list).
+__device__ __forceinline__ int *touched_of(const Topo &t, int k) { return t.touched + (size_t)(k & 1) * t.n; }
 __device__ __forceinline__ int *wl_of(const Topo &t, int slot) { return (slot & 1) ? t.wl1 : t.wl0; }
 
 // Range guards: a corrupt triangulation must never turn into an out-of-bounds
@@ -233,6 +239,7 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
     round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
+    const int epoch = t.ctl[K_FL_EPOCH];
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
         const int2 cd = t.cand[idx];
         const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
@@ -282,6 +289,9 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
         t.vert_he[c] = s1 + 0;
         t.vert_he[d] = s2 + 0;
         t.cand_won[idx] = 1;
+        // the new diagonal joins two disks that may never have been tested for overlap
+        const int e = s1 + 2 < s2 + 2 ? s1 + 2 : s2 + 2;
+        if (atomicExch(&t.fl_stamp[e], epoch) != epoch) t.fl[atomicAdd(&t.ctl[K_FL_N], 1)] = e;
         atomicAdd(&t.acc[A_FLIPS], 1ull);
         if (cd.y & (int)0x80000000) atomicAdd(&t.acc[A_INV_FLIPS], 1ull);
     }
@@ -369,7 +379,7 @@ __global__ void k_repair_check(int *ctl, int rep, int last) {
 __device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, int k) {
     if (atomicExch(&t.vstamp[v], stamp) != stamp) {
         int pos = atomicAdd(&t.ctl[K_TOUCH + k], 1);
-        t.touched[pos] = v;
+        touched_of(t, k)[pos] = v;
     }
 }
 
@@ -402,9 +412,72 @@ __global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
     if (found) atomicAdd(&t.ctl[K_OVL + k], found);
 }
 
-// Overlap round k found nothing: the overlap loop of this step is done.
-__global__ void k_ovl_check(int *ctl, int k) {
+// Detection after overlap round kprev of the same step.  A Delaunay edge can
+// only overlap now if one of its disks moved in round kprev (every disk of an
+// edge that overlapped at round kprev's detection moved) or if a flip since
+// that detection created it; every other edge was tested then and neither of
+// its disks has moved.  So only the stars of the disks moved by round kprev
+// and the flipped list are tested, each edge once (det_stamp).
+__device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, double keep, int k, int &found) {
+    const int tw = t.he_twin[h];
+    if (bad_he(t, tw)) return topo_err(t);
+    const int e = h < tw ? h : tw;
+    if (atomicExch(&t.det_stamp[e], stamp) == stamp) return;
+    const int a = t.he_v[e], b = t.he_v[bd_next(e)];
+    if (bad_v(t, a) || bad_v(t, b)) return topo_err(t);
+    if (a >= t.n || b >= t.n) return;
+    const double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
+    const double d = sqrt(dx * dx + dy * dy);
+    if (d < (t.rad[a] + t.rad[b]) * keep) {
+        ++found;
+        mark_touched(t, a, stamp, k);
+        mark_touched(t, b, stamp, k);
+    }
+}
+
+__global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev) {
+#pragma clang fp contract(off)
+    if (stopped(t.ctl)) return;
+    stamp += t.base->vbase;
+    const int nprev = t.ctl[K_TOUCH + kprev];
+    const int nfl = t.ctl[K_FL_N];
+    const int *prev = touched_of(t, kprev);
+    int found = 0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nprev + nfl; idx += gridDim.x * blockDim.x) {
+        if (idx >= nprev) {
+            const int e = t.fl[idx - nprev];
+            if (bad_he(t, e)) {
+                topo_err(t);
+                continue;
+            }
+            detect_edge(t, e, stamp, keep, k, found);
+            continue;
+        }
+        const int v = prev[idx];
+        const int h0 = t.vert_he[v];
+        if (bad_he(t, h0)) {
+            topo_err(t);
+            continue;
+        }
+        int h = h0, guard = 0;
+        do {
+            detect_edge(t, h, stamp, keep, k, found);
+            h = t.he_twin[bd_prev(h)];
+            if (bad_he(t, h) || ++guard > 4096) {
+                topo_err(t);
+                break;
+            }
+        } while (h != h0);
+    }
+    if (found) atomicAdd(&t.ctl[K_OVL + k], found);
+}
+
+// Overlap round k found nothing: the overlap loop of this step is done.  The
+// flipped list restarts for the edges flipped after this detection.
+__global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
     if (stopped(ctl)) return;
+    ctl[K_FL_N] = 0;
+    ctl[K_FL_EPOCH] = stamp + base->vbase;
     if (ctl[K_TOPO] != 0) {
         ctl[K_REASON] = HALT_TOPOLOGY;
         ctl[K_STAGE] = k;
@@ -433,8 +506,9 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
     const int ntouched = t.ctl[K_TOUCH + k];
+    const int *touched = touched_of(t, k);
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
-        const int v = t.touched[idx];
+        const int v = touched[idx];
         const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
         const double L = t.Lr[t.rep_of[v]];
         t.newpos[idx] = make_double2(xv, yv);
@@ -532,8 +606,9 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
         t.ctl[K_TAPE_ENT] += ntouched;
         t.ctl[K_TAPE_DIR] += 1;
     }
+    const int *touched = touched_of(t, k);
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
-        const int v = t.touched[idx];
+        const int v = touched[idx];
         const double2 np = t.newpos[idx];
         t.oldpos[idx] = make_double2(t.x[v], t.y[v]);
         ((double *)t.x)[v] = np.x;
@@ -577,8 +652,9 @@ __global__ void k_snapshot(Topo t, int *snap_v, int *snap_twin, int *snap_vh, in
 
 __global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
     const int ntouched = t.ctl[K_TOUCH + k];
+    const int *touched = touched_of(t, k);
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
-        const int v = t.touched[idx];
+        const int v = touched[idx];
         xa[v] = t.oldpos[idx].x;
         ya[v] = t.oldpos[idx].y;
     }
@@ -648,8 +724,16 @@ void launch_ovl_detect(Sim &s, int vstamp, int k) {
                        1.0 - s.p.contact_tol, k);
 }
 
-void launch_ovl_check(Sim &s, int k) {
-    hipLaunchKernelGGL(k_ovl_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k);
+void launch_ovl_check(Sim &s, int k, int vstamp) {
+    hipLaunchKernelGGL(k_ovl_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k, vstamp - s.vbase,
+                       (const StepBase *)s.dbase);
+}
+
+void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev) {
+    vstamp -= s.vbase;
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_ovl_detect_local, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, vstamp,
+                       1.0 - s.p.contact_tol, k, kprev);
 }
 
 void launch_final_check(Sim &s, int k) {

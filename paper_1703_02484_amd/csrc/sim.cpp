@@ -401,11 +401,19 @@ void write_base(Sim &s) {
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
     enqueue_repair(s, c, true, true, s.budget_em_rounds, &rep_first);
+    // the first detection after the move scans every edge, later ones only what round k-1 changed
+    auto detect = [&](int k) {
+        const int stamp = ++s.vround;
+        if (orounds.size() == 1)
+            launch_ovl_detect(s, stamp, k);
+        else
+            launch_ovl_detect_local(s, stamp, k, orounds[orounds.size() - 2]);
+        launch_ovl_check(s, k, stamp);
+    };
     for (int j = 0; j < s.budget_overlaps; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);
-        launch_ovl_detect(s, ++s.vround, k);
-        launch_ovl_check(s, k);
+        detect(k);
         launch_ovl_gather(s, k);
         launch_ovl_apply(s, k, s.round_id + 1, c.slot);
         enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first);
@@ -413,8 +421,7 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
     {
         const int k = c.take_oround();
         orounds.push_back(k);
-        launch_ovl_detect(s, ++s.vround, k);
-        launch_ovl_check(s, k);
+        detect(k);
         launch_final_check(s, k);
     }
     skin_check(s, false);
@@ -927,7 +934,7 @@ void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
-                    s.touched, s.newpos, s.oldpos, s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
+                    s.touched, s.det_stamp, s.fl_stamp, s.fl, s.newpos, s.oldpos, s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
                     s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
     for (void *p : ptrs)
@@ -1137,7 +1144,10 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.wl[1] = dalloc<int>(s.H);
     s.cand = dalloc<int2>(s.H / 2 + 64);
     s.cand_won = dalloc<int>(s.H / 2 + 64);
-    s.touched = dalloc<int>(n);
+    s.touched = dalloc<int>(2 * (size_t)n);
+    s.det_stamp = dalloc<int>(s.H);
+    s.fl_stamp = dalloc<int>(s.H);
+    s.fl = dalloc<int>(s.H / 2 + 64);
     s.newpos = dalloc<double2>(n);
     s.oldpos = dalloc<double2>(n);
     s.snap_v = dalloc<int>(s.H);
@@ -1194,6 +1204,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     check(hipMemsetAsync(s.claim, 0, sizeof(unsigned long long) * s.T, s.stream), "claim");
     check(hipMemsetAsync(s.tri_stamp, 0, sizeof(int) * s.T, s.stream), "tri_stamp");
     check(hipMemsetAsync(s.edge_stamp, 0, sizeof(int) * s.H, s.stream), "edge_stamp");
+    check(hipMemsetAsync(s.det_stamp, 0, sizeof(int) * s.H, s.stream), "det_stamp");
+    check(hipMemsetAsync(s.fl_stamp, 0xFF, sizeof(int) * s.H, s.stream), "fl_stamp");
     check(hipMemsetAsync(s.vstamp, 0, sizeof(int) * (n + 1), s.stream), "vstamp");
     check(hipMemsetAsync(s.acc, 0, sizeof(unsigned long long) * N_ACC, s.stream), "acc");
     check(hipMemsetAsync(s.ctl, 0, sizeof(int) * N_CTL, s.stream), "ctl");
