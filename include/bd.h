@@ -280,8 +280,9 @@ int bd_kernel_time(bd_sim *sim, double *force_ms, int64_t *force_launches);
  * from its checkpoint (recomputation instead of storing every step), records
  * what the reverse sweep needs, and sweeps it backwards; the handle is left
  * at the final step with its counters unchanged.  It may be called again
- * with another grad_xy.  Device memory: one checkpoint per segment plus the
- * positions of one segment.
+ * with another grad_xy.  Device memory: one checkpoint per segment, the
+ * positions of one segment and, when they fit in 8 GiB, the force partial
+ * sums of one segment (otherwise the sweep recomputes them).
  */
 int bd_adjoint_begin(bd_sim *sim, int64_t nsteps, int32_t checkpoint_every);
 int bd_adjoint_backward(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K);

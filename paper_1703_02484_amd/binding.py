@@ -21,8 +21,8 @@ BD_PREC_FP32 = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
-            "bd_set_positions", "bd_set_graph_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time", "bd_adjoint_begin",
-            "bd_adjoint_backward", "bd_destroy")
+            "bd_set_positions", "bd_set_graph_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
+            "bd_adjoint_begin", "bd_adjoint_backward", "bd_destroy")
 
 
 class ForceParams(ctypes.Structure):

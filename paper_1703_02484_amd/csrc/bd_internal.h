@@ -98,6 +98,8 @@ struct Tape {
     int *ecnt = nullptr;                   // [cap_ent] overlapping partners
     int *enb = nullptr;                    // [cap_ent][MAXACT] their ids, in summation order
     int2 *dir = nullptr;                   // [cap_dir] (first entry, count) of each round
+    void *phi = nullptr;                   // [cap_steps][part_cap] force partial sums of each step, or
+                                           // null (then the sweep recomputes them)
     std::vector<int> step_dir_end;         // rounds recorded up to the end of each step
 };
 

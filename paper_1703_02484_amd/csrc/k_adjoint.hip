@@ -275,14 +275,17 @@ void launch_adj_step(Sim &s, int t) {
     else
         hipLaunchKernelGGL(k_adj_cast<double2>, dim3(nb), dim3(kAdjBlock), 0, s.stream, s.n, px, py, a.lam,
                            s.sorted_id, a.pj4, (double2 *)s.pj);
-    launch_force(s);   // Phi at the positions before the step
+    // Phi at the positions before the step: kept by the replay, else recomputed
+    const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
+    const void *phi = tp.phi ? (const char *)tp.phi + (size_t)t * s.part_cap * vec : s.part;
+    if (!tp.phi) launch_force(s);
     if (s.fp32)
         hipLaunchKernelGGL(k_adj_dk_rows<float2>, dim3(nb), dim3(kAdjBlock), 0, s.stream, s.n, s.S,
-                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.pos_of, a.lam, s.p.dt,
+                           (const float2 *)phi, s.reps, s.rep_of, s.chunk_spec, s.pos_of, a.lam, s.p.dt,
                            a.dk_rows);
     else
         hipLaunchKernelGGL(k_adj_dk_rows<double2>, dim3(nb), dim3(kAdjBlock), 0, s.stream, s.n, s.S,
-                           (const double2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.pos_of, a.lam, s.p.dt,
+                           (const double2 *)phi, s.reps, s.rep_of, s.chunk_spec, s.pos_of, a.lam, s.p.dt,
                            a.dk_rows);
     hipLaunchKernelGGL(k_adj_dk_blocks, dim3(nblocks((long long)a.dk_blocks * s.S * s.S)), dim3(kAdjBlock), 0,
                        s.stream, s.n, s.S, a.dk_blocks, s.sp, a.dk_rows, a.dk_blk);

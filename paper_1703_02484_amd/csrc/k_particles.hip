@@ -252,7 +252,8 @@ struct EmArgs {
 // translation, stream 1: rotation), move, reflect at the walls, keep the
 // previous state for the reversal check and for error rollback.
 template <typename T2>
-__global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict__ base, const T2 *__restrict__ part, const RepInfo *__restrict__ reps,
+__global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict__ base, const T2 *__restrict__ part,
+                                            const RepInfo *__restrict__ reps,
                                             const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
                                             const double *__restrict__ K, const int *__restrict__ pos_of,
                                             const int *__restrict__ sp, const double *__restrict__ rad,
@@ -458,11 +459,13 @@ void launch_em(Sim &s) {
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
     if (s.fp32)
-        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, (const float2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
+                           (const float2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
     else
-        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, (const double2 *)s.part, s.reps,
+        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
+                           (const double2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
                            s.acc, s.use_nl ? s.fsr : nullptr, wf);
 }

@@ -315,7 +315,8 @@ void verlet_rebuild(Sim &s) {
             s.need_rebuild = false;
             return;
         }
-        if (need > 96 || s.nl_cap >= 96) throw DeviceError{hipErrorInvalidValue, "neighbour list capacity (96) exceeded"};
+        if (need > 96 || s.nl_cap >= 96)
+            throw DeviceError{hipErrorInvalidValue, "neighbour list capacity (96) exceeded"};
         check(hipFree(s.nl), "free nl");
         s.nl = nullptr;
         drop_graphs(s);   // captured steps hold the old list pointer
@@ -515,6 +516,12 @@ int one_step(Sim &s) {
         check(hipMemcpyAsync(tp.py + off, s.y, bytes, hipMemcpyDeviceToDevice, s.stream), "tape y");
     }
     compute_forces(s);
+    if (s.adj.tape.on && s.adj.tape.phi) {   // adjoint tape: the step's force partial sums
+        const size_t bytes = (size_t)s.part_cap * (s.fp32 ? sizeof(float2) : sizeof(double2));
+        check(hipMemcpyAsync((char *)s.adj.tape.phi + (size_t)s.adj.tape.step_idx * bytes, s.part, bytes,
+                             hipMemcpyDeviceToDevice, s.stream),
+              "tape phi");
+    }
     launch_em(s);
     plan.em_rounds = s.budget_em_rounds;
     plan.ovl_rounds = s.budget_ovl_rounds;
@@ -934,7 +941,8 @@ void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
-                    s.touched, s.det_stamp, s.fl_stamp, s.fl, s.newpos, s.oldpos, s.snap_v, s.snap_twin, s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
+                    s.touched, s.det_stamp, s.fl_stamp, s.fl, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
+                    s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
                     s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
     for (void *p : ptrs)
@@ -960,7 +968,8 @@ bool finite(double v) { return std::isfinite(v); }
 int validate_params(const bd_force_params *fp, const bd_params *p, std::string &err) {
     if (!fp || !p) return err = "NULL argument", BD_ERR_INVALID_ARG;
     if (fp->S < 1 || fp->S > BD_MAX_SPECIES || !fp->K) return err = "S out of range or K NULL", BD_ERR_INVALID_ARG;
-    if (fp->kind != BD_FORCE_POWER && fp->kind != BD_FORCE_SCREENED) return err = "unknown force kind", BD_ERR_INVALID_ARG;
+    if (fp->kind != BD_FORCE_POWER && fp->kind != BD_FORCE_SCREENED)
+        return err = "unknown force kind", BD_ERR_INVALID_ARG;
     for (int k = 0; k < fp->S * fp->S; ++k)
         if (!finite(fp->K[k])) return err = "K has a non-finite entry", BD_ERR_INVALID_ARG;
     if (!finite(fp->q) || !finite(fp->A) || !finite(fp->lambda) || !finite(fp->cutoff) || !finite(fp->skin))
@@ -987,7 +996,8 @@ int validate_system(int n, const double *xy, const double *radii, const int32_t 
     if (!finite(L) || !(L > 0)) return err = "box side must be finite and > 0", BD_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) {
         double r = radii[i], x = xy[2 * i], y = xy[2 * i + 1];
-        if (!finite(r) || !(r > 0) || !finite(x) || !finite(y)) return err = "bad radius or position", BD_ERR_INVALID_ARG;
+        if (!finite(r) || !(r > 0) || !finite(x) || !finite(y))
+            return err = "bad radius or position", BD_ERR_INVALID_ARG;
         if (species[i] < 0 || species[i] >= S) return err = "species out of range", BD_ERR_INVALID_ARG;
         if (theta && !finite(theta[i])) return err = "non-finite theta", BD_ERR_INVALID_ARG;
         if (x < r || x > L - r || y < r || y > L - r) return err = "disk outside the walls", BD_ERR_BAD_INPUT;
@@ -1018,7 +1028,8 @@ int validate_system(int n, const double *xy, const double *radii, const int32_t 
 int validate_batch(int R, const int32_t *n_per, const double *xy, const double *radii, const int32_t *species,
                    const double *theta, const double *L_per, const bd_force_params *fp, const bd_params *p,
                    std::string &err) {
-    if (R < 1 || !n_per || !xy || !radii || !species || !L_per) return err = "NULL argument or R < 1", BD_ERR_INVALID_ARG;
+    if (R < 1 || !n_per || !xy || !radii || !species || !L_per)
+        return err = "NULL argument or R < 1", BD_ERR_INVALID_ARG;
     int rc = validate_params(fp, p, err);
     if (rc != BD_OK) return rc;
     if (R > 1 && fp->cutoff > 0) return err = "short-range forces need one system per handle", BD_ERR_INVALID_ARG;
@@ -1181,7 +1192,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
         s.scan_tmp = dalloc<char>(s.scan_bytes);
     }
     s.acc = dalloc<unsigned long long>(N_ACC);
-    if (hipHostMalloc((void **)&s.hctl, sizeof(int) * N_CTL, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+    if (hipHostMalloc((void **)&s.hctl, sizeof(int) * N_CTL, hipHostMallocDefault) != hipSuccess)
+        throw std::bad_alloc();
     if (hipHostMalloc((void **)&s.hacc, sizeof(unsigned long long) * N_ACC, hipHostMallocDefault) != hipSuccess)
         throw std::bad_alloc();
 
@@ -1290,7 +1302,7 @@ void ck_restore(Sim &s, const Checkpoint &c) {
 }
 
 void tape_free(Tape &tp) {
-    void *ptrs[] = {tp.px, tp.py, tp.emwf, tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir};
+    void *ptrs[] = {tp.px, tp.py, tp.emwf, tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir, tp.phi};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     tp = Tape();
@@ -1360,6 +1372,12 @@ int adjoint_begin(Sim &s, int64_t nsteps, int every) {
     tp.py = dalloc<double>((size_t)every * n);
     tp.emwf = dalloc<signed char>((size_t)every * 2 * n);
     tape_alloc_rounds(tp, std::max(4096, 2 * n), std::max(256, 64 * every));
+    // keep each step's force partial sums when they fit in 8 GiB (else the sweep recomputes them)
+    const size_t phi_bytes = (size_t)every * s.part_cap * (s.fp32 ? sizeof(float2) : sizeof(double2));
+    if (phi_bytes <= (8ull << 30)) {
+        void *p = nullptr;
+        if (hipMalloc(&p, phi_bytes) == hipSuccess) tp.phi = p;
+    }
     a.ready = true;
     return BD_OK;
 }
