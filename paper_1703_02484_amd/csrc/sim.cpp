@@ -40,6 +40,11 @@ struct DeviceError {
     const char *what;
 };
 
+// A request the library cannot serve (reported as BD_ERR_INVALID_ARG).
+struct UnsupportedError {
+    const char *what;
+};
+
 inline void check(hipError_t e, const char *what) {
     if (e != hipSuccess) throw DeviceError{e, what};
 }
@@ -316,7 +321,7 @@ void verlet_rebuild(Sim &s) {
             return;
         }
         if (need > 96 || s.nl_cap >= 96)
-            throw DeviceError{hipErrorInvalidValue, "neighbour list capacity (96) exceeded"};
+            throw UnsupportedError{"more than 96 disks within cutoff + skin of one disk (neighbour list capacity)"};
         check(hipFree(s.nl), "free nl");
         s.nl = nullptr;
         drop_graphs(s);   // captured steps hold the old list pointer
@@ -1478,6 +1483,9 @@ int guarded(Sim &s, F &&f) {
     } catch (const DeviceError &e) {
         s.last_error = std::string(e.what) + ": " + hipGetErrorString(e.e);
         return BD_ERR_DEVICE;
+    } catch (const UnsupportedError &e) {
+        s.last_error = e.what;
+        return BD_ERR_INVALID_ARG;
     } catch (const std::bad_alloc &) {
         s.last_error = "out of memory";
         return BD_ERR_OOM;

@@ -307,3 +307,26 @@ def test_full_size_c3_verlet():
     check_delaunay(np.concatenate([x, g.frame()]), g.triangles())
     assert count_overlaps(x) == 0
     assert st["host_rebuilds"] == 0
+
+
+def test_verlet_list_capacity_grows():
+    # cutoff 7 + skin 1 at phi = 0.5: about 32 neighbours per disk, more than the
+    # initial list capacity; the build grows the lists once and forces stay exact
+    w = synth.make("C3", n=3000)
+    g = binding.Sim.from_workload(w, cutoff=7.0, skin=1.0)
+    fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=7.0)
+    fg = g.forces()
+    assert np.abs(fg - fo).max() <= 1e-12 * _force_scale(fo)
+    g.step(5)
+    o = oracle.OracleSim.from_workload(w, cutoff=7.0)
+    o.step(5)
+    assert rel_err(g.state()[0], o.state()[0]) <= 1e-9
+
+
+def test_verlet_list_capacity_exceeded_is_an_error(capfd):
+    # cutoff 15: over 96 neighbours per disk, beyond the largest list capacity
+    w = synth.make("C3", n=3000)
+    with pytest.raises(binding.BDError) as e:
+        binding.Sim.from_workload(w, cutoff=15.0, skin=1.0)
+    assert e.value.code == -1
+    assert "capacity" in capfd.readouterr().err
