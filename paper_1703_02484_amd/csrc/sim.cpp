@@ -454,7 +454,11 @@ Sim::StepGraph &step_graph(Sim &s) {
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
     Sim::StepGraph g;
+    // stamps inside the graph count from the base of the step it is replayed for
     const int r0 = s.round_id, v0 = s.vround;
+    const int rbase_live = s.rbase, vbase_live = s.vbase;
+    s.rbase = r0;
+    s.vbase = v0;
     g.pre = capture(s, [&] {
         launch_step_begin(s);
         if (!s.use_nl) launch_cast(s);
@@ -478,6 +482,8 @@ Sim::StepGraph &step_graph(Sim &s) {
     g.c_oround = c.oround;
     s.round_id = r0;   // capturing ran nothing
     s.vround = v0;
+    s.rbase = rbase_live;
+    s.vbase = vbase_live;
     s.graphs.emplace_back(key, std::move(g));
     return s.graphs.back().second;
 }

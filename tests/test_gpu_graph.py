@@ -81,3 +81,24 @@ def test_graph_forward_gives_same_gradients():
         out.append((g.state()[0], *g.adjoint_backward(lamT)))
     for u, v in zip(out[0], out[1]):
         assert np.array_equal(u, v)
+
+
+def test_switching_modes_midway():
+    # launch-by-launch steps, then graph batches, then launch-by-launch again, in a
+    # dense box where steps halt and the host finishes them: identical to all-eager
+    n = 600
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=9)
+    mk = lambda: binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0,
+                             dt=2e-2, seed=4)
+    a, b = mk(), mk()
+    a.step(5)
+    b.step(5)
+    b.set_graph_mode(True)
+    a.step(10)
+    b.step(10)
+    _same(a, b)
+    b.set_graph_mode(False)
+    a.step(3)
+    b.step(3)
+    _same(a, b)
