@@ -203,6 +203,13 @@ int bd_forces(bd_sim *sim, double *f_out);
 int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
 
 /*
+ * Positions (2n doubles, x and y interleaved, caller order) and angles (n
+ * doubles) into device memory of the handle's GPU (either may be NULL);
+ * returns when they are written.
+ */
+int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out);
+
+/*
  * Finite triangles of the resident triangulation, counter-clockwise: 3 int32
  * per triangle into tri_out (room for cap triangles; 2 (n + m) is always
  * enough), count into *ntri_out.  Ids 0..n-1 are disks in caller order; ids
@@ -246,6 +253,16 @@ int bd_set_positions(bd_sim *sim, const double *xy);
  */
 int bd_set_graph_mode(bd_sim *sim, int enable);
 
+/*
+ * Device memory of handles created after this call comes from alloc_fn /
+ * free_fn (called with the handle's stream and ctx), e.g. a framework's
+ * caching allocator; NULL for both restores hipMalloc / hipFree.  A handle
+ * keeps the allocator it was created with.  Pinned host staging buffers are
+ * always hipHostMalloc'd.  BD_ERR_INVALID_ARG if only one function is given.
+ */
+int bd_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
+                     void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx);
+
 /* Runs later work on hip_stream (a hipStream_t; NULL = the library's own stream). */
 int bd_set_stream(bd_sim *sim, void *hip_stream);
 
@@ -286,6 +303,8 @@ int bd_kernel_time(bd_sim *sim, double *force_ms, int64_t *force_launches);
  */
 int bd_adjoint_begin(bd_sim *sim, int64_t nsteps, int32_t checkpoint_every);
 int bd_adjoint_backward(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K);
+/* The same with all three arrays in device memory of the handle's GPU; returns when they are written. */
+int bd_adjoint_backward_dev(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K);
 
 /* Frees everything; accepts NULL. */
 void bd_destroy(bd_sim *sim);

@@ -36,16 +36,32 @@ class RolloutSpec:
 
 
 class Rollout(torch.autograd.Function):
+    """Host tensors go through host copies; CUDA tensors (float64, on the handle's GPU) are read and
+    written in place through the device-pointer entry points."""
+
     @staticmethod
     def forward(ctx, K, x0, spec, nsteps, every):
         sim = binding.Sim(x0.detach().cpu().numpy(), spec.radii, spec.species, spec.theta,
                           K.detach().cpu().numpy(), **spec.params)
         sim.adjoint_begin(int(nsteps), int(every))
         ctx.sim = sim
+        if x0.is_cuda:
+            xT = torch.empty(x0.shape, dtype=torch.float64, device=x0.device)
+            torch.cuda.current_stream(x0.device).synchronize()   # xT's memory is free on torch's stream
+            sim.state_dev(xT.data_ptr())
+            return xT
         return torch.from_numpy(sim.state()[0])
 
     @staticmethod
     def backward(ctx, grad):
+        if grad.is_cuda:
+            g = grad.detach().to(torch.float64).contiguous()
+            g0 = torch.empty_like(g)
+            S = ctx.sim._S
+            gK = torch.empty((S, S), dtype=torch.float64, device=g.device)
+            torch.cuda.current_stream(g.device).synchronize()   # grad is complete before the library reads it
+            ctx.sim.adjoint_backward_dev(g.data_ptr(), g0.data_ptr(), gK.data_ptr())
+            return gK, g0, None, None, None
         g0, gK = ctx.sim.adjoint_backward(grad.detach().cpu().contiguous().numpy())
         return torch.from_numpy(gK), torch.from_numpy(g0), None, None, None
 
@@ -57,6 +73,6 @@ def rollout(K: torch.Tensor, x0: torch.Tensor, spec: RolloutSpec, nsteps: int, e
 
 def msd_loss(xT: torch.Tensor, x0: torch.Tensor, species: np.ndarray, s: int = 0) -> torch.Tensor:
     """Mean squared displacement of the particles of species s."""
-    mask = torch.from_numpy(np.asarray(species) == s)
+    mask = torch.from_numpy(np.asarray(species) == s).to(xT.device)
     d = xT[mask] - x0[mask]
     return (d * d).sum() / mask.sum()

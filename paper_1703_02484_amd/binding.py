@@ -22,7 +22,8 @@ BD_PREC_FP32 = 1
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
             "bd_set_positions", "bd_set_graph_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
-            "bd_adjoint_begin", "bd_adjoint_backward", "bd_destroy")
+            "bd_adjoint_begin", "bd_adjoint_backward", "bd_adjoint_backward_dev", "bd_get_state_dev",
+            "bd_set_allocator", "bd_destroy")
 
 
 class ForceParams(ctypes.Structure):
@@ -69,6 +70,35 @@ class BDError(RuntimeError):
 
 
 _lib = None
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = None   # keeps the installed callbacks alive
+
+
+def use_torch_allocator(enable: bool = True):
+    """Device memory of handles created from now on comes from torch's caching allocator (or hipMalloc again)."""
+    global _allocator_refs
+    lib = load()
+    if not enable:
+        lib.bd_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
+        _allocator_refs = None
+        return
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:   # out of memory: the library reports BD_ERR_OOM
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    rc = lib.bd_set_allocator(refs[0], refs[1], None)
+    if rc != 0:
+        raise BDError(rc, "bd_set_allocator failed")
+    _allocator_refs = refs
 
 
 def load() -> ctypes.CDLL:
@@ -118,6 +148,12 @@ def load() -> ctypes.CDLL:
     lib.bd_adjoint_begin.restype = ctypes.c_int
     lib.bd_adjoint_backward.argtypes = [V, V, V, V]
     lib.bd_adjoint_backward.restype = ctypes.c_int
+    lib.bd_adjoint_backward_dev.argtypes = [V, V, V, V]
+    lib.bd_adjoint_backward_dev.restype = ctypes.c_int
+    lib.bd_get_state_dev.argtypes = [V, V, V]
+    lib.bd_get_state_dev.restype = ctypes.c_int
+    lib.bd_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, V]
+    lib.bd_set_allocator.restype = ctypes.c_int
     lib.bd_destroy.argtypes = [V]
     lib.bd_destroy.restype = None
     _lib = lib
@@ -299,6 +335,15 @@ class Sim:
     def adjoint_begin(self, nsteps: int, checkpoint_every: int):
         """Advance nsteps steps keeping checkpoints for ``adjoint_backward``."""
         self._check(self._lib.bd_adjoint_begin(self._h, int(nsteps), int(checkpoint_every)), "bd_adjoint_begin")
+
+    def state_dev(self, xy_out: int, theta_out: int = 0):
+        """Positions and angles into device buffers (raw device pointers, e.g. ``tensor.data_ptr()``)."""
+        self._check(self._lib.bd_get_state_dev(self._h, xy_out or None, theta_out or None), "bd_get_state_dev")
+
+    def adjoint_backward_dev(self, grad_xy: int, grad_xy0: int, grad_K: int):
+        """``adjoint_backward`` on device buffers (raw device pointers)."""
+        self._check(self._lib.bd_adjoint_backward_dev(self._h, grad_xy, grad_xy0 or None, grad_K or None),
+                    "bd_adjoint_backward_dev")
 
     def adjoint_backward(self, grad_xy):
         """dL/dx at the first step and dL/dK from dL/dx at the last step of ``adjoint_begin``."""

@@ -163,6 +163,10 @@ struct Sim {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
+    // device allocator installed with bd_set_allocator when the handle was created (null: hipMalloc)
+    void *(*user_alloc)(size_t, void *, void *) = nullptr;
+    void (*user_free)(void *, void *, void *) = nullptr;
+    void *user_ctx = nullptr;
 
     // particle state (caller order)
     double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr;

@@ -30,6 +30,15 @@
 namespace bd {
 namespace {
 
+__global__ void k_interleave(int n, const double *__restrict__ x, const double *__restrict__ y,
+                             double *__restrict__ xy) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        xy[2 * (size_t)i] = x[i];
+        xy[2 * (size_t)i + 1] = y[i];
+    }
+}
+
 __global__ void k_fill_int(int *p, int count, int value) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = value;
@@ -49,13 +58,50 @@ inline void check(hipError_t e, const char *what) {
     if (e != hipSuccess) throw DeviceError{e, what};
 }
 
+// Device memory comes from hipMalloc or from the allocator installed with
+// bd_set_allocator when the handle was created (the handle keeps using the
+// one it started with).  The handle being served is thread-local while a call
+// runs, so the helpers below need no handle argument.
+struct Allocator {
+    void *(*alloc)(size_t, void *, void *) = nullptr;
+    void (*free)(void *, void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+thread_local Sim *tl_sim = nullptr;
+
+struct UseSim {   // marks the handle served by this thread for the duration of a call
+    Sim *prev;
+    explicit UseSim(Sim &s) : prev(tl_sim) { tl_sim = &s; }
+    ~UseSim() { tl_sim = prev; }
+};
+
+void *raw_alloc(size_t bytes) {
+    Sim *s = tl_sim;
+    if (s && s->user_alloc) {
+        void *p = s->user_alloc(bytes, (void *)s->stream, s->user_ctx);
+        if (!p) throw std::bad_alloc();
+        return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) throw std::bad_alloc();
+    return p;
+}
+
+void dfree(void *p) {
+    if (!p) return;
+    Sim *s = tl_sim;
+    if (s && s->user_free)
+        s->user_free(p, (void *)s->stream, s->user_ctx);
+    else
+        (void)hipFree(p);
+}
+
 template <typename T>
 T *dalloc(size_t count) {
-    void *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) throw std::bad_alloc();
-    return (T *)p;
+    return (T *)raw_alloc(count * sizeof(T));
 }
 
 void fill_int(Sim &s, int *p, int count, int value) {
@@ -322,7 +368,7 @@ void verlet_rebuild(Sim &s) {
         }
         if (need > 96 || s.nl_cap >= 96)
             throw UnsupportedError{"more than 96 disks within cutoff + skin of one disk (neighbour list capacity)"};
-        check(hipFree(s.nl), "free nl");
+        dfree(s.nl);
         s.nl = nullptr;
         drop_graphs(s);   // captured steps hold the old list pointer
         s.nl_cap = 96;
@@ -853,8 +899,8 @@ double time_force(Sim &s, int reps) {
 // Allocates tiles / part for the largest of the given tilings.
 void alloc_force_buffers(Sim &s, long long max_tiles, long long max_part) {
     const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
-    if (s.tiles) check(hipFree(s.tiles), "free tiles");
-    if (s.part) check(hipFree(s.part), "free part");
+    dfree(s.tiles);
+    dfree(s.part);
     s.tiles = nullptr;
     s.part = nullptr;
     s.tiles = dalloc<Tile>((size_t)max_tiles);
@@ -957,10 +1003,10 @@ void free_all(Sim &s) {
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
                     s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        dfree(p);
     drop_graphs(s);
-    if (s.dbase) (void)hipFree(s.dbase);
-    if (s.ring) (void)hipFree(s.ring);
+    dfree(s.dbase);
+    dfree(s.ring);
     if (s.hring) (void)hipHostFree(s.hring);
     if (s.hbase) (void)hipHostFree(s.hbase);
     if (s.hctl) (void)hipHostFree(s.hctl);
@@ -1263,7 +1309,7 @@ void ck_alloc(Sim &s, Checkpoint &c) {
 void ck_free(Checkpoint &c) {
     void *ptrs[] = {c.x, c.y, c.xo, c.yo, c.th, c.tho, c.he_v, c.he_twin, c.vert_he};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        dfree(p);
     c = Checkpoint();
 }
 
@@ -1315,14 +1361,14 @@ void ck_restore(Sim &s, const Checkpoint &c) {
 void tape_free(Tape &tp) {
     void *ptrs[] = {tp.px, tp.py, tp.emwf, tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir, tp.phi};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        dfree(p);
     tp = Tape();
 }
 
 void tape_alloc_rounds(Tape &tp, int cap_ent, int cap_dir) {
     void *ptrs[] = {tp.ev, tp.eold, tp.edisp, tp.ewf, tp.ecnt, tp.enb, tp.dir};
     for (void *p : ptrs)
-        if (p) check(hipFree(p), "tape free");
+        dfree(p);
     tp.cap_ent = cap_ent;
     tp.cap_dir = cap_dir;
     tp.ev = dalloc<int>(cap_ent);
@@ -1340,7 +1386,7 @@ void adj_free(Sim &s) {
     tape_free(a.tape);
     void *ptrs[] = {a.lam, a.nu, a.bx, a.by, a.pj4, a.gpart, a.dk_rows, a.dk_blk, a.dk};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        dfree(p);
     a = AdjState();
 }
 
@@ -1386,8 +1432,11 @@ int adjoint_begin(Sim &s, int64_t nsteps, int every) {
     // keep each step's force partial sums when they fit in 8 GiB (else the sweep recomputes them)
     const size_t phi_bytes = (size_t)every * s.part_cap * (s.fp32 ? sizeof(float2) : sizeof(double2));
     if (phi_bytes <= (8ull << 30)) {
-        void *p = nullptr;
-        if (hipMalloc(&p, phi_bytes) == hipSuccess) tp.phi = p;
+        try {
+            tp.phi = raw_alloc(phi_bytes);
+        } catch (const std::bad_alloc &) {
+            tp.phi = nullptr;
+        }
     }
     a.ready = true;
     return BD_OK;
@@ -1432,7 +1481,7 @@ int record_segment(Sim &s, int seg, int len) {
     return BD_ERR_DEVICE;
 }
 
-int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK) {
+int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK, bool dev = false) {
     AdjState &a = s.adj;
     if (!a.ready) {
         s.last_error = "bd_adjoint_begin has not been run";
@@ -1440,7 +1489,9 @@ int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK) {
     }
     Tape &tp = a.tape;
     const int nseg = (int)a.ck.size() - 1;
-    check(hipMemcpyAsync(a.lam, gT, sizeof(double2) * s.n, hipMemcpyHostToDevice, s.stream), "lambda");
+    check(hipMemcpyAsync(a.lam, gT, sizeof(double2) * s.n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s.stream),
+          "lambda");
     check(hipMemsetAsync(a.dk_blk, 0, sizeof(double) * a.dk_blocks * s.S * s.S, s.stream), "dk");
     int rc = BD_OK;
     std::vector<int2> dir;
@@ -1461,8 +1512,9 @@ int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK) {
     }
     if (rc == BD_OK) {
         launch_adj_dk_final(s);
-        if (g0) check(hipMemcpyAsync(g0, a.lam, sizeof(double2) * s.n, hipMemcpyDeviceToHost, s.stream), "grad x0");
-        if (gK) check(hipMemcpyAsync(gK, a.dk, sizeof(double) * s.S * s.S, hipMemcpyDeviceToHost, s.stream), "grad K");
+        const hipMemcpyKind out = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (g0) check(hipMemcpyAsync(g0, a.lam, sizeof(double2) * s.n, out, s.stream), "grad x0");
+        if (gK) check(hipMemcpyAsync(gK, a.dk, sizeof(double) * s.S * s.S, out, s.stream), "grad K");
         check(hipStreamSynchronize(s.stream), "sync");
     }
     ck_restore(s, a.ck[nseg]);   // back to the end of the forward pass
@@ -1484,6 +1536,7 @@ const char *err_name(int code) {
 
 template <typename F>
 int guarded(Sim &s, F &&f) {
+    UseSim use(s);
     try {
         return f();
     } catch (const DeviceError &e) {
@@ -1540,11 +1593,18 @@ int bd_batch_init(bd_sim **out, int32_t R, const int32_t *n_per, const double *x
     }
     bd_sim *h = new (std::nothrow) bd_sim();
     if (!h) return BD_ERR_OOM;
+    {
+        std::lock_guard<std::mutex> lk(bd::g_alloc_mu);
+        h->s.user_alloc = bd::g_alloc.alloc;
+        h->s.user_free = bd::g_alloc.free;
+        h->s.user_ctx = bd::g_alloc.ctx;
+    }
     rc = bd::guarded(h->s, [&] {
         return bd::init_impl(h->s, R, n_per, xy, radii, species, theta, L_per, seed_per, fp, p);
     });
     if (rc != BD_OK) {
         std::fprintf(stderr, "bd_batch_init: %s\n", h->s.last_error.c_str());
+        bd::UseSim use(h->s);
         bd::free_all(h->s);
         delete h;
         return rc;
@@ -1576,6 +1636,27 @@ int bd_adjoint_backward(bd_sim *sim, const double *grad_xy, double *grad_xy0, do
     if (!sim || !grad_xy) return BD_ERR_INVALID_ARG;
     Sim &s = sim->s;
     return bd::guarded(s, [&] { return bd::adjoint_backward(s, grad_xy, grad_xy0, grad_K); });
+}
+
+int bd_adjoint_backward_dev(bd_sim *sim, const double *grad_xy, double *grad_xy0, double *grad_K) {
+    if (!sim || !grad_xy) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] { return bd::adjoint_backward(s, grad_xy, grad_xy0, grad_K, true); });
+}
+
+int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out) {
+    if (!sim) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] {
+        if (xy_out)
+            hipLaunchKernelGGL(bd::k_interleave, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n, s.x, s.y,
+                               xy_out);
+        if (theta_out)
+            bd::check(hipMemcpyAsync(theta_out, s.th, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream),
+                      "theta");
+        bd::check(hipStreamSynchronize(s.stream), "sync");
+        return (int)BD_OK;
+    });
 }
 
 int bd_batch_layout(bd_sim *sim, int32_t *R_out, int32_t *disk_off, int32_t *frame_off) {
@@ -1804,8 +1885,21 @@ int bd_kernel_time(bd_sim *sim, double *force_ms, int64_t *force_launches) {
 void bd_destroy(bd_sim *sim) {
     if (!sim) return;
     (void)hipStreamSynchronize(sim->s.stream);
-    bd::free_all(sim->s);
+    {
+        bd::UseSim use(sim->s);
+        bd::free_all(sim->s);
+    }
     delete sim;
+}
+
+int bd_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),
+                     void (*free_fn)(void *ptr, void *stream, void *ctx), void *ctx) {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return BD_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(bd::g_alloc_mu);
+    bd::g_alloc.alloc = alloc_fn;
+    bd::g_alloc.free = free_fn;
+    bd::g_alloc.ctx = alloc_fn ? ctx : nullptr;
+    return BD_OK;
 }
 
 }  // extern "C"

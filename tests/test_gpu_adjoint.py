@@ -197,3 +197,36 @@ def test_adjoint_of_a_batch_sums_dK_over_systems():
         tot_lhs += np.sum(g0[doff[r]:doff[r + 1]] * v)
     tot_lhs += gK[0, 0]
     assert abs(tot_lhs - total) <= 1e-10 * abs(total)
+
+
+def test_autograd_with_device_tensors_matches_host_tensors():
+    w = synth.make("C5", n=200)
+    spec = bdad.RolloutSpec.from_workload(w)
+    grads = []
+    for dev in ("cpu", "cuda"):
+        K = torch.tensor(w.K, dtype=torch.float64, device=dev, requires_grad=True)
+        x0 = torch.tensor(w.xy, dtype=torch.float64, device=dev, requires_grad=True)
+        loss = bdad.msd_loss(bdad.rollout(K, x0, spec, 5, 2), x0, w.species)
+        loss.backward()
+        grads.append((loss.item(), K.grad.cpu().numpy(), x0.grad.cpu().numpy()))
+    assert grads[0][0] == grads[1][0]
+    assert np.array_equal(grads[0][1], grads[1][1]) and np.array_equal(grads[0][2], grads[1][2])
+
+
+def test_torch_caching_allocator_gives_identical_results():
+    w = synth.make("C2", n=2000)
+    a = binding.Sim.from_workload(w)
+    binding.use_torch_allocator(True)
+    try:
+        b = binding.Sim.from_workload(w)
+    finally:
+        binding.use_torch_allocator(False)
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    xy = torch.empty((w.n, 2), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    b.state_dev(xy.data_ptr())
+    assert np.array_equal(xy.cpu().numpy(), b.state()[0])
+    b.close()
+    a.close()
