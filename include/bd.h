@@ -179,7 +179,7 @@ typedef struct bd_force_config {
     int32_t tiles;        /* tiles per force evaluation */
     int32_t grid;         /* workgroups launched per force evaluation */
     int32_t tuned;        /* 1: chosen by timing, 2: taken from the tuning cache, 0: fixed rule */
-    double tuned_ms;      /* force time of the chosen tiling when timed, else 0 */
+    double tuned_ms;      /* force + partial-sum reduction time of the chosen tiling when timed, else 0 */
 } bd_force_config;
 int bd_get_force_config(bd_sim *sim, bd_force_config *out);
 

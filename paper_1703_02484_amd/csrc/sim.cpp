@@ -876,24 +876,29 @@ void write_tune_file() {
     std::rename(tmp.c_str(), path);
 }
 
+// Median time of the force launch plus the per-particle reduction of its
+// partial sums (the update kernel's gather, which grows with the chunk count).
 double time_force(Sim &s, int reps) {
     hipEvent_t a, b;
     check(hipEventCreate(&a), "event");
     check(hipEventCreate(&b), "event");
     launch_force(s);   // warm-up
-    float best = 1e30f;
+    launch_reduce_forces(s);
+    std::vector<float> t;
     for (int k = 0; k < reps; ++k) {
         check(hipEventRecord(a, s.stream), "event");
         launch_force(s);
+        launch_reduce_forces(s);
         check(hipEventRecord(b, s.stream), "event");
         check(hipEventSynchronize(b), "event sync");
         float ms = 0.f;
         check(hipEventElapsedTime(&ms, a, b), "elapsed");
-        best = std::min(best, ms);
+        t.push_back(ms);
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    return best;
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
 }
 
 // Allocates tiles / part for the largest of the given tilings.
@@ -972,14 +977,42 @@ void setup_force(Sim &s) {
     }
     alloc_force_buffers(s, max_tiles, max_part);
     launch_cast(s);
-    TuneChoice best{0, 0, 0, 1e30};
+    // bring the clocks up before timing anything
+    {
+        Tiling t = make_tiling(s, dchunk, 4);
+        upload_tiling(s, t, dchunk, 4, 0);
+        hipEvent_t e0, e1;
+        check(hipEventCreate(&e0), "event");
+        check(hipEventCreate(&e1), "event");
+        float ms = 0.f;
+        for (int k = 0; k < 200 && ms < 50.f; ++k) {
+            check(hipEventRecord(e0, s.stream), "event");
+            for (int j = 0; j < 4; ++j) launch_force(s);
+            check(hipEventRecord(e1, s.stream), "event");
+            check(hipEventSynchronize(e1), "event sync");
+            float dt = 0.f;
+            check(hipEventElapsedTime(&dt, e0, e1), "elapsed");
+            ms += dt;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    // first pass over every candidate, then the best few again
+    std::vector<TuneChoice> scored;
     for (const auto &cp : cands) {
         Tiling t = make_tiling(s, cp.first, cp.second);
         for (int pers = 0; pers <= 1; ++pers) {
             upload_tiling(s, t, cp.first, cp.second, pers);
-            const double ms = time_force(s, 3);
-            if (ms < best.ms) best = TuneChoice{cp.first, cp.second, pers, ms};
+            scored.push_back(TuneChoice{cp.first, cp.second, pers, time_force(s, 5)});
         }
+    }
+    std::sort(scored.begin(), scored.end(), [](const TuneChoice &x, const TuneChoice &y) { return x.ms < y.ms; });
+    TuneChoice best{0, 0, 0, 1e30};
+    for (size_t i = 0; i < scored.size() && i < 3; ++i) {
+        const TuneChoice &c = scored[i];
+        upload_tiling(s, make_tiling(s, c.chunk, c.per_lane), c.chunk, c.per_lane, c.persistent);
+        const double ms = time_force(s, 9);
+        if (ms < best.ms) best = TuneChoice{c.chunk, c.per_lane, c.persistent, ms};
     }
     Tiling t = make_tiling(s, best.chunk, best.per_lane);
     alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
