@@ -182,6 +182,7 @@ struct Sim {
     int ntiles = 0;
     int *chunk_spec = nullptr;       // species of each chunk
     long long part_cap = 0;          // elements allocated for part
+    long long tiles_cap = 0;         // tiles allocated
     int chunk_len = 0;               // j per chunk (last chunk of a species may be shorter)
     int per_lane = 4;                // i per lane: a tile holds 256 * per_lane particles
     int persistent = 0;              // 1: fixed grid pulling tiles from a queue

@@ -788,6 +788,9 @@ Tiling make_tiling(const Sim &s, int chunk, int per_lane) {
 }
 
 void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persistent) {
+    // the force kernel writes part[pbase + i] for every tile: never launch a tiling the buffers cannot hold
+    if ((long long)t.tiles.size() > s.tiles_cap || t.part_len > s.part_cap)
+        throw DeviceError{hipErrorInvalidValue, "force tiling larger than its buffers"};
     check(hipMemcpyAsync(s.tiles, t.tiles.data(), sizeof(Tile) * t.tiles.size(), hipMemcpyHostToDevice, s.stream),
           "tiles");
     check(hipMemcpyAsync(s.chunk_spec, t.chunk_spec.data(), sizeof(int) * t.chunk_spec.size(), hipMemcpyHostToDevice,
@@ -910,6 +913,7 @@ void alloc_force_buffers(Sim &s, long long max_tiles, long long max_part) {
     s.part = nullptr;
     s.tiles = dalloc<Tile>((size_t)max_tiles);
     s.part = dalloc<char>(vec * (size_t)max_part);
+    s.tiles_cap = max_tiles;
     s.part_cap = max_part;
 }
 
@@ -956,8 +960,9 @@ void setup_force(Sim &s) {
         }
     }
     // candidates: chunk lengths around the fixed rule, both tile heights, both launch forms
-    std::vector<int> chunks;
-    for (int c = std::max(256, dchunk / 8); c <= std::min(65536, dchunk * 4); c *= 2) chunks.push_back(c);
+    std::vector<int> chunks{dchunk};   // the fixed rule is always a candidate
+    for (int c = std::max(256, dchunk / 8); c <= std::min(65536, dchunk * 4); c *= 2)
+        if (c != dchunk) chunks.push_back(c);
     const long long part_limit = (2ll << 30) / (long long)vec;
     long long max_tiles = 0, max_part = 0;
     std::vector<std::pair<int, int>> cands;   // (chunk, per_lane)
@@ -977,10 +982,10 @@ void setup_force(Sim &s) {
     }
     alloc_force_buffers(s, max_tiles, max_part);
     launch_cast(s);
-    // bring the clocks up before timing anything
+    // bring the clocks up before timing anything (with the first candidate, which the buffers hold)
     {
-        Tiling t = make_tiling(s, dchunk, 4);
-        upload_tiling(s, t, dchunk, 4, 0);
+        Tiling t = make_tiling(s, cands[0].first, cands[0].second);
+        upload_tiling(s, t, cands[0].first, cands[0].second, 0);
         hipEvent_t e0, e1;
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
