@@ -215,7 +215,11 @@ inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 // topology snapshot, the rounds, the validation and the check that halts the
 // step when the budget was too small or a triangle stayed inverted.
 void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots) {
-    launch_snapshot(s);
+    // The repair after the move keeps the triangulation of the step's start
+    // positions: a later repair of the same step that fails replays the
+    // whole move from there (the Delaunay triangulation of the end positions
+    // is unique), so the repairs after overlap rounds need no copy of their own.
+    if (full) launch_snapshot(s);
     const int rep = c.take_rep();
     if (first_slots) first_slots->push_back(c.slot);
     int last = -1;
@@ -675,14 +679,13 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
         hc.oround = c.oround;
         if (reason == HALT_REPAIR_BUDGET || reason == HALT_INVALID) {
             // repair slot `stage`: 0 is the repair after the update, j >= 1 the one after overlap round j-1
-            const MoveFrom from = stage == 0 ? MoveFrom::Previous : MoveFrom::Touched;
-            const int k = stage == 0 ? 0 : orounds[stage - 1];
+            // a failure replays the step's whole move from the copy taken before its first repair
             if (reason == HALT_REPAIR_BUDGET) {
                 hc.slot = next_slot(last);   // its worklist holds the edges still to evaluate
-                bool snapped = false;
-                if (!host_flip_rounds(s, hc, false, false, &snapped)) rc = kinetic_replay(s, hc, from, k);
+                if (!host_flip_rounds(s, hc, false, false, nullptr))
+                    rc = kinetic_replay(s, hc, MoveFrom::Previous, 0);
             } else {
-                rc = kinetic_replay(s, hc, from, k);
+                rc = kinetic_replay(s, hc, MoveFrom::Previous, 0);
             }
         }
         if (rc == BD_OK) rc = host_overlap_loop(s, hc, rounds);
