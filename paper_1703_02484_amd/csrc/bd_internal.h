@@ -34,8 +34,9 @@ enum Ctl {
     K_TAPE_DIR = 12,   // adjoint tape: overlap rounds recorded in this step
     K_TAPE_OVF = 13,   // adjoint tape: 1 = capacity exceeded, 2 = a disk had more than MAXACT partners
     K_FL_N = 14,       // edges flipped since the last overlap detection (list length)
-    K_FL_EPOCH = 15,   // stamp of the last overlap detection (dedupes that list)
-    K_CAND = 16,                     // [MAXR] flip candidates of round slot j
+    K_FL_EPOCH = 15,   // stamp of the last overlap detection (dedupes the flipped lists)
+    K_VT_N = 16,       // triangles rewritten by flips since the last overlap detection (list length)
+    K_CAND = 17,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -213,6 +214,8 @@ struct Sim {
     int *det_stamp = nullptr;        // [H] edge tested by the current local overlap detection
     int *fl_stamp = nullptr;         // [H] edge recorded in the flipped list in the current epoch
     int *fl = nullptr;               // [H/2 + 64] edges flipped since the last overlap detection
+    int *vt_stamp = nullptr;         // [T] triangle recorded in the rewritten list in the current epoch
+    int *vt = nullptr;               // [T + 64] triangles rewritten by flips since the last overlap detection
     double2 *newpos = nullptr;
     double2 *oldpos = nullptr;       // positions of touched disks before an overlap round
     // repair fallback: topology snapshot and the move it must replay
@@ -274,6 +277,9 @@ void launch_flip_eval_list(Sim &s, int round, int slot);
 void launch_flip_apply(Sim &s, int round, int slot);
 void launch_flip_fix(Sim &s, int round, int slot);
 void launch_validate(Sim &s, int rep);
+// validation after the repair that follows overlap round k: triangles at the disks round k moved and
+// triangles rewritten by flips since round k's detection
+void launch_validate_local(Sim &s, int rep, int k);
 void launch_repair_check(Sim &s, int rep, int last);
 void launch_snapshot(Sim &s);
 // overlap correction (k: overlap-round slot)

@@ -56,7 +56,7 @@ struct Topo {
     int *cand_won;
     int *wl0, *wl1;
     int *touched;           // [2][n], by overlap-round parity
-    int *det_stamp, *fl_stamp, *fl;
+    int *det_stamp, *fl_stamp, *fl, *vt_stamp, *vt;
     double2 *newpos, *oldpos;
     int *ctl;
     unsigned long long *acc;
@@ -98,6 +98,8 @@ Topo topo_of(Sim &s) {
     t.det_stamp = s.det_stamp;
     t.fl_stamp = s.fl_stamp;
     t.fl = s.fl;
+    t.vt_stamp = s.vt_stamp;
+    t.vt = s.vt;
     t.newpos = s.newpos;
     t.oldpos = s.oldpos;
     t.ctl = s.ctl;
@@ -292,6 +294,9 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
         // the new diagonal joins two disks that may never have been tested for overlap
         const int e = s1 + 2 < s2 + 2 ? s1 + 2 : s2 + 2;
         if (atomicExch(&t.fl_stamp[e], epoch) != epoch) t.fl[atomicAdd(&t.ctl[K_FL_N], 1)] = e;
+        // both rewritten triangles, for the validation that ends the repair
+        if (atomicExch(&t.vt_stamp[t1], epoch) != epoch) t.vt[atomicAdd(&t.ctl[K_VT_N], 1)] = t1;
+        if (atomicExch(&t.vt_stamp[t2], epoch) != epoch) t.vt[atomicAdd(&t.ctl[K_VT_N], 1)] = t2;
         atomicAdd(&t.acc[A_FLIPS], 1ull);
         if (cd.y & (int)0x80000000) atomicAdd(&t.acc[A_INV_FLIPS], 1ull);
     }
@@ -339,17 +344,58 @@ __global__ void k_flip_fix(Topo t, int round, int slot) {
 }
 
 // Counts finite triangles that are not positively oriented after repair `rep`.
+__device__ __forceinline__ void validate_tri(const Topo &t, int tri, int rep) {
+    const int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
+    if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c)) {
+        atomicAdd(&t.ctl[K_INV + rep], 1);
+        topo_err(t);
+        return;
+    }
+    if (a >= t.inf || b >= t.inf || c >= t.inf) return;
+    if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctl[K_INV + rep], 1);
+}
+
 __global__ void k_validate(Topo t, int rep) {
     if (stopped(t.ctl)) return;
-    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
-        int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
-        if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c)) {
-            atomicAdd(&t.ctl[K_INV + rep], 1);
+    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x)
+        validate_tri(t, tri, rep);
+}
+
+// After the repair that follows overlap round k the triangulation was valid
+// before the round, so a triangle can only have lost its orientation if one
+// of its disks moved in round k or a flip rewrote it: only those are checked
+// (a triangle may be checked more than once; the count only has to be > 0).
+__global__ void k_validate_local(Topo t, int rep, int k) {
+    if (stopped(t.ctl)) return;
+    const int nmoved = t.ctl[K_TOUCH + k];
+    const int nvt = t.ctl[K_VT_N];
+    const int *moved = touched_of(t, k);
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nmoved + nvt; idx += gridDim.x * blockDim.x) {
+        if (idx >= nmoved) {
+            const int tri = t.vt[idx - nmoved];
+            if ((unsigned)tri >= (unsigned)t.T) {
+                topo_err(t);
+                continue;
+            }
+            validate_tri(t, tri, rep);
+            continue;
+        }
+        const int v = moved[idx];
+        const int h0 = t.vert_he[v];
+        if (bad_he(t, h0)) {
             topo_err(t);
             continue;
         }
-        if (a >= t.inf || b >= t.inf || c >= t.inf) continue;
-        if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctl[K_INV + rep], 1);
+        int h = h0, guard = 0;
+        do {
+            validate_tri(t, h / 3, rep);
+            h = t.he_twin[bd_prev(h)];
+            if (bad_he(t, h) || ++guard > 4096) {
+                atomicAdd(&t.ctl[K_INV + rep], 1);
+                topo_err(t);
+                break;
+            }
+        } while (h != h0);
     }
 }
 
@@ -477,6 +523,7 @@ __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kp
 __global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
     if (stopped(ctl)) return;
     ctl[K_FL_N] = 0;
+    ctl[K_VT_N] = 0;
     ctl[K_FL_EPOCH] = stamp + base->vbase;
     if (ctl[K_TOPO] != 0) {
         ctl[K_REASON] = HALT_TOPOLOGY;
@@ -711,6 +758,11 @@ void launch_flip_fix(Sim &s, int round, int slot) {
 void launch_validate(Sim &s, int rep) {
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_validate, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, rep);
+}
+
+void launch_validate_local(Sim &s, int rep, int k) {
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_validate_local, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, rep, k);
 }
 
 void launch_repair_check(Sim &s, int rep, int last) {

@@ -214,7 +214,8 @@ inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 // Enqueues one repair of `rounds` flip rounds with no host read-back: a
 // topology snapshot, the rounds, the validation and the check that halts the
 // step when the budget was too small or a triangle stayed inverted.
-void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots) {
+void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots,
+                    int oround = -1) {
     // The repair after the move keeps the triangulation of the step's start
     // positions: a later repair of the same step that fails replays the
     // whole move from there (the Delaunay triangulation of the end positions
@@ -234,7 +235,10 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
         launch_flip_fix(s, r, slot);
         last = slot;
     }
-    launch_validate(s, rep);
+    if (oround >= 0)
+        launch_validate_local(s, rep, oround);
+    else
+        launch_validate(s, rep);
     launch_repair_check(s, rep, last);
 }
 
@@ -472,7 +476,7 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
         detect(k);
         launch_ovl_gather(s, k);
         launch_ovl_apply(s, k, s.round_id + 1, c.slot);
-        enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first);
+        enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first, k);
     }
     {
         const int k = c.take_oround();
@@ -1039,7 +1043,7 @@ void free_all(Sim &s) {
     void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
-                    s.touched, s.det_stamp, s.fl_stamp, s.fl, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
+                    s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
                     s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
                     s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
@@ -1257,6 +1261,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.det_stamp = dalloc<int>(s.H);
     s.fl_stamp = dalloc<int>(s.H);
     s.fl = dalloc<int>(s.H / 2 + 64);
+    s.vt_stamp = dalloc<int>(s.T);
+    s.vt = dalloc<int>(s.T + 64);
     s.newpos = dalloc<double2>(n);
     s.oldpos = dalloc<double2>(n);
     s.snap_v = dalloc<int>(s.H);
@@ -1316,6 +1322,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     check(hipMemsetAsync(s.edge_stamp, 0, sizeof(int) * s.H, s.stream), "edge_stamp");
     check(hipMemsetAsync(s.det_stamp, 0, sizeof(int) * s.H, s.stream), "det_stamp");
     check(hipMemsetAsync(s.fl_stamp, 0xFF, sizeof(int) * s.H, s.stream), "fl_stamp");
+    check(hipMemsetAsync(s.vt_stamp, 0xFF, sizeof(int) * s.T, s.stream), "vt_stamp");
     check(hipMemsetAsync(s.vstamp, 0, sizeof(int) * (n + 1), s.stream), "vstamp");
     check(hipMemsetAsync(s.acc, 0, sizeof(unsigned long long) * N_ACC, s.stream), "acc");
     check(hipMemsetAsync(s.ctl, 0, sizeof(int) * N_CTL, s.stream), "ctl");
