@@ -75,11 +75,17 @@ def run_short_range(steps, warmup):
     # ~4 list entries x 4 (mean neighbours within cutoff + skin at phi = 0.5), force 16
     bytes_per_disk = 16 + 4 + 4 + 4 * 4 + 16
     gbs = bytes_per_disk * w.n / avg_s / 1e9
+    # whole step, algorithmic bytes per disk: update 64, force 56, one repair scan 64, first
+    # overlap detection 64, per overlap round gather + apply 84, list rebuild amortised 10
+    rounds = d["overlap_rounds_total"] / steps
+    step_bytes = w.n * (64 + bytes_per_disk + 64 + 64 + 84 * rounds + 10)
+    step_gbs = step_bytes * steps / elapsed / 1e9
     return {"workload": f"C3: N={w.n} screened A=1 lam=0.5 cutoff 2.5 skin 0.5, Verlet lists, FP64 pair forces, "
                         f"phi=0.50, dt={w.dt}",
             "value": w.n * steps / elapsed, "unit": "particle-steps/s", "steps": steps, "warmup": warmup,
             "ms_per_step": 1e3 * elapsed / steps,
             "force_nl_ms": avg_s * 1e3, "force_nl_gbs_algorithmic": gbs, "force_nl_frac_hbm": gbs / 8000.0,
+            "step_gbs_algorithmic": step_gbs, "step_frac_hbm": step_gbs / 8000.0,
             "overlap_rounds_per_step": d["overlap_rounds_total"] / steps,
             "flips_per_step": d["flips_total"] / steps, "verlet_rebuilds": d["verlet_rebuilds"],
             "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"]}

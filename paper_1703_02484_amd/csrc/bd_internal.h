@@ -244,6 +244,7 @@ struct Sim {
     unsigned long long *hacc = nullptr;
     // round budgets of the enqueued step (adapted to recent steps)
     int budget_em_rounds = 5, budget_ovl_rounds = 4, budget_overlaps = 3;
+    int slack[3] = {0, 0, 0};        // steps in a row that needed less than each budget
 
     AdjState adj;
 

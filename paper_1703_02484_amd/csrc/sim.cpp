@@ -707,11 +707,22 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
             if (h[K_CAND + rep_first[rep] + j] == 0) return j + 1;
         return budget + 2;
     };
-    auto adapt = [](int &budget, int used) {
-        if (used >= budget)
+    // grow at once when a budget ran out; shrink by one only after kShrinkAfter
+    // steps in a row that needed less (a halted step costs far more than a few
+    // extra no-op launches)
+    constexpr int kShrinkAfter = 16;
+    auto adapt = [&](int &budget, int used, int &slack) {
+        if (used >= budget) {
             budget = std::min(8, used + 1);
-        else if (used + 1 < budget)
-            budget = std::max(2, budget - 1);
+            slack = 0;
+        } else if (used + 1 < budget) {
+            if (++slack >= kShrinkAfter) {
+                budget = std::max(2, budget - 1);
+                slack = 0;
+            }
+        } else {
+            slack = 0;
+        }
     };
     const int hreason = h[K_HALT] ? h[K_REASON] : 0;
     // repair slot that stopped the budgeted sequence (none for an overlap budget halt)
@@ -719,15 +730,16 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     s.budget_em_rounds = plan.em_rounds;
     s.budget_ovl_rounds = plan.ovl_rounds;
     if (halt_rep > 0)
-        adapt(s.budget_em_rounds, used_rounds(0, plan.em_rounds));
+        adapt(s.budget_em_rounds, used_rounds(0, plan.em_rounds), s.slack[0]);
     else if (hreason == HALT_REPAIR_BUDGET)
-        adapt(s.budget_em_rounds, plan.em_rounds + 2);
+        adapt(s.budget_em_rounds, plan.em_rounds + 2, s.slack[0]);
     int ovl_used = 0;
     for (int r = 1; r < (int)rep_first.size() && r <= rounds && r < halt_rep; ++r)
         ovl_used = std::max(ovl_used, used_rounds(r, plan.ovl_rounds));
     if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = plan.ovl_rounds + 2;
-    if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used);
-    s.budget_overlaps = std::max(2, std::min(8, rounds + 1));
+    if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used, s.slack[1]);
+    s.budget_overlaps = plan.overlaps;
+    adapt(s.budget_overlaps, rounds, s.slack[2]);
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
