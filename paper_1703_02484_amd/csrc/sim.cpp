@@ -457,6 +457,13 @@ void write_base(Sim &s) {
     s.vbase = s.vround;
 }
 
+// Overlap rounds enqueued per step: the adaptive budget, never more than the
+// caller's round cap (the host loop enforces the cap beyond that).
+int overlaps_budget(const Sim &s) {
+    const int cap = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
+    return std::min(s.budget_overlaps, cap);
+}
+
 // The budgeted part of a step after the update: repair rounds, then overlap
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
@@ -470,7 +477,8 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
             launch_ovl_detect_local(s, stamp, k, orounds[orounds.size() - 2]);
         launch_ovl_check(s, k, stamp);
     };
-    for (int j = 0; j < s.budget_overlaps; ++j) {
+    const int nover = overlaps_budget(s);
+    for (int j = 0; j < nover; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);
         detect(k);
@@ -504,7 +512,7 @@ hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
 // inside are relative to the bases of the step being replayed.
 Sim::StepGraph &step_graph(Sim &s) {
     const long long key = ((long long)s.budget_em_rounds << 32) | ((long long)s.budget_ovl_rounds << 16) |
-                          (long long)s.budget_overlaps;
+                          (long long)overlaps_budget(s);
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
     Sim::StepGraph g;
@@ -590,7 +598,7 @@ int one_step(Sim &s) {
     launch_em(s);
     plan.em_rounds = s.budget_em_rounds;
     plan.ovl_rounds = s.budget_ovl_rounds;
-    plan.overlaps = s.budget_overlaps;
+    plan.overlaps = overlaps_budget(s);
     enqueue_rounds(s, plan.c, plan.orounds, plan.rep_first);
     read_ctl(s);
     return finish_step(s, s.hctl, plan);
@@ -623,7 +631,7 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
         StepPlan plan;
         plan.em_rounds = s.budget_em_rounds;
         plan.ovl_rounds = s.budget_ovl_rounds;
-        plan.overlaps = s.budget_overlaps;
+        plan.overlaps = overlaps_budget(s);
         plan.c.slot = g.c_slot;
         plan.c.rep = g.c_rep;
         plan.c.oround = g.c_oround;
@@ -738,7 +746,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
         ovl_used = std::max(ovl_used, used_rounds(r, plan.ovl_rounds));
     if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = plan.ovl_rounds + 2;
     if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used, s.slack[1]);
-    s.budget_overlaps = plan.overlaps;
+    s.budget_overlaps = std::max(s.budget_overlaps, plan.overlaps);
     adapt(s.budget_overlaps, rounds, s.slack[2]);
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
