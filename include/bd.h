@@ -254,6 +254,15 @@ int bd_set_positions(bd_sim *sim, const double *xy);
 int bd_set_graph_mode(bd_sim *sim, int enable);
 
 /*
+ * How the overlap rounds of a step after its first detection are launched:
+ * mode 0 one launch per phase (detection, gather, apply, each flip-round
+ * phase, validation), mode 1 all of them in one workgroup separated by
+ * barriers (for rounds that move few disks, where launches dominate), -1
+ * (default) chosen from the problem size.  Results are identical.
+ */
+int bd_set_tail_mode(bd_sim *sim, int mode);
+
+/*
  * Device memory of handles created after this call comes from alloc_fn /
  * free_fn (called with the handle's stream and ctx), e.g. a framework's
  * caching allocator; NULL for both restores hipMalloc / hipFree.  A handle

@@ -21,7 +21,7 @@ BD_PREC_FP32 = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
-            "bd_set_positions", "bd_set_graph_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
+            "bd_set_positions", "bd_set_graph_mode", "bd_set_tail_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
             "bd_adjoint_begin", "bd_adjoint_backward", "bd_adjoint_backward_dev", "bd_get_state_dev",
             "bd_set_allocator", "bd_destroy")
 
@@ -72,16 +72,14 @@ class BDError(RuntimeError):
 _lib = None
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
-_allocator_refs = None   # keeps the installed callbacks alive
+_allocator_refs = []   # every installed callback pair stays alive: handles keep the allocator they started with
 
 
 def use_torch_allocator(enable: bool = True):
     """Device memory of handles created from now on comes from torch's caching allocator (or hipMalloc again)."""
-    global _allocator_refs
     lib = load()
     if not enable:
         lib.bd_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
-        _allocator_refs = None
         return
     import torch
 
@@ -95,10 +93,10 @@ def use_torch_allocator(enable: bool = True):
         torch.cuda.caching_allocator_delete(int(ptr))
 
     refs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _allocator_refs.append(refs)
     rc = lib.bd_set_allocator(refs[0], refs[1], None)
     if rc != 0:
         raise BDError(rc, "bd_set_allocator failed")
-    _allocator_refs = refs
 
 
 def load() -> ctypes.CDLL:
@@ -136,6 +134,8 @@ def load() -> ctypes.CDLL:
     lib.bd_get_frame.restype = ctypes.c_int
     lib.bd_set_positions.argtypes = [V, V]
     lib.bd_set_positions.restype = ctypes.c_int
+    lib.bd_set_tail_mode.argtypes = [V, ctypes.c_int]
+    lib.bd_set_tail_mode.restype = ctypes.c_int
     lib.bd_set_graph_mode.argtypes = [V, ctypes.c_int]
     lib.bd_set_graph_mode.restype = ctypes.c_int
     lib.bd_set_stream.argtypes = [V, V]
@@ -319,6 +319,10 @@ class Sim:
 
     def set_graph_mode(self, on: bool = True):
         self._check(self._lib.bd_set_graph_mode(self._h, 1 if on else 0), "bd_set_graph_mode")
+
+    def set_tail_mode(self, mode: int):
+        """0: one launch per phase; 1: overlap rounds after the first detection in one workgroup; -1: automatic."""
+        self._check(self._lib.bd_set_tail_mode(self._h, int(mode)), "bd_set_tail_mode")
 
     def set_stream(self, stream_handle: Optional[int]):
         self._check(self._lib.bd_set_stream(self._h, stream_handle), "bd_set_stream")

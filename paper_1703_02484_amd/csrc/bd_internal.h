@@ -228,6 +228,8 @@ struct Sim {
     int rbase = 0, vbase = 0;        // bases currently on the device; launches pass stamp - base
     // captured steps (one graph triple per round-budget setting)
     bool use_graph = false;
+    int tail_mode = -1;              // overlap rounds after the first detection: 0 launch per phase,
+                                     // 1 one workgroup, -1 chosen from the problem size
     struct StepGraph {
         hipGraphExec_t pre = nullptr, force = nullptr, post = nullptr;
         int r_used = 0, v_used = 0;
@@ -294,6 +296,22 @@ void launch_ovl_apply(Sim &s, int k, int next_round, int slot);
 // kinetic fallback helpers
 void launch_scatter_oldpos(Sim &s, int k);            // xa[v] = old position for disks touched in round k
 void launch_interp(Sim &s, int i, int k);             // x = xa + (i/k)(xb - xa); exactly xb when i == k
+
+// The overlap rounds of a step after the first detection, run by one
+// workgroup (phases separated by workgroup barriers instead of launches);
+// the same rounds, slots and stamps as the launch-per-phase sequence.
+constexpr int MAXTAIL = 8;
+struct TailPlan {
+    int nover;                     // budgeted overlap rounds
+    int rounds;                    // flip rounds per repair
+    int k[MAXTAIL + 1];            // overlap-round slot of round j; k[nover] is the final detection
+    int stamp[MAXTAIL + 1];        // detection stamps (relative; round 0's detection ran before)
+    int next_round[MAXTAIL];       // first flip round of the repair after round j (relative)
+    int slot0[MAXTAIL];            // its first round slot
+    int rep[MAXTAIL];              // its repair slot
+    double f, cap_frac, keep;
+};
+void launch_tail(Sim &s, const TailPlan &plan);
 
 // adjoint sweep (k_adjoint.hip)
 void launch_adj_round(Sim &s, int first_entry, int count);     // one recorded overlap round, reversed

@@ -212,12 +212,12 @@ __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
     }
 }
 
-__global__ void k_flip_eval_list(Topo t, int round, int slot) {
+__device__ __forceinline__ void flip_eval_list_body(const Topo &t, int round, int slot, int i0, int stride) {
     if (stopped(t.ctl)) return;
     round += t.base->rbase;
     const int count = t.ctl[K_WL + slot];
     const int *wl = wl_of(t, slot);
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < count; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < count; idx += stride) {
         int h = wl[idx];
         if (bad_he(t, h)) {
             topo_err(t);
@@ -237,12 +237,16 @@ __global__ void k_flip_eval_list(Topo t, int round, int slot) {
     }
 }
 
-__global__ void k_flip_apply(Topo t, int round, int slot) {
+__global__ void k_flip_eval_list(Topo t, int round, int slot) {
+    flip_eval_list_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__device__ __forceinline__ void flip_apply_body(const Topo &t, int round, int slot, int i0, int stride) {
     round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
     const int epoch = t.ctl[K_FL_EPOCH];
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < ncand; idx += stride) {
         const int2 cd = t.cand[idx];
         const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
         const unsigned long long key = claim_key(round, h);
@@ -302,13 +306,17 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
     }
 }
 
-__global__ void k_flip_fix(Topo t, int round, int slot) {
+__global__ void k_flip_apply(Topo t, int round, int slot) {
+    flip_apply_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+__device__ __forceinline__ void flip_fix_body(const Topo &t, int round, int slot, int i0, int stride) {
     round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
     const int next = round + 1;
     const int nslot = slot + 1 == MAXR ? 0 : slot + 1;   // slots are used circularly
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncand; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < ncand; idx += stride) {
         const int2 cd = t.cand[idx];
         const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
         if (!t.cand_won[idx]) {
@@ -343,6 +351,10 @@ __global__ void k_flip_fix(Topo t, int round, int slot) {
     }
 }
 
+__global__ void k_flip_fix(Topo t, int round, int slot) {
+    flip_fix_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
 // Counts finite triangles that are not positively oriented after repair `rep`.
 __device__ __forceinline__ void validate_tri(const Topo &t, int tri, int rep) {
     const int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
@@ -365,12 +377,12 @@ __global__ void k_validate(Topo t, int rep) {
 // before the round, so a triangle can only have lost its orientation if one
 // of its disks moved in round k or a flip rewrote it: only those are checked
 // (a triangle may be checked more than once; the count only has to be > 0).
-__global__ void k_validate_local(Topo t, int rep, int k) {
+__device__ __forceinline__ void validate_local_body(const Topo &t, int rep, int k, int i0, int stride) {
     if (stopped(t.ctl)) return;
     const int nmoved = t.ctl[K_TOUCH + k];
     const int nvt = t.ctl[K_VT_N];
     const int *moved = touched_of(t, k);
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nmoved + nvt; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < nmoved + nvt; idx += stride) {
         if (idx >= nmoved) {
             const int tri = t.vt[idx - nmoved];
             if ((unsigned)tri >= (unsigned)t.T) {
@@ -399,9 +411,13 @@ __global__ void k_validate_local(Topo t, int rep, int k) {
     }
 }
 
+__global__ void k_validate_local(Topo t, int rep, int k) {
+    validate_local_body(t, rep, k, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
 // End of repair `rep` whose last round used slot `last`: halt the step when the
 // repair did not finish inside its round budget or left an invalid triangle.
-__global__ void k_repair_check(int *ctl, int rep, int last) {
+__device__ __forceinline__ void repair_check_body(int *ctl, int rep, int last) {
     if (stopped(ctl)) return;
     int reason = 0;
     if (ctl[K_TOPO] != 0)
@@ -416,6 +432,10 @@ __global__ void k_repair_check(int *ctl, int rep, int last) {
         ctl[K_LAST] = last;
         ctl[K_HALT] = 1;
     }
+}
+
+__global__ void k_repair_check(int *ctl, int rep, int last) {
+    repair_check_body(ctl, rep, last);
 }
 
 // ---------------------------------------------------------------- overlaps
@@ -481,7 +501,7 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     }
 }
 
-__global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev) {
+__device__ __forceinline__ void ovl_detect_local_body(const Topo &t, int stamp, double keep, int k, int kprev, int i0, int stride) {
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
     stamp += t.base->vbase;
@@ -489,7 +509,7 @@ __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kp
     const int nfl = t.ctl[K_FL_N];
     const int *prev = touched_of(t, kprev);
     int found = 0;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nprev + nfl; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < nprev + nfl; idx += stride) {
         if (idx >= nprev) {
             const int e = t.fl[idx - nprev];
             if (bad_he(t, e)) {
@@ -518,9 +538,13 @@ __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kp
     if (found) atomicAdd(&t.ctl[K_OVL + k], found);
 }
 
+__global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev) {
+    ovl_detect_local_body(t, stamp, keep, k, kprev, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
 // Overlap round k found nothing: the overlap loop of this step is done.  The
 // flipped list restarts for the edges flipped after this detection.
-__global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
+__device__ __forceinline__ void ovl_check_body(int *ctl, int k, int stamp, const StepBase *base) {
     if (stopped(ctl)) return;
     ctl[K_FL_N] = 0;
     ctl[K_VT_N] = 0;
@@ -537,24 +561,32 @@ __global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
         ctl[K_OVL_ROUNDS] = k + 1;
 }
 
+__global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
+    ovl_check_body(ctl, k, stamp, base);
+}
+
 // After the last budgeted round: overlaps remain, the host continues.
-__global__ void k_final_check(int *ctl, int k) {
+__device__ __forceinline__ void final_check_body(int *ctl, int k) {
     if (stopped(ctl)) return;
     ctl[K_REASON] = HALT_OVERLAP_BUDGET;
     ctl[K_STAGE] = k;
     ctl[K_HALT] = 1;
 }
 
+__global__ void k_final_check(int *ctl, int k) {
+    final_check_body(ctl, k);
+}
+
 // Gather: for a queued disk, sum the Jacobi displacement over its star
 // (Sec. 2.3 displacement along the unit vector, factor f), starting at the
 // neighbour of smallest id so the summation order is independent of flip
 // history; truncate the sum to cap_frac * r (Sec. 4.4); reflect at the walls.
-__global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double keep) {
+__device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, double cap_frac, double keep, int i0, int stride) {
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
     const int ntouched = t.ctl[K_TOUCH + k];
     const int *touched = touched_of(t, k);
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < ntouched; idx += stride) {
         const int v = touched[idx];
         const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
         const double L = t.Lr[t.rep_of[v]];
@@ -636,14 +668,18 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
     }
 }
 
+__global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double keep) {
+    ovl_gather_body(t, k, f, cap_frac, keep, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
 // Apply: write the new positions (keeping the old ones for a replay) and queue
 // every edge of the moved disk's triangles (incident and link edges) as the
 // worklist of round slot `slot`, the first round of the following repair.
-__global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
+__device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_round, int slot, int i0, int stride) {
     if (stopped(t.ctl)) return;
     next_round += t.base->rbase;
     const int ntouched = t.ctl[K_TOUCH + k];
-    if (t.tev != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (t.tev != nullptr && i0 == 0) {
         // adjoint tape: close the round's entries (written by the gather)
         const int di = t.tdir_base + t.ctl[K_TAPE_DIR];
         if (di < t.tcap_dir)
@@ -654,7 +690,7 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
         t.ctl[K_TAPE_DIR] += 1;
     }
     const int *touched = touched_of(t, k);
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ntouched; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < ntouched; idx += stride) {
         const int v = touched[idx];
         const double2 np = t.newpos[idx];
         t.oldpos[idx] = make_double2(t.x[v], t.y[v]);
@@ -683,6 +719,65 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
             }
         } while (h != h0 && ++guard < 4096);
     }
+}
+
+__global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
+    ovl_apply_body(t, k, next_round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+// The overlap rounds after the first detection in one workgroup: each phase
+// is the body of the corresponding kernel run with the workgroup's threads,
+// and a barrier separates phases (workgroup-scope release/acquire, so every
+// thread sees the previous phase's writes).  Halts follow the same rules.
+constexpr int kTailBlock = 1024;
+
+__global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
+    const int i0 = threadIdx.x, stride = blockDim.x;
+#define TAIL_SYNC()                  \
+    do {                             \
+        __syncthreads();             \
+        if (stopped(t.ctl)) return;  \
+        __syncthreads();             \
+    } while (0)
+    TAIL_SYNC();
+    for (int j = 0; j < p.nover; ++j) {
+        const int k = p.k[j];
+        if (j > 0) {
+            ovl_detect_local_body(t, p.stamp[j], p.keep, k, p.k[j - 1], i0, stride);
+            __syncthreads();
+            if (i0 == 0) ovl_check_body(t.ctl, k, p.stamp[j], t.base);
+            TAIL_SYNC();
+        }
+        ovl_gather_body(t, k, p.f, p.cap_frac, p.keep, i0, stride);
+        TAIL_SYNC();
+        ovl_apply_body(t, k, p.next_round[j], p.slot0[j], i0, stride);
+        TAIL_SYNC();
+        int last = -1;
+        for (int r = 0; r < p.rounds; ++r) {
+            int slot = p.slot0[j] + r;
+            if (slot >= MAXR) slot -= MAXR;
+            const int round = p.next_round[j] + r;
+            flip_eval_list_body(t, round, slot, i0, stride);
+            TAIL_SYNC();
+            flip_apply_body(t, round, slot, i0, stride);
+            TAIL_SYNC();
+            flip_fix_body(t, round, slot, i0, stride);
+            TAIL_SYNC();
+            last = slot;
+        }
+        validate_local_body(t, p.rep[j], k, i0, stride);
+        __syncthreads();
+        if (i0 == 0) repair_check_body(t.ctl, p.rep[j], last);
+        TAIL_SYNC();
+    }
+    const int k = p.k[p.nover];
+    ovl_detect_local_body(t, p.stamp[p.nover], p.keep, k, p.k[p.nover - 1], i0, stride);
+    __syncthreads();
+    if (i0 == 0) {
+        ovl_check_body(t.ctl, k, p.stamp[p.nover], t.base);
+        final_check_body(t.ctl, k);
+    }
+#undef TAIL_SYNC
 }
 
 // Topology snapshot before a repair (skipped once the step has stopped, so the
@@ -802,6 +897,11 @@ void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
     next_round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, next_round, slot);
+}
+
+void launch_tail(Sim &s, const TailPlan &plan) {
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailBlock), 0, s.stream, t, plan);
 }
 
 void launch_snapshot(Sim &s) {

@@ -464,6 +464,13 @@ int overlaps_budget(const Sim &s) {
     return std::min(s.budget_overlaps, cap);
 }
 
+// Whether the overlap rounds after the first detection run in one workgroup:
+// chosen from the problem size unless set (the rounds then touch few disks).
+bool tail_fused(const Sim &s) {
+    if (s.tail_mode >= 0) return s.tail_mode == 1;
+    return s.n <= (1 << 18);
+}
+
 // The budgeted part of a step after the update: repair rounds, then overlap
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
@@ -478,15 +485,47 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
         launch_ovl_check(s, k, stamp);
     };
     const int nover = overlaps_budget(s);
-    for (int j = 0; j < nover; ++j) {
+    if (tail_fused(s) && nover <= MAXTAIL && s.budget_ovl_rounds >= 1) {
+        // same slots, stamps and round ids as the launch-per-phase sequence below
+        TailPlan plan{};
+        plan.nover = nover;
+        plan.rounds = s.budget_ovl_rounds;
+        plan.f = s.p.overlap_factor;
+        plan.cap_frac = s.p.cap_frac;
+        plan.keep = 1.0 - s.p.contact_tol;
+        for (int j = 0; j < nover; ++j) {
+            const int k = c.take_oround();
+            orounds.push_back(k);
+            plan.k[j] = k;
+            if (j == 0) {
+                detect(k);
+                plan.stamp[0] = 0;
+            } else {
+                plan.stamp[j] = ++s.vround - s.vbase;
+            }
+            plan.next_round[j] = s.round_id + 1 - s.rbase;
+            plan.slot0[j] = c.slot;
+            plan.rep[j] = c.take_rep();
+            rep_first.push_back(c.slot);
+            for (int r = 0; r < plan.rounds; ++r) {
+                ++s.round_id;
+                c.take_slot();
+            }
+        }
         const int k = c.take_oround();
         orounds.push_back(k);
-        detect(k);
-        launch_ovl_gather(s, k);
-        launch_ovl_apply(s, k, s.round_id + 1, c.slot);
-        enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first, k);
-    }
-    {
+        plan.k[nover] = k;
+        plan.stamp[nover] = ++s.vround - s.vbase;
+        launch_tail(s, plan);
+    } else {
+        for (int j = 0; j < nover; ++j) {
+            const int k = c.take_oround();
+            orounds.push_back(k);
+            detect(k);
+            launch_ovl_gather(s, k);
+            launch_ovl_apply(s, k, s.round_id + 1, c.slot);
+            enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first, k);
+        }
         const int k = c.take_oround();
         orounds.push_back(k);
         detect(k);
@@ -512,7 +551,7 @@ hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
 // inside are relative to the bases of the step being replayed.
 Sim::StepGraph &step_graph(Sim &s) {
     const long long key = ((long long)s.budget_em_rounds << 32) | ((long long)s.budget_ovl_rounds << 16) |
-                          (long long)overlaps_budget(s);
+                          ((long long)overlaps_budget(s) << 1) | (tail_fused(s) ? 1 : 0);
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
     Sim::StepGraph g;
@@ -1890,6 +1929,16 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         s.need_rebuild = true;
         bd::Cursor c;
         return bd::host_repair(s, c, true, false, bd::MoveFrom::Previous, 0);
+    });
+}
+
+int bd_set_tail_mode(bd_sim *sim, int mode) {
+    if (!sim || mode < -1 || mode > 1) return BD_ERR_INVALID_ARG;
+    Sim &s = sim->s;
+    return bd::guarded(s, [&] {
+        bd::check(hipStreamSynchronize(s.stream), "sync");
+        s.tail_mode = mode;
+        return (int)BD_OK;
     });
 }
 

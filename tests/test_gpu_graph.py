@@ -102,3 +102,34 @@ def test_switching_modes_midway():
     a.step(3)
     b.step(3)
     _same(a, b)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_tail_in_one_workgroup_equals_launch_per_phase(graph):
+    # overlap rounds after the first detection run by one workgroup or launched
+    # phase by phase: same results, including steps that halt and are finished
+    # by the host
+    n = 600
+    L = synth.box_side(n, 0.5)
+    xy = synth.rsa(n, L, 1.0, seed=12)
+    mk = lambda: binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0,
+                             dt=2e-2, seed=6)
+    a, b = mk(), mk()
+    a.set_tail_mode(0)
+    b.set_tail_mode(1)
+    a.set_graph_mode(graph)
+    b.set_graph_mode(graph)
+    for _ in range(10):
+        a.step(1)
+        b.step(1)
+        _same(a, b)
+    assert b.state()[3]["overlap_rounds_max"] >= 3
+    w = synth.make("C2", n=3000)
+    a, b = binding.Sim.from_workload(w), binding.Sim.from_workload(w)
+    a.set_tail_mode(0)
+    b.set_tail_mode(1)
+    a.set_graph_mode(graph)
+    b.set_graph_mode(graph)
+    a.step(25)
+    b.step(25)
+    _same(a, b)
