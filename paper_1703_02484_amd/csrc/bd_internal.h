@@ -312,6 +312,8 @@ struct TailPlan {
     double f, cap_frac, keep;
 };
 void launch_tail(Sim &s, const TailPlan &plan);
+// rounds [round0, round0 + rounds) of a repair whose first evaluation ran already, in one workgroup
+void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds);
 
 // adjoint sweep (k_adjoint.hip)
 void launch_adj_round(Sim &s, int first_entry, int count);     // one recorded overlap round, reversed

@@ -780,6 +780,34 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
 #undef TAIL_SYNC
 }
 
+// The flip rounds of the repair after the move, once its first evaluation
+// (every edge, many workgroups) has run: that round's apply and fix, then the
+// remaining rounds, in one workgroup.
+__global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0, int slot0, int rounds) {
+    const int i0 = threadIdx.x, stride = blockDim.x;
+#define TAIL_SYNC()                  \
+    do {                             \
+        __syncthreads();             \
+        if (stopped(t.ctl)) return;  \
+        __syncthreads();             \
+    } while (0)
+    TAIL_SYNC();
+    for (int r = 0; r < rounds; ++r) {
+        int slot = slot0 + r;
+        if (slot >= MAXR) slot -= MAXR;
+        const int round = round0 + r;
+        if (r > 0) {
+            flip_eval_list_body(t, round, slot, i0, stride);
+            TAIL_SYNC();
+        }
+        flip_apply_body(t, round, slot, i0, stride);
+        TAIL_SYNC();
+        flip_fix_body(t, round, slot, i0, stride);
+        TAIL_SYNC();
+    }
+#undef TAIL_SYNC
+}
+
 // Topology snapshot before a repair (skipped once the step has stopped, so the
 // snapshot of the failing repair survives).
 __global__ void k_snapshot(Topo t, int *snap_v, int *snap_twin, int *snap_vh, int nvh) {
@@ -902,6 +930,11 @@ void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
 void launch_tail(Sim &s, const TailPlan &plan) {
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailBlock), 0, s.stream, t, plan);
+}
+
+void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds) {
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_repair_rounds, dim3(1), dim3(kTailBlock), 0, s.stream, t, round0 - s.rbase, slot0, rounds);
 }
 
 void launch_snapshot(Sim &s) {

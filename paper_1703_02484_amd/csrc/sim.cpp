@@ -210,6 +210,8 @@ struct Cursor {
 
 inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 
+bool tail_fused(const Sim &s);
+
 // ------------------------------------------------------------------ budgeted sequence
 // Enqueues one repair of `rounds` flip rounds with no host read-back: a
 // topology snapshot, the rounds, the validation and the check that halts the
@@ -224,6 +226,21 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
     const int rep = c.take_rep();
     if (first_slots) first_slots->push_back(c.slot);
     int last = -1;
+    if (full && rounds >= 1 && tail_fused(s)) {
+        // the first evaluation scans every edge; the rest of the rounds run in one workgroup
+        const int r0 = ++s.round_id;
+        const int slot0 = c.take_slot();
+        launch_flip_eval_full(s, r0, slot0, reversal);
+        last = slot0;
+        for (int j = 1; j < rounds; ++j) {
+            ++s.round_id;
+            last = c.take_slot();
+        }
+        launch_repair_rounds(s, r0, slot0, rounds);
+        launch_validate(s, rep);
+        launch_repair_check(s, rep, last);
+        return;
+    }
     for (int j = 0; j < rounds; ++j) {
         const int r = ++s.round_id;
         const int slot = c.take_slot();
