@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernel by kernel instead of replaying graphs")
+    ap.add_argument("--tail-mode", type=int, default=-1, choices=[-1, 0, 1],
+                    help="overlap rounds: 0 one launch per phase, 1 one workgroup, -1 automatic")
     ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the secondary 256-system batched measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the secondary gradient measurement")
@@ -266,6 +268,7 @@ def main():
         return
     w = synth.make(args.workload, n=args.n)
     sim = binding.Sim.from_workload(w)
+    sim.set_tail_mode(args.tail_mode)
     # the same steps launched kernel by kernel, for comparison with the graph replay timed below
     sim.step(args.warmup)
     torch.cuda.synchronize()
