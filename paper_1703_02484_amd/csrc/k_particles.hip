@@ -304,7 +304,9 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         }
         th[i] = t0 + a.amp_r * nr;
     }
-    if (clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
+    // one atomic per wavefront (every lane is here)
+    for (int off = 32; off > 0; off >>= 1) clamps += __shfl_xor(clamps, off);
+    if (__lane_id() == 0 && clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
 }
 
 template <typename T2>

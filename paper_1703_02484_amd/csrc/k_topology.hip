@@ -42,7 +42,7 @@ namespace bd {
 namespace {
 
 constexpr int kMaxGrid = 512;      // full scans over triangles
-constexpr int kListGrid = 128;     // worklist-driven launches (usually a few hundred items, often none)
+constexpr int kListGridMax = 128;  // worklist-driven launches (usually a few hundred items, often none)
 
 struct Topo {
     int n, inf, nvert, T;   // disks, first infinite-vertex id, all vertex ids, triangles
@@ -136,6 +136,38 @@ __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
     return ((unsigned long long)(unsigned)round << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)e);
 }
 
+// Counters shared by the whole grid are updated once per wavefront: lanes
+// that take a list position get consecutive ones from a single atomic, and
+// event counts are summed over the wavefront first (same-address atomics
+// serialise in the cache, and thousands of them per launch dominate a scan).
+__device__ __forceinline__ int wave_reserve(int *counter, bool want) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader);
+    return want ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// Sum over the (fully active) wavefront, added by one lane.
+__device__ __forceinline__ void wave_sum_add(int *counter, int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (__lane_id() == 0 && v != 0) atomicAdd(counter, v);
+}
+
+__device__ __forceinline__ void wave_count(int *counter, bool event) {
+    const unsigned long long m = __ballot(event);
+    if (m != 0 && __lane_id() == __ffsll((unsigned long long)m) - 1) atomicAdd(counter, __popcll(m));
+}
+
+__device__ __forceinline__ void wave_count64(unsigned long long *counter, bool event) {
+    const unsigned long long m = __ballot(event);
+    if (m != 0 && __lane_id() == __ffsll((unsigned long long)m) - 1)
+        atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
 // Appends edge e to the worklist of round slot `slot` once per stamp.  The
 // lanes of a wavefront that push at the same time reserve their positions
 // with one atomic on the shared counter.
@@ -181,18 +213,18 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
         // Sec. 4.3: the pair passed through each other if the edge vector reversed
         double ox = t.xo[b] - t.xo[a], oy = t.yo[b] - t.yo[a];
         double mx = t.x[b] - t.x[a], my = t.y[b] - t.y[a];
-        if (ox * mx + oy * my < 0.0) atomicAdd(&t.acc[A_REVERSALS], 1ull);
+        wave_count64(&t.acc[A_REVERSALS], ox * mx + oy * my < 0.0);
     }
     bool inverted = false;
     const int rule = bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, &inverted);
-    if (inverted) atomicAdd(&t.ctl[K_INVQ + slot], 1);
+    wave_count(&t.ctl[K_INVQ + slot], inverted);
     if (rule == BD_NOFLIP) return;
     if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
         // blocked for now (c-d may disappear in this very round): look again next round
         push_edge(t, h, round + 1, slot + 1 == MAXR ? 0 : slot + 1);
         return;
     }
-    int pos = atomicAdd(&t.ctl[K_CAND + slot], 1);
+    const int pos = wave_reserve(&t.ctl[K_CAND + slot], true);
     t.cand[pos] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
     const unsigned long long key = claim_key(round, h);
     atomicMax(&t.claim[t1], key);
@@ -297,12 +329,18 @@ __device__ __forceinline__ void flip_apply_body(const Topo &t, int round, int sl
         t.cand_won[idx] = 1;
         // the new diagonal joins two disks that may never have been tested for overlap
         const int e = s1 + 2 < s2 + 2 ? s1 + 2 : s2 + 2;
-        if (atomicExch(&t.fl_stamp[e], epoch) != epoch) t.fl[atomicAdd(&t.ctl[K_FL_N], 1)] = e;
+        const bool new_e = atomicExch(&t.fl_stamp[e], epoch) != epoch;
+        const int pe = wave_reserve(&t.ctl[K_FL_N], new_e);
+        if (new_e) t.fl[pe] = e;
         // both rewritten triangles, for the validation that ends the repair
-        if (atomicExch(&t.vt_stamp[t1], epoch) != epoch) t.vt[atomicAdd(&t.ctl[K_VT_N], 1)] = t1;
-        if (atomicExch(&t.vt_stamp[t2], epoch) != epoch) t.vt[atomicAdd(&t.ctl[K_VT_N], 1)] = t2;
-        atomicAdd(&t.acc[A_FLIPS], 1ull);
-        if (cd.y & (int)0x80000000) atomicAdd(&t.acc[A_INV_FLIPS], 1ull);
+        const bool new_t1 = atomicExch(&t.vt_stamp[t1], epoch) != epoch;
+        const bool new_t2 = atomicExch(&t.vt_stamp[t2], epoch) != epoch;
+        const int p1 = wave_reserve(&t.ctl[K_VT_N], new_t1);
+        const int p2 = wave_reserve(&t.ctl[K_VT_N], new_t2);
+        if (new_t1) t.vt[p1] = t1;
+        if (new_t2) t.vt[p2] = t2;
+        wave_count64(&t.acc[A_FLIPS], true);
+        wave_count64(&t.acc[A_INV_FLIPS], (cd.y & (int)0x80000000) != 0);
     }
 }
 
@@ -443,10 +481,9 @@ __global__ void k_repair_check(int *ctl, int rep, int last) {
 // (Algorithm 2 test, Sec. 2.3 contact distance); both ends are queued once
 // per round.
 __device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, int k) {
-    if (atomicExch(&t.vstamp[v], stamp) != stamp) {
-        int pos = atomicAdd(&t.ctl[K_TOUCH + k], 1);
-        touched_of(t, k)[pos] = v;
-    }
+    const bool fresh = atomicExch(&t.vstamp[v], stamp) != stamp;
+    const int pos = wave_reserve(&t.ctl[K_TOUCH + k], fresh);
+    if (fresh) touched_of(t, k)[pos] = v;
 }
 
 __global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
@@ -475,7 +512,7 @@ __global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
             }
         }
     }
-    if (found) atomicAdd(&t.ctl[K_OVL + k], found);
+    wave_sum_add(&t.ctl[K_OVL + k], found);   // every lane of the wavefront is here
 }
 
 // Detection after overlap round kprev of the same step.  A Delaunay edge can
@@ -535,7 +572,7 @@ __device__ __forceinline__ void ovl_detect_local_body(const Topo &t, int stamp, 
             }
         } while (h != h0);
     }
-    if (found) atomicAdd(&t.ctl[K_OVL + k], found);
+    wave_sum_add(&t.ctl[K_OVL + k], found);   // every lane of the wavefront is here
 }
 
 __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev) {
@@ -658,7 +695,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             double sc = cap / len;
             sx = sx * sc;
             sy = sy * sc;
-            atomicAdd(&t.acc[A_CAP_HITS], 1ull);
+            wave_count64(&t.acc[A_CAP_HITS], true);
         }
         if (room) {
             t.tewf[2 * (size_t)e] = bd_wall_slope(xv + sx, rv, L);
@@ -851,6 +888,14 @@ inline int grid_for(long items, int cap = kMaxGrid) {
     return (int)(b < cap ? b : cap);
 }
 
+// Workgroups of the worklist-driven launches: most of them find a short or
+// empty list, and an empty launch costs more the more workgroups it has, so
+// the grid grows with the problem (lists grow with it), from 16 to 128.
+inline int list_grid(const Sim &s) {
+    const int g = s.n / 2048;
+    return g < 16 ? 16 : (g > kListGridMax ? kListGridMax : g);
+}
+
 }  // namespace
 
 void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
@@ -863,19 +908,19 @@ void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
 void launch_flip_eval_list(Sim &s, int round, int slot) {
     round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_list, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_eval_list, dim3(list_grid(s)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_apply(Sim &s, int round, int slot) {
     round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_apply, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_apply, dim3(list_grid(s)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_flip_fix(Sim &s, int round, int slot) {
     round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_fix, dim3(grid_for(s.H / 2, kListGrid)), dim3(256), 0, s.stream, t, round, slot);
+    hipLaunchKernelGGL(k_flip_fix, dim3(list_grid(s)), dim3(256), 0, s.stream, t, round, slot);
 }
 
 void launch_validate(Sim &s, int rep) {
@@ -885,7 +930,7 @@ void launch_validate(Sim &s, int rep) {
 
 void launch_validate_local(Sim &s, int rep, int k) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_validate_local, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, rep, k);
+    hipLaunchKernelGGL(k_validate_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, rep, k);
 }
 
 void launch_repair_check(Sim &s, int rep, int last) {
@@ -907,7 +952,7 @@ void launch_ovl_check(Sim &s, int k, int vstamp) {
 void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_detect_local, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, vstamp,
+    hipLaunchKernelGGL(k_ovl_detect_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, vstamp,
                        1.0 - s.p.contact_tol, k, kprev);
 }
 
@@ -917,14 +962,14 @@ void launch_final_check(Sim &s, int k) {
 
 void launch_ovl_gather(Sim &s, int k) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_gather, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
+    hipLaunchKernelGGL(k_ovl_gather, dim3(list_grid(s)), dim3(256), 0, s.stream, t, k, s.p.overlap_factor,
                        s.p.cap_frac, 1.0 - s.p.contact_tol);
 }
 
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot) {
     next_round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_apply, dim3(grid_for(s.n, kListGrid)), dim3(256), 0, s.stream, t, k, next_round, slot);
+    hipLaunchKernelGGL(k_ovl_apply, dim3(list_grid(s)), dim3(256), 0, s.stream, t, k, next_round, slot);
 }
 
 void launch_tail(Sim &s, const TailPlan &plan) {

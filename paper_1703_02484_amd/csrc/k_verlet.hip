@@ -3,11 +3,13 @@
 // grouping the particles of each cell).
 //
 // Lists hold every disk j within r_list = r_cut + skin of disk i at build
-// time, sorted by id, stored slot-major (nl[k * n + i]) for coalesced reads.
+// time, in a fixed order (cells of the 3 x 3 block in turn, ids ascending
+// inside a cell), stored slot-major (nl[k * n + i]) for coalesced reads.
 // They stay valid while no disk has moved more than skin / 2 since the build:
 // then every pair with d <= r_cut at force time is in the list.  The build is a
-// counting sort of the disks by cell (count, exclusive scan, scatter) followed
-// by one thread per disk scanning the 3 x 3 cells around it.
+// counting sort of the disks by cell (count, exclusive scan, scatter, sort of
+// each cell's few ids) followed by one thread per disk scanning the 3 x 3
+// cells around it.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -39,9 +41,27 @@ __global__ void k_cell_scatter(int n, const int *__restrict__ cell_of, const int
     cell_items[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
 }
 
-// One thread per disk: collect neighbours within r_list from the 3 x 3 cells,
-// keep them sorted by id (insertion), write min(count, cap) of them.  The
-// position at build time is kept for the skin test.
+// One thread per cell: the scatter filled each cell in arbitrary order; sort
+// it by id (cells hold a few disks) so that the lists below are deterministic.
+__global__ void k_cell_sort(int ncell, const int *__restrict__ cell_start, int *__restrict__ cell_items) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int b = cell_start[c], e = cell_start[c + 1];
+    for (int p = b + 1; p < e; ++p) {
+        const int v = cell_items[p];
+        int q = p;
+        while (q > b && cell_items[q - 1] > v) {
+            cell_items[q] = cell_items[q - 1];
+            --q;
+        }
+        cell_items[q] = v;
+    }
+}
+
+// One thread per disk: neighbours within r_list from the 3 x 3 cells, in cell
+// order and by id inside a cell, written straight to the slot-major list (at
+// most CAP; the largest count above CAP is reported so the caller can grow the
+// lists).  The position at build time is kept for the skin test.
 template <int CAP>
 __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restrict__ x, const double *__restrict__ y,
                                                   double inv_cell, int nc, double rl2,
@@ -54,7 +74,6 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
     if (i >= n) return;
     const double xi = x[i], yi = y[i];
     const int cx = cell_coord(xi, inv_cell, nc), cy = cell_coord(yi, inv_cell, nc);
-    int list[CAP];
     int cnt = 0;
     for (int gy = cy - 1; gy <= cy + 1; ++gy) {
         if (gy < 0 || gy >= nc) continue;
@@ -66,22 +85,13 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
                 if (j == i) continue;
                 const double dx = xi - x[j], dy = yi - y[j];
                 if (dx * dx + dy * dy > rl2) continue;
-                if (cnt < CAP) {
-                    int k = cnt;
-                    while (k > 0 && list[k - 1] > j) {
-                        list[k] = list[k - 1];
-                        --k;
-                    }
-                    list[k] = j;
-                }
+                if (cnt < CAP) nl[(size_t)cnt * n + i] = j;
                 ++cnt;
             }
         }
     }
     if (cnt > CAP) atomicMax(overflow, cnt);
-    const int m = cnt < CAP ? cnt : CAP;
-    for (int k = 0; k < m; ++k) nl[(size_t)k * n + i] = list[k];
-    nl_cnt[i] = m;
+    nl_cnt[i] = cnt < CAP ? cnt : CAP;
     xb[i] = xi;
     yb[i] = yi;
 }
@@ -152,6 +162,8 @@ void launch_verlet_build(Sim &s) {
     (void)hipcub::DeviceScan::ExclusiveSum(s.scan_tmp, bytes, s.cell_count, s.cell_start, s.nl_ncell + 1, s.stream);
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.cell_of, s.cell_start,
                        s.cell_fill, s.cell_items);
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks(s.nl_ncell)), dim3(256), 0, s.stream, s.nl_ncell, s.cell_start,
+                       s.cell_items);
     const double rl = s.fp.cutoff + s.fp.skin;
     if (s.nl_cap <= 32)
         hipLaunchKernelGGL(k_nl_build<32>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,

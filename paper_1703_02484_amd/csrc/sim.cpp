@@ -481,11 +481,11 @@ int overlaps_budget(const Sim &s) {
     return std::min(s.budget_overlaps, cap);
 }
 
-// Whether the overlap rounds after the first detection run in one workgroup:
-// chosen from the problem size unless set (the rounds then touch few disks).
+// Whether the overlap rounds after the first detection run in one workgroup.
 bool tail_fused(const Sim &s) {
-    if (s.tail_mode >= 0) return s.tail_mode == 1;
-    return s.n <= (1 << 18);
+    // one workgroup measured slower than one launch per phase on 65,536 disks (the
+    // phases are latency chains that spread better over many CUs): off unless asked for
+    return s.tail_mode == 1;
 }
 
 // The budgeted part of a step after the update: repair rounds, then overlap
