@@ -775,9 +775,9 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     // steps in a row that needed less (a halted step costs far more than a few
     // extra no-op launches)
     constexpr int kShrinkAfter = 16;
-    auto adapt = [&](int &budget, int used, int &slack) {
+    auto adapt = [&](int &budget, int used, int &slack, int most = 8) {
         if (used >= budget) {
-            budget = std::min(8, used + 1);
+            budget = std::min(most, used + 1);
             slack = 0;
         } else if (used + 1 < budget) {
             if (++slack >= kShrinkAfter) {
@@ -803,7 +803,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = plan.ovl_rounds + 2;
     if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used, s.slack[1]);
     s.budget_overlaps = std::max(s.budget_overlaps, plan.overlaps);
-    adapt(s.budget_overlaps, rounds, s.slack[2]);
+    adapt(s.budget_overlaps, rounds, s.slack[2], MAXO / 2);   // contact-factor runs need ~20 rounds
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
