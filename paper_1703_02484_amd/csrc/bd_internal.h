@@ -169,14 +169,19 @@ struct Sim {
     void (*user_free)(void *, void *, void *) = nullptr;
     void *user_ctx = nullptr;
 
-    // particle state (caller order)
+    // particle state, in the library's order: inside each system the disks
+    // follow the Hilbert curve over the box (neighbours in space are
+    // neighbours in memory); perm maps it back to the caller's order
     double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr;
     double *th = nullptr, *tho = nullptr, *rad = nullptr;
     int *sp = nullptr;
     int *sp_sorted = nullptr;        // species in sorted order
+    std::vector<int> perm_h;         // library index -> caller index
+    int *perm = nullptr;             // device copy of perm_h
+    int *key_id = nullptr;           // caller index inside the disk's system (noise key)
     // force stage
-    int *sorted_id = nullptr;        // sorted index -> caller id (species-sorted)
-    int *pos_of = nullptr;           // caller id -> sorted index
+    int *sorted_id = nullptr;        // sorted index -> library index (species-sorted)
+    int *pos_of = nullptr;           // library index -> sorted index
     void *pj = nullptr;              // float2 / double2 [n], sorted order
     void *part = nullptr;            // [nchunks][n] float2 / double2 partial sums
     Tile *tiles = nullptr;           // force tiles, longest first
@@ -324,6 +329,7 @@ void launch_adj_dk_final(Sim &s);
 // Delaunay triangulation of (x[i], y[i]) with infinite vertex n, as half-edge
 // arrays of 3(2n-2) entries.  Returns 0, or -1 when all points are collinear
 // or two coincide.
+uint64_t hilbert_index(uint32_t x, uint32_t y, int bits);
 int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_v, std::vector<int> &he_twin);
 
 // Fixed frame points closing the triangulation outside the walls of [0, L]^2.

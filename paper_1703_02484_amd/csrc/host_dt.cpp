@@ -18,9 +18,10 @@
 #include "geom.h"
 
 namespace bd {
-namespace {
 
-uint64_t hilbert_d(uint32_t x, uint32_t y, int bits) {
+// Distance of cell (x, y) along the Hilbert curve over a 2^bits x 2^bits grid
+// (the rotate-and-reflect recursion of the curve, one bit level at a time).
+uint64_t hilbert_index(uint32_t x, uint32_t y, int bits) {
     uint64_t d = 0;
     for (uint32_t s = 1u << (bits - 1); s > 0; s >>= 1) {
         uint32_t rx = (x & s) ? 1 : 0;
@@ -38,6 +39,8 @@ uint64_t hilbert_d(uint32_t x, uint32_t y, int bits) {
     }
     return d;
 }
+
+namespace {
 
 struct Mesh {
     int n, inf;
@@ -259,7 +262,7 @@ int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_
     const double scale = span > 0 ? 65535.0 / span : 0.0;
     std::vector<uint64_t> key(n);
     for (int i = 0; i < n; ++i)
-        key[i] = hilbert_d((uint32_t)((x[i] - x0) * scale), (uint32_t)((y[i] - y0) * scale), 16);
+        key[i] = hilbert_index((uint32_t)((x[i] - x0) * scale), (uint32_t)((y[i] - y0) * scale), 16);
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });

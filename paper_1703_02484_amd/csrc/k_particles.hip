@@ -256,6 +256,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
                                             const RepInfo *__restrict__ reps,
                                             const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
                                             const double *__restrict__ K, const int *__restrict__ pos_of,
+                                            const int *__restrict__ key_id,
                                             const int *__restrict__ sp, const double *__restrict__ rad,
                                             double *__restrict__ x, double *__restrict__ y,
                                             double *__restrict__ xo, double *__restrict__ yo,
@@ -275,8 +276,8 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         } else {
             gather_force<T2>(part, ri, chunk_spec, K, a.S, sp[i], pos_of[i], fx, fy);
         }
-        // noise keyed by the system's seed and the particle's id inside its system
-        const unsigned id = (unsigned)(i - ri.off);
+        // noise keyed by the system's seed and the caller's index of the disk inside its system
+        const unsigned id = (unsigned)key_id[i];
         const unsigned long long step = (unsigned long long)base->step;
         const unsigned slo = (unsigned)step;
         const unsigned shi = (unsigned)(step >> 32);
@@ -463,13 +464,13 @@ void launch_em(Sim &s) {
     if (s.fp32)
         hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
                            (const float2 *)s.part, s.reps,
-                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
-                           s.acc, s.use_nl ? s.fsr : nullptr, wf);
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
+                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf);
     else
         hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
                            (const double2 *)s.part, s.reps,
-                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho,
-                           s.acc, s.use_nl ? s.fsr : nullptr, wf);
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
+                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf);
 }
 
 void launch_reduce_forces(Sim &s) {

@@ -486,33 +486,74 @@ __device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, in
     if (fresh) touched_of(t, k)[pos] = v;
 }
 
-__global__ void k_ovl_detect(Topo t, int stamp, double keep, int k) {
+// Full detection.  A step's first detection finds tens of thousands of
+// overlapping pairs on a large system; the disks it marks are staged in the
+// workgroup's LDS and copied out with one reservation on the shared counter
+// per kDetStage entries, not one per wavefront and edge (same-address
+// atomics from every CU serialise and dominated this scan).
+constexpr int kDetBlock = 256;
+constexpr int kDetStage = 4096;
+constexpr int kDetPerIter = 6 * kDetBlock;   // at most two disks for each of three edges per thread
+
+__device__ __forceinline__ void det_flush(const Topo &t, int k, int *buf, int &cnt, int &base) {
+    // every thread of the workgroup is here, after a barrier
+    if (threadIdx.x == 0) base = atomicAdd(&t.ctl[K_TOUCH + k], cnt);
+    __syncthreads();
+    int *out = touched_of(t, k) + base;
+    for (int i = threadIdx.x; i < cnt; i += kDetBlock) out[i] = buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int stamp, double keep, int k) {
 #pragma clang fp contract(off)
-    if (stopped(t.ctl)) return;
+    __shared__ int buf[kDetStage];
+    __shared__ int cnt, base, nfound;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
     stamp += t.base->vbase;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        nfound = 0;
+    }
+    __syncthreads();
     int found = 0;
-    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
+    for (int t0 = blockIdx.x * kDetBlock; t0 < t.T; t0 += gridDim.x * kDetBlock) {   // same trip count for the workgroup
+        const int tri = t0 + threadIdx.x;
+        if (tri < t.T) {
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            int h = 3 * tri + e;
-            int tw = t.he_twin[h];
-            if (h > tw) continue;
-            int a = t.he_v[h], b = t.he_v[bd_next(h)];
-            if (bad_v(t, a) || bad_v(t, b)) {
-                topo_err(t);
-                continue;
-            }
-            if (a >= t.n || b >= t.n) continue;   // frame points and the infinite vertex never overlap
-            double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
-            double d = sqrt(dx * dx + dy * dy);
-            if (d < (t.rad[a] + t.rad[b]) * keep) {
-                ++found;
-                mark_touched(t, a, stamp, k);
-                mark_touched(t, b, stamp, k);
+            for (int e = 0; e < 3; ++e) {
+                const int h = 3 * tri + e;
+                const int tw = t.he_twin[h];
+                if (h > tw) continue;
+                const int a = t.he_v[h], b = t.he_v[bd_next(h)];
+                if (bad_v(t, a) || bad_v(t, b)) {
+                    topo_err(t);
+                    continue;
+                }
+                if (a >= t.n || b >= t.n) continue;   // frame points and the infinite vertex never overlap
+                const double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
+                const double d = sqrt(dx * dx + dy * dy);
+                if (d < (t.rad[a] + t.rad[b]) * keep) {
+                    ++found;
+                    const bool fa = atomicExch(&t.vstamp[a], stamp) != stamp;
+                    const bool fb = atomicExch(&t.vstamp[b], stamp) != stamp;
+                    if (fa || fb) {
+                        int p = atomicAdd(&cnt, (fa ? 1 : 0) + (fb ? 1 : 0));
+                        if (fa) buf[p++] = a;
+                        if (fb) buf[p] = b;
+                    }
+                }
             }
         }
+        __syncthreads();
+        if (cnt > kDetStage - kDetPerIter) det_flush(t, k, buf, cnt, base);
     }
-    wave_sum_add(&t.ctl[K_OVL + k], found);   // every lane of the wavefront is here
+    for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
+    if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
+    __syncthreads();
+    if (cnt > 0) det_flush(t, k, buf, cnt, base);
+    if (threadIdx.x == 0 && nfound) atomicAdd(&t.ctl[K_OVL + k], nfound);
 }
 
 // Detection after overlap round kprev of the same step.  A Delaunay edge can
@@ -940,7 +981,7 @@ void launch_repair_check(Sim &s, int rep, int last) {
 void launch_ovl_detect(Sim &s, int vstamp, int k) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, vstamp,
+    hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(kDetBlock), 0, s.stream, t, vstamp,
                        1.0 - s.p.contact_tol, k);
 }
 

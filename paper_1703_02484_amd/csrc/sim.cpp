@@ -30,13 +30,31 @@
 namespace bd {
 namespace {
 
-__global__ void k_interleave(int n, const double *__restrict__ x, const double *__restrict__ y,
-                             double *__restrict__ xy) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        xy[2 * (size_t)i] = x[i];
-        xy[2 * (size_t)i + 1] = y[i];
+// library order -> caller order (perm: library index -> caller index)
+__global__ void k_to_caller(int n, const int *__restrict__ perm, const double *__restrict__ x,
+                            const double *__restrict__ y, const double *__restrict__ th, double *__restrict__ xy,
+                            double *__restrict__ th_out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        const size_t i = (size_t)perm[k];
+        if (xy) {
+            xy[2 * i] = x[k];
+            xy[2 * i + 1] = y[k];
+        }
+        if (th_out) th_out[i] = th[k];
     }
+}
+
+__global__ void k_scatter2(int n, const int *__restrict__ perm, const double2 *__restrict__ in,
+                           double2 *__restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[perm[k]] = in[k];
+}
+
+__global__ void k_gather2(int n, const int *__restrict__ perm, const double2 *__restrict__ in,
+                          double2 *__restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = in[perm[k]];
 }
 
 __global__ void k_fill_int(int *p, int count, int value) {
@@ -1116,7 +1134,7 @@ void adj_free(Sim &s);
 
 void free_all(Sim &s) {
     adj_free(s);
-    void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.sorted_id, s.pos_of, s.pj, s.part,
+    void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.perm, s.key_id, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
@@ -1239,6 +1257,44 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     const int n = s.off_h[R];
     s.L_h.assign(L_per, L_per + R);
     s.seed_h.assign(seed_per, seed_per + R);
+    // Library order: inside each system the disks sorted along the Hilbert
+    // curve over [0, L]^2 on a 2^16 grid (ties in caller order).  Every
+    // gather of an edge's or a neighbour's endpoints then stays in a few cache
+    // lines; the caller's order returns at every entry point that takes or
+    // gives per-disk data, and the noise stays keyed by the caller's index.
+    s.perm_h.resize(n);
+    std::vector<int> key_h(n);
+    for (int r = 0; r < R; ++r) {
+        const int o = s.off_h[r], nr = n_per[r];
+        const double scale = 65535.0 / L_per[r];
+        std::vector<uint64_t> key(nr);
+        for (int i = 0; i < nr; ++i) {
+            const double cx = std::min(std::max(xy[2 * (size_t)(o + i)] * scale, 0.0), 65535.0);
+            const double cy = std::min(std::max(xy[2 * (size_t)(o + i) + 1] * scale, 0.0), 65535.0);
+            key[i] = hilbert_index((uint32_t)cx, (uint32_t)cy, 16);
+        }
+        int *pr = s.perm_h.data() + o;
+        std::iota(pr, pr + nr, 0);
+        std::stable_sort(pr, pr + nr, [&](int a, int b) { return key[a] < key[b]; });
+        for (int k = 0; k < nr; ++k) {
+            key_h[o + k] = pr[k];
+            pr[k] += o;
+        }
+    }
+    std::vector<double> xy_l(2 * (size_t)n), rad_l(n), th_l(theta ? n : 0);
+    std::vector<int32_t> sp_l(n);
+    for (int k = 0; k < n; ++k) {
+        const int i = s.perm_h[k];
+        xy_l[2 * (size_t)k] = xy[2 * (size_t)i];
+        xy_l[2 * (size_t)k + 1] = xy[2 * (size_t)i + 1];
+        rad_l[k] = radii[i];
+        sp_l[k] = species[i];
+        if (theta) th_l[k] = theta[i];
+    }
+    xy = xy_l.data();
+    radii = rad_l.data();
+    species = sp_l.data();
+    if (theta) theta = th_l.data();
     // frame points of every system
     std::vector<std::vector<double>> fxs(R), fys(R);
     s.foff_h.assign(R + 1, 0);
@@ -1313,6 +1369,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.rad = dalloc<double>(nva);
     s.sp = dalloc<int>(n);
     s.sp_sorted = dalloc<int>(n);
+    s.perm = dalloc<int>(n);
+    s.key_id = dalloc<int>(n);
     s.rep_of = dalloc<int>(n);
     s.Lr = dalloc<double>(R);
     s.sorted_id = dalloc<int>(n);
@@ -1388,6 +1446,8 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     std::vector<int> sps(n);
     for (int k = 0; k < n; ++k) sps[k] = species[sorted[k]];
     check(hipMemcpyAsync(s.sp_sorted, sps.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sp_sorted");
+    check(hipMemcpyAsync(s.perm, s.perm_h.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "perm");
+    check(hipMemcpyAsync(s.key_id, key_h.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "key_id");
     check(hipMemcpyAsync(s.rep_of, hrep.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "rep_of");
     check(hipMemcpyAsync(s.Lr, L_per, sizeof(double) * R, hipMemcpyHostToDevice, s.stream), "Lr");
     check(hipMemcpyAsync(s.sorted_id, sorted.data(), sizeof(int) * n, hipMemcpyHostToDevice, s.stream), "sorted");
@@ -1613,9 +1673,19 @@ int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK, bool dev 
     }
     Tape &tp = a.tape;
     const int nseg = (int)a.ck.size() - 1;
-    check(hipMemcpyAsync(a.lam, gT, sizeof(double2) * s.n, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                         s.stream),
-          "lambda");
+    const int nb = (s.n + 255) / 256;
+    std::vector<double> hl;
+    if (dev) {
+        hipLaunchKernelGGL(k_gather2, dim3(nb), dim3(256), 0, s.stream, s.n, (const int *)s.perm, (const double2 *)gT,
+                           a.lam);
+    } else {
+        hl.resize(2 * (size_t)s.n);
+        for (int k = 0; k < s.n; ++k) {
+            hl[2 * (size_t)k] = gT[2 * (size_t)s.perm_h[k]];
+            hl[2 * (size_t)k + 1] = gT[2 * (size_t)s.perm_h[k] + 1];
+        }
+        check(hipMemcpyAsync(a.lam, hl.data(), sizeof(double2) * s.n, hipMemcpyHostToDevice, s.stream), "lambda");
+    }
     check(hipMemsetAsync(a.dk_blk, 0, sizeof(double) * a.dk_blocks * s.S * s.S, s.stream), "dk");
     int rc = BD_OK;
     std::vector<int2> dir;
@@ -1637,9 +1707,20 @@ int adjoint_backward(Sim &s, const double *gT, double *g0, double *gK, bool dev 
     if (rc == BD_OK) {
         launch_adj_dk_final(s);
         const hipMemcpyKind out = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-        if (g0) check(hipMemcpyAsync(g0, a.lam, sizeof(double2) * s.n, out, s.stream), "grad x0");
+        if (g0 && dev)
+            hipLaunchKernelGGL(k_scatter2, dim3(nb), dim3(256), 0, s.stream, s.n, (const int *)s.perm,
+                               (const double2 *)a.lam, (double2 *)g0);
+        if (g0 && !dev) {
+            hl.resize(2 * (size_t)s.n);
+            check(hipMemcpyAsync(hl.data(), a.lam, sizeof(double2) * s.n, out, s.stream), "grad x0");
+        }
         if (gK) check(hipMemcpyAsync(gK, a.dk, sizeof(double) * s.S * s.S, out, s.stream), "grad K");
         check(hipStreamSynchronize(s.stream), "sync");
+        if (g0 && !dev)
+            for (int k = 0; k < s.n; ++k) {
+                g0[2 * (size_t)s.perm_h[k]] = hl[2 * (size_t)k];
+                g0[2 * (size_t)s.perm_h[k] + 1] = hl[2 * (size_t)k + 1];
+            }
     }
     ck_restore(s, a.ck[nseg]);   // back to the end of the forward pass
     return rc;
@@ -1772,12 +1853,9 @@ int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out) {
     if (!sim) return BD_ERR_INVALID_ARG;
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
-        if (xy_out)
-            hipLaunchKernelGGL(bd::k_interleave, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n, s.x, s.y,
-                               xy_out);
-        if (theta_out)
-            bd::check(hipMemcpyAsync(theta_out, s.th, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream),
-                      "theta");
+        if (xy_out || theta_out)
+            hipLaunchKernelGGL(bd::k_to_caller, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n,
+                               (const int *)s.perm, s.x, s.y, s.th, xy_out, theta_out);
         bd::check(hipStreamSynchronize(s.stream), "sync");
         return (int)BD_OK;
     });
@@ -1825,15 +1903,20 @@ int bd_forces(bd_sim *sim, double *f_out) {
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
         bd::compute_forces(s);
+        std::vector<double> hf(2 * (size_t)s.n);
         if (s.use_nl) {
-            bd::check(hipMemcpyAsync(f_out, s.fsr, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
+            bd::check(hipMemcpyAsync(hf.data(), s.fsr, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
                       "forces copy");
         } else {
             bd::launch_reduce_forces(s);
-            bd::check(hipMemcpyAsync(f_out, s.fout, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
+            bd::check(hipMemcpyAsync(hf.data(), s.fout, sizeof(double) * 2 * s.n, hipMemcpyDeviceToHost, s.stream),
                       "forces copy");
         }
         bd::check(hipStreamSynchronize(s.stream), "sync");
+        for (int k = 0; k < s.n; ++k) {
+            f_out[2 * (size_t)s.perm_h[k]] = hf[2 * (size_t)k];
+            f_out[2 * (size_t)s.perm_h[k] + 1] = hf[2 * (size_t)k + 1];
+        }
         return (int)BD_OK;
     });
 }
@@ -1842,22 +1925,25 @@ int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_o
     if (!sim) return BD_ERR_INVALID_ARG;
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
-        std::vector<double> hx(s.n), hy(s.n);
+        std::vector<double> hx(s.n), hy(s.n), ht(s.n);
         if (xy_out) {
             bd::check(hipMemcpyAsync(hx.data(), s.x, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "x");
             bd::check(hipMemcpyAsync(hy.data(), s.y, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "y");
         }
         if (theta_out)
-            bd::check(hipMemcpyAsync(theta_out, s.th, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "th");
+            bd::check(hipMemcpyAsync(ht.data(), s.th, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "th");
         bd::check(hipMemcpyAsync(s.hacc, s.acc, sizeof(unsigned long long) * bd::N_ACC, hipMemcpyDeviceToHost,
                                  s.stream),
                   "acc");
         bd::check(hipStreamSynchronize(s.stream), "sync");
-        if (xy_out)
-            for (int i = 0; i < s.n; ++i) {
-                xy_out[2 * i] = hx[i];
-                xy_out[2 * i + 1] = hy[i];
+        for (int k = 0; k < s.n; ++k) {
+            const size_t i = (size_t)s.perm_h[k];
+            if (xy_out) {
+                xy_out[2 * i] = hx[k];
+                xy_out[2 * i + 1] = hy[k];
             }
+            if (theta_out) theta_out[i] = ht[k];
+        }
         if (step_out) *step_out = s.step;
         if (stats_out) {
             bd_stats st = s.st;
@@ -1887,9 +1973,10 @@ int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *nt
                 s.last_error = "triangle buffer too small";
                 return (int)BD_ERR_INVALID_ARG;
             }
-            tri_out[3 * cnt] = a;
-            tri_out[3 * cnt + 1] = b;
-            tri_out[3 * cnt + 2] = c;
+            // disks in the caller's numbering; frame points keep theirs
+            tri_out[3 * cnt] = a < s.n ? s.perm_h[a] : a;
+            tri_out[3 * cnt + 1] = b < s.n ? s.perm_h[b] : b;
+            tri_out[3 * cnt + 2] = c < s.n ? s.perm_h[c] : c;
             ++cnt;
         }
         *ntri_out = cnt;
@@ -1929,8 +2016,8 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         for (int r = 0; r < s.R; ++r) {
             const double L = s.L_h[r];
             for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) {
-                hx[i] = xy[2 * i];
-                hy[i] = xy[2 * i + 1];
+                hx[i] = xy[2 * (size_t)s.perm_h[i]];
+                hy[i] = xy[2 * (size_t)s.perm_h[i] + 1];
                 if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || hx[i] < hr[i] || hx[i] > L - hr[i] ||
                     hy[i] < hr[i] || hy[i] > L - hr[i]) {
                     s.last_error = "position outside the walls or not finite";
