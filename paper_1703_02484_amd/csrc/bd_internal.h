@@ -36,7 +36,8 @@ enum Ctl {
     K_FL_N = 14,       // edges flipped since the last overlap detection (list length)
     K_FL_EPOCH = 15,   // stamp of the last overlap detection (dedupes the flipped lists)
     K_VT_N = 16,       // triangles rewritten by flips since the last overlap detection (list length)
-    K_CAND = 17,                     // [MAXR] flip candidates of round slot j
+    K_TICKET = 17,     // workgroups finished in the current launch (last-workgroup checks; back to 0 after)
+    K_CAND = 18,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -77,7 +78,8 @@ struct StepBase {
     int stop;        // 0 run; 1 the step batch_idx halted; 2 lists must be rebuilt first
     int batch_idx;   // steps of the current batch completed on the device
 };
-constexpr int kRing = 64;      // most steps queued at once in graph mode
+constexpr int kRing = 64;
+constexpr size_t kMaxGraphs = 16;   // captured step graphs kept per handle (one per budget setting)      // most steps queued at once in graph mode
 
 constexpr int MAXACT = 16;    // overlapping partners recorded per disk and round (adjoint tape)
 
@@ -104,6 +106,16 @@ struct Tape {
     std::vector<int> step_dir_end;         // rounds recorded up to the end of each step
 };
 
+// Round budgets of the captured step, adapted to what recent steps needed.
+struct Budgets {
+    int em = 5;         // flip rounds of the repair after the move
+    int overlaps = 3;   // overlap rounds
+    int ovl[MAXO];      // flip rounds of the repair after overlap round j
+    Budgets() {
+        for (int &b : ovl) b = 4;
+    }
+};
+
 // Device copy of the state at one step (adjoint checkpoints).
 struct Checkpoint {
     double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr, *th = nullptr, *tho = nullptr;
@@ -111,7 +123,7 @@ struct Checkpoint {
     int64_t step = 0;
     bd_stats st{};
     unsigned long long acc[8] = {};
-    int budgets[3] = {0, 0, 0};
+    Budgets budgets;
 };
 
 struct AdjState {
@@ -241,7 +253,7 @@ struct Sim {
         int c_slot = 0, c_rep = 0, c_oround = 0;
         std::vector<int> orounds, rep_first;
     };
-    std::vector<std::pair<long long, StepGraph>> graphs;
+    std::vector<std::pair<std::vector<int>, StepGraph>> graphs;
     int *ring = nullptr;             // [kRing][N_CTL] control block of each queued step
     int *hring = nullptr;            // pinned mirror
     // control block and accumulators
@@ -250,8 +262,9 @@ struct Sim {
     int *hctl = nullptr;             // pinned mirror of ctl
     unsigned long long *hacc = nullptr;
     // round budgets of the enqueued step (adapted to recent steps)
-    int budget_em_rounds = 5, budget_ovl_rounds = 4, budget_overlaps = 3;
-    int slack[3] = {0, 0, 0};        // steps in a row that needed less than each budget
+    Budgets budget;
+    int slack_em = 0, slack_over = 0;   // steps in a row that needed less than each budget
+    int slack_ovl[MAXO] = {};
 
     AdjState adj;
 
@@ -284,18 +297,16 @@ void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal);
 void launch_flip_eval_list(Sim &s, int round, int slot);
 void launch_flip_apply(Sim &s, int round, int slot);
 void launch_flip_fix(Sim &s, int round, int slot);
-void launch_validate(Sim &s, int rep);
+void launch_validate(Sim &s, int rep, int last = -1);   // last >= 0: also the repair check
 // validation after the repair that follows overlap round k: triangles at the disks round k moved and
 // triangles rewritten by flips since round k's detection
-void launch_validate_local(Sim &s, int rep, int k);
-void launch_repair_check(Sim &s, int rep, int last);
+void launch_validate_local(Sim &s, int rep, int k, int last = -1);
 void launch_snapshot(Sim &s);
 // overlap correction (k: overlap-round slot)
-void launch_ovl_detect(Sim &s, int vstamp, int k);
+// check: 0 none, 1 the overlap check of round k, 2 that and the final check
+void launch_ovl_detect(Sim &s, int vstamp, int k, int check = 0);
 // detection after round kprev: only edges at disks moved by round kprev and edges flipped since
-void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev);
-void launch_ovl_check(Sim &s, int k, int vstamp);
-void launch_final_check(Sim &s, int k);
+void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev, int check = 0);
 void launch_ovl_gather(Sim &s, int k);
 void launch_ovl_apply(Sim &s, int k, int next_round, int slot);
 // kinetic fallback helpers
@@ -308,7 +319,7 @@ void launch_interp(Sim &s, int i, int k);             // x = xa + (i/k)(xb - xa)
 constexpr int MAXTAIL = 8;
 struct TailPlan {
     int nover;                     // budgeted overlap rounds
-    int rounds;                    // flip rounds per repair
+    int rounds[MAXTAIL];           // flip rounds of the repair after round j
     int k[MAXTAIL + 1];            // overlap-round slot of round j; k[nover] is the final detection
     int stamp[MAXTAIL + 1];        // detection stamps (relative; round 0's detection ran before)
     int next_round[MAXTAIL];       // first flip round of the repair after round j (relative)

@@ -122,6 +122,10 @@ Topo topo_of(Sim &s) {
 }
 
 __device__ __forceinline__ bool stopped(const int *ctl) { return (ctl[K_HALT] | ctl[K_DONE]) != 0; }
+// Read of a counter that other workgroups of the running launch update with atomics.
+__device__ __forceinline__ int ctl_read(const int *ctl, int i) {
+    return __hip_atomic_load(ctl + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // Disks queued by overlap round k (two buffers, so a round can read the previous round's list).
 __device__ __forceinline__ int *touched_of(const Topo &t, int k) { return t.touched + (size_t)(k & 1) * t.n; }
 __device__ __forceinline__ int *wl_of(const Topo &t, int slot) { return (slot & 1) ? t.wl1 : t.wl0; }
@@ -166,6 +170,32 @@ __device__ __forceinline__ void wave_count64(unsigned long long *counter, bool e
     const unsigned long long m = __ballot(event);
     if (m != 0 && __lane_id() == __ffsll((unsigned long long)m) - 1)
         atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
+// Whether the calling workgroup is the last of the grid to get here; every
+// thread of every workgroup calls it once, at the end of the kernel, thread 0
+// with released = true if it added to a counter the check reads.  The last
+// one sees those counters complete (each adder releases before its ticket,
+// the last taker acquires after) and resets the ticket for the next launch.
+// An index error (K_TOPO) may reach the check late; the host reads it at the
+// end of the step.  A check
+// that would otherwise be a one-thread launch of its own runs there.
+__device__ __forceinline__ bool last_workgroup(int *ctl, bool released) {
+    __shared__ int last;
+    // the counters a check reads are added by thread 0 of each workgroup: it
+    // releases them before the ticket is taken (no acquire here, which would
+    // drop the cache for the wavefronts still running)
+    if (released) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        last = atomicAdd(&ctl[K_TICKET], 1) == (int)gridDim.x - 1;
+        if (last) {
+            atomicExch(&ctl[K_TICKET], 0);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
+    return last != 0;
 }
 
 // Appends edge e to the worklist of round slot `slot` once per stamp.  The
@@ -394,28 +424,23 @@ __global__ void k_flip_fix(Topo t, int round, int slot) {
 }
 
 // Counts finite triangles that are not positively oriented after repair `rep`.
-__device__ __forceinline__ void validate_tri(const Topo &t, int tri, int rep) {
+// inv: the repair's invalid-triangle counter, or a workgroup's share of it in LDS
+__device__ __forceinline__ void validate_tri(const Topo &t, int tri, int *inv) {
     const int a = t.he_v[3 * tri], b = t.he_v[3 * tri + 1], c = t.he_v[3 * tri + 2];
     if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c)) {
-        atomicAdd(&t.ctl[K_INV + rep], 1);
+        atomicAdd(inv, 1);
         topo_err(t);
         return;
     }
     if (a >= t.inf || b >= t.inf || c >= t.inf) return;
-    if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(&t.ctl[K_INV + rep], 1);
-}
-
-__global__ void k_validate(Topo t, int rep) {
-    if (stopped(t.ctl)) return;
-    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x)
-        validate_tri(t, tri, rep);
+    if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(inv, 1);
 }
 
 // After the repair that follows overlap round k the triangulation was valid
 // before the round, so a triangle can only have lost its orientation if one
 // of its disks moved in round k or a flip rewrote it: only those are checked
 // (a triangle may be checked more than once; the count only has to be > 0).
-__device__ __forceinline__ void validate_local_body(const Topo &t, int rep, int k, int i0, int stride) {
+__device__ __forceinline__ void validate_local_body(const Topo &t, int *inv, int k, int i0, int stride) {
     if (stopped(t.ctl)) return;
     const int nmoved = t.ctl[K_TOUCH + k];
     const int nvt = t.ctl[K_VT_N];
@@ -427,7 +452,7 @@ __device__ __forceinline__ void validate_local_body(const Topo &t, int rep, int 
                 topo_err(t);
                 continue;
             }
-            validate_tri(t, tri, rep);
+            validate_tri(t, tri, inv);
             continue;
         }
         const int v = moved[idx];
@@ -438,10 +463,10 @@ __device__ __forceinline__ void validate_local_body(const Topo &t, int rep, int 
         }
         int h = h0, guard = 0;
         do {
-            validate_tri(t, h / 3, rep);
+            validate_tri(t, h / 3, inv);
             h = t.he_twin[bd_prev(h)];
             if (bad_he(t, h) || ++guard > 4096) {
-                atomicAdd(&t.ctl[K_INV + rep], 1);
+                atomicAdd(inv, 1);
                 topo_err(t);
                 break;
             }
@@ -449,20 +474,16 @@ __device__ __forceinline__ void validate_local_body(const Topo &t, int rep, int 
     }
 }
 
-__global__ void k_validate_local(Topo t, int rep, int k) {
-    validate_local_body(t, rep, k, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
 // End of repair `rep` whose last round used slot `last`: halt the step when the
 // repair did not finish inside its round budget or left an invalid triangle.
 __device__ __forceinline__ void repair_check_body(int *ctl, int rep, int last) {
     if (stopped(ctl)) return;
     int reason = 0;
-    if (ctl[K_TOPO] != 0)
+    if (ctl_read(ctl, K_TOPO) != 0)
         reason = HALT_TOPOLOGY;
-    else if (ctl[K_CAND + last] != 0)
+    else if (ctl_read(ctl, K_CAND + last) != 0)
         reason = HALT_REPAIR_BUDGET;
-    else if (ctl[K_INV + rep] != 0)
+    else if (ctl_read(ctl, K_INV + rep) != 0)
         reason = HALT_INVALID;
     if (reason) {
         ctl[K_REASON] = reason;
@@ -472,8 +493,36 @@ __device__ __forceinline__ void repair_check_body(int *ctl, int rep, int last) {
     }
 }
 
-__global__ void k_repair_check(int *ctl, int rep, int last) {
-    repair_check_body(ctl, rep, last);
+// Validation of repair `rep`; with last >= 0 the last workgroup also runs the
+// repair's check (last: slot of its final round).
+// Adds a workgroup's count (in LDS) to a shared counter from thread 0; every
+// thread calls it.  Returns true in thread 0 when it added something.
+__device__ __forceinline__ bool add_block_count(int *counter, const int *block_count) {
+    __syncthreads();
+    if (threadIdx.x != 0 || *block_count == 0) return false;
+    atomicAdd(counter, *block_count);
+    return true;
+}
+
+__global__ void k_validate(Topo t, int rep, int last) {
+    __shared__ int inv;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
+    if (threadIdx.x == 0) inv = 0;
+    __syncthreads();
+    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x)
+        validate_tri(t, tri, &inv);
+    const bool added = add_block_count(&t.ctl[K_INV + rep], &inv);
+    if (last >= 0 && last_workgroup(t.ctl, added) && threadIdx.x == 0) repair_check_body(t.ctl, rep, last);
+}
+
+__global__ void k_validate_local(Topo t, int rep, int k, int last) {
+    __shared__ int inv;
+    if (stopped(t.ctl)) return;
+    if (threadIdx.x == 0) inv = 0;
+    __syncthreads();
+    validate_local_body(t, &inv, k, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    const bool added = add_block_count(&t.ctl[K_INV + rep], &inv);
+    if (last >= 0 && last_workgroup(t.ctl, added) && threadIdx.x == 0) repair_check_body(t.ctl, rep, last);
 }
 
 // ---------------------------------------------------------------- overlaps
@@ -484,6 +533,17 @@ __device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, in
     const bool fresh = atomicExch(&t.vstamp[v], stamp) != stamp;
     const int pos = wave_reserve(&t.ctl[K_TOUCH + k], fresh);
     if (fresh) touched_of(t, k)[pos] = v;
+}
+
+__device__ __forceinline__ void ovl_check_body(int *ctl, int k, int stamp, const StepBase *base);
+__device__ __forceinline__ void final_check_body(int *ctl, int k);
+
+// Check after detection k (check = 1), and the final check after the last
+// budgeted detection (check = 2), run by the detection's last workgroup.
+__device__ __forceinline__ void detect_checks(const Topo &t, int k, int stamp, int check, bool released) {
+    if (check == 0 || !last_workgroup(t.ctl, released) || threadIdx.x != 0) return;
+    ovl_check_body(t.ctl, k, stamp, t.base);
+    if (check == 2) final_check_body(t.ctl, k);
 }
 
 // Full detection.  A step's first detection finds tens of thousands of
@@ -506,12 +566,12 @@ __device__ __forceinline__ void det_flush(const Topo &t, int k, int *buf, int &c
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int stamp, double keep, int k) {
+__global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, double keep, int k, int check) {
 #pragma clang fp contract(off)
     __shared__ int buf[kDetStage];
     __shared__ int cnt, base, nfound;
     if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
-    stamp += t.base->vbase;
+    const int stamp = rstamp + t.base->vbase;
     if (threadIdx.x == 0) {
         cnt = 0;
         nfound = 0;
@@ -553,7 +613,9 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int stamp, dou
     if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
     __syncthreads();
     if (cnt > 0) det_flush(t, k, buf, cnt, base);
-    if (threadIdx.x == 0 && nfound) atomicAdd(&t.ctl[K_OVL + k], nfound);
+    const bool added = threadIdx.x == 0 && nfound != 0;
+    if (added) atomicAdd(&t.ctl[K_OVL + k], nfound);
+    detect_checks(t, k, rstamp, check, added);
 }
 
 // Detection after overlap round kprev of the same step.  A Delaunay edge can
@@ -579,9 +641,10 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     }
 }
 
-__device__ __forceinline__ void ovl_detect_local_body(const Topo &t, int stamp, double keep, int k, int kprev, int i0, int stride) {
+// Returns the overlapping edges this thread found (the caller adds them to K_OVL + k).
+__device__ __forceinline__ int ovl_detect_local_body(const Topo &t, int stamp, double keep, int k, int kprev, int i0, int stride) {
 #pragma clang fp contract(off)
-    if (stopped(t.ctl)) return;
+    if (stopped(t.ctl)) return 0;
     stamp += t.base->vbase;
     const int nprev = t.ctl[K_TOUCH + kprev];
     const int nfl = t.ctl[K_FL_N];
@@ -613,11 +676,20 @@ __device__ __forceinline__ void ovl_detect_local_body(const Topo &t, int stamp, 
             }
         } while (h != h0);
     }
-    wave_sum_add(&t.ctl[K_OVL + k], found);   // every lane of the wavefront is here
+    return found;
 }
 
-__global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev) {
-    ovl_detect_local_body(t, stamp, keep, k, kprev, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+__global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev, int check) {
+    __shared__ int nfound;
+    if (stopped(t.ctl)) return;
+    if (threadIdx.x == 0) nfound = 0;
+    __syncthreads();
+    int found = ovl_detect_local_body(t, stamp, keep, k, kprev, blockIdx.x * blockDim.x + threadIdx.x,
+                                      gridDim.x * blockDim.x);
+    for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
+    if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
+    const bool added = add_block_count(&t.ctl[K_OVL + k], &nfound);
+    detect_checks(t, k, stamp, check, added);
 }
 
 // Overlap round k found nothing: the overlap loop of this step is done.  The
@@ -627,20 +699,16 @@ __device__ __forceinline__ void ovl_check_body(int *ctl, int k, int stamp, const
     ctl[K_FL_N] = 0;
     ctl[K_VT_N] = 0;
     ctl[K_FL_EPOCH] = stamp + base->vbase;
-    if (ctl[K_TOPO] != 0) {
+    if (ctl_read(ctl, K_TOPO) != 0) {
         ctl[K_REASON] = HALT_TOPOLOGY;
         ctl[K_STAGE] = k;
         ctl[K_HALT] = 1;
         return;
     }
-    if (ctl[K_OVL + k] == 0)
+    if (ctl_read(ctl, K_OVL + k) == 0)
         ctl[K_DONE] = 1;
     else
         ctl[K_OVL_ROUNDS] = k + 1;
-}
-
-__global__ void k_ovl_check(int *ctl, int k, int stamp, const StepBase *base) {
-    ovl_check_body(ctl, k, stamp, base);
 }
 
 // After the last budgeted round: overlaps remain, the host continues.
@@ -649,10 +717,6 @@ __device__ __forceinline__ void final_check_body(int *ctl, int k) {
     ctl[K_REASON] = HALT_OVERLAP_BUDGET;
     ctl[K_STAGE] = k;
     ctl[K_HALT] = 1;
-}
-
-__global__ void k_final_check(int *ctl, int k) {
-    final_check_body(ctl, k);
 }
 
 // Gather: for a queued disk, sum the Jacobi displacement over its star
@@ -821,7 +885,7 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
     for (int j = 0; j < p.nover; ++j) {
         const int k = p.k[j];
         if (j > 0) {
-            ovl_detect_local_body(t, p.stamp[j], p.keep, k, p.k[j - 1], i0, stride);
+            wave_sum_add(&t.ctl[K_OVL + k], ovl_detect_local_body(t, p.stamp[j], p.keep, k, p.k[j - 1], i0, stride));
             __syncthreads();
             if (i0 == 0) ovl_check_body(t.ctl, k, p.stamp[j], t.base);
             TAIL_SYNC();
@@ -831,7 +895,7 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
         ovl_apply_body(t, k, p.next_round[j], p.slot0[j], i0, stride);
         TAIL_SYNC();
         int last = -1;
-        for (int r = 0; r < p.rounds; ++r) {
+        for (int r = 0; r < p.rounds[j]; ++r) {
             int slot = p.slot0[j] + r;
             if (slot >= MAXR) slot -= MAXR;
             const int round = p.next_round[j] + r;
@@ -843,13 +907,13 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
             TAIL_SYNC();
             last = slot;
         }
-        validate_local_body(t, p.rep[j], k, i0, stride);
+        validate_local_body(t, &t.ctl[K_INV + p.rep[j]], k, i0, stride);
         __syncthreads();
         if (i0 == 0) repair_check_body(t.ctl, p.rep[j], last);
         TAIL_SYNC();
     }
     const int k = p.k[p.nover];
-    ovl_detect_local_body(t, p.stamp[p.nover], p.keep, k, p.k[p.nover - 1], i0, stride);
+    wave_sum_add(&t.ctl[K_OVL + k], ovl_detect_local_body(t, p.stamp[p.nover], p.keep, k, p.k[p.nover - 1], i0, stride));
     __syncthreads();
     if (i0 == 0) {
         ovl_check_body(t.ctl, k, p.stamp[p.nover], t.base);
@@ -964,41 +1028,28 @@ void launch_flip_fix(Sim &s, int round, int slot) {
     hipLaunchKernelGGL(k_flip_fix, dim3(list_grid(s)), dim3(256), 0, s.stream, t, round, slot);
 }
 
-void launch_validate(Sim &s, int rep) {
+void launch_validate(Sim &s, int rep, int last) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, rep);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, rep, last);
 }
 
-void launch_validate_local(Sim &s, int rep, int k) {
+void launch_validate_local(Sim &s, int rep, int k, int last) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_validate_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, rep, k);
+    hipLaunchKernelGGL(k_validate_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, rep, k, last);
 }
 
-void launch_repair_check(Sim &s, int rep, int last) {
-    hipLaunchKernelGGL(k_repair_check, dim3(1), dim3(1), 0, s.stream, s.ctl, rep, last);
-}
-
-void launch_ovl_detect(Sim &s, int vstamp, int k) {
+void launch_ovl_detect(Sim &s, int vstamp, int k, int check) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(kDetBlock), 0, s.stream, t, vstamp,
-                       1.0 - s.p.contact_tol, k);
+                       1.0 - s.p.contact_tol, k, check);
 }
 
-void launch_ovl_check(Sim &s, int k, int vstamp) {
-    hipLaunchKernelGGL(k_ovl_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k, vstamp - s.vbase,
-                       (const StepBase *)s.dbase);
-}
-
-void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev) {
+void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev, int check) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_detect_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, vstamp,
-                       1.0 - s.p.contact_tol, k, kprev);
-}
-
-void launch_final_check(Sim &s, int k) {
-    hipLaunchKernelGGL(k_final_check, dim3(1), dim3(1), 0, s.stream, s.ctl, k);
+                       1.0 - s.p.contact_tol, k, kprev, check);
 }
 
 void launch_ovl_gather(Sim &s, int k) {

@@ -255,8 +255,7 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
             last = c.take_slot();
         }
         launch_repair_rounds(s, r0, slot0, rounds);
-        launch_validate(s, rep);
-        launch_repair_check(s, rep, last);
+        launch_validate(s, rep, last);
         return;
     }
     for (int j = 0; j < rounds; ++j) {
@@ -271,10 +270,9 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
         last = slot;
     }
     if (oround >= 0)
-        launch_validate_local(s, rep, oround);
+        launch_validate_local(s, rep, oround, last);
     else
-        launch_validate(s, rep);
-    launch_repair_check(s, rep, last);
+        launch_validate(s, rep, last);
 }
 
 // ------------------------------------------------------------------ host-driven path
@@ -493,10 +491,17 @@ void write_base(Sim &s) {
 }
 
 // Overlap rounds enqueued per step: the adaptive budget, never more than the
-// caller's round cap (the host loop enforces the cap beyond that).
+// caller's round cap (the host loop enforces the cap beyond that) nor more
+// than the step's flip-round slots hold.
 int overlaps_budget(const Sim &s) {
     const int cap = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
-    return std::min(s.budget_overlaps, cap);
+    const int nover = std::min(s.budget.overlaps, cap);
+    int slots = s.budget.em;
+    for (int j = 0; j < nover; ++j) {
+        if (slots + s.budget.ovl[j] > MAXR) return j;
+        slots += s.budget.ovl[j];
+    }
+    return nover;
 }
 
 // Whether the overlap rounds after the first detection run in one workgroup.
@@ -509,22 +514,22 @@ bool tail_fused(const Sim &s) {
 // The budgeted part of a step after the update: repair rounds, then overlap
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
-    enqueue_repair(s, c, true, true, s.budget_em_rounds, &rep_first);
-    // the first detection after the move scans every edge, later ones only what round k-1 changed
-    auto detect = [&](int k) {
+    enqueue_repair(s, c, true, true, s.budget.em, &rep_first);
+    // the first detection after the move scans every edge, later ones only
+    // what round k-1 changed; the detection's last workgroup runs the round's
+    // check (and after the last budgeted round the final check)
+    auto detect = [&](int k, int check) {
         const int stamp = ++s.vround;
         if (orounds.size() == 1)
-            launch_ovl_detect(s, stamp, k);
+            launch_ovl_detect(s, stamp, k, check);
         else
-            launch_ovl_detect_local(s, stamp, k, orounds[orounds.size() - 2]);
-        launch_ovl_check(s, k, stamp);
+            launch_ovl_detect_local(s, stamp, k, orounds[orounds.size() - 2], check);
     };
     const int nover = overlaps_budget(s);
-    if (tail_fused(s) && nover <= MAXTAIL && s.budget_ovl_rounds >= 1) {
+    if (tail_fused(s) && nover <= MAXTAIL) {
         // same slots, stamps and round ids as the launch-per-phase sequence below
         TailPlan plan{};
         plan.nover = nover;
-        plan.rounds = s.budget_ovl_rounds;
         plan.f = s.p.overlap_factor;
         plan.cap_frac = s.p.cap_frac;
         plan.keep = 1.0 - s.p.contact_tol;
@@ -533,7 +538,7 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
             orounds.push_back(k);
             plan.k[j] = k;
             if (j == 0) {
-                detect(k);
+                detect(k, 1);
                 plan.stamp[0] = 0;
             } else {
                 plan.stamp[j] = ++s.vround - s.vbase;
@@ -542,7 +547,8 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
             plan.slot0[j] = c.slot;
             plan.rep[j] = c.take_rep();
             rep_first.push_back(c.slot);
-            for (int r = 0; r < plan.rounds; ++r) {
+            plan.rounds[j] = s.budget.ovl[j];
+            for (int r = 0; r < plan.rounds[j]; ++r) {
                 ++s.round_id;
                 c.take_slot();
             }
@@ -556,15 +562,14 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
         for (int j = 0; j < nover; ++j) {
             const int k = c.take_oround();
             orounds.push_back(k);
-            detect(k);
+            detect(k, 1);
             launch_ovl_gather(s, k);
             launch_ovl_apply(s, k, s.round_id + 1, c.slot);
-            enqueue_repair(s, c, false, false, s.budget_ovl_rounds, &rep_first, k);
+            enqueue_repair(s, c, false, false, s.budget.ovl[j], &rep_first, k);
         }
         const int k = c.take_oround();
         orounds.push_back(k);
-        detect(k);
-        launch_final_check(s, k);
+        detect(k, 2);
     }
     skin_check(s, false);
 }
@@ -585,10 +590,18 @@ hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
 // [clear counters, cast] [force] [update, budgeted rounds, checks].  Stamps
 // inside are relative to the bases of the step being replayed.
 Sim::StepGraph &step_graph(Sim &s) {
-    const long long key = ((long long)s.budget_em_rounds << 32) | ((long long)s.budget_ovl_rounds << 16) |
-                          ((long long)overlaps_budget(s) << 1) | (tail_fused(s) ? 1 : 0);
+    const int nover = overlaps_budget(s);
+    std::vector<int> key = {s.budget.em, nover, tail_fused(s) ? 1 : 0};
+    for (int j = 0; j < nover; ++j) key.push_back(s.budget.ovl[j]);
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
+    if (s.graphs.size() >= kMaxGraphs) {   // the least recently captured goes (nothing of it is in flight)
+        Sim::StepGraph &old = s.graphs.front().second;
+        (void)hipGraphExecDestroy(old.pre);
+        (void)hipGraphExecDestroy(old.force);
+        (void)hipGraphExecDestroy(old.post);
+        s.graphs.erase(s.graphs.begin());
+    }
     Sim::StepGraph g;
     // stamps inside the graph count from the base of the step it is replayed for
     const int r0 = s.round_id, v0 = s.vround;
@@ -641,7 +654,8 @@ void timed(Sim &s, const std::function<void()> &work) {
 struct StepPlan {
     Cursor c;
     std::vector<int> orounds, rep_first;   // overlap-round slot and first round slot of each repair
-    int em_rounds = 0, ovl_rounds = 0, overlaps = 0;   // round budgets the step ran with
+    Budgets b;                             // round budgets the step ran with
+    int overlaps = 0;                      // overlap rounds enqueued
 };
 
 int finish_step(Sim &s, const int *h_in, const StepPlan &plan);
@@ -670,8 +684,7 @@ int one_step(Sim &s) {
               "tape phi");
     }
     launch_em(s);
-    plan.em_rounds = s.budget_em_rounds;
-    plan.ovl_rounds = s.budget_ovl_rounds;
+    plan.b = s.budget;
     plan.overlaps = overlaps_budget(s);
     enqueue_rounds(s, plan.c, plan.orounds, plan.rep_first);
     read_ctl(s);
@@ -703,8 +716,7 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
         check(hipMemcpyAsync(s.hring, s.ring, sizeof(int) * N_CTL * nrec, hipMemcpyDeviceToHost, s.stream), "ring");
         check(hipStreamSynchronize(s.stream), "sync");
         StepPlan plan;
-        plan.em_rounds = s.budget_em_rounds;
-        plan.ovl_rounds = s.budget_ovl_rounds;
+        plan.b = s.budget;
         plan.overlaps = overlaps_budget(s);
         plan.c.slot = g.c_slot;
         plan.c.rep = g.c_rep;
@@ -749,8 +761,8 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     for (int j = 0; j < rounds; ++j) s.st.overlap_edges_total += h[K_OVL + orounds[j]];
     for (int j = 0; j < c.slot; ++j) s.st.flip_rounds_total += h[K_CAND + j] > 0 ? 1 : 0;
     int rc = BD_OK;
-    if (h[K_HALT]) {
-        const int reason = h[K_REASON], stage = h[K_STAGE], last = h[K_LAST];
+    if (h[K_HALT] || h[K_TOPO]) {
+        const int reason = h[K_TOPO] ? HALT_TOPOLOGY : h[K_REASON], stage = h[K_STAGE], last = h[K_LAST];
         if (reason == HALT_TOPOLOGY) {
             s.last_error = "triangulation index out of range";
             rollback(s);
@@ -809,19 +821,25 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     const int hreason = h[K_HALT] ? h[K_REASON] : 0;
     // repair slot that stopped the budgeted sequence (none for an overlap budget halt)
     const int halt_rep = (hreason == HALT_REPAIR_BUDGET || hreason == HALT_INVALID) ? h[K_STAGE] : 1 << 30;
-    s.budget_em_rounds = plan.em_rounds;
-    s.budget_ovl_rounds = plan.ovl_rounds;
+    s.budget = plan.b;
     if (halt_rep > 0)
-        adapt(s.budget_em_rounds, used_rounds(0, plan.em_rounds), s.slack[0]);
+        adapt(s.budget.em, used_rounds(0, plan.b.em), s.slack_em);
     else if (hreason == HALT_REPAIR_BUDGET)
-        adapt(s.budget_em_rounds, plan.em_rounds + 2, s.slack[0]);
-    int ovl_used = 0;
-    for (int r = 1; r < (int)rep_first.size() && r <= rounds && r < halt_rep; ++r)
-        ovl_used = std::max(ovl_used, used_rounds(r, plan.ovl_rounds));
-    if (hreason == HALT_REPAIR_BUDGET && halt_rep > 0) ovl_used = plan.ovl_rounds + 2;
-    if (ovl_used > 0) adapt(s.budget_ovl_rounds, ovl_used, s.slack[1]);
-    s.budget_overlaps = std::max(s.budget_overlaps, plan.overlaps);
-    adapt(s.budget_overlaps, rounds, s.slack[2], MAXO / 2);   // contact-factor runs need ~20 rounds
+        adapt(s.budget.em, plan.b.em + 2, s.slack_em);
+    // each overlap round's repair has its own budget: the later rounds move
+    // fewer disks and need fewer flip rounds; one that did not run this step
+    // counts as needing the least
+    for (int j = 0; j < plan.overlaps; ++j) {
+        const int r = j + 1;
+        int used = 1;
+        if (r == halt_rep && hreason == HALT_REPAIR_BUDGET)
+            used = plan.b.ovl[j] + 2;
+        else if (r < (int)rep_first.size() && r <= rounds && r < halt_rep)
+            used = used_rounds(r, plan.b.ovl[j]);
+        adapt(s.budget.ovl[j], used, s.slack_ovl[j]);
+    }
+    s.budget.overlaps = std::max(s.budget.overlaps, plan.overlaps);
+    adapt(s.budget.overlaps, rounds, s.slack_over, MAXO / 2);   // contact-factor runs need ~20 rounds
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
@@ -1516,9 +1534,7 @@ void ck_save(Sim &s, Checkpoint &c) {
     check(hipStreamSynchronize(s.stream), "checkpoint");
     c.step = s.step;
     c.st = s.st;
-    c.budgets[0] = s.budget_em_rounds;
-    c.budgets[1] = s.budget_ovl_rounds;
-    c.budgets[2] = s.budget_overlaps;
+    c.budgets = s.budget;
 }
 
 void ck_restore(Sim &s, const Checkpoint &c) {
@@ -1537,9 +1553,7 @@ void ck_restore(Sim &s, const Checkpoint &c) {
     check(hipStreamSynchronize(s.stream), "restore");
     s.step = c.step;
     s.st = c.st;
-    s.budget_em_rounds = c.budgets[0];
-    s.budget_ovl_rounds = c.budgets[1];
-    s.budget_overlaps = c.budgets[2];
+    s.budget = c.budgets;
 }
 
 void tape_free(Tape &tp) {
