@@ -32,19 +32,31 @@ PEAK_FP64_TFLOPS = 78.6
 
 # HBM bytes per k_force launch on the default workload from two rocprofv3 --pmc passes
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
-# 1 GiB copy; valid only for the kernel source it was measured on (sha1 below).
-MEASURED_TRAFFIC = {"sha1": "8bac9cffa81cb2ad39614b828de57ecf8b0b0d69", "workload": "C2", "n": 65536,
-                    "bytes_per_launch": 24767440.7}
+# 1 GiB copy; valid only for the force kernel's source it was measured on (sha1 of
+# the force section of k_particles.hip, see force_source_sha1).
+MEASURED_TRAFFIC = {"sha1": "36fd7a94939733b5f8346554da55c2376a8c2442", "workload": "C2", "n": 65536,
+                    "force_config": {"chunk": 2048, "per_lane": 2, "persistent": 0},
+                    "bytes_per_launch": 25247878.2}
 
 
-def measured_traffic(workload, n):
+def force_source_sha1():
+    """sha1 of the all-pairs force section of k_particles.hip (d^-3, pair loops, tiles, launches)."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1703_02484_amd", "csrc", "k_particles.hip")
-    with open(src, "rb") as fh:
-        h = hashlib.sha1(fh.read()).hexdigest()
+    with open(src) as fh:
+        text = fh.read()
+    a = text.index("// ---------------------------------------------------------------- forces")
+    b = text.index("// F_i = sum_c K[s_i][spec(c)] Phi_{i,c} over the chunks")
+    return hashlib.sha1(text[a:b].encode()).hexdigest()
+
+
+def measured_traffic(workload, n, fcfg):
+    h = force_source_sha1()
     m = MEASURED_TRAFFIC
     if h != m["sha1"] or workload != m["workload"] or n != m["n"]:
+        return None
+    if any(fcfg[k] != v for k, v in m["force_config"].items()):   # counted on another launch configuration
         return None
     return m["bytes_per_launch"]
 
@@ -335,7 +347,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": measured_traffic(w.name, n),
+            "traffic": measured_traffic(w.name, n, fcfg),
             "traffic_unit": "bytes per launch",
             "flops_per_launch": FLOPS_PER_PAIR * pairs,
             "avg_launch_ms": avg_force_s * 1e3,
