@@ -41,8 +41,10 @@
 namespace bd {
 namespace {
 
-constexpr int kMaxGrid = 512;      // full scans over triangles
-constexpr int kListGridMax = 128;  // worklist-driven launches (usually a few hundred items, often none)
+constexpr int kMaxGrid = 512;      // full scans over triangles that take per-workgroup atomics
+constexpr int kScanGrid = 4096;    // full scans without them (many waves in flight hide the gathers' latency)
+constexpr int kScanBlock = 1024;   // full scans with per-workgroup atomics: few workgroups, many waves
+constexpr int kListGridMax = 256;  // worklist-driven launches (usually a few hundred items, often none)
 
 struct Topo {
     int n, inf, nvert, T;   // disks, first infinite-vertex id, all vertex ids, triangles
@@ -504,7 +506,7 @@ __device__ __forceinline__ bool add_block_count(int *counter, const int *block_c
     return true;
 }
 
-__global__ void k_validate(Topo t, int rep, int last) {
+__global__ __launch_bounds__(kScanBlock) void k_validate(Topo t, int rep, int last) {
     __shared__ int inv;
     if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
     if (threadIdx.x == 0) inv = 0;
@@ -551,8 +553,8 @@ __device__ __forceinline__ void detect_checks(const Topo &t, int k, int stamp, i
 // workgroup's LDS and copied out with one reservation on the shared counter
 // per kDetStage entries, not one per wavefront and edge (same-address
 // atomics from every CU serialise and dominated this scan).
-constexpr int kDetBlock = 256;
-constexpr int kDetStage = 4096;
+constexpr int kDetBlock = kScanBlock;
+constexpr int kDetStage = 16384;   // 64 KiB of LDS
 constexpr int kDetPerIter = 6 * kDetBlock;   // at most two disks for each of three edges per thread
 
 __device__ __forceinline__ void det_flush(const Topo &t, int k, int *buf, int &cnt, int &base) {
@@ -952,14 +954,21 @@ __global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0
 
 // Topology snapshot before a repair (skipped once the step has stopped, so the
 // snapshot of the failing repair survives).
-__global__ void k_snapshot(Topo t, int *snap_v, int *snap_twin, int *snap_vh, int nvh) {
+__global__ void k_snapshot(Topo t, int *snap_v, int *snap_twin, int *snap_vh, int nvh, int vec) {
     if (stopped(t.ctl)) return;
     const int H = 3 * t.T;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x) {
+    const int H4 = vec ? H / 4 : 0, N4 = vec ? nvh / 4 : 0;   // 16-byte copies when aligned, then the tails
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H4; i += stride) {
+        reinterpret_cast<int4 *>(snap_v)[i] = reinterpret_cast<const int4 *>(t.he_v)[i];
+        reinterpret_cast<int4 *>(snap_twin)[i] = reinterpret_cast<const int4 *>(t.he_twin)[i];
+        if (i < N4) reinterpret_cast<int4 *>(snap_vh)[i] = reinterpret_cast<const int4 *>(t.vert_he)[i];
+    }
+    for (int i = 4 * H4 + blockIdx.x * blockDim.x + threadIdx.x; i < H; i += stride) {
         snap_v[i] = t.he_v[i];
         snap_twin[i] = t.he_twin[i];
-        if (i < nvh) snap_vh[i] = t.vert_he[i];
     }
+    for (int i = 4 * N4 + blockIdx.x * blockDim.x + threadIdx.x; i < nvh; i += stride) snap_vh[i] = t.vert_he[i];
 }
 
 __global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
@@ -997,7 +1006,7 @@ inline int grid_for(long items, int cap = kMaxGrid) {
 // empty list, and an empty launch costs more the more workgroups it has, so
 // the grid grows with the problem (lists grow with it), from 16 to 128.
 inline int list_grid(const Sim &s) {
-    const int g = s.n / 2048;
+    const int g = s.n / 1024;
     return g < 16 ? 16 : (g > kListGridMax ? kListGridMax : g);
 }
 
@@ -1006,7 +1015,7 @@ inline int list_grid(const Sim &s) {
 void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
     round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, round, slot,
+    hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T, kScanGrid)), dim3(256), 0, s.stream, t, round, slot,
                        reversal ? 1 : 0);
 }
 
@@ -1030,7 +1039,7 @@ void launch_flip_fix(Sim &s, int round, int slot) {
 
 void launch_validate(Sim &s, int rep, int last) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(s.T)), dim3(256), 0, s.stream, t, rep, last);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for((s.T + 3) / 4)), dim3(kScanBlock), 0, s.stream, t, rep, last);
 }
 
 void launch_validate_local(Sim &s, int rep, int k, int last) {
@@ -1041,7 +1050,7 @@ void launch_validate_local(Sim &s, int rep, int k, int last) {
 void launch_ovl_detect(Sim &s, int vstamp, int k, int check) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for(s.T)), dim3(kDetBlock), 0, s.stream, t, vstamp,
+    hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for((s.T + 3) / 4)), dim3(kDetBlock), 0, s.stream, t, vstamp,
                        1.0 - s.p.contact_tol, k, check);
 }
 
@@ -1076,8 +1085,11 @@ void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds) {
 
 void launch_snapshot(Sim &s) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_snapshot, dim3(grid_for(s.H)), dim3(256), 0, s.stream, t, s.snap_v, s.snap_twin, s.snap_vh,
-                       s.nv + s.R);
+    const void *p[] = {s.he_v, s.he_twin, s.vert_he, s.snap_v, s.snap_twin, s.snap_vh};
+    int vec = 1;
+    for (const void *q : p) vec &= ((uintptr_t)q % 16 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_snapshot, dim3(grid_for(s.H / 4, kScanGrid)), dim3(256), 0, s.stream, t, s.snap_v,
+                       s.snap_twin, s.snap_vh, s.nv + s.R, vec);
 }
 
 void launch_scatter_oldpos(Sim &s, int k) {
