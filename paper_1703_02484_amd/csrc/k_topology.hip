@@ -200,19 +200,54 @@ __device__ __forceinline__ bool last_workgroup(int *ctl, bool released) {
     return last != 0;
 }
 
+// Workgroup staging of worklist appends (LDS): lanes take stage positions
+// with one LDS atomic per wavefront; at the end of the launch the workgroup
+// reserves its entries on the shared counter with one atomic and copies them
+// out.  Entries beyond the stage's capacity go to the list directly.
+template <int CAP>
+struct Stage {
+    int buf[CAP];
+    int cnt, base;
+};
+
+template <int CAP>
+__device__ __forceinline__ void stage_init(Stage<CAP> &st) {
+    if (threadIdx.x == 0) st.cnt = 0;
+    __syncthreads();
+}
+
+// Every thread of the workgroup calls it once, at the end.
+template <int CAP>
+__device__ __forceinline__ void stage_flush(Stage<CAP> &st, int *counter, int *list) {
+    __syncthreads();
+    const int n = st.cnt < CAP ? st.cnt : CAP;
+    if (threadIdx.x == 0 && n > 0) st.base = atomicAdd(counter, n);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) list[st.base + i] = st.buf[i];
+}
+
 // Appends edge e to the worklist of round slot `slot` once per stamp.  The
-// lanes of a wavefront that push at the same time reserve their positions
-// with one atomic on the shared counter.
-__device__ __forceinline__ void push_edge(const Topo &t, int e, int stamp, int slot) {
+// lanes of a wavefront that push at the same time take their positions with
+// one atomic, on the workgroup's stage when there is one, else on the shared
+// counter.
+template <int CAP = 1>
+__device__ __forceinline__ void push_edge(const Topo &t, int e, int stamp, int slot, Stage<CAP> *st = nullptr) {
     const bool fresh = atomicExch(&t.edge_stamp[e], stamp) != stamp;
     const unsigned long long m = __ballot(fresh);
     if (m == 0) return;
     const int lane = __lane_id();
     const int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
-    if (lane == leader) base = atomicAdd(&t.ctl[K_WL + slot], __popcll(m));
+    if (lane == leader) base = atomicAdd(st ? &st->cnt : &t.ctl[K_WL + slot], __popcll(m));
     base = __shfl(base, leader);
-    if (fresh) wl_of(t, slot)[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+    if (!fresh) return;
+    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (!st)
+        wl_of(t, slot)[pos] = e;
+    else if (pos < CAP)
+        st->buf[pos] = e;
+    else
+        wl_of(t, slot)[atomicAdd(&t.ctl[K_WL + slot], 1)] = e;
 }
 
 // Is d already a neighbour of the finite vertex c?  A flip of (a, b) into
@@ -380,7 +415,9 @@ __global__ void k_flip_apply(Topo t, int round, int slot) {
     flip_apply_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
-__device__ __forceinline__ void flip_fix_body(const Topo &t, int round, int slot, int i0, int stride) {
+template <int CAP = 1>
+__device__ __forceinline__ void flip_fix_body(const Topo &t, int round, int slot, int i0, int stride,
+                                              Stage<CAP> *st = nullptr) {
     round += t.base->rbase;
     if (stopped(t.ctl)) return;
     const int ncand = t.ctl[K_CAND + slot];
@@ -390,7 +427,7 @@ __device__ __forceinline__ void flip_fix_body(const Topo &t, int round, int slot
         const int2 cd = t.cand[idx];
         const int h = cd.x, t1 = h / 3, t2 = cd.y & 0x7FFFFFFF;
         if (!t.cand_won[idx]) {
-            if (t.tri_stamp[t1] != round && t.tri_stamp[t2] != round) push_edge(t, h, next, nslot);
+            if (t.tri_stamp[t1] != round && t.tri_stamp[t2] != round) push_edge(t, h, next, nslot, st);
             continue;
         }
         const int outer[4] = {3 * t1 + 0, 3 * t1 + 1, 3 * t2 + 0, 3 * t2 + 1};
@@ -414,15 +451,22 @@ __device__ __forceinline__ void flip_fix_body(const Topo &t, int round, int slot
                 tw = o;
                 t.he_twin[o] = nh;
             }
-            push_edge(t, nh < tw ? nh : tw, next, nslot);
+            push_edge(t, nh < tw ? nh : tw, next, nslot, st);
         }
         const int d1 = 3 * t1 + 2, d2 = 3 * t2 + 2;
-        push_edge(t, d1 < d2 ? d1 : d2, next, nslot);
+        push_edge(t, d1 < d2 ? d1 : d2, next, nslot, st);
     }
 }
 
+constexpr int kFixStage = 2048;
+
 __global__ void k_flip_fix(Topo t, int round, int slot) {
-    flip_fix_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    __shared__ Stage<kFixStage> st;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
+    stage_init(st);
+    flip_fix_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
+    const int nslot = slot + 1 == MAXR ? 0 : slot + 1;
+    stage_flush(st, &t.ctl[K_WL + nslot], wl_of(t, nslot));
 }
 
 // Counts finite triangles that are not positively oriented after repair `rep`.
@@ -819,7 +863,9 @@ __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double ke
 // Apply: write the new positions (keeping the old ones for a replay) and queue
 // every edge of the moved disk's triangles (incident and link edges) as the
 // worklist of round slot `slot`, the first round of the following repair.
-__device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_round, int slot, int i0, int stride) {
+template <int CAP = 1>
+__device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_round, int slot, int i0, int stride,
+                                               Stage<CAP> *st = nullptr) {
     if (stopped(t.ctl)) return;
     next_round += t.base->rbase;
     const int ntouched = t.ctl[K_TOUCH + k];
@@ -854,8 +900,8 @@ __device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_ro
                 topo_err(t);
                 break;
             }
-            push_edge(t, h < tw ? h : tw, next_round, slot);
-            push_edge(t, l < lt ? l : lt, next_round, slot);
+            push_edge(t, h < tw ? h : tw, next_round, slot, st);
+            push_edge(t, l < lt ? l : lt, next_round, slot, st);
             h = t.he_twin[bd_prev(h)];
             if (bad_he(t, h)) {
                 topo_err(t);
@@ -865,8 +911,14 @@ __device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_ro
     }
 }
 
+constexpr int kApplyStage = 4096;
+
 __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
-    ovl_apply_body(t, k, next_round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    __shared__ Stage<kApplyStage> st;
+    if (stopped(t.ctl)) return;
+    stage_init(st);
+    ovl_apply_body(t, k, next_round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
+    stage_flush(st, &t.ctl[K_WL + slot], wl_of(t, slot));
 }
 
 // The overlap rounds after the first detection in one workgroup: each phase
