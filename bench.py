@@ -100,7 +100,8 @@ def run_short_range(steps, warmup):
             "step_gbs_algorithmic": step_gbs, "step_frac_hbm": step_gbs / 8000.0,
             "overlap_rounds_per_step": d["overlap_rounds_total"] / steps,
             "flips_per_step": d["flips_total"] / steps, "verlet_rebuilds": d["verlet_rebuilds"],
-            "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"]}
+            "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"],
+            "host_continued_steps": d["host_continued"]}
 
 
 def run_batched(steps, warmup, loop_steps):
@@ -137,7 +138,7 @@ def run_batched(steps, warmup, loop_steps):
            "force_ms": avg_s * 1e3, "force_tflops": tflops, "force_frac_fp64": tflops / PEAK_FP64_TFLOPS,
            "force_config": cfg,
            "overlap_rounds_per_step": (st1["overlap_rounds_total"] - st0["overlap_rounds_total"]) / steps,
-           "host_rebuilds": st1["host_rebuilds"]}
+           "host_rebuilds": st1["host_rebuilds"], "host_continued_steps": st1["host_continued"]}
     # the same batch with FP32 pair sums (positions and predicates stay FP64)
     b32 = binding.Sim.from_workloads(ws, fp32=True)
     b32.set_graph_mode(True)
@@ -338,6 +339,7 @@ def main():
             "flip_rounds_per_step": d["flip_rounds_total"] / args.steps,
             "kinetic_repairs": d["kinetic_repairs"],
             "host_rebuilds": d["host_rebuilds"],
+            "host_continued_steps": d["host_continued"],
         },
         "roofline": {
             "kernel": "all-pairs force (" + ("k_force_queue" if fcfg["persistent"] else "k_force") + ")",

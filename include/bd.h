@@ -113,7 +113,8 @@ typedef struct bd_stats {
     int64_t kinetic_repairs;        /* repairs redone on the device in sub-steps (multi-edge crossings) */
     int64_t host_rebuilds;          /* repairs that fell back to a host triangulation */
     int64_t verlet_rebuilds;        /* neighbour-list rebuilds (cutoff > 0) */
-    int64_t reserved[3];
+    int64_t host_continued;         /* steps whose enqueued rounds ran out and the host finished */
+    int64_t reserved[2];
 } bd_stats;
 
 typedef struct bd_sim bd_sim;

@@ -53,11 +53,11 @@ class ForceConfig(ctypes.Structure):
 
 STAT_NAMES = ("steps", "overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "cap_hits",
               "reversals", "noise_clamps", "flips_total", "inversion_flips", "flip_rounds_total", "kinetic_repairs",
-              "host_rebuilds", "verlet_rebuilds")
+              "host_rebuilds", "verlet_rebuilds", "host_continued")
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_int64) for name in STAT_NAMES] + [("reserved", ctypes.c_int64 * 3)]
+    _fields_ = [(name, ctypes.c_int64) for name in STAT_NAMES] + [("reserved", ctypes.c_int64 * 2)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name in STAT_NAMES}

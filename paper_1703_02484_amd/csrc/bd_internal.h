@@ -37,7 +37,8 @@ enum Ctl {
     K_FL_EPOCH = 15,   // stamp of the last overlap detection (dedupes the flipped lists)
     K_VT_N = 16,       // triangles rewritten by flips since the last overlap detection (list length)
     K_TICKET = 17,     // workgroups finished in the current launch (last-workgroup checks; back to 0 after)
-    K_CAND = 18,                     // [MAXR] flip candidates of round slot j
+    K_NL_BUILT = 18,   // the neighbour lists were rebuilt on the device at the start of this step
+    K_CAND = 19,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -45,7 +46,13 @@ enum Ctl {
     K_OVL = K_TOUCH + MAXO,          // [MAXO] overlapping edges found by overlap round k
     N_CTL = K_OVL + MAXO
 };
-enum HaltReason { HALT_REPAIR_BUDGET = 1, HALT_INVALID = 2, HALT_TOPOLOGY = 3, HALT_OVERLAP_BUDGET = 4 };
+enum HaltReason {
+    HALT_REPAIR_BUDGET = 1,
+    HALT_INVALID = 2,
+    HALT_TOPOLOGY = 3,
+    HALT_OVERLAP_BUDGET = 4,
+    HALT_NL_CAPACITY = 5   // a rebuild inside a queued step found more neighbours than the lists hold
+};
 
 enum Acc {
     A_FLIPS = 0,
@@ -75,11 +82,13 @@ struct Tile {
 struct StepBase {
     long long step;
     int rbase, vbase;
-    int stop;        // 0 run; 1 the step batch_idx halted; 2 lists must be rebuilt first
+    int stop;        // 0 run; 1 the step batch_idx halted; 2 the ring is full
     int batch_idx;   // steps of the current batch completed on the device
+    int nl_req;      // the skin test of the last step asks for new neighbour lists
+    int nl_now;      // this step rebuilds them before its force (copied from nl_req when it begins)
 };
-constexpr int kRing = 64;
-constexpr size_t kMaxGraphs = 16;   // captured step graphs kept per handle (one per budget setting)      // most steps queued at once in graph mode
+constexpr int kRing = 64;            // most steps queued at once in graph mode
+constexpr size_t kMaxGraphs = 16;    // captured step graphs kept per handle (one per budget setting)
 
 constexpr int MAXACT = 16;    // overlapping partners recorded per disk and round (adjoint tape)
 
@@ -218,8 +227,7 @@ struct Sim {
     int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_items = nullptr;
     double *xbuild = nullptr, *ybuild = nullptr;
     double2 *fsr = nullptr;          // short-range forces, caller order
-    void *scan_tmp = nullptr;
-    size_t scan_bytes = 0;
+    int *scan_bsum = nullptr;        // per-block totals of the cell-count scan
     // triangulation (half-edge SoA, ghosts included)
     int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
     unsigned long long *claim = nullptr;
@@ -245,6 +253,7 @@ struct Sim {
     int rbase = 0, vbase = 0;        // bases currently on the device; launches pass stamp - base
     // captured steps (one graph triple per round-budget setting)
     bool use_graph = false;
+    int batch_hint = kRing;          // graph steps queued per batch (adapts to the steps between stops)
     int tail_mode = -1;              // overlap rounds after the first detection: 0 launch per phase,
                                      // 1 one workgroup, -1 chosen from the problem size
     struct StepGraph {
@@ -288,8 +297,9 @@ int force_max_grid(Sim &s, int per_lane);            // resident workgroups of t
 void launch_em(Sim &s);
 void launch_reduce_forces(Sim &s);
 // short-range path (k_verlet.hip)
-size_t verlet_scan_bytes(int ncells);
+int verlet_scan_blocks(int ncells);
 void launch_verlet_build(Sim &s);
+void launch_verlet_build_requested(Sim &s);   // the same kernels, each doing nothing unless the step asks (graph mode)
 void launch_force_nl(Sim &s);
 void launch_skin_check(Sim &s);
 // triangulation (slot: round slot in ctl; rep: repair slot)

@@ -262,11 +262,11 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
                                             double *__restrict__ xo, double *__restrict__ yo,
                                             double *__restrict__ th, double *__restrict__ tho,
                                             unsigned long long *__restrict__ acc, const double2 *__restrict__ fdirect,
-                                            signed char *__restrict__ wf) {
+                                            signed char *__restrict__ wf, const int *__restrict__ ctl) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
-    if (base->stop) return;
+    if (base->stop || ctl[K_HALT]) return;   // K_HALT this early: the step's neighbour lists overflowed
     if (i < a.n) {
         const RepInfo ri = reps[rep_of[i]];
         double fx, fy;
@@ -329,15 +329,22 @@ __global__ void k_zero_one(int *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-__global__ void k_step_begin(int *__restrict__ ctl, const StepBase *__restrict__ base) {
-    if (base->stop) return;   // keep the halted step's control block for the host
+__global__ void k_step_begin(int *__restrict__ ctl, StepBase *__restrict__ base) {
+    if (base->stop) {   // keep the halted step's control block for the host; no list rebuild
+        if (threadIdx.x == 0) base->nl_now = 0;
+        return;
+    }
     for (int i = threadIdx.x; i < N_CTL; i += blockDim.x) ctl[i] = 0;
+    if (threadIdx.x == 0) {   // a rebuild the last step's skin test asked for happens in this step
+        base->nl_now = base->nl_req;
+        base->nl_req = 0;
+    }
 }
 
 // End of a queued step: record its control block in the ring (this kernel),
 // then either advance the step counter and the stamp bases, or stop the
-// batch when the step halted (the host finishes it) or needs new neighbour
-// lists (k_step_advance).
+// batch when the step halted (the host finishes it) or the ring is full
+// (k_step_advance).
 __global__ void k_step_record(const int *__restrict__ ctl, const StepBase *__restrict__ base,
                               int *__restrict__ ring) {
     if (base->stop) return;
@@ -356,13 +363,13 @@ __global__ void k_step_advance(const int *__restrict__ ctl, StepBase *__restrict
     base->rbase += r_used;
     base->vbase += v_used;
     base->batch_idx = idx + 1;
-    if (ctl[K_NL_REBUILD] || idx + 1 >= kRing) base->stop = 2;
+    if (idx + 1 >= kRing) base->stop = 2;
 }
 
 }  // namespace
 
 void launch_step_begin(Sim &s) {
-    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s.stream, s.ctl, (const StepBase *)s.dbase);
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s.stream, s.ctl, s.dbase);
 }
 
 void launch_step_end(Sim &s, int r_used, int v_used) {
@@ -465,12 +472,12 @@ void launch_em(Sim &s) {
         hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
                            (const float2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
-                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf);
+                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf, (const int *)s.ctl);
     else
         hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
                            (const double2 *)s.part, s.reps,
                            s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
-                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf);
+                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf, (const int *)s.ctl);
 }
 
 void launch_reduce_forces(Sim &s) {

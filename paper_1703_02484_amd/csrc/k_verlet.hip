@@ -9,9 +9,10 @@
 // then every pair with d <= r_cut at force time is in the list.  The build is a
 // counting sort of the disks by cell (count, exclusive scan, scatter, sort of
 // each cell's few ids) followed by one thread per disk scanning the 3 x 3
-// cells around it.
+// cells around it.  In graph mode the build kernels are part of every
+// queued step and do nothing unless the previous step's skin test asked for
+// new lists (`req` points at the step's flag; null: always build).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include "bd_internal.h"
 #include "geom.h"
@@ -25,27 +26,68 @@ __device__ __forceinline__ int cell_coord(double v, double inv_cell, int nc) {
 }
 
 __global__ void k_cell_count(int n, const double *__restrict__ x, const double *__restrict__ y, double inv_cell,
-                             int nc, int *__restrict__ cell_of, int *__restrict__ cell_count) {
+                             int nc, int *__restrict__ cell_of, int *__restrict__ cell_count, const int *req) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (req && !*req)) return;
     int c = cell_coord(y[i], inv_cell, nc) * nc + cell_coord(x[i], inv_cell, nc);
     cell_of[i] = c;
     atomicAdd(&cell_count[c], 1);
 }
 
+// Exclusive scan of the cell counts (m = cells + 1 entries; the last count is
+// 0, so start[m - 1] = n): each 1024-entry block scans in LDS and records its
+// total, then every block adds the totals of the blocks before it.
+constexpr int kScanBlk = 1024;
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_local(int m, const int *__restrict__ cnt, int *__restrict__ start,
+                                                         int *__restrict__ bsum, const int *req) {
+    __shared__ int buf[kScanBlk];
+    if (req && !*req) return;
+    const int i = blockIdx.x * kScanBlk + threadIdx.x;
+    const int v = i < m ? cnt[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlk; off <<= 1) {
+        const int add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (i < m) start[i] = buf[threadIdx.x] - v;
+    if (threadIdx.x == kScanBlk - 1) bsum[blockIdx.x] = buf[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kScanBlk) void k_scan_offsets(int m, int *__restrict__ start,
+                                                           const int *__restrict__ bsum, const int *req) {
+    __shared__ int total;
+    if ((req && !*req) || blockIdx.x == 0) return;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    int acc = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlk) acc += bsum[b];
+    if (acc) atomicAdd(&total, acc);
+    __syncthreads();
+    const int i = blockIdx.x * kScanBlk + threadIdx.x;
+    if (i < m) start[i] += total;
+}
+
 __global__ void k_cell_scatter(int n, const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                               int *__restrict__ cell_fill, int *__restrict__ cell_items) {
+                               int *__restrict__ cell_fill, int *__restrict__ cell_items, const int *req) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (req && !*req)) return;
     int c = cell_of[i];
     cell_items[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
 }
 
 // One thread per cell: the scatter filled each cell in arbitrary order; sort
 // it by id (cells hold a few disks) so that the lists below are deterministic.
-__global__ void k_cell_sort(int ncell, const int *__restrict__ cell_start, int *__restrict__ cell_items) {
+// The cell's count and fill counter are zeroed for the next build.
+__global__ void k_cell_sort(int ncell, const int *__restrict__ cell_start, int *__restrict__ cell_items,
+                            int *__restrict__ cell_count, int *__restrict__ cell_fill, const int *req) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
+    if (c >= ncell || (req && !*req)) return;
+    cell_count[c] = 0;
+    cell_fill[c] = 0;
     const int b = cell_start[c], e = cell_start[c + 1];
     for (int p = b + 1; p < e; ++p) {
         const int v = cell_items[p];
@@ -68,10 +110,10 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
                                                   const int *__restrict__ cell_start,
                                                   const int *__restrict__ cell_items, int *__restrict__ nl,
                                                   int *__restrict__ nl_cnt, double *__restrict__ xb,
-                                                  double *__restrict__ yb, int *__restrict__ overflow) {
+                                                  double *__restrict__ yb, int *__restrict__ overflow, const int *req) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (req && !*req)) return;
     const double xi = x[i], yi = y[i];
     const int cx = cell_coord(xi, inv_cell, nc), cy = cell_coord(yi, inv_cell, nc);
     int cnt = 0;
@@ -102,10 +144,11 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
                                                   const int *__restrict__ sp, const double *__restrict__ K, int S,
                                                   int kind, double q, double A, double lam, double rc,
                                                   const int *__restrict__ nl, const int *__restrict__ nl_cnt,
-                                                  double2 *__restrict__ f, const StepBase *__restrict__ base) {
+                                                  double2 *__restrict__ f, const StepBase *__restrict__ base,
+                                                  const int *__restrict__ ctl) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || base->stop) return;
+    if (i >= n || base->stop || ctl[K_HALT]) return;   // K_HALT: the lists of this step overflowed
     const double xi = x[i], yi = y[i];
     const int si = sp[i];
     const int m = nl_cnt[i];
@@ -129,62 +172,94 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
 
 // Skin test at the end of a step: has any disk moved more than skin / 2 since
 // the lists were built?  (strict, displacement including corrections and walls)
+// The request also goes to the step base, where the next queued step finds it.
+// (Steps queued after one that halted run it too, harmlessly: the host clears
+// both flags before it tests the halted step's final positions itself.)
 __global__ void k_skin_check(int n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ xb, const double *__restrict__ yb, double half_skin2,
-                             int *__restrict__ flag) {
+                             int *__restrict__ flag, StepBase *__restrict__ base) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool out = false;
     if (i < n) {
         const double dx = x[i] - xb[i], dy = y[i] - yb[i];
         out = dx * dx + dy * dy > half_skin2;
     }
-    if (__ballot(out) != 0 && __lane_id() == 0) atomicOr(flag, 1);
+    if (__ballot(out) != 0 && __lane_id() == 0) {
+        atomicOr(flag, 1);
+        atomicOr(&base->nl_req, 1);
+    }
+}
+
+// After a rebuild inside a queued step: count it, and stop the step before its
+// force if a disk had more neighbours than the lists hold (the host grows them
+// and runs the step again).
+__global__ void k_nl_check(int *__restrict__ ctl, const StepBase *__restrict__ base) {
+    if (threadIdx.x != 0 || base->stop || !base->nl_now) return;
+    ctl[K_NL_BUILT] = 1;
+    if (ctl[K_NL_OVERFLOW] > 0) {
+        ctl[K_REASON] = HALT_NL_CAPACITY;
+        ctl[K_STAGE] = 0;
+        ctl[K_HALT] = 1;
+    }
 }
 
 inline int blocks(int n) { return (n + 255) / 256; }
 
 }  // namespace
 
-// Sizes the scan's temporary storage; called once at init.
-size_t verlet_scan_bytes(int ncells) {
-    size_t bytes = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (int *)nullptr, (int *)nullptr, ncells + 1);
-    return bytes;
-}
+// Blocks of the cell-count scan (cells + 1 entries); sizes its per-block totals.
+int verlet_scan_blocks(int ncells) { return (ncells + 1 + kScanBlk - 1) / kScanBlk; }
 
-// Rebuilds the lists from the current positions.  The caller zeroed
-// cell_count, cell_fill and the overflow flag.
-void launch_verlet_build(Sim &s) {
+namespace {
+
+// The build kernels; req = null builds unconditionally (the caller zeroed
+// cell_count, cell_fill and the overflow flag), else only when *req != 0.
+void enqueue_build(Sim &s, const int *req) {
     const double inv_cell = (double)s.nl_nc / s.L_h[0];
+    const int m = s.nl_ncell + 1;
     hipLaunchKernelGGL(k_cell_count, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell, s.nl_nc,
-                       s.cell_of, s.cell_count);
-    size_t bytes = s.scan_bytes;
-    (void)hipcub::DeviceScan::ExclusiveSum(s.scan_tmp, bytes, s.cell_count, s.cell_start, s.nl_ncell + 1, s.stream);
+                       s.cell_of, s.cell_count, req);
+    hipLaunchKernelGGL(k_scan_local, dim3(verlet_scan_blocks(s.nl_ncell)), dim3(kScanBlk), 0, s.stream, m,
+                       (const int *)s.cell_count, s.cell_start, s.scan_bsum, req);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(verlet_scan_blocks(s.nl_ncell)), dim3(kScanBlk), 0, s.stream, m,
+                       s.cell_start, (const int *)s.scan_bsum, req);
     hipLaunchKernelGGL(k_cell_scatter, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.cell_of, s.cell_start,
-                       s.cell_fill, s.cell_items);
+                       s.cell_fill, s.cell_items, req);
     hipLaunchKernelGGL(k_cell_sort, dim3(blocks(s.nl_ncell)), dim3(256), 0, s.stream, s.nl_ncell, s.cell_start,
-                       s.cell_items);
+                       s.cell_items, s.cell_count, s.cell_fill, req);
     const double rl = s.fp.cutoff + s.fp.skin;
     if (s.nl_cap <= 32)
         hipLaunchKernelGGL(k_nl_build<32>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
-                           s.ctl + K_NL_OVERFLOW);
+                           s.ctl + K_NL_OVERFLOW, req);
     else
         hipLaunchKernelGGL(k_nl_build<96>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
-                           s.ctl + K_NL_OVERFLOW);
+                           s.ctl + K_NL_OVERFLOW, req);
+}
+
+}  // namespace
+
+// Rebuilds the lists from the current positions.  The caller zeroed
+// cell_count, cell_fill and the overflow flag.
+void launch_verlet_build(Sim &s) { enqueue_build(s, nullptr); }
+
+void launch_verlet_build_requested(Sim &s) {
+    StepBase *b = (StepBase *)s.dbase;
+    enqueue_build(s, &b->nl_now);
+    hipLaunchKernelGGL(k_nl_check, dim3(1), dim3(64), 0, s.stream, s.ctl, (const StepBase *)s.dbase);
 }
 
 void launch_force_nl(Sim &s) {
     hipLaunchKernelGGL(k_force_nl, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sp, s.Kd, s.S,
                        s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff, s.nl, s.nl_cnt, s.fsr,
-                       (const StepBase *)s.dbase);
+                       (const StepBase *)s.dbase, (const int *)s.ctl);
 }
 
 void launch_skin_check(Sim &s) {
     const double h = 0.5 * s.fp.skin;
     hipLaunchKernelGGL(k_skin_check, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, s.xbuild, s.ybuild,
-                       h * h, s.ctl + K_NL_REBUILD);
+                       h * h, s.ctl + K_NL_REBUILD, (StepBase *)s.dbase);
 }
 
 }  // namespace bd

@@ -485,6 +485,8 @@ void write_base(Sim &s) {
     s.hbase->vbase = s.vround;
     s.hbase->stop = 0;
     s.hbase->batch_idx = 0;
+    s.hbase->nl_req = 0;   // the host rebuilds lists that are due before it queues steps
+    s.hbase->nl_now = 0;
     check(hipMemcpyAsync(s.dbase, s.hbase, sizeof(StepBase), hipMemcpyHostToDevice, s.stream), "step base");
     s.rbase = s.round_id;
     s.vbase = s.vround;
@@ -611,6 +613,7 @@ Sim::StepGraph &step_graph(Sim &s) {
     g.pre = capture(s, [&] {
         launch_step_begin(s);
         if (!s.use_nl) launch_cast(s);
+        if (s.use_nl) launch_verlet_build_requested(s);
     });
     g.force = capture(s, [&] {
         if (s.use_nl)
@@ -699,7 +702,9 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
     while (nsteps > 0) {
         if (s.use_nl && s.need_rebuild) verlet_rebuild(s);
         Sim::StepGraph &g = step_graph(s);
-        const int m = (int)std::min<int64_t>(nsteps, kRing);
+        // steps queued after one that stops still cost their launches: queue about as many
+        // steps as recently ran between stops (neighbour-list rebuilds, budget growth)
+        const int m = (int)std::min<int64_t>(nsteps, std::min(kRing, s.batch_hint));
         write_base(s);
         for (int k = 0; k < m; ++k) {
             check(hipGraphLaunch(g.pre, s.stream), "graph launch");
@@ -713,6 +718,11 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
         hb = *s.hbase;
         const int done = hb.batch_idx;
         const int nrec = done + (hb.stop == 1 ? 1 : 0);
+        // a step queued after a stop costs several batch boundaries, so grow slowly
+        if (hb.stop == 1)
+            s.batch_hint = std::max(4, nrec);
+        else if (nrec == m)
+            s.batch_hint = std::min(kRing, s.batch_hint + std::max(1, s.batch_hint / 4));
         check(hipMemcpyAsync(s.hring, s.ring, sizeof(int) * N_CTL * nrec, hipMemcpyDeviceToHost, s.stream), "ring");
         check(hipStreamSynchronize(s.stream), "sync");
         StepPlan plan;
@@ -730,7 +740,16 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
             s.vbase = s.vround;
             s.round_id += r_used;
             s.vround += v_used;
-            int rc = finish_step(s, s.hring + (size_t)j * N_CTL, plan);
+            const int *hj = s.hring + (size_t)j * N_CTL;
+            int rc;
+            if (hj[K_HALT] && hj[K_REASON] == HALT_NL_CAPACITY) {
+                // the step stopped before its force: the lists grow (the captured steps go),
+                // then the step runs again launch by launch
+                verlet_rebuild(s);
+                rc = one_step(s);
+            } else {
+                rc = finish_step(s, hj, plan);
+            }
             if (rc != BD_OK) {
                 write_base(s);
                 return rc;
@@ -752,6 +771,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     const std::vector<int> &orounds = plan.orounds;
     const std::vector<int> &rep_first = plan.rep_first;
     s.need_rebuild = s.use_nl && h[K_NL_REBUILD] != 0;
+    if (h[K_NL_BUILT]) ++s.st.verlet_rebuilds;   // rebuilt on the device at the start of this step
     // bookkeeping of the budgeted part: overlap rounds that moved disks
     int rounds = h[K_OVL_ROUNDS];
     if (h[K_HALT]) {
@@ -769,6 +789,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
             return BD_ERR_TRIANGULATION;
         }
         // continue host-driven after the halting point
+        ++s.st.host_continued;
         fill_int(s, s.ctl + K_HALT, 1, 0);
         fill_int(s, s.ctl + K_DONE, 1, 0);
         Cursor hc;
@@ -1158,7 +1179,7 @@ void free_all(Sim &s) {
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
                     s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
-                    s.xbuild, s.ybuild, s.fsr, s.scan_tmp};
+                    s.xbuild, s.ybuild, s.fsr, s.scan_bsum};
     for (void *p : ptrs)
         dfree(p);
     drop_graphs(s);
@@ -1444,8 +1465,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
         s.xbuild = dalloc<double>(n);
         s.ybuild = dalloc<double>(n);
         s.fsr = dalloc<double2>(n);
-        s.scan_bytes = verlet_scan_bytes(s.nl_ncell);
-        s.scan_tmp = dalloc<char>(s.scan_bytes);
+        s.scan_bsum = dalloc<int>(verlet_scan_blocks(s.nl_ncell));
     }
     s.acc = dalloc<unsigned long long>(N_ACC);
     if (hipHostMalloc((void **)&s.hctl, sizeof(int) * N_CTL, hipHostMallocDefault) != hipSuccess)
