@@ -39,6 +39,24 @@ MEASURED_TRAFFIC = {"sha1": "36fd7a94939733b5f8346554da55c2376a8c2442", "workloa
                     "bytes_per_launch": 25247878.2}
 
 
+FORCE_KERNELS = {0: "k_force", 1: "k_force_queue", 2: "k_force_sym"}
+# VALU instructions per pair evaluation in the force kernels' inner loops (read off their gfx950 ISA):
+# ordinary forms, per ordered pair: 2 sub, mul + FMA for d^2, v_rsq, 2 mul for d^-3, 2 FMA;
+# symmetric form (FP32), per unordered pair: the same, 2 FMA for j's side, and one DPP move
+# (a step moves x, y and both sums of each of a lane's 2 j: 8 moves for its 8 pairs)
+VALU_PER_PAIR = {0: 9.0, 1: 9.0, 2: 12.0}
+LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: one VALU lane-op per slot
+
+
+def valu_issue_frac(fcfg, n, seconds, fp32):
+    """Fraction of the VALU issue slots the force launch used (FP32 only; FP64 math is not one op per flop)."""
+    if not fp32:
+        return None
+    form = fcfg["persistent"]
+    pairs = n * (n - 1) / 2 if form == 2 else n * (n - 1)
+    return VALU_PER_PAIR[form] * pairs / seconds / LANE_ISSUE_PER_S
+
+
 def force_source_sha1():
     """sha1 of the all-pairs force section of k_particles.hip (d^-3, pair loops, tiles, launches)."""
     import hashlib
@@ -342,8 +360,10 @@ def main():
             "host_continued_steps": d["host_continued"],
         },
         "roofline": {
-            "kernel": "all-pairs force (" + ("k_force_queue" if fcfg["persistent"] else "k_force") + ")",
+            "kernel": "all-pairs force (" + FORCE_KERNELS[fcfg["persistent"]] + ")",
             "force_config": fcfg,
+            "flop_convention": "12 flops per ordered pair (the all-pairs force's work, however it is evaluated)",
+            "valu_issue_frac": valu_issue_frac(fcfg, n, avg_force_s, w.fp32_forces),
             "bound": "alu",
             "achieved": achieved,
             "peak": peak,

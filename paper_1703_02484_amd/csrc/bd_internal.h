@@ -73,6 +73,16 @@ struct Tile {
     long long work;   // (i1 - i0) * (je - js), for ordering
 };
 
+// Symmetric form of the all-pairs force: chunks A = [i0, i1) and B = [j0, j1)
+// of one system (A before B, or A itself), each pair evaluated once and both
+// sides written: part[pbase_i + i] (i in A, sum over B) and part[pbase_j + j]
+// (j in B, sum over A; not for A itself).
+constexpr int kSymChunk = 1024;   // longest chunk of the symmetric form
+struct SymTile {
+    int i0, i1, j0, j1;
+    long long pbase_i, pbase_j;
+};
+
 // Per-step values that kernels read from device memory, so that a captured
 // step can be replayed: the noise counter and the bases of the flip-round and
 // overlap-round stamps (kernels receive stamps relative to these bases).
@@ -205,14 +215,18 @@ struct Sim {
     int *pos_of = nullptr;           // library index -> sorted index
     void *pj = nullptr;              // float2 / double2 [n], sorted order
     void *part = nullptr;            // [nchunks][n] float2 / double2 partial sums
-    Tile *tiles = nullptr;           // force tiles, longest first
+    Tile *tiles = nullptr;           // force tiles, longest first (symmetric form: the adjoint's tiles)
     int ntiles = 0;
+    SymTile *stiles = nullptr;       // symmetric form: chunk pairs, then each chunk with itself
+    int nstiles = 0;
+    long long stiles_cap = 0;
     int *chunk_spec = nullptr;       // species of each chunk
     long long part_cap = 0;          // elements allocated for part
     long long tiles_cap = 0;         // tiles allocated
     int chunk_len = 0;               // j per chunk (last chunk of a species may be shorter)
     int per_lane = 4;                // i per lane: a tile holds 256 * per_lane particles
-    int persistent = 0;              // 1: fixed grid pulling tiles from a queue
+    int persistent = 0;              // launch form: 0 workgroup per tile, 1 fixed grid pulling tiles from a queue,
+                                     // 2 symmetric chunk pairs (SymTile)
     int force_grid = 0;              // workgroups of the persistent launch
     int tuned = 0;                   // 1: tiling chosen by timing, 2: from the tuning cache, 0: fixed rule
     double tuned_ms = 0.0;           // force time of the chosen configuration when tuned, else 0

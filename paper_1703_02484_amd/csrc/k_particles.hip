@@ -196,6 +196,142 @@ __global__ __launch_bounds__(kForceBlock) void k_force_queue(const T2 *__restric
     }
 }
 
+// Symmetric form (inverse-square law).  A tile is a pair of chunks A, B of
+// one system: each of the 4 wavefronts owns up to 256 particles i of A, 4 per
+// lane, in registers.  The particles j of B pass through the wavefront in
+// groups of 128 (2 per lane); a group turns around the wavefront one lane per
+// step (DPP wave_rol: lane l takes lane l+1's values) for 64 steps, so every
+// lane meets every j of the group once.  g = (r_i - r_j)/d^3 is added to i's
+// sum and subtracted from j's sum, which travels with j; after the 64 steps
+// each j is back in its lane and the wavefront leaves its sums in LDS.  At the
+// end the 4 wavefronts' sums are added in wavefront order (deterministic) and
+// written for B's particles (slot of chunk A).  A chunk paired with itself
+// (j0 == i0) takes i's side only, with d^2 floored so that i == j adds 0.
+// Padding i (j) sit at +BIG (-BIG): their g underflow to exactly 0.
+template <typename T>
+__device__ __forceinline__ T rot1(T v);
+template <>
+__device__ __forceinline__ float rot1<float>(float v) {   // every lane has a source: no old value needed
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ double rot1<double>(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x134, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T sym_big();
+template <>
+__device__ __forceinline__ float sym_big<float>() { return 1e18f; }   // (2e18)^2 finite, (1e18)^-3 underflows
+template <>
+__device__ __forceinline__ double sym_big<double>() { return 1e150; }
+
+constexpr int kSymP = 4, kSymQ = 2;
+
+// The 64 steps of one group of j (every lane active: the rotation reads all lanes).
+template <typename T, bool SELF>
+__device__ __forceinline__ void sym_group(const T (&xi)[kSymP], const T (&yi)[kSymP], T (&fx)[kSymP],
+                                          T (&fy)[kSymP], T (&xj)[kSymQ], T (&yj)[kSymQ], T (&gx)[kSymQ],
+                                          T (&gy)[kSymQ]) {
+    for (int t = 0; t < 64; ++t) {
+#pragma unroll
+        for (int q = 0; q < kSymQ; ++q) {
+#pragma unroll
+            for (int p = 0; p < kSymP; ++p) {
+                const T dx = xi[p] - xj[q];
+                const T dy = yi[p] - yj[q];
+                T d2 = dx * dx + dy * dy;
+                if (SELF) d2 = d2 > self_floor<T>() ? d2 : self_floor<T>();
+                const T inv3 = inv_cube<T>(d2);
+                const T ex = dx * inv3, ey = dy * inv3;
+                fx[p] += ex;
+                fy[p] += ey;
+                gx[q] -= ex;
+                gy[q] -= ey;
+            }
+            xj[q] = rot1(xj[q]);
+            yj[q] = rot1(yj[q]);
+            gx[q] = rot1(gx[q]);
+            gy[q] = rot1(gy[q]);
+        }
+    }
+}
+
+template <typename T, typename T2>
+__global__ __launch_bounds__(kForceBlock) void k_force_sym(const T2 *__restrict__ pj,
+                                                           const SymTile *__restrict__ tiles,
+                                                           T2 *__restrict__ part, const StepBase *__restrict__ base) {
+    __shared__ T2 jsum[kForceBlock / 64][kSymChunk];
+    if (base->stop) return;
+    const SymTile tl = tiles[blockIdx.x];
+    const bool self = tl.j0 == tl.i0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ni = tl.i1 - tl.i0, nj = tl.j1 - tl.j0;
+    const T big = sym_big<T>();
+    T xi[kSymP], yi[kSymP], fx[kSymP], fy[kSymP];
+#pragma unroll
+    for (int p = 0; p < kSymP; ++p) {
+        const int k = wave * 64 * kSymP + p * 64 + lane;
+        const T2 v = pj[tl.i0 + (k < ni ? k : 0)];
+        xi[p] = k < ni ? v.x : big;
+        yi[p] = k < ni ? v.y : big;
+        fx[p] = (T)0;
+        fy[p] = (T)0;
+    }
+    for (int jg = 0; jg < nj; jg += 64 * kSymQ) {   // same trip count in every lane
+        T xj[kSymQ], yj[kSymQ], gx[kSymQ], gy[kSymQ];
+#pragma unroll
+        for (int q = 0; q < kSymQ; ++q) {
+            const int k = jg + q * 64 + lane;
+            const T2 v = pj[tl.j0 + (k < nj ? k : 0)];
+            xj[q] = k < nj ? v.x : -big;
+            yj[q] = k < nj ? v.y : -big;
+            gx[q] = (T)0;
+            gy[q] = (T)0;
+        }
+        if (self)
+            sym_group<T, true>(xi, yi, fx, fy, xj, yj, gx, gy);
+        else
+            sym_group<T, false>(xi, yi, fx, fy, xj, yj, gx, gy);
+        if (!self) {
+#pragma unroll
+            for (int q = 0; q < kSymQ; ++q) {
+                const int k = jg + q * 64 + lane;
+                if (k < nj) {
+                    T2 g;
+                    g.x = gx[q];
+                    g.y = gy[q];
+                    jsum[wave][k] = g;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kSymP; ++p) {
+        const int k = wave * 64 * kSymP + p * 64 + lane;
+        if (k < ni) {
+            T2 v;
+            v.x = fx[p];
+            v.y = fy[p];
+            part[tl.pbase_i + tl.i0 + k] = v;
+        }
+    }
+    if (self) return;   // uniform in the workgroup
+    __syncthreads();
+    for (int k = threadIdx.x; k < nj; k += kForceBlock) {
+        T2 a = jsum[0][k];
+#pragma unroll
+        for (int w = 1; w < kForceBlock / 64; ++w) {
+            a.x += jsum[w][k].x;
+            a.y += jsum[w][k].y;
+        }
+        part[tl.pbase_j + tl.j0 + k] = a;
+    }
+}
+
 // F_i = sum_c K[s_i][spec(c)] Phi_{i,c} over the chunks of i's system, FP64,
 // fixed chunk order; k is i's sorted index.
 template <typename T2>
@@ -429,6 +565,17 @@ int max_grid_p(bool fast) {
 // Tiles of 256 * per_lane particles; per_lane is 2 or 4.
 void launch_force(Sim &s) {
     LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
+    if (s.persistent == 2) {   // symmetric chunk pairs (the host builds them only for the inverse-square law)
+        if (s.fp32)
+            hipLaunchKernelGGL((k_force_sym<float, float2>), dim3(s.nstiles), dim3(kForceBlock), 0, s.stream,
+                               (const float2 *)s.pj, (const SymTile *)s.stiles, (float2 *)s.part,
+                               (const StepBase *)s.dbase);
+        else
+            hipLaunchKernelGGL((k_force_sym<double, double2>), dim3(s.nstiles), dim3(kForceBlock), 0, s.stream,
+                               (const double2 *)s.pj, (const SymTile *)s.stiles, (double2 *)s.part,
+                               (const StepBase *)s.dbase);
+        return;
+    }
     if (s.persistent) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);
     if (s.fp32) {
         if (s.per_lane == 2)

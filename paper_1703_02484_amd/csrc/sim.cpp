@@ -872,10 +872,11 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
 // Chunks of one species range [js, je): nc = round(cnt / chunk) equal parts,
 // lengths rounded up to a multiple of 8.  Depends only on the range and the
 // chunk length, so a system is cut the same way alone or in a batch.
-void cut_species(int js, int je, int chunk, std::vector<int2> &out) {
+void cut_species(int js, int je, int chunk, std::vector<int2> &out, bool cap = false) {
     const int cnt = je - js;
     if (cnt <= 0) return;
-    int nc = std::max(1, (int)std::llround((double)cnt / chunk));
+    // cap: no part longer than chunk (a multiple of 8)
+    int nc = cap ? (cnt + chunk - 1) / chunk : std::max(1, (int)std::llround((double)cnt / chunk));
     int len = (cnt + nc - 1) / nc;
     len = (len + 7) / 8 * 8;
     for (int j = js; j < je; j += len) out.push_back(make_int2(j, std::min(je, j + len)));
@@ -883,12 +884,16 @@ void cut_species(int js, int je, int chunk, std::vector<int2> &out) {
 
 struct Tiling {
     std::vector<Tile> tiles;
+    std::vector<SymTile> stiles;   // symmetric form only
     std::vector<int> chunk_spec;
     std::vector<RepInfo> reps;
     long long part_len = 0;
 };
 
-Tiling make_tiling(const Sim &s, int chunk, int per_lane) {
+// sym: chunks of at most kSymChunk and the symmetric form's tile list (every
+// pair of chunks of a system once, then every chunk with itself); the
+// ordinary tiles of the same chunks are kept for the adjoint sweep.
+Tiling make_tiling(const Sim &s, int chunk, int per_lane, bool sym = false) {
     Tiling t;
     t.reps.resize(s.R);
     const int ib_len = 256 * per_lane;
@@ -902,10 +907,13 @@ Tiling make_tiling(const Sim &s, int chunk, int per_lane) {
         ri.L = s.L_h[r];
         ri.seed = s.seed_h[r];
         int nch = 0;
+        std::vector<int2> all;   // this system's chunks in order
         for (int b = 0; b < s.S; ++b) {
             ch.clear();
-            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], chunk, ch);
+            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], sym ? kSymChunk : chunk, ch,
+                        sym);
             for (const int2 &c : ch) {
+                all.push_back(c);
                 t.chunk_spec.push_back(b);
                 for (int i0 = ri.off; i0 < ri.off + ri.n; i0 += ib_len) {
                     Tile tl;
@@ -921,16 +929,35 @@ Tiling make_tiling(const Sim &s, int chunk, int per_lane) {
             }
         }
         ri.nch = nch;
+        if (sym) {
+            const long long base = ri.poff - ri.off;
+            for (int a = 0; a < nch; ++a)
+                for (int b = a; b < nch; ++b)
+                    t.stiles.push_back(SymTile{all[a].x, all[a].y, all[b].x, all[b].y, base + (long long)b * ri.n,
+                                               base + (long long)a * ri.n});
+        }
         t.part_len += (long long)nch * ri.n;
     }
     std::stable_sort(t.tiles.begin(), t.tiles.end(), [](const Tile &a, const Tile &b) { return a.work > b.work; });
+    std::stable_sort(t.stiles.begin(), t.stiles.end(), [](const SymTile &a, const SymTile &b) {
+        return (long long)(a.i1 - a.i0) * (a.j1 - a.j0) > (long long)(b.i1 - b.i0) * (b.j1 - b.j0);
+    });
     return t;
 }
 
 void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persistent) {
     // the force kernel writes part[pbase + i] for every tile: never launch a tiling the buffers cannot hold
-    if ((long long)t.tiles.size() > s.tiles_cap || t.part_len > s.part_cap)
+    if ((long long)t.tiles.size() > s.tiles_cap || t.part_len > s.part_cap ||
+        (long long)t.stiles.size() > s.stiles_cap || (persistent == 2) != !t.stiles.empty())
         throw DeviceError{hipErrorInvalidValue, "force tiling larger than its buffers"};
+    for (const SymTile &st : t.stiles)   // the kernel holds at most kSymChunk particles of each side
+        if (st.i1 - st.i0 > kSymChunk || st.j1 - st.j0 > kSymChunk || st.i1 <= st.i0 || st.j1 <= st.j0)
+            throw DeviceError{hipErrorInvalidValue, "symmetric force tile out of shape"};
+    if (!t.stiles.empty())
+        check(hipMemcpyAsync(s.stiles, t.stiles.data(), sizeof(SymTile) * t.stiles.size(), hipMemcpyHostToDevice,
+                             s.stream),
+              "symmetric tiles");
+    s.nstiles = (int)t.stiles.size();
     check(hipMemcpyAsync(s.tiles, t.tiles.data(), sizeof(Tile) * t.tiles.size(), hipMemcpyHostToDevice, s.stream),
           "tiles");
     check(hipMemcpyAsync(s.chunk_spec, t.chunk_spec.data(), sizeof(int) * t.chunk_spec.size(), hipMemcpyHostToDevice,
@@ -942,7 +969,9 @@ void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persist
     s.chunk_len = chunk;
     s.per_lane = per_lane;
     s.persistent = persistent;
-    s.force_grid = persistent ? std::min(s.ntiles, force_max_grid(s, per_lane)) : s.ntiles;
+    s.force_grid = persistent == 2 ? s.nstiles
+                   : persistent   ? std::min(s.ntiles, force_max_grid(s, per_lane))
+                                  : s.ntiles;
 }
 
 // Fixed rule: the smallest power-of-two chunk (>= 64) that keeps the launch
@@ -1045,16 +1074,20 @@ double time_force(Sim &s, int reps) {
 }
 
 // Allocates tiles / part for the largest of the given tilings.
-void alloc_force_buffers(Sim &s, long long max_tiles, long long max_part) {
+void alloc_force_buffers(Sim &s, long long max_tiles, long long max_part, long long max_stiles = 0) {
     const size_t vec = s.fp32 ? sizeof(float2) : sizeof(double2);
     dfree(s.tiles);
     dfree(s.part);
+    dfree(s.stiles);
     s.tiles = nullptr;
     s.part = nullptr;
+    s.stiles = nullptr;
     s.tiles = dalloc<Tile>((size_t)max_tiles);
     s.part = dalloc<char>(vec * (size_t)max_part);
+    if (max_stiles > 0) s.stiles = dalloc<SymTile>((size_t)max_stiles);
     s.tiles_cap = max_tiles;
     s.part_cap = max_part;
+    s.stiles_cap = max_stiles;
 }
 
 void setup_force(Sim &s) {
@@ -1075,6 +1108,12 @@ void setup_force(Sim &s) {
         upload_tiling(s, t, s.p.force_chunk, 4, 0);
         return;
     }
+    if (s.p.force_chunk == -1) {   // the symmetric form, pinned
+        Tiling t = make_tiling(s, kSymChunk, 4, true);
+        alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len, (long long)t.stiles.size());
+        upload_tiling(s, t, kSymChunk, 4, 2);
+        return;
+    }
     long double pairs = 0;
     for (int r = 0; r < s.R; ++r) pairs += (long double)(s.off_h[r + 1] - s.off_h[r]) * (s.off_h[r + 1] - s.off_h[r]);
     const int dchunk = default_chunk(s);
@@ -1091,8 +1130,8 @@ void setup_force(Sim &s) {
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
             const TuneChoice c = it->second;
-            Tiling t = make_tiling(s, c.chunk, c.per_lane);
-            alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+            Tiling t = make_tiling(s, c.chunk, c.per_lane, c.persistent == 2);
+            alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len, (long long)t.stiles.size());
             upload_tiling(s, t, c.chunk, c.per_lane, c.persistent);
             s.tuned = 2;
             s.tuned_ms = c.ms;
@@ -1120,7 +1159,19 @@ void setup_force(Sim &s) {
         upload_tiling(s, t, dchunk, 4, 0);
         return;
     }
-    alloc_force_buffers(s, max_tiles, max_part);
+    // the symmetric form (inverse-square law): every pair of chunks once
+    long long max_stiles = 0;
+    bool sym_ok = false;
+    if (s.kind_fast) {
+        Tiling t = make_tiling(s, kSymChunk, 4, true);
+        if (t.part_len <= part_limit) {
+            sym_ok = true;
+            max_tiles = std::max(max_tiles, (long long)t.tiles.size());
+            max_part = std::max(max_part, t.part_len);
+            max_stiles = (long long)t.stiles.size();
+        }
+    }
+    alloc_force_buffers(s, max_tiles, max_part, max_stiles);
     launch_cast(s);
     // bring the clocks up before timing anything (with the first candidate, which the buffers hold)
     {
@@ -1151,16 +1202,20 @@ void setup_force(Sim &s) {
             scored.push_back(TuneChoice{cp.first, cp.second, pers, time_force(s, 5)});
         }
     }
+    if (sym_ok) {
+        upload_tiling(s, make_tiling(s, kSymChunk, 4, true), kSymChunk, 4, 2);
+        scored.push_back(TuneChoice{kSymChunk, 4, 2, time_force(s, 5)});
+    }
     std::sort(scored.begin(), scored.end(), [](const TuneChoice &x, const TuneChoice &y) { return x.ms < y.ms; });
     TuneChoice best{0, 0, 0, 1e30};
     for (size_t i = 0; i < scored.size() && i < 3; ++i) {
         const TuneChoice &c = scored[i];
-        upload_tiling(s, make_tiling(s, c.chunk, c.per_lane), c.chunk, c.per_lane, c.persistent);
+        upload_tiling(s, make_tiling(s, c.chunk, c.per_lane, c.persistent == 2), c.chunk, c.per_lane, c.persistent);
         const double ms = time_force(s, 9);
         if (ms < best.ms) best = TuneChoice{c.chunk, c.per_lane, c.persistent, ms};
     }
-    Tiling t = make_tiling(s, best.chunk, best.per_lane);
-    alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
+    Tiling t = make_tiling(s, best.chunk, best.per_lane, best.persistent == 2);
+    alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len, (long long)t.stiles.size());
     upload_tiling(s, t, best.chunk, best.per_lane, best.persistent);
     s.tuned = 1;
     s.tuned_ms = best.ms;
@@ -1179,7 +1234,7 @@ void free_all(Sim &s) {
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
                     s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
-                    s.xbuild, s.ybuild, s.fsr, s.scan_bsum};
+                    s.xbuild, s.ybuild, s.fsr, s.scan_bsum, s.stiles};
     for (void *p : ptrs)
         dfree(p);
     drop_graphs(s);
@@ -1219,8 +1274,11 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
         return err = "step parameter out of range", BD_ERR_INVALID_ARG;
     if (p->force_precision != BD_PREC_FP32 && p->force_precision != BD_PREC_FP64)
         return err = "unknown force precision", BD_ERR_INVALID_ARG;
-    if (p->force_chunk != 0 && (p->force_chunk < 64 || p->force_chunk > 65536))
-        return err = "force_chunk must be 0 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->force_chunk != 0 && p->force_chunk != -1 && (p->force_chunk < 64 || p->force_chunk > 65536))
+        return err = "force_chunk must be 0, -1 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->force_chunk == -1 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
+        return err = "force_chunk = -1 (symmetric form) needs the inverse-square law without cutoff",
+               BD_ERR_INVALID_ARG;
     return BD_OK;
 }
 
