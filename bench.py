@@ -34,9 +34,9 @@ PEAK_FP64_TFLOPS = 78.6
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
 # 1 GiB copy; valid only for the force kernel's source it was measured on (sha1 of
 # the force section of k_particles.hip, see force_source_sha1).
-MEASURED_TRAFFIC = {"sha1": "36fd7a94939733b5f8346554da55c2376a8c2442", "workload": "C2", "n": 65536,
-                    "force_config": {"chunk": 2048, "per_lane": 2, "persistent": 0},
-                    "bytes_per_launch": 25247878.2}
+MEASURED_TRAFFIC = {"sha1": "a047b965d262062df32d9ce602a396608ca24db2", "workload": "C2", "n": 65536,
+                    "force_config": {"chunk": 1024, "per_lane": 4, "persistent": 2},
+                    "bytes_per_launch": 38057885.2}
 
 
 FORCE_KERNELS = {0: "k_force", 1: "k_force_queue", 2: "k_force_sym"}
