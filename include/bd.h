@@ -95,7 +95,8 @@ typedef struct bd_params {
     int32_t force_precision;     /* bd_precision */
     int32_t force_chunk;         /* all-pairs force: j per chunk (64..65536); 0 lets the library choose,
                                     by timing the candidate tilings once per workload shape when the pair
-                                    count is large (see bd_get_force_config) */
+                                    count is large (see bd_get_force_config); -1 / -2: the symmetric form
+                                    (inverse-square law only) with chunks of at most 1024 / 512 */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
@@ -176,7 +177,9 @@ int bd_batch_layout(bd_sim *sim, int32_t *R_out, int32_t *disk_off, int32_t *fra
 typedef struct bd_force_config {
     int32_t chunk;        /* j per chunk (results depend on it at rounding level) */
     int32_t per_lane;     /* i per lane; a tile holds 256 * per_lane particles i */
-    int32_t persistent;   /* 1: fixed grid taking tiles from a queue; 0: one workgroup per tile */
+    int32_t persistent;   /* launch form: 0 one workgroup per tile (i-block x chunk); 1 a fixed grid taking
+                             those tiles from a queue; 2 symmetric: one workgroup per pair of chunks,
+                             each pair of disks evaluated once and both sums written */
     int32_t tiles;        /* tiles per force evaluation */
     int32_t grid;         /* workgroups launched per force evaluation */
     int32_t tuned;        /* 1: chosen by timing, 2: taken from the tuning cache, 0: fixed rule */

@@ -77,7 +77,7 @@ struct Tile {
 // of one system (A before B, or A itself), each pair evaluated once and both
 // sides written: part[pbase_i + i] (i in A, sum over B) and part[pbase_j + j]
 // (j in B, sum over A; not for A itself).
-constexpr int kSymChunk = 1024;   // longest chunk of the symmetric form
+constexpr int kSymChunk = 1024;   // longest chunk of the symmetric form (256 per_lane, per_lane 2 or 4)
 struct SymTile {
     int i0, i1, j0, j1;
     long long pbase_i, pbase_j;

@@ -197,8 +197,8 @@ __global__ __launch_bounds__(kForceBlock) void k_force_queue(const T2 *__restric
 }
 
 // Symmetric form (inverse-square law).  A tile is a pair of chunks A, B of
-// one system: each of the 4 wavefronts owns up to 256 particles i of A, 4 per
-// lane, in registers.  The particles j of B pass through the wavefront in
+// one system (at most 256 P disks each): each of the 4 wavefronts owns up to
+// 64 P particles i of A, P per lane, in registers.  The particles j of B pass through the wavefront in
 // groups of 128 (2 per lane); a group turns around the wavefront one lane per
 // step (DPP wave_rol: lane l takes lane l+1's values) for 64 steps, so every
 // lane meets every j of the group once.  g = (r_i - r_j)/d^3 is added to i's
@@ -229,18 +229,17 @@ __device__ __forceinline__ float sym_big<float>() { return 1e18f; }   // (2e18)^
 template <>
 __device__ __forceinline__ double sym_big<double>() { return 1e150; }
 
-constexpr int kSymP = 4, kSymQ = 2;
+constexpr int kSymQ = 2;
 
 // The 64 steps of one group of j (every lane active: the rotation reads all lanes).
-template <typename T, bool SELF>
-__device__ __forceinline__ void sym_group(const T (&xi)[kSymP], const T (&yi)[kSymP], T (&fx)[kSymP],
-                                          T (&fy)[kSymP], T (&xj)[kSymQ], T (&yj)[kSymQ], T (&gx)[kSymQ],
-                                          T (&gy)[kSymQ]) {
+template <typename T, int P, bool SELF>
+__device__ __forceinline__ void sym_group(const T (&xi)[P], const T (&yi)[P], T (&fx)[P], T (&fy)[P],
+                                          T (&xj)[kSymQ], T (&yj)[kSymQ], T (&gx)[kSymQ], T (&gy)[kSymQ]) {
     for (int t = 0; t < 64; ++t) {
 #pragma unroll
         for (int q = 0; q < kSymQ; ++q) {
 #pragma unroll
-            for (int p = 0; p < kSymP; ++p) {
+            for (int p = 0; p < P; ++p) {
                 const T dx = xi[p] - xj[q];
                 const T dy = yi[p] - yj[q];
                 T d2 = dx * dx + dy * dy;
@@ -260,11 +259,12 @@ __device__ __forceinline__ void sym_group(const T (&xi)[kSymP], const T (&yi)[kS
     }
 }
 
-template <typename T, typename T2>
+template <typename T, typename T2, int P>
 __global__ __launch_bounds__(kForceBlock) void k_force_sym(const T2 *__restrict__ pj,
                                                            const SymTile *__restrict__ tiles,
                                                            T2 *__restrict__ part, const StepBase *__restrict__ base) {
-    __shared__ T2 jsum[kForceBlock / 64][kSymChunk];
+    constexpr int kSymP = P;
+    __shared__ T2 jsum[kForceBlock / 64][kForceBlock * P];   // chunks hold at most 256 P disks
     if (base->stop) return;
     const SymTile tl = tiles[blockIdx.x];
     const bool self = tl.j0 == tl.i0;
@@ -293,9 +293,9 @@ __global__ __launch_bounds__(kForceBlock) void k_force_sym(const T2 *__restrict_
             gy[q] = (T)0;
         }
         if (self)
-            sym_group<T, true>(xi, yi, fx, fy, xj, yj, gx, gy);
+            sym_group<T, P, true>(xi, yi, fx, fy, xj, yj, gx, gy);
         else
-            sym_group<T, false>(xi, yi, fx, fy, xj, yj, gx, gy);
+            sym_group<T, P, false>(xi, yi, fx, fy, xj, yj, gx, gy);
         if (!self) {
 #pragma unroll
             for (int q = 0; q < kSymQ; ++q) {
@@ -341,9 +341,26 @@ __device__ __forceinline__ void gather_force(const T2 *__restrict__ part, const 
     fx = 0.0;
     fy = 0.0;
     const long long row = ri.poff + (k - ri.off);
-    for (int c = 0; c < ri.nch; ++c) {
-        double w = K[si * S + chunk_spec[ri.cfirst + c]];
-        T2 v = part[row + (long long)c * ri.n];
+    const double *Ki = K + si * S;
+    int c = 0;
+    // 8 chunks at a time: the loads are all issued before the sums, which keep the chunk order
+    for (; c + 8 <= ri.nch; c += 8) {
+        T2 v[8];
+        double w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[u] = part[row + (long long)(c + u) * ri.n];
+            w[u] = Ki[chunk_spec[ri.cfirst + c + u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            fx += w[u] * (double)v[u].x;
+            fy += w[u] * (double)v[u].y;
+        }
+    }
+    for (; c < ri.nch; ++c) {
+        const double w = Ki[chunk_spec[ri.cfirst + c]];
+        const T2 v = part[row + (long long)c * ri.n];
         fx += w * (double)v.x;
         fy += w * (double)v.y;
     }
@@ -566,14 +583,21 @@ int max_grid_p(bool fast) {
 void launch_force(Sim &s) {
     LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
     if (s.persistent == 2) {   // symmetric chunk pairs (the host builds them only for the inverse-square law)
-        if (s.fp32)
-            hipLaunchKernelGGL((k_force_sym<float, float2>), dim3(s.nstiles), dim3(kForceBlock), 0, s.stream,
-                               (const float2 *)s.pj, (const SymTile *)s.stiles, (float2 *)s.part,
-                               (const StepBase *)s.dbase);
+        const dim3 g(s.nstiles), b(kForceBlock);
+        const SymTile *st = s.stiles;
+        const StepBase *base = s.dbase;
+        if (s.fp32 && s.per_lane == 2)
+            hipLaunchKernelGGL((k_force_sym<float, float2, 2>), g, b, 0, s.stream, (const float2 *)s.pj, st,
+                               (float2 *)s.part, base);
+        else if (s.fp32)
+            hipLaunchKernelGGL((k_force_sym<float, float2, 4>), g, b, 0, s.stream, (const float2 *)s.pj, st,
+                               (float2 *)s.part, base);
+        else if (s.per_lane == 2)
+            hipLaunchKernelGGL((k_force_sym<double, double2, 2>), g, b, 0, s.stream, (const double2 *)s.pj, st,
+                               (double2 *)s.part, base);
         else
-            hipLaunchKernelGGL((k_force_sym<double, double2>), dim3(s.nstiles), dim3(kForceBlock), 0, s.stream,
-                               (const double2 *)s.pj, (const SymTile *)s.stiles, (double2 *)s.part,
-                               (const StepBase *)s.dbase);
+            hipLaunchKernelGGL((k_force_sym<double, double2, 4>), g, b, 0, s.stream, (const double2 *)s.pj, st,
+                               (double2 *)s.part, base);
         return;
     }
     if (s.persistent) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);

@@ -890,7 +890,7 @@ struct Tiling {
     long long part_len = 0;
 };
 
-// sym: chunks of at most kSymChunk and the symmetric form's tile list (every
+// sym: chunks of at most 256 per_lane and the symmetric form's tile list (every
 // pair of chunks of a system once, then every chunk with itself); the
 // ordinary tiles of the same chunks are kept for the adjoint sweep.
 Tiling make_tiling(const Sim &s, int chunk, int per_lane, bool sym = false) {
@@ -910,8 +910,8 @@ Tiling make_tiling(const Sim &s, int chunk, int per_lane, bool sym = false) {
         std::vector<int2> all;   // this system's chunks in order
         for (int b = 0; b < s.S; ++b) {
             ch.clear();
-            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], sym ? kSymChunk : chunk, ch,
-                        sym);
+            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], sym ? 256 * per_lane : chunk,
+                        ch, sym);
             for (const int2 &c : ch) {
                 all.push_back(c);
                 t.chunk_spec.push_back(b);
@@ -950,8 +950,9 @@ void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persist
     if ((long long)t.tiles.size() > s.tiles_cap || t.part_len > s.part_cap ||
         (long long)t.stiles.size() > s.stiles_cap || (persistent == 2) != !t.stiles.empty())
         throw DeviceError{hipErrorInvalidValue, "force tiling larger than its buffers"};
-    for (const SymTile &st : t.stiles)   // the kernel holds at most kSymChunk particles of each side
-        if (st.i1 - st.i0 > kSymChunk || st.j1 - st.j0 > kSymChunk || st.i1 <= st.i0 || st.j1 <= st.j0)
+    for (const SymTile &st : t.stiles)   // the kernel holds at most 256 per_lane particles of each side
+        if (st.i1 - st.i0 > 256 * per_lane || st.j1 - st.j0 > 256 * per_lane || st.i1 <= st.i0 || st.j1 <= st.j0 ||
+            (per_lane != 2 && per_lane != 4))
             throw DeviceError{hipErrorInvalidValue, "symmetric force tile out of shape"};
     if (!t.stiles.empty())
         check(hipMemcpyAsync(s.stiles, t.stiles.data(), sizeof(SymTile) * t.stiles.size(), hipMemcpyHostToDevice,
@@ -1108,10 +1109,11 @@ void setup_force(Sim &s) {
         upload_tiling(s, t, s.p.force_chunk, 4, 0);
         return;
     }
-    if (s.p.force_chunk == -1) {   // the symmetric form, pinned
-        Tiling t = make_tiling(s, kSymChunk, 4, true);
+    if (s.p.force_chunk < 0) {   // the symmetric form, pinned: -1 chunks of 1024 (4 per lane), -2 of 512
+        const int pl = s.p.force_chunk == -1 ? 4 : 2;
+        Tiling t = make_tiling(s, 256 * pl, pl, true);
         alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len, (long long)t.stiles.size());
-        upload_tiling(s, t, kSymChunk, 4, 2);
+        upload_tiling(s, t, 256 * pl, pl, 2);
         return;
     }
     long double pairs = 0;
@@ -1161,16 +1163,16 @@ void setup_force(Sim &s) {
     }
     // the symmetric form (inverse-square law): every pair of chunks once
     long long max_stiles = 0;
-    bool sym_ok = false;
-    if (s.kind_fast) {
-        Tiling t = make_tiling(s, kSymChunk, 4, true);
-        if (t.part_len <= part_limit) {
-            sym_ok = true;
+    std::vector<int> sym_pl;   // symmetric candidates: chunks of 512 (2 per lane) or 1024 (4 per lane)
+    if (s.kind_fast)
+        for (int pl : {2, 4}) {
+            Tiling t = make_tiling(s, 256 * pl, pl, true);
+            if (t.part_len > part_limit) continue;
+            sym_pl.push_back(pl);
             max_tiles = std::max(max_tiles, (long long)t.tiles.size());
             max_part = std::max(max_part, t.part_len);
-            max_stiles = (long long)t.stiles.size();
+            max_stiles = std::max(max_stiles, (long long)t.stiles.size());
         }
-    }
     alloc_force_buffers(s, max_tiles, max_part, max_stiles);
     launch_cast(s);
     // bring the clocks up before timing anything (with the first candidate, which the buffers hold)
@@ -1202,9 +1204,9 @@ void setup_force(Sim &s) {
             scored.push_back(TuneChoice{cp.first, cp.second, pers, time_force(s, 5)});
         }
     }
-    if (sym_ok) {
-        upload_tiling(s, make_tiling(s, kSymChunk, 4, true), kSymChunk, 4, 2);
-        scored.push_back(TuneChoice{kSymChunk, 4, 2, time_force(s, 5)});
+    for (int pl : sym_pl) {
+        upload_tiling(s, make_tiling(s, 256 * pl, pl, true), 256 * pl, pl, 2);
+        scored.push_back(TuneChoice{256 * pl, pl, 2, time_force(s, 5)});
     }
     std::sort(scored.begin(), scored.end(), [](const TuneChoice &x, const TuneChoice &y) { return x.ms < y.ms; });
     TuneChoice best{0, 0, 0, 1e30};
@@ -1274,10 +1276,11 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
         return err = "step parameter out of range", BD_ERR_INVALID_ARG;
     if (p->force_precision != BD_PREC_FP32 && p->force_precision != BD_PREC_FP64)
         return err = "unknown force precision", BD_ERR_INVALID_ARG;
-    if (p->force_chunk != 0 && p->force_chunk != -1 && (p->force_chunk < 64 || p->force_chunk > 65536))
-        return err = "force_chunk must be 0, -1 or in [64, 65536]", BD_ERR_INVALID_ARG;
-    if (p->force_chunk == -1 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
-        return err = "force_chunk = -1 (symmetric form) needs the inverse-square law without cutoff",
+    if (p->force_chunk != 0 && p->force_chunk != -1 && p->force_chunk != -2 &&
+        (p->force_chunk < 64 || p->force_chunk > 65536))
+        return err = "force_chunk must be 0, -1, -2 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->force_chunk < 0 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
+        return err = "force_chunk < 0 (symmetric form) needs the inverse-square law without cutoff",
                BD_ERR_INVALID_ARG;
     return BD_OK;
 }

@@ -20,19 +20,22 @@ def _scale(f):
     return np.abs(f).max()
 
 
+@pytest.mark.parametrize("pin", [-1, -2])
 @pytest.mark.parametrize("n", [3, 65, 1000, 1025, 4099])
-def test_symmetric_forces_fp32(n):
+def test_symmetric_forces_fp32(n, pin):
     w = synth.make("C2", n=n)
-    g = binding.Sim.from_workload(w, force_chunk=-1)
-    assert g.force_config()["persistent"] == 2
+    g = binding.Sim.from_workload(w, force_chunk=pin)
+    cfg = g.force_config()
+    assert cfg["persistent"] == 2 and cfg["per_lane"] == (4 if pin == -1 else 2)
     fo = oracle.forces(w.xy, w.species, w.K)
     assert np.abs(g.forces() - fo).max() <= 1e-4 * _scale(fo)
 
 
+@pytest.mark.parametrize("pin", [-1, -2])
 @pytest.mark.parametrize("n", [700, 2500])
-def test_symmetric_forces_fp64(n):
+def test_symmetric_forces_fp64(n, pin):
     w = synth.make("C1", n=n)
-    g = binding.Sim.from_workload(w, force_chunk=-1)
+    g = binding.Sim.from_workload(w, force_chunk=pin)
     fo = oracle.forces(w.xy, w.species, w.K)
     assert np.abs(g.forces() - fo).max() <= 1e-12 * _scale(fo)
 
@@ -76,10 +79,11 @@ def test_symmetric_bitwise_run_to_run():
     assert np.array_equal(a.state()[0], b.state()[0])
 
 
-def test_symmetric_adjoint_matches_oracle_jvp():
+@pytest.mark.parametrize("pin", [-1, -2])
+def test_symmetric_adjoint_matches_oracle_jvp(pin):
     w = synth.make("C5", n=1500)
     steps = 8
-    g = binding.Sim.from_workload(w, force_chunk=-1)
+    g = binding.Sim.from_workload(w, force_chunk=pin)
     g.adjoint_begin(steps, 3)
     o = oracle.OracleSim.from_workload(w)
     rng = np.random.default_rng(2)
