@@ -94,8 +94,7 @@ def run_short_range(steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
-    sim.state()
-    torch.cuda.synchronize()
+    torch.cuda.synchronize()   # every stream of the device, the library's included
     elapsed = time.perf_counter() - t0
     force_ms, launches = sim.kernel_time()
     st1 = sim.state()[3]
@@ -141,7 +140,6 @@ def run_batched(steps, warmup, loop_steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
-    b.state()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     force_ms, launches = b.kernel_time()
@@ -165,7 +163,7 @@ def run_batched(steps, warmup, loop_steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b32.step(steps)
-    b32.state()
+    torch.cuda.synchronize()
     el32 = time.perf_counter() - t0
     f32_ms, f32_launches = b32.kernel_time()
     out["fp32"] = {"value": ntot * steps / el32, "unit": "particle-steps/s", "ms_per_step": 1e3 * el32 / steps,
@@ -183,8 +181,6 @@ def run_batched(steps, warmup, loop_steps):
     for _ in range(loop_steps):
         for s in singles:
             s.step(1)
-    for s in singles:
-        s.state()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     for s in singles:
@@ -212,14 +208,15 @@ def run_adjoint():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain.step(50)
-    plain.state()
+    torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     plain.close()
     g = binding.Sim.from_workload(w)
     t0 = time.perf_counter()
     g.adjoint_begin(50, 10)
-    xT = g.state()[0]
+    torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    xT = g.state()[0]
     s0 = w.species == 0
     lamT = np.zeros_like(xT)
     lamT[s0] = 2.0 * (xT[s0] - w.xy[s0]) / s0.sum()
@@ -292,7 +289,7 @@ def main():
                                                "dispatches": 5}}), flush=True)
         return
     if args.only:
-        fn = {"short_range": lambda: run_short_range(max(10, args.steps // 4), 5),
+        fn = {"short_range": lambda: run_short_range(max(10, args.steps // 4), 20),
               "batched": lambda: run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100)),
               "adjoint": run_adjoint}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
@@ -305,7 +302,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(max(1, args.steps // 4))
-    sim.state()
+    torch.cuda.synchronize()
     eager_ms = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 4)
     sim.set_graph_mode(not args.no_graph)
     sim.step(args.warmup)
@@ -314,8 +311,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps)
-    sim.state()            # synchronises the library stream
-    torch.cuda.synchronize()
+    torch.cuda.synchronize()   # every stream of the device, the library's included
     elapsed = time.perf_counter() - t0
     force_ms, launches = sim.kernel_time()
     st1 = sim.state()[3]
@@ -379,7 +375,7 @@ def main():
         },
     }
     if not args.no_short_range and args.workload == "C2":
-        out["short_range"] = run_short_range(max(10, args.steps // 4), 5)
+        out["short_range"] = run_short_range(max(10, args.steps // 4), 20)
     if not args.no_batched and args.workload == "C2":
         out["batched"] = run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100))
     if not args.no_adjoint and args.workload == "C2":

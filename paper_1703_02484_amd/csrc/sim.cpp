@@ -718,11 +718,12 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
         hb = *s.hbase;
         const int done = hb.batch_idx;
         const int nrec = done + (hb.stop == 1 ? 1 : 0);
-        // a step queued after a stop costs several batch boundaries, so grow slowly
+        // stops are rare (a halted step; list rebuilds happen inside the queued steps): after one,
+        // queue as many steps as ran before it, then double back up to the ring size
         if (hb.stop == 1)
             s.batch_hint = std::max(4, nrec);
         else if (nrec == m)
-            s.batch_hint = std::min(kRing, s.batch_hint + std::max(1, s.batch_hint / 4));
+            s.batch_hint = std::min(kRing, 2 * s.batch_hint);
         check(hipMemcpyAsync(s.hring, s.ring, sizeof(int) * N_CTL * nrec, hipMemcpyDeviceToHost, s.stream), "ring");
         check(hipStreamSynchronize(s.stream), "sync");
         StepPlan plan;
@@ -825,7 +826,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     // grow at once when a budget ran out; shrink by one only after kShrinkAfter
     // steps in a row that needed less (a halted step costs far more than a few
     // extra no-op launches)
-    constexpr int kShrinkAfter = 16;
+    constexpr int kShrinkAfter = 64;
     auto adapt = [&](int &budget, int used, int &slack, int most = 8) {
         if (used >= budget) {
             budget = std::min(most, used + 1);
