@@ -328,7 +328,10 @@ void launch_validate_local(Sim &s, int rep, int k, int last = -1);
 void launch_snapshot(Sim &s);
 // overlap correction (k: overlap-round slot)
 // check: 0 none, 1 the overlap check of round k, 2 that and the final check
-void launch_ovl_detect(Sim &s, int vstamp, int k, int check = 0);
+// vrep >= 0: the same pass validates every triangle for repair vrep (last round slot vlast) and checks it first
+void launch_ovl_detect(Sim &s, int vstamp, int k, int check = 0, int vrep = -1, int vlast = -1);
+// validation after overlap round k's repair fused with round knew's detection (stars walked once)
+void launch_validate_detect_local(Sim &s, int rep, int k, int last, int vstamp, int knew, int check);
 // detection after round kprev: only edges at disks moved by round kprev and edges flipped since
 void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev, int check = 0);
 void launch_ovl_gather(Sim &s, int k);

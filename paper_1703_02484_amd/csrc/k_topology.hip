@@ -612,21 +612,27 @@ __device__ __forceinline__ void det_flush(const Topo &t, int k, int *buf, int &c
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, double keep, int k, int check) {
+// vrep >= 0: the same pass also validates every triangle for the repair in
+// slot vrep (last round slot vlast), whose check the last workgroup runs
+// before the detection's.
+__global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, double keep, int k, int check, int vrep,
+                                                          int vlast) {
 #pragma clang fp contract(off)
     __shared__ int buf[kDetStage];
-    __shared__ int cnt, base, nfound;
-    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
+    __shared__ int cnt, base, nfound, inv;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags before its last workgroup
     const int stamp = rstamp + t.base->vbase;
     if (threadIdx.x == 0) {
         cnt = 0;
         nfound = 0;
+        inv = 0;
     }
     __syncthreads();
     int found = 0;
     for (int t0 = blockIdx.x * kDetBlock; t0 < t.T; t0 += gridDim.x * kDetBlock) {   // same trip count for the workgroup
         const int tri = t0 + threadIdx.x;
         if (tri < t.T) {
+            if (vrep >= 0) validate_tri(t, tri, &inv);
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
                 const int h = 3 * tri + e;
@@ -659,9 +665,15 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
     if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
     __syncthreads();
     if (cnt > 0) det_flush(t, k, buf, cnt, base);
-    const bool added = threadIdx.x == 0 && nfound != 0;
-    if (added) atomicAdd(&t.ctl[K_OVL + k], nfound);
-    detect_checks(t, k, rstamp, check, added);
+    const bool a_ovl = threadIdx.x == 0 && nfound != 0;
+    if (a_ovl) atomicAdd(&t.ctl[K_OVL + k], nfound);
+    const bool a_inv = vrep >= 0 && add_block_count(&t.ctl[K_INV + vrep], &inv);
+    if (check == 0) return;
+    if (last_workgroup(t.ctl, a_ovl || a_inv) && threadIdx.x == 0) {
+        if (vrep >= 0) repair_check_body(t.ctl, vrep, vlast);
+        ovl_check_body(t.ctl, k, rstamp, t.base);
+        if (check == 2) final_check_body(t.ctl, k);
+    }
 }
 
 // Detection after overlap round kprev of the same step.  A Delaunay edge can
@@ -723,6 +735,78 @@ __device__ __forceinline__ int ovl_detect_local_body(const Topo &t, int stamp, d
         } while (h != h0);
     }
     return found;
+}
+
+// The validation of the repair after overlap round k fused with the next
+// detection (round knew): both walk the stars of the disks round k moved, so
+// one walk checks each triangle's orientation and tests each edge; then the
+// triangles flips rewrote (validation) and the diagonals they created
+// (detection).  The last workgroup runs the repair's check, then the
+// detection's (check = 1) and the final check (check = 2).  On a repair that
+// fails its check the detection's marks are never read: the host continues
+// with rounds of its own slots and stamps.
+__global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int stamp, double keep, int knew,
+                                        int check) {
+#pragma clang fp contract(off)
+    __shared__ int inv, nfound;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags before its last workgroup
+    if (threadIdx.x == 0) {
+        inv = 0;
+        nfound = 0;
+    }
+    __syncthreads();
+    const int st = stamp + t.base->vbase;
+    const int nmoved = t.ctl[K_TOUCH + k];
+    const int nvt = t.ctl[K_VT_N];
+    const int nfl = t.ctl[K_FL_N];
+    const int *moved = touched_of(t, k);
+    int found = 0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nmoved + nvt + nfl; idx += gridDim.x * blockDim.x) {
+        if (idx >= nmoved + nvt) {
+            const int e = t.fl[idx - nmoved - nvt];
+            if (bad_he(t, e)) {
+                topo_err(t);
+                continue;
+            }
+            detect_edge(t, e, st, keep, knew, found);
+            continue;
+        }
+        if (idx >= nmoved) {
+            const int tri = t.vt[idx - nmoved];
+            if ((unsigned)tri >= (unsigned)t.T) {
+                topo_err(t);
+                continue;
+            }
+            validate_tri(t, tri, &inv);
+            continue;
+        }
+        const int v = moved[idx];
+        const int h0 = t.vert_he[v];
+        if (bad_he(t, h0)) {
+            topo_err(t);
+            continue;
+        }
+        int h = h0, guard = 0;
+        do {
+            validate_tri(t, h / 3, &inv);
+            detect_edge(t, h, st, keep, knew, found);
+            h = t.he_twin[bd_prev(h)];
+            if (bad_he(t, h) || ++guard > 4096) {
+                atomicAdd(&inv, 1);
+                topo_err(t);
+                break;
+            }
+        } while (h != h0);
+    }
+    for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
+    if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
+    const bool a1 = add_block_count(&t.ctl[K_INV + rep], &inv);
+    const bool a2 = add_block_count(&t.ctl[K_OVL + knew], &nfound);
+    if (last_workgroup(t.ctl, a1 || a2) && threadIdx.x == 0) {
+        repair_check_body(t.ctl, rep, last);
+        ovl_check_body(t.ctl, knew, stamp, t.base);
+        if (check == 2) final_check_body(t.ctl, knew);
+    }
 }
 
 __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kprev, int check) {
@@ -1099,11 +1183,18 @@ void launch_validate_local(Sim &s, int rep, int k, int last) {
     hipLaunchKernelGGL(k_validate_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, rep, k, last);
 }
 
-void launch_ovl_detect(Sim &s, int vstamp, int k, int check) {
+void launch_ovl_detect(Sim &s, int vstamp, int k, int check, int vrep, int vlast) {
     vstamp -= s.vbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_ovl_detect, dim3(grid_for((s.T + 3) / 4)), dim3(kDetBlock), 0, s.stream, t, vstamp,
-                       1.0 - s.p.contact_tol, k, check);
+                       1.0 - s.p.contact_tol, k, check, vrep, vlast);
+}
+
+void launch_validate_detect_local(Sim &s, int rep, int k, int last, int vstamp, int knew, int check) {
+    vstamp -= s.vbase;
+    Topo t = topo_of(s);
+    hipLaunchKernelGGL(k_validate_detect_local, dim3(list_grid(s)), dim3(256), 0, s.stream, t, rep, k, last, vstamp,
+                       1.0 - s.p.contact_tol, knew, check);
 }
 
 void launch_ovl_detect_local(Sim &s, int vstamp, int k, int kprev, int check) {

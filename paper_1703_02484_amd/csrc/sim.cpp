@@ -234,8 +234,14 @@ bool tail_fused(const Sim &s);
 // Enqueues one repair of `rounds` flip rounds with no host read-back: a
 // topology snapshot, the rounds, the validation and the check that halts the
 // step when the budget was too small or a triangle stayed inverted.
+// The overlap detection that follows a repair, run in the same launch as the
+// repair's validation (same triangles or stars): round slot, stamp, check.
+struct FusedDetect {
+    int k, stamp, check;
+};
+
 void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots,
-                    int oround = -1) {
+                    int oround = -1, const FusedDetect *fd = nullptr) {
     // The repair after the move keeps the triangulation of the step's start
     // positions: a later repair of the same step that fails replays the
     // whole move from there (the Delaunay triangulation of the end positions
@@ -269,7 +275,11 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
         launch_flip_fix(s, r, slot);
         last = slot;
     }
-    if (oround >= 0)
+    if (fd && oround >= 0)
+        launch_validate_detect_local(s, rep, oround, last, fd->stamp, fd->k, fd->check);
+    else if (fd)
+        launch_ovl_detect(s, fd->stamp, fd->k, fd->check, rep, last);
+    else if (oround >= 0)
         launch_validate_local(s, rep, oround, last);
     else
         launch_validate(s, rep, last);
@@ -516,6 +526,28 @@ bool tail_fused(const Sim &s) {
 // The budgeted part of a step after the update: repair rounds, then overlap
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
+    const int nover = overlaps_budget(s);
+    if (!tail_fused(s) || nover > MAXTAIL || nover == 0) {
+        // Each detection runs in the launch that validates the repair before it: the first one
+        // scans every triangle (after the repair of the move), later ones the stars of the disks
+        // the previous round moved and the diagonals flipped since; the launch's last workgroup
+        // runs the repair's check, then the round's (and after the last budgeted round the final one).
+        int k = c.take_oround();
+        orounds.push_back(k);
+        FusedDetect fd{k, ++s.vround, nover == 0 ? 2 : 1};
+        enqueue_repair(s, c, true, true, s.budget.em, &rep_first, -1, &fd);
+        for (int j = 0; j < nover; ++j) {
+            launch_ovl_gather(s, k);
+            launch_ovl_apply(s, k, s.round_id + 1, c.slot);
+            const int knext = c.take_oround();
+            orounds.push_back(knext);
+            FusedDetect fn{knext, ++s.vround, j + 1 == nover ? 2 : 1};
+            enqueue_repair(s, c, false, false, s.budget.ovl[j], &rep_first, k, &fn);
+            k = knext;
+        }
+        skin_check(s, false);
+        return;
+    }
     enqueue_repair(s, c, true, true, s.budget.em, &rep_first);
     // the first detection after the move scans every edge, later ones only
     // what round k-1 changed; the detection's last workgroup runs the round's
@@ -527,52 +559,37 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
         else
             launch_ovl_detect_local(s, stamp, k, orounds[orounds.size() - 2], check);
     };
-    const int nover = overlaps_budget(s);
-    if (tail_fused(s) && nover <= MAXTAIL) {
-        // same slots, stamps and round ids as the launch-per-phase sequence below
-        TailPlan plan{};
-        plan.nover = nover;
-        plan.f = s.p.overlap_factor;
-        plan.cap_frac = s.p.cap_frac;
-        plan.keep = 1.0 - s.p.contact_tol;
-        for (int j = 0; j < nover; ++j) {
-            const int k = c.take_oround();
-            orounds.push_back(k);
-            plan.k[j] = k;
-            if (j == 0) {
-                detect(k, 1);
-                plan.stamp[0] = 0;
-            } else {
-                plan.stamp[j] = ++s.vround - s.vbase;
-            }
-            plan.next_round[j] = s.round_id + 1 - s.rbase;
-            plan.slot0[j] = c.slot;
-            plan.rep[j] = c.take_rep();
-            rep_first.push_back(c.slot);
-            plan.rounds[j] = s.budget.ovl[j];
-            for (int r = 0; r < plan.rounds[j]; ++r) {
-                ++s.round_id;
-                c.take_slot();
-            }
-        }
+    // rounds after the first detection in one workgroup (same slots, stamps and round ids)
+    TailPlan plan{};
+    plan.nover = nover;
+    plan.f = s.p.overlap_factor;
+    plan.cap_frac = s.p.cap_frac;
+    plan.keep = 1.0 - s.p.contact_tol;
+    for (int j = 0; j < nover; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);
-        plan.k[nover] = k;
-        plan.stamp[nover] = ++s.vround - s.vbase;
-        launch_tail(s, plan);
-    } else {
-        for (int j = 0; j < nover; ++j) {
-            const int k = c.take_oround();
-            orounds.push_back(k);
+        plan.k[j] = k;
+        if (j == 0) {
             detect(k, 1);
-            launch_ovl_gather(s, k);
-            launch_ovl_apply(s, k, s.round_id + 1, c.slot);
-            enqueue_repair(s, c, false, false, s.budget.ovl[j], &rep_first, k);
+            plan.stamp[0] = 0;
+        } else {
+            plan.stamp[j] = ++s.vround - s.vbase;
         }
-        const int k = c.take_oround();
-        orounds.push_back(k);
-        detect(k, 2);
+        plan.next_round[j] = s.round_id + 1 - s.rbase;
+        plan.slot0[j] = c.slot;
+        plan.rep[j] = c.take_rep();
+        rep_first.push_back(c.slot);
+        plan.rounds[j] = s.budget.ovl[j];
+        for (int r = 0; r < plan.rounds[j]; ++r) {
+            ++s.round_id;
+            c.take_slot();
+        }
     }
+    const int k = c.take_oround();
+    orounds.push_back(k);
+    plan.k[nover] = k;
+    plan.stamp[nover] = ++s.vround - s.vbase;
+    launch_tail(s, plan);
     skin_check(s, false);
 }
 
