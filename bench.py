@@ -34,9 +34,9 @@ PEAK_FP64_TFLOPS = 78.6
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
 # 1 GiB copy; valid only for the force kernel's source it was measured on (sha1 of
 # the force section of k_particles.hip, see force_source_sha1).
-MEASURED_TRAFFIC = {"sha1": "a047b965d262062df32d9ce602a396608ca24db2", "workload": "C2", "n": 65536,
+MEASURED_TRAFFIC = {"sha1": "7efc455d0a748e35a14d19dc8b5778ebcb99d4f3", "workload": "C2", "n": 65536,
                     "force_config": {"chunk": 1024, "per_lane": 4, "persistent": 2},
-                    "bytes_per_launch": 38057885.2}
+                    "bytes_per_launch": 38070172.9}
 
 
 FORCE_KERNELS = {0: "k_force", 1: "k_force_queue", 2: "k_force_sym"}
