@@ -261,7 +261,10 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
             last = c.take_slot();
         }
         launch_repair_rounds(s, r0, slot0, rounds);
-        launch_validate(s, rep, last);
+        if (fd)
+            launch_ovl_detect(s, fd->stamp, fd->k, fd->check, rep, last);
+        else
+            launch_validate(s, rep, last);
         return;
     }
     for (int j = 0; j < rounds; ++j) {

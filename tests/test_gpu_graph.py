@@ -132,6 +132,24 @@ def test_switching_modes_midway():
 
 
 @pytest.mark.parametrize("graph", [False, True])
+def test_tail_mode_with_more_rounds_than_one_workgroup_takes(graph):
+    # contact factor 1/2: ~20 overlap rounds per step, so the round budget
+    # outgrows what one workgroup runs and the step falls back to launches per
+    # phase while the repair after the move still runs in one workgroup
+    w = synth.make("C5", n=2048)
+    a, b = binding.Sim.from_workload(w), binding.Sim.from_workload(w)
+    a.set_tail_mode(0)
+    b.set_tail_mode(1)
+    a.set_graph_mode(graph)
+    b.set_graph_mode(graph)
+    for _ in range(4):
+        a.step(2)
+        b.step(2)
+        _same(a, b)
+    assert b.state()[3]["overlap_rounds_max"] > 8
+
+
+@pytest.mark.parametrize("graph", [False, True])
 def test_tail_in_one_workgroup_equals_launch_per_phase(graph):
     # overlap rounds after the first detection run by one workgroup or launched
     # phase by phase: same results, including steps that halt and are finished
