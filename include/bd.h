@@ -261,8 +261,9 @@ int bd_set_graph_mode(bd_sim *sim, int enable);
  * How the overlap rounds of a step after its first detection are launched:
  * mode 0 one launch per phase (detection, gather, apply, each flip-round
  * phase, validation), mode 1 all of them in one workgroup separated by
- * barriers, -1 (default) the library's choice (currently one launch per
- * phase, which measured faster on 65,536 disks).  Results are identical.
+ * barriers, -1 (default) the library's choice: one workgroup for handles of
+ * at most 32,768 disks (measured faster on 16,384), else one launch per phase
+ * (faster on 65,536 and more).  Results are identical.
  */
 int bd_set_tail_mode(bd_sim *sim, int mode);
 

@@ -343,7 +343,7 @@ void launch_interp(Sim &s, int i, int k);             // x = xa + (i/k)(xb - xa)
 // The overlap rounds of a step after the first detection, run by one
 // workgroup (phases separated by workgroup barriers instead of launches);
 // the same rounds, slots and stamps as the launch-per-phase sequence.
-constexpr int MAXTAIL = 8;
+constexpr int MAXTAIL = 24;
 struct TailPlan {
     int nover;                     // budgeted overlap rounds
     int rounds[MAXTAIL];           // flip rounds of the repair after round j

@@ -521,9 +521,13 @@ int overlaps_budget(const Sim &s) {
 
 // Whether the overlap rounds after the first detection run in one workgroup.
 bool tail_fused(const Sim &s) {
-    // one workgroup measured slower than one launch per phase on 65,536 disks (the
-    // phases are latency chains that spread better over many CUs): off unless asked for
-    return s.tail_mode == 1;
+    // Library choice: one workgroup for handles of at most 32,768 disks.  Measured per step
+    // with graph replay: 16,384 disks 10-21 % faster in one workgroup (the lists of the later
+    // rounds hold tens of items and a launch costs more than a barrier); 65,536 disks 13 %
+    // slower and 1M disks 15x slower (the phases are latency chains over thousands of items
+    // that spread better over many CUs).
+    constexpr int kTailMaxDisks = 32768;
+    return s.tail_mode == 1 || (s.tail_mode == -1 && s.n <= kTailMaxDisks);
 }
 
 // The budgeted part of a step after the update: repair rounds, then overlap
