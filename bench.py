@@ -44,7 +44,7 @@ FORCE_KERNELS = {0: "k_force", 1: "k_force_queue", 2: "k_force_sym"}
 # ordinary forms, per ordered pair: 2 sub, mul + FMA for d^2, v_rsq, 2 mul for d^-3, 2 FMA;
 # symmetric form (FP32), per unordered pair: the same, 2 FMA for j's side, and one DPP move
 # (a step moves x, y and both sums of each of a lane's 2 j: 8 moves for its 8 pairs)
-VALU_PER_PAIR = {0: 9.0, 1: 9.0, 2: 12.0}
+VALU_PER_PAIR = {0: 9.0, 1: 9.0}   # symmetric form: 11 + 4 / per_lane (the 4 moves per j are shared by per_lane i)
 LANE_ISSUE_PER_S = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: one VALU lane-op per slot
 
 
@@ -54,7 +54,8 @@ def valu_issue_frac(fcfg, n, seconds, fp32):
         return None
     form = fcfg["persistent"]
     pairs = n * (n - 1) / 2 if form == 2 else n * (n - 1)
-    return VALU_PER_PAIR[form] * pairs / seconds / LANE_ISSUE_PER_S
+    per_pair = 11.0 + 4.0 / fcfg["per_lane"] if form == 2 else VALU_PER_PAIR[form]
+    return per_pair * pairs / seconds / LANE_ISSUE_PER_S
 
 
 def force_source_sha1():

@@ -95,8 +95,9 @@ typedef struct bd_params {
     int32_t force_precision;     /* bd_precision */
     int32_t force_chunk;         /* all-pairs force: j per chunk (64..65536); 0 lets the library choose,
                                     by timing the candidate tilings once per workload shape when the pair
-                                    count is large (see bd_get_force_config); -1 / -2: the symmetric form
-                                    (inverse-square law only) with chunks of at most 1024 / 512 */
+                                    count is large (see bd_get_force_config); -1 / -2 / -3: the symmetric
+                                    form (inverse-square law only) with chunks of at most 1024 (4 per
+                                    lane) / 512 (2 per lane) / 1024 (8 per lane, 2 wavefronts) */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */

@@ -259,12 +259,12 @@ __device__ __forceinline__ void sym_group(const T (&xi)[P], const T (&yi)[P], T 
     }
 }
 
-template <typename T, typename T2, int P>
-__global__ __launch_bounds__(kForceBlock) void k_force_sym(const T2 *__restrict__ pj,
-                                                           const SymTile *__restrict__ tiles,
-                                                           T2 *__restrict__ part, const StepBase *__restrict__ base) {
+// W wavefronts per workgroup; a chunk holds at most 64 W P disks.
+template <typename T, typename T2, int P, int W>
+__global__ __launch_bounds__(64 * W) void k_force_sym(const T2 *__restrict__ pj, const SymTile *__restrict__ tiles,
+                                                      T2 *__restrict__ part, const StepBase *__restrict__ base) {
     constexpr int kSymP = P;
-    __shared__ T2 jsum[kForceBlock / 64][kForceBlock * P];   // chunks hold at most 256 P disks
+    __shared__ T2 jsum[W][64 * W * P];
     if (base->stop) return;
     const SymTile tl = tiles[blockIdx.x];
     const bool self = tl.j0 == tl.i0;
@@ -321,10 +321,10 @@ __global__ __launch_bounds__(kForceBlock) void k_force_sym(const T2 *__restrict_
     }
     if (self) return;   // uniform in the workgroup
     __syncthreads();
-    for (int k = threadIdx.x; k < nj; k += kForceBlock) {
+    for (int k = threadIdx.x; k < nj; k += 64 * W) {
         T2 a = jsum[0][k];
 #pragma unroll
-        for (int w = 1; w < kForceBlock / 64; ++w) {
+        for (int w = 1; w < W; ++w) {
             a.x += jsum[w][k].x;
             a.y += jsum[w][k].y;
         }
@@ -583,21 +583,29 @@ int max_grid_p(bool fast) {
 void launch_force(Sim &s) {
     LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
     if (s.persistent == 2) {   // symmetric chunk pairs (the host builds them only for the inverse-square law)
-        const dim3 g(s.nstiles), b(kForceBlock);
+        // per_lane 2 / 4: 4 wavefronts (chunks of 512 / 1024); 8: 2 wavefronts (chunks of 1024)
+        const dim3 g(s.nstiles), b4(256), b2(128);
         const SymTile *st = s.stiles;
         const StepBase *base = s.dbase;
-        if (s.fp32 && s.per_lane == 2)
-            hipLaunchKernelGGL((k_force_sym<float, float2, 2>), g, b, 0, s.stream, (const float2 *)s.pj, st,
-                               (float2 *)s.part, base);
-        else if (s.fp32)
-            hipLaunchKernelGGL((k_force_sym<float, float2, 4>), g, b, 0, s.stream, (const float2 *)s.pj, st,
-                               (float2 *)s.part, base);
-        else if (s.per_lane == 2)
-            hipLaunchKernelGGL((k_force_sym<double, double2, 2>), g, b, 0, s.stream, (const double2 *)s.pj, st,
-                               (double2 *)s.part, base);
-        else
-            hipLaunchKernelGGL((k_force_sym<double, double2, 4>), g, b, 0, s.stream, (const double2 *)s.pj, st,
-                               (double2 *)s.part, base);
+        if (s.fp32) {
+            const float2 *pj = (const float2 *)s.pj;
+            float2 *part = (float2 *)s.part;
+            if (s.per_lane == 2)
+                hipLaunchKernelGGL((k_force_sym<float, float2, 2, 4>), g, b4, 0, s.stream, pj, st, part, base);
+            else if (s.per_lane == 4)
+                hipLaunchKernelGGL((k_force_sym<float, float2, 4, 4>), g, b4, 0, s.stream, pj, st, part, base);
+            else
+                hipLaunchKernelGGL((k_force_sym<float, float2, 8, 2>), g, b2, 0, s.stream, pj, st, part, base);
+        } else {
+            const double2 *pj = (const double2 *)s.pj;
+            double2 *part = (double2 *)s.part;
+            if (s.per_lane == 2)
+                hipLaunchKernelGGL((k_force_sym<double, double2, 2, 4>), g, b4, 0, s.stream, pj, st, part, base);
+            else if (s.per_lane == 4)
+                hipLaunchKernelGGL((k_force_sym<double, double2, 4, 4>), g, b4, 0, s.stream, pj, st, part, base);
+            else
+                hipLaunchKernelGGL((k_force_sym<double, double2, 8, 2>), g, b2, 0, s.stream, pj, st, part, base);
+        }
         return;
     }
     if (s.persistent) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);

@@ -918,10 +918,13 @@ struct Tiling {
 // sym: chunks of at most 256 per_lane and the symmetric form's tile list (every
 // pair of chunks of a system once, then every chunk with itself); the
 // ordinary tiles of the same chunks are kept for the adjoint sweep.
+// Longest chunk of the symmetric form for a per_lane setting (2, 4: 4 wavefronts; 8: 2 wavefronts).
+inline int sym_cap(int per_lane) { return per_lane == 8 ? 1024 : 256 * per_lane; }
+
 Tiling make_tiling(const Sim &s, int chunk, int per_lane, bool sym = false) {
     Tiling t;
     t.reps.resize(s.R);
-    const int ib_len = 256 * per_lane;
+    const int ib_len = 256 * std::min(per_lane, 4);   // ordinary tiles (and the adjoint's) hold 2 or 4 per lane
     std::vector<int2> ch;
     for (int r = 0; r < s.R; ++r) {
         RepInfo &ri = t.reps[r];
@@ -935,8 +938,8 @@ Tiling make_tiling(const Sim &s, int chunk, int per_lane, bool sym = false) {
         std::vector<int2> all;   // this system's chunks in order
         for (int b = 0; b < s.S; ++b) {
             ch.clear();
-            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1], sym ? 256 * per_lane : chunk,
-                        ch, sym);
+            cut_species(s.bstart_h[r * (s.S + 1) + b], s.bstart_h[r * (s.S + 1) + b + 1],
+                        sym ? sym_cap(per_lane) : chunk, ch, sym);
             for (const int2 &c : ch) {
                 all.push_back(c);
                 t.chunk_spec.push_back(b);
@@ -975,9 +978,9 @@ void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persist
     if ((long long)t.tiles.size() > s.tiles_cap || t.part_len > s.part_cap ||
         (long long)t.stiles.size() > s.stiles_cap || (persistent == 2) != !t.stiles.empty())
         throw DeviceError{hipErrorInvalidValue, "force tiling larger than its buffers"};
-    for (const SymTile &st : t.stiles)   // the kernel holds at most 256 per_lane particles of each side
-        if (st.i1 - st.i0 > 256 * per_lane || st.j1 - st.j0 > 256 * per_lane || st.i1 <= st.i0 || st.j1 <= st.j0 ||
-            (per_lane != 2 && per_lane != 4))
+    for (const SymTile &st : t.stiles)   // the kernel holds at most sym_cap(per_lane) particles of each side
+        if (st.i1 - st.i0 > sym_cap(per_lane) || st.j1 - st.j0 > sym_cap(per_lane) || st.i1 <= st.i0 ||
+            st.j1 <= st.j0 || (per_lane != 2 && per_lane != 4 && per_lane != 8))
             throw DeviceError{hipErrorInvalidValue, "symmetric force tile out of shape"};
     if (!t.stiles.empty())
         check(hipMemcpyAsync(s.stiles, t.stiles.data(), sizeof(SymTile) * t.stiles.size(), hipMemcpyHostToDevice,
@@ -1134,11 +1137,11 @@ void setup_force(Sim &s) {
         upload_tiling(s, t, s.p.force_chunk, 4, 0);
         return;
     }
-    if (s.p.force_chunk < 0) {   // the symmetric form, pinned: -1 chunks of 1024 (4 per lane), -2 of 512
-        const int pl = s.p.force_chunk == -1 ? 4 : 2;
-        Tiling t = make_tiling(s, 256 * pl, pl, true);
+    if (s.p.force_chunk < 0) {   // the symmetric form, pinned: -1 chunks of 1024 (4 per lane), -2 of 512, -3 1024 (8)
+        const int pl = s.p.force_chunk == -1 ? 4 : s.p.force_chunk == -2 ? 2 : 8;
+        Tiling t = make_tiling(s, sym_cap(pl), pl, true);
         alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len, (long long)t.stiles.size());
-        upload_tiling(s, t, 256 * pl, pl, 2);
+        upload_tiling(s, t, sym_cap(pl), pl, 2);
         return;
     }
     long double pairs = 0;
@@ -1188,10 +1191,10 @@ void setup_force(Sim &s) {
     }
     // the symmetric form (inverse-square law): every pair of chunks once
     long long max_stiles = 0;
-    std::vector<int> sym_pl;   // symmetric candidates: chunks of 512 (2 per lane) or 1024 (4 per lane)
+    std::vector<int> sym_pl;   // symmetric candidates: chunks of 512 (2 per lane) or 1024 (4 or 8 per lane)
     if (s.kind_fast)
-        for (int pl : {2, 4}) {
-            Tiling t = make_tiling(s, 256 * pl, pl, true);
+        for (int pl : {2, 4, 8}) {
+            Tiling t = make_tiling(s, sym_cap(pl), pl, true);
             if (t.part_len > part_limit) continue;
             sym_pl.push_back(pl);
             max_tiles = std::max(max_tiles, (long long)t.tiles.size());
@@ -1230,8 +1233,8 @@ void setup_force(Sim &s) {
         }
     }
     for (int pl : sym_pl) {
-        upload_tiling(s, make_tiling(s, 256 * pl, pl, true), 256 * pl, pl, 2);
-        scored.push_back(TuneChoice{256 * pl, pl, 2, time_force(s, 5)});
+        upload_tiling(s, make_tiling(s, sym_cap(pl), pl, true), sym_cap(pl), pl, 2);
+        scored.push_back(TuneChoice{sym_cap(pl), pl, 2, time_force(s, 5)});
     }
     std::sort(scored.begin(), scored.end(), [](const TuneChoice &x, const TuneChoice &y) { return x.ms < y.ms; });
     TuneChoice best{0, 0, 0, 1e30};
@@ -1301,9 +1304,9 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
         return err = "step parameter out of range", BD_ERR_INVALID_ARG;
     if (p->force_precision != BD_PREC_FP32 && p->force_precision != BD_PREC_FP64)
         return err = "unknown force precision", BD_ERR_INVALID_ARG;
-    if (p->force_chunk != 0 && p->force_chunk != -1 && p->force_chunk != -2 &&
-        (p->force_chunk < 64 || p->force_chunk > 65536))
-        return err = "force_chunk must be 0, -1, -2 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->force_chunk != 0 && (p->force_chunk < -3 || (p->force_chunk > 0 && p->force_chunk < 64) ||
+                                p->force_chunk > 65536))
+        return err = "force_chunk must be 0, -1, -2, -3 or in [64, 65536]", BD_ERR_INVALID_ARG;
     if (p->force_chunk < 0 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
         return err = "force_chunk < 0 (symmetric form) needs the inverse-square law without cutoff",
                BD_ERR_INVALID_ARG;

@@ -20,18 +20,18 @@ def _scale(f):
     return np.abs(f).max()
 
 
-@pytest.mark.parametrize("pin", [-1, -2])
+@pytest.mark.parametrize("pin", [-1, -2, -3])
 @pytest.mark.parametrize("n", [3, 65, 1000, 1025, 4099])
 def test_symmetric_forces_fp32(n, pin):
     w = synth.make("C2", n=n)
     g = binding.Sim.from_workload(w, force_chunk=pin)
     cfg = g.force_config()
-    assert cfg["persistent"] == 2 and cfg["per_lane"] == (4 if pin == -1 else 2)
+    assert cfg["persistent"] == 2 and cfg["per_lane"] == {-1: 4, -2: 2, -3: 8}[pin]
     fo = oracle.forces(w.xy, w.species, w.K)
     assert np.abs(g.forces() - fo).max() <= 1e-4 * _scale(fo)
 
 
-@pytest.mark.parametrize("pin", [-1, -2])
+@pytest.mark.parametrize("pin", [-1, -2, -3])
 @pytest.mark.parametrize("n", [700, 2500])
 def test_symmetric_forces_fp64(n, pin):
     w = synth.make("C1", n=n)
@@ -40,9 +40,10 @@ def test_symmetric_forces_fp64(n, pin):
     assert np.abs(g.forces() - fo).max() <= 1e-12 * _scale(fo)
 
 
-def test_symmetric_full_size_c2_sampled():
+@pytest.mark.parametrize("pin", [-1, -3])
+def test_symmetric_full_size_c2_sampled(pin):
     w = synth.make("C2")
-    g = binding.Sim.from_workload(w, force_chunk=-1)
+    g = binding.Sim.from_workload(w, force_chunk=pin)
     fg = g.forces()
     idx = np.sort(np.random.default_rng(0).choice(w.n, 512, replace=False))
     fo = oracle.forces(w.xy, w.species, w.K, idx=idx)
@@ -79,7 +80,7 @@ def test_symmetric_bitwise_run_to_run():
     assert np.array_equal(a.state()[0], b.state()[0])
 
 
-@pytest.mark.parametrize("pin", [-1, -2])
+@pytest.mark.parametrize("pin", [-1, -2, -3])
 def test_symmetric_adjoint_matches_oracle_jvp(pin):
     w = synth.make("C5", n=1500)
     steps = 8
