@@ -34,7 +34,7 @@ PEAK_FP64_TFLOPS = 78.6
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
 # 1 GiB copy; valid only for the force kernel's source it was measured on (sha1 of
 # the force section of k_particles.hip, see force_source_sha1).
-MEASURED_TRAFFIC = {"sha1": "7efc455d0a748e35a14d19dc8b5778ebcb99d4f3", "workload": "C2", "n": 65536,
+MEASURED_TRAFFIC = {"sha1": "8870e362d2e8ecd5129e68e70c2f28629f2b9428", "workload": "C2", "n": 65536,
                     "force_config": {"chunk": 1024, "per_lane": 4, "persistent": 2},
                     "bytes_per_launch": 38070172.9}
 
