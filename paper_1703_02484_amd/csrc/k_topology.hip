@@ -1011,6 +1011,17 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
 // thread sees the previous phase's writes).  Halts follow the same rules.
 constexpr int kTailBlock = 1024;
 
+// In one workgroup, after a barrier: true when flip round `slot` has nothing
+// left to do, before its evaluation (empty worklist) or after it (no
+// candidate).  A round without a candidate queues no edge, so every later
+// round of the repair would find an empty worklist as well: leaving the loop
+// there gives the same result as running the remaining rounds.  The counters
+// were last written by atomics before the barrier and are not written again
+// before the decision, so every thread reads the same value.
+__device__ __forceinline__ bool rounds_done(const Topo &t, int slot, bool evaluated) {
+    return ctl_read(t.ctl, (evaluated ? K_CAND : K_WL) + slot) == 0;
+}
+
 __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
     const int i0 = threadIdx.x, stride = blockDim.x;
 #define TAIL_SYNC()                  \
@@ -1037,13 +1048,15 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
             int slot = p.slot0[j] + r;
             if (slot >= MAXR) slot -= MAXR;
             const int round = p.next_round[j] + r;
+            last = slot;
+            if (rounds_done(t, slot, false)) break;
             flip_eval_list_body(t, round, slot, i0, stride);
             TAIL_SYNC();
+            if (rounds_done(t, slot, true)) break;
             flip_apply_body(t, round, slot, i0, stride);
             TAIL_SYNC();
             flip_fix_body(t, round, slot, i0, stride);
             TAIL_SYNC();
-            last = slot;
         }
         validate_local_body(t, &t.ctl[K_INV + p.rep[j]], k, i0, stride);
         __syncthreads();
@@ -1077,9 +1090,11 @@ __global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0
         if (slot >= MAXR) slot -= MAXR;
         const int round = round0 + r;
         if (r > 0) {
+            if (rounds_done(t, slot, false)) break;
             flip_eval_list_body(t, round, slot, i0, stride);
             TAIL_SYNC();
         }
+        if (rounds_done(t, slot, true)) break;
         flip_apply_body(t, round, slot, i0, stride);
         TAIL_SYNC();
         flip_fix_body(t, round, slot, i0, stride);
