@@ -745,23 +745,18 @@ __device__ __forceinline__ int ovl_detect_local_body(const Topo &t, int stamp, d
 // detection's (check = 1) and the final check (check = 2).  On a repair that
 // fails its check the detection's marks are never read: the host continues
 // with rounds of its own slots and stamps.
-__global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int stamp, double keep, int knew,
-                                        int check) {
+// Body: inv is the repair's invalid-triangle counter, or a workgroup's share
+// of it in LDS; the stamp st is absolute.  Returns the overlapping edges this thread found (the caller adds them
+// to K_OVL + knew).
+__device__ __forceinline__ int validate_detect_local_body(const Topo &t, int *inv, int k, int st, double keep,
+                                                          int knew, int i0, int stride) {
 #pragma clang fp contract(off)
-    __shared__ int inv, nfound;
-    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags before its last workgroup
-    if (threadIdx.x == 0) {
-        inv = 0;
-        nfound = 0;
-    }
-    __syncthreads();
-    const int st = stamp + t.base->vbase;
     const int nmoved = t.ctl[K_TOUCH + k];
     const int nvt = t.ctl[K_VT_N];
     const int nfl = t.ctl[K_FL_N];
     const int *moved = touched_of(t, k);
     int found = 0;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nmoved + nvt + nfl; idx += gridDim.x * blockDim.x) {
+    for (int idx = i0; idx < nmoved + nvt + nfl; idx += stride) {
         if (idx >= nmoved + nvt) {
             const int e = t.fl[idx - nmoved - nvt];
             if (bad_he(t, e)) {
@@ -777,7 +772,7 @@ __global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int st
                 topo_err(t);
                 continue;
             }
-            validate_tri(t, tri, &inv);
+            validate_tri(t, tri, inv);
             continue;
         }
         const int v = moved[idx];
@@ -788,16 +783,30 @@ __global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int st
         }
         int h = h0, guard = 0;
         do {
-            validate_tri(t, h / 3, &inv);
+            validate_tri(t, h / 3, inv);
             detect_edge(t, h, st, keep, knew, found);
             h = t.he_twin[bd_prev(h)];
             if (bad_he(t, h) || ++guard > 4096) {
-                atomicAdd(&inv, 1);
+                atomicAdd(inv, 1);
                 topo_err(t);
                 break;
             }
         } while (h != h0);
     }
+    return found;
+}
+
+__global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int stamp, double keep, int knew,
+                                        int check) {
+    __shared__ int inv, nfound;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags before its last workgroup
+    if (threadIdx.x == 0) {
+        inv = 0;
+        nfound = 0;
+    }
+    __syncthreads();
+    int found = validate_detect_local_body(t, &inv, k, stamp + t.base->vbase, keep, knew,
+                                           blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
     for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
     if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
     const bool a1 = add_block_count(&t.ctl[K_INV + rep], &inv);
@@ -1033,12 +1042,6 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
     TAIL_SYNC();
     for (int j = 0; j < p.nover; ++j) {
         const int k = p.k[j];
-        if (j > 0) {
-            wave_sum_add(&t.ctl[K_OVL + k], ovl_detect_local_body(t, p.stamp[j], p.keep, k, p.k[j - 1], i0, stride));
-            __syncthreads();
-            if (i0 == 0) ovl_check_body(t.ctl, k, p.stamp[j], t.base);
-            TAIL_SYNC();
-        }
         ovl_gather_body(t, k, p.f, p.cap_frac, p.keep, i0, stride);
         TAIL_SYNC();
         ovl_apply_body(t, k, p.next_round[j], p.slot0[j], i0, stride);
@@ -1058,17 +1061,20 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
             flip_fix_body(t, round, slot, i0, stride);
             TAIL_SYNC();
         }
-        validate_local_body(t, &t.ctl[K_INV + p.rep[j]], k, i0, stride);
+        // this repair's validation with the next round's detection, one walk
+        // over the stars of the disks round k moved; then the repair's check
+        // and the detection's, as the last workgroup of the fused launch does
+        const int knew = p.k[j + 1];
+        wave_sum_add(&t.ctl[K_OVL + knew],
+                     validate_detect_local_body(t, &t.ctl[K_INV + p.rep[j]], k, p.stamp[j + 1] + t.base->vbase,
+                                                p.keep, knew, i0, stride));
         __syncthreads();
-        if (i0 == 0) repair_check_body(t.ctl, p.rep[j], last);
+        if (i0 == 0) {
+            repair_check_body(t.ctl, p.rep[j], last);
+            ovl_check_body(t.ctl, knew, p.stamp[j + 1], t.base);
+            if (j + 1 == p.nover) final_check_body(t.ctl, knew);
+        }
         TAIL_SYNC();
-    }
-    const int k = p.k[p.nover];
-    wave_sum_add(&t.ctl[K_OVL + k], ovl_detect_local_body(t, p.stamp[p.nover], p.keep, k, p.k[p.nover - 1], i0, stride));
-    __syncthreads();
-    if (i0 == 0) {
-        ovl_check_body(t.ctl, k, p.stamp[p.nover], t.base);
-        final_check_body(t.ctl, k);
     }
 #undef TAIL_SYNC
 }
