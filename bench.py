@@ -122,9 +122,20 @@ def run_short_range(steps, warmup):
             "host_continued_steps": d["host_continued"]}
 
 
+def loop_pin(cfg):
+    """bd_params options that give a single-system handle the batch's force form: same chunking, particles
+    per lane and launch form, so each system's sums are cut and added in the same order."""
+    if cfg["persistent"] == 2:
+        return {"force_chunk": {4: -1, 2: -2, 8: -3}[cfg["per_lane"]]}
+    return {"force_chunk": cfg["chunk"], "force_per_lane": cfg["per_lane"], "force_launch": cfg["persistent"]}
+
+
 def run_batched(steps, warmup, loop_steps):
     """Batched systems (256 replicas, N_r log-uniform in [2048, 32768], FP64) in one handle, against a loop
-    that steps one handle per system with the same tiling (identical arithmetic, so equal accuracy)."""
+    that steps one handle per system pinned to the batch's own force form (same chunks, same launch form,
+    same summation order).  After timing, every single handle is advanced to the batch's step and its
+    positions are compared with its system in the batch (equal accuracy means identical positions)."""
+    import numpy as np
     import torch
 
     from paper_1703_02484_amd import binding, synth
@@ -144,7 +155,8 @@ def run_batched(steps, warmup, loop_steps):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     force_ms, launches = b.kernel_time()
-    st1 = b.state()[3]
+    xb, _, step_b, st1 = b.state()
+    _, doff, _ = b.layout()
     b.close()
     avg_s = force_ms / 1e3 / max(launches, 1)
     tflops = FLOPS_PER_PAIR * pairs / avg_s / 1e12
@@ -172,8 +184,11 @@ def run_batched(steps, warmup, loop_steps):
                    "force_tflops": FLOPS_PER_PAIR * pairs / (f32_ms / 1e3 / max(f32_launches, 1)) / 1e12,
                    "force_config": b32.force_config()}
     b32.close()
-    # the same systems, one handle each, stepped one after another
-    singles = [binding.Sim.from_workload(w, force_chunk=cfg["chunk"]) for w in ws]
+    # the same systems, one handle each (pinned to the batch's force form), stepped one after another
+    pin = loop_pin(cfg)
+    singles = [binding.Sim.from_workload(w, **pin) for w in ws]
+    same_form = all(all(s.force_config()[k] == cfg[k] for k in ("chunk", "per_lane", "persistent"))
+                    for s in singles)
     for s in singles:
         s.set_graph_mode(True)
         s.step(1)
@@ -184,10 +199,18 @@ def run_batched(steps, warmup, loop_steps):
             s.step(1)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    for s in singles:
+    # advance every single handle to the batch's step and compare positions
+    worst = 0.0
+    for r, s in enumerate(singles):
+        s.step(step_b - 1 - loop_steps)
+        worst = max(worst, float(np.abs(s.state()[0] - xb[doff[r]:doff[r + 1]]).max()))
         s.close()
+    if worst != 0.0:
+        print(f"warning: batch and per-system loop differ by {worst:.3e}", file=sys.stderr)
     out["per_system_loop"] = {"value": ntot * loop_steps / el, "unit": "particle-steps/s", "steps": loop_steps,
-                              "ms_per_step": 1e3 * el / loop_steps}
+                              "ms_per_step": 1e3 * el / loop_steps, "force_pin": pin,
+                              "same_force_form_as_batch": same_form,
+                              "max_abs_position_diff_vs_batch": worst, "compared_at_step": step_b}
     out["speedup_vs_loop"] = out["value"] / out["per_system_loop"]["value"]
     return out
 
@@ -227,12 +250,31 @@ def run_adjoint():
     st = g.state()[3]
     g.close()
     pairs = w.n * (w.n - 1)
-    return {"workload": f"C5: N={w.n}, S=2, K=1e-2, FP64 all pairs, contact factor 1/2, 50 steps, checkpoints every 10, "
+    return {"workload": f"C5: N={w.n}, S=2, K=1e-2, FP64 all pairs, contact factor 1/2 (the contact option of the "
+                        f"overlap rule; the paper's own runs use factor 1), 50 steps, checkpoints every 10, "
                         f"loss = MSD of species 0",
             "forward_plain_s": t_plain, "forward_with_checkpoints_s": t_fwd, "backward_s": t_bwd,
             "backward_over_forward": t_bwd / t_plain,
             "backward_pair_interactions_per_s": 2 * 50 * pairs / t_bwd,
             "adjoint_flops_per_pair": 28, "overlap_rounds_forward": st["overlap_rounds_total"]}
+
+
+def host_cpu():
+    """Model name of the host CPU and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
 
 
 def cpu_baseline(w):
@@ -242,8 +284,10 @@ def cpu_baseline(w):
     t0 = time.perf_counter()
     o.step(1)
     dt = time.perf_counter() - t0
+    model, ncpu, usable = host_cpu()
     return {"value": w.n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full step of the same workload (N={w.n}), FP64 sequential oracle, {dt:.1f} s"}
+            "cpu_model": model, "nproc": ncpu, "usable_cpus": usable,
+            "sample": f"1 full step of the same workload (N={w.n}), FP64 sequential oracle on one thread, {dt:.1f} s"}
 
 
 def main():

@@ -98,6 +98,10 @@ typedef struct bd_params {
                                     count is large (see bd_get_force_config); -1 / -2 / -3: the symmetric
                                     form (inverse-square law only) with chunks of at most 1024 (4 per
                                     lane) / 512 (2 per lane) / 1024 (8 per lane, 2 wavefronts) */
+    int32_t force_per_lane;      /* with force_chunk > 0: particles i per lane, 2 or 4 (0: 4); a tile holds
+                                    256 * force_per_lane particles i */
+    int32_t force_launch;        /* with force_chunk > 0: 0 one workgroup per tile, 1 a resident grid taking
+                                    the tiles from a queue (the autotuner's two launch forms) */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
@@ -120,6 +124,8 @@ typedef struct bd_stats {
 } bd_stats;
 
 typedef struct bd_sim bd_sim;
+/* A batch of independent systems (bd_batch_init) is a handle of the same type. */
+typedef struct bd_sim bd_batch;
 
 /* Name of an error code (static string). */
 const char *bd_strerror(int code);
@@ -205,7 +211,7 @@ int bd_forces(bd_sim *sim, double *f_out);
  * doubles, may be NULL), step_out (may be NULL), stats_out (may be NULL).
  * Synchronises the library's stream.
  */
-int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
+int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
 
 /*
  * Positions (2n doubles, x and y interleaved, caller order) and angles (n
@@ -221,7 +227,7 @@ int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out);
  * n..n+m-1 are the frame points of bd_get_frame.  BD_ERR_INVALID_ARG if cap
  * is short.
  */
-int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out);
+int bd_get_triangulation(const bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out);
 
 /*
  * The triangulated point set is the disks plus m fixed frame points outside
@@ -323,6 +329,26 @@ int bd_adjoint_backward_dev(bd_sim *sim, const double *grad_xy, double *grad_xy0
 
 /* Frees everything; accepts NULL. */
 void bd_destroy(bd_sim *sim);
+
+/*
+ * Batch and adjoint calls under the names of the interface specification of
+ * this library.  Each has the contract of the call it names:
+ *   bd_batch_step(b, n)                 = bd_step(b, n)
+ *   bd_batch_get_state(b, xy, th, s, st)= bd_get_state(b, xy, th, s, st), all
+ *                                         systems concatenated (bd_batch_layout)
+ *   bd_batch_destroy(b)                 = bd_destroy(b)
+ *   bd_rollout(sim, n, every)           = bd_adjoint_begin(sim, n, every);
+ *                                         every must fit in int32
+ *   bd_backward(sim, gT, gK, g0)        = bd_adjoint_backward(sim, gT, g0, gK)
+ *                                         (note the order: dL/dK before dL/dx0)
+ *   bd_backward_dev(sim, gT, gK, g0)    = bd_adjoint_backward_dev(sim, gT, g0, gK)
+ */
+int bd_batch_step(bd_batch *b, int64_t nsteps);
+int bd_batch_get_state(const bd_batch *b, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out);
+void bd_batch_destroy(bd_batch *b);
+int bd_rollout(bd_sim *sim, int64_t nsteps, int64_t checkpoint_every);
+int bd_backward(bd_sim *sim, const double *grad_xy, double *grad_K, double *grad_xy0);
+int bd_backward_dev(bd_sim *sim, const double *grad_xy, double *grad_K, double *grad_xy0);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,9 @@ def _load():
     lib.orc_forces.argtypes = [ctypes.c_int, V, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, V, ctypes.c_int, V]
     lib.orc_forces.restype = None
+    lib.orc_force_tangent.argtypes = [ctypes.c_int, V, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, V, V, V]
+    lib.orc_force_tangent.restype = None
     lib.orc_wall.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.orc_wall.restype = ctypes.c_double
     lib.orc_overlap_round.argtypes = [ctypes.c_int, V, V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -183,6 +186,20 @@ def forces(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, idx=
         out = np.zeros((ix.size, 2), dtype=np.float64)
         lib.orc_forces(n, _p(xy), _p(sp), S, _p(K), 0 if kind == "power" else 1, q, A, lam, cutoff, _p(ix),
                        int(ix.size), _p(out))
+    return out
+
+
+def force_tangent(xy, species, K, txy, tK=None, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0) -> np.ndarray:
+    """Directional derivative of the pair forces along (txy, tK), the oracle's forward-mode rule."""
+    lib = _load()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    t = np.ascontiguousarray(txy, dtype=np.float64).reshape(-1, 2)
+    tk = None if tK is None else np.ascontiguousarray(tK, dtype=np.float64)
+    out = np.zeros_like(xy)
+    lib.orc_force_tangent(xy.shape[0], _p(xy), _p(sp), K.shape[0], _p(K), 0 if kind == "power" else 1, q, A, lam,
+                          cutoff, _p(t), None if tk is None else _p(tk), _p(out))
     return out
 
 

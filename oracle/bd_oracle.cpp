@@ -727,6 +727,17 @@ void orc_forces(int n, const double *xy, const int *sp, int S, const double *K, 
     forces_subset(fm, n, xy, sp, idx, idx ? m : n, out);
 }
 
+// Tangent of the pair forces: d F / d(xy, K) applied to (txy, tK) (S*S, may be NULL).
+void orc_force_tangent(int n, const double *xy, const int *sp, int S, const double *K, int kind, double q,
+                       double A, double lam, double cutoff, const double *txy, const double *tK, double *out) {
+    ForceModel fm;
+    fm.S = S;
+    fm.K.assign(K, K + S * S);
+    fm.kind = kind; fm.q = q; fm.A = A; fm.lam = lam; fm.cutoff = cutoff;
+    std::vector<double> zero(S * S, 0.0);
+    force_tangent(fm, n, xy, sp, txy, tK ? tK : zero.data(), out);
+}
+
 double orc_wall(double c, double r, double L) { return wall(c, r, L); }
 
 // One overlap round over the current Delaunay edges of xy (in place).

@@ -23,7 +23,8 @@ EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
             "bd_set_positions", "bd_set_graph_mode", "bd_set_tail_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
             "bd_adjoint_begin", "bd_adjoint_backward", "bd_adjoint_backward_dev", "bd_get_state_dev",
-            "bd_set_allocator", "bd_destroy")
+            "bd_set_allocator", "bd_destroy", "bd_batch_step", "bd_batch_get_state", "bd_batch_destroy",
+            "bd_rollout", "bd_backward", "bd_backward_dev")
 
 
 class ForceParams(ctypes.Structure):
@@ -39,7 +40,8 @@ class Params(ctypes.Structure):
                 ("noise_clip", ctypes.c_double), ("contact_tol", ctypes.c_double),
                 ("max_overlap_rounds", ctypes.c_int32),
                 ("max_flip_rounds", ctypes.c_int32), ("force_precision", ctypes.c_int32),
-                ("force_chunk", ctypes.c_int32)]
+                ("force_chunk", ctypes.c_int32), ("force_per_lane", ctypes.c_int32),
+                ("force_launch", ctypes.c_int32)]
 
 
 class ForceConfig(ctypes.Structure):
@@ -156,6 +158,18 @@ def load() -> ctypes.CDLL:
     lib.bd_set_allocator.restype = ctypes.c_int
     lib.bd_destroy.argtypes = [V]
     lib.bd_destroy.restype = None
+    lib.bd_batch_step.argtypes = [V, ctypes.c_int64]
+    lib.bd_batch_step.restype = ctypes.c_int
+    lib.bd_batch_get_state.argtypes = [V, V, V, P(ctypes.c_int64), P(Stats)]
+    lib.bd_batch_get_state.restype = ctypes.c_int
+    lib.bd_batch_destroy.argtypes = [V]
+    lib.bd_batch_destroy.restype = None
+    lib.bd_rollout.argtypes = [V, ctypes.c_int64, ctypes.c_int64]
+    lib.bd_rollout.restype = ctypes.c_int
+    lib.bd_backward.argtypes = [V, V, V, V]
+    lib.bd_backward.restype = ctypes.c_int
+    lib.bd_backward_dev.argtypes = [V, V, V, V]
+    lib.bd_backward_dev.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -165,7 +179,8 @@ def _ptr(a: np.ndarray) -> int:
 
 
 def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, step0, overlap_factor, cap_frac,
-            noise_clip, contact_tol, max_overlap_rounds, max_flip_rounds, fp32, force_chunk):
+            noise_clip, contact_tol, max_overlap_rounds, max_flip_rounds, fp32, force_chunk, force_per_lane,
+            force_launch):
     Km = np.ascontiguousarray(K, dtype=np.float64)
     fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
                      skin, _ptr(Km))
@@ -178,12 +193,14 @@ def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, st
     p.max_overlap_rounds, p.max_flip_rounds = max_overlap_rounds, max_flip_rounds
     p.force_precision = BD_PREC_FP32 if fp32 else BD_PREC_FP64
     p.force_chunk = force_chunk
+    p.force_per_lane, p.force_launch = force_per_lane, force_launch
     return fp, p, Km
 
 
 _DEFAULTS = dict(kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, skin=0.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0,
                  step0=0, overlap_factor=1.0, cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9,
-                 max_overlap_rounds=10000, max_flip_rounds=200, fp32=False, force_chunk=0)
+                 max_overlap_rounds=10000, max_flip_rounds=200, fp32=False, force_chunk=0, force_per_lane=0,
+                 force_launch=0)
 
 
 class Sim:

@@ -12,11 +12,13 @@
 #define BD_HD __host__ __device__ __forceinline__
 
 // Twice the signed area of (a, b, c); > 0 for a counter-clockwise turn.
+// Translated to a: (b - a) x (c - a), the fixed expression form both the
+// device and the host evaluate.
 BD_HD double bd_orient(double ax, double ay, double bx, double by, double cx, double cy) {
 #pragma clang fp contract(off)
-    double acx = ax - cx, acy = ay - cy;
-    double bcx = bx - cx, bcy = by - cy;
-    return acx * bcy - acy * bcx;
+    double bax = bx - ax, bay = by - ay;
+    double cax = cx - ax, cay = cy - ay;
+    return bax * cay - bay * cax;
 }
 
 // > 0 when d is strictly inside the circle through the CCW triangle (a, b, c).

@@ -1131,10 +1131,11 @@ void setup_force(Sim &s) {
         upload_tiling(s, t, 65536, 4, 0);
         return;
     }
-    if (s.p.force_chunk > 0) {
-        Tiling t = make_tiling(s, s.p.force_chunk, 4);
+    if (s.p.force_chunk > 0) {   // pinned: chunk length, particles per lane and launch form
+        const int pl = s.p.force_per_lane == 2 ? 2 : 4;
+        Tiling t = make_tiling(s, s.p.force_chunk, pl);
         alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
-        upload_tiling(s, t, s.p.force_chunk, 4, 0);
+        upload_tiling(s, t, s.p.force_chunk, pl, s.p.force_launch == 1 ? 1 : 0);
         return;
     }
     if (s.p.force_chunk < 0) {   // the symmetric form, pinned: -1 chunks of 1024 (4 per lane), -2 of 512, -3 1024 (8)
@@ -1307,6 +1308,9 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
     if (p->force_chunk != 0 && (p->force_chunk < -3 || (p->force_chunk > 0 && p->force_chunk < 64) ||
                                 p->force_chunk > 65536))
         return err = "force_chunk must be 0, -1, -2, -3 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->force_per_lane != 0 && p->force_per_lane != 2 && p->force_per_lane != 4)
+        return err = "force_per_lane must be 0, 2 or 4", BD_ERR_INVALID_ARG;
+    if (p->force_launch != 0 && p->force_launch != 1) return err = "force_launch must be 0 or 1", BD_ERR_INVALID_ARG;
     if (p->force_chunk < 0 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
         return err = "force_chunk < 0 (symmetric form) needs the inverse-square law without cutoff",
                BD_ERR_INVALID_ARG;
@@ -2044,9 +2048,10 @@ int bd_forces(bd_sim *sim, double *f_out) {
     });
 }
 
-int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out) {
+int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_out, bd_stats *stats_out) {
     if (!sim) return BD_ERR_INVALID_ARG;
-    Sim &s = sim->s;
+    // reading the state changes nothing the caller sees; only the detail of a failure is recorded
+    Sim &s = const_cast<bd_sim *>(sim)->s;
     return bd::guarded(s, [&] {
         std::vector<double> hx(s.n), hy(s.n), ht(s.n);
         if (xy_out) {
@@ -2081,9 +2086,9 @@ int bd_get_state(bd_sim *sim, double *xy_out, double *theta_out, int64_t *step_o
     });
 }
 
-int bd_get_triangulation(bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out) {
+int bd_get_triangulation(const bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out) {
     if (!sim || !tri_out || !ntri_out) return BD_ERR_INVALID_ARG;
-    Sim &s = sim->s;
+    Sim &s = const_cast<bd_sim *>(sim)->s;
     return bd::guarded(s, [&] {
         std::vector<int> hv(s.H);
         bd::check(hipMemcpyAsync(hv.data(), s.he_v, sizeof(int) * s.H, hipMemcpyDeviceToHost, s.stream), "he_v");
@@ -2234,6 +2239,28 @@ void bd_destroy(bd_sim *sim) {
         bd::free_all(sim->s);
     }
     delete sim;
+}
+
+int bd_batch_step(bd_batch *b, int64_t nsteps) { return bd_step(b, nsteps); }
+
+int bd_batch_get_state(const bd_batch *b, double *xy_out, double *theta_out, int64_t *step_out,
+                       bd_stats *stats_out) {
+    return bd_get_state(b, xy_out, theta_out, step_out, stats_out);
+}
+
+void bd_batch_destroy(bd_batch *b) { bd_destroy(b); }
+
+int bd_rollout(bd_sim *sim, int64_t nsteps, int64_t checkpoint_every) {
+    if (checkpoint_every < 1 || checkpoint_every > INT32_MAX) return BD_ERR_INVALID_ARG;
+    return bd_adjoint_begin(sim, nsteps, (int32_t)checkpoint_every);
+}
+
+int bd_backward(bd_sim *sim, const double *grad_xy, double *grad_K, double *grad_xy0) {
+    return bd_adjoint_backward(sim, grad_xy, grad_xy0, grad_K);
+}
+
+int bd_backward_dev(bd_sim *sim, const double *grad_xy, double *grad_K, double *grad_xy0) {
+    return bd_adjoint_backward_dev(sim, grad_xy, grad_xy0, grad_K);
 }
 
 int bd_set_allocator(void *(*alloc_fn)(size_t bytes, void *stream, void *ctx),

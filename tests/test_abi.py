@@ -45,6 +45,7 @@ int main(void) {{
   printf("%zu %zu\\n", offsetof(bd_stats, kinetic_repairs), offsetof(bd_stats, host_rebuilds));
   printf("%zu %zu %zu\\n", offsetof(bd_params, force_chunk), sizeof(bd_force_config),
          offsetof(bd_force_config, tuned_ms));
+  printf("%zu %zu\\n", offsetof(bd_params, force_per_lane), offsetof(bd_params, force_launch));
   return 0;
 }}
 """)
@@ -59,6 +60,7 @@ int main(void) {{
     assert vals[9:11] == [S.kinetic_repairs.offset, S.host_rebuilds.offset]
     C = binding.ForceConfig
     assert vals[11:14] == [P.force_chunk.offset, ctypes.sizeof(C), C.tuned_ms.offset]
+    assert vals[14:16] == [P.force_per_lane.offset, P.force_launch.offset]
 
 
 def test_params_default():
@@ -105,9 +107,11 @@ def test_rejects_too_few_disks():
     assert e.value.code == -1
 
 
-def test_rejects_bad_force_chunk():
+@pytest.mark.parametrize("kw", [dict(force_chunk=12), dict(force_chunk=512, force_per_lane=3),
+                                dict(force_chunk=512, force_launch=2), dict(force_chunk=-4)])
+def test_rejects_bad_force_form(kw):
     with pytest.raises(binding.BDError) as e:
-        _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], force_chunk=12)
+        _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], **kw)
     assert e.value.code == -1
 
 

@@ -230,3 +230,37 @@ def test_torch_caching_allocator_gives_identical_results():
     assert np.array_equal(xy.cpu().numpy(), b.state()[0])
     b.close()
     a.close()
+
+
+def test_spec_named_calls_equal_the_library_calls():
+    # bd_rollout / bd_backward (dL/dK before dL/dx0) and the bd_batch_* names run the same work as
+    # bd_adjoint_begin / bd_adjoint_backward and bd_step / bd_get_state / bd_destroy
+    import ctypes
+
+    w = synth.make("C5", n=600)
+    lib = binding.load()
+    a = binding.Sim.from_workload(w)
+    a.adjoint_begin(6, 3)
+    lam = np.random.default_rng(4).normal(size=(w.n, 2))
+    g0a, gKa = a.adjoint_backward(lam)
+    b = binding.Sim.from_workload(w)
+    assert lib.bd_rollout(b._h, 6, 3) == 0
+    lam_c = np.ascontiguousarray(lam)
+    g0b = np.zeros((w.n, 2))
+    gKb = np.zeros(w.K.shape)
+    assert lib.bd_backward(b._h, lam_c.ctypes.data, gKb.ctypes.data, g0b.ctypes.data) == 0
+    assert np.array_equal(g0a, g0b) and np.array_equal(gKa, gKb)
+    assert lib.bd_rollout(b._h, 6, 0) == -1
+    # batch names
+    ws = synth.make_batch(3, seed=5, lo=300, hi=900)
+    c = binding.Sim.from_workloads(ws)
+    d = binding.Sim.from_workloads(ws)
+    c.step(4)
+    assert lib.bd_batch_step(d._h, 4) == 0
+    xy = np.zeros((d.n, 2))
+    step = ctypes.c_int64()
+    st = binding.Stats()
+    assert lib.bd_batch_get_state(d._h, xy.ctypes.data, None, ctypes.byref(step), ctypes.byref(st)) == 0
+    assert step.value == 4 and np.array_equal(xy, c.state()[0])
+    lib.bd_batch_destroy(d._h)
+    d._h = None

@@ -142,20 +142,33 @@ def test_fig6_two_edge_crossing_is_replayed_on_device():
 
 
 # ------------------------------------------------------------------ trajectories
-def _run_parity(w, steps, tol, check_every=10, **over):
-    g, o = _pair(w, **over)
+def _run_parity(w, steps, tol, check_every=10, graph=False, tail_mode=-1, gpu_over=None, **over):
+    """Steps the library and the oracle side by side; every check_every steps the positions, angles,
+    step counter and triangle sets are compared.  graph: the library replays captured steps (queued
+    check_every at a time); tail_mode: how its overlap rounds are launched; gpu_over: options for the
+    library only (e.g. a pinned force form)."""
+    g = binding.Sim.from_workload(w, **over, **(gpu_over or {}))
+    o = oracle.OracleSim.from_workload(w, **over)
+    g.set_tail_mode(tail_mode)
+    g.set_graph_mode(graph)
     worst = 0.0
-    for s in range(steps):
-        g.step(1)
-        o.step(1)
-        if (s + 1) % check_every == 0 or s + 1 == steps:
-            xg, tg, sg, stg = g.state()
-            xo, to, so, sto = o.state()
-            worst = max(worst, rel_err(xg, xo))
-            assert worst <= tol, (s, worst)
-            assert np.abs(tg - to).max() <= max(tol, 1e-12)
-            assert sg == so
-            assert tri_set(g.triangles()) == tri_set(o.triangles()), s
+    done = 0
+    while done < steps:
+        k = min(check_every, steps - done)
+        if graph:
+            g.step(k)
+        else:
+            for _ in range(k):
+                g.step(1)
+        o.step(k)
+        done += k
+        xg, tg, sg, stg = g.state()
+        xo, to, so, sto = o.state()
+        worst = max(worst, rel_err(xg, xo))
+        assert worst <= tol, (done, worst)
+        assert np.abs(tg - to).max() <= max(tol, 1e-12)
+        assert sg == so
+        assert tri_set(g.triangles()) == tri_set(o.triangles()), done
     stg, sto = g.state()[3], o.state()[3]
     for k in ("overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "reversals", "noise_clamps"):
         assert stg[k] == sto[k], (k, stg[k], sto[k])
@@ -171,6 +184,42 @@ def test_trajectory_c1_fp64_100_steps():
 def test_trajectory_c2_fp32_reduced_100_steps():
     worst, st = _run_parity(synth.make("C2", n=4096), 100, 1e-4)
     assert st["flips_total"] > 0
+
+
+@pytest.mark.parametrize("tail_mode", [0, 1])
+def test_trajectory_c1_fp64_100_steps_graph(tail_mode):
+    # graph replay (the benchmark's mode) against the oracle directly, both overlap-round launch forms
+    worst, st = _run_parity(synth.make("C1"), 100, 1e-9, graph=True, tail_mode=tail_mode)
+    assert st["overlap_rounds_total"] > 0
+
+
+@pytest.mark.parametrize("tail_mode", [0, 1])
+def test_trajectory_c2_fp32_reduced_100_steps_graph(tail_mode):
+    worst, st = _run_parity(synth.make("C2", n=4096), 100, 1e-4, graph=True, tail_mode=tail_mode)
+    assert st["flips_total"] > 0
+
+
+@pytest.mark.parametrize("pin", [-1, -2, -3])
+def test_trajectory_c2_fp32_symmetric_graph_launch_per_phase(pin):
+    # the timed C2 path at reduced size: symmetric force, graph replay, overlap rounds launched per phase
+    worst, st = _run_parity(synth.make("C2", n=3000), 100, 1e-4, graph=True, tail_mode=0,
+                            gpu_over=dict(force_chunk=pin))
+    assert st["overlap_rounds_total"] > 0
+
+
+def test_reversal_count_exact_for_a_disk_driven_through_its_neighbour():
+    # the oracle's pinned case (one Delaunay edge reverses; Sec. 4.3 criterion) through the library
+    from tests.test_oracle import reversal_case
+
+    xy, th, kw = reversal_case()
+    n = xy.shape[0]
+    g = binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), **kw)
+    o = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), **kw)
+    g.step(1)
+    o.step(1)
+    assert g.state()[3]["reversals"] == 1 == o.state()[3]["reversals"]
+    assert rel_err(g.state()[0], o.state()[0]) <= 1e-12
+    assert tri_set(g.triangles()) == tri_set(o.triangles())
 
 
 def test_trajectory_c5_contact_factor_fp64():

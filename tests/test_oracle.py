@@ -390,6 +390,47 @@ def test_reversal_counter_fires_on_huge_step():
     assert sim.state()[3]["reversals"] > 0
 
 
+# A disk driven straight through its right-hand neighbour in one step (Sec. 4.3
+# reversal criterion).  D = 0 and K = 0: every disk moves v0 dt = 6 along its
+# director; A (theta = 0) moves right, all others (theta = pi) move left, so
+# only pairs containing A change their separation, by (12, 0).  Placed by hand
+# so that among the Delaunay edges of the positions before the move exactly one
+# (A-B) reverses; the case also separates the plausible mistakes: counted on
+# the triangulation after the move the answer is 3, with the sign flipped 18.
+REV_A = (20.0, 30.0)
+REV_OTHERS = [(3.0, 0.2), (9.2, 0.3), (9.6, 2.9), (-0.5, -3.2), (-0.4, 3.3), (15.5, 0.1), (10.0, -3.2),
+              (3.0, -5.6), (3.2, 5.8)]
+
+
+def reversal_case():
+    a = np.array(REV_A)
+    xy = np.array([a] + [a + np.array(v) for v in REV_OTHERS])
+    th = np.array([0.0] + [math.pi] * len(REV_OTHERS))
+    return xy, th, dict(L=60.0, D=0.0, dt=1.0, v0=6.0, Dr=0.0, seed=1)
+
+
+def test_reversal_count_exact_for_a_disk_driven_through_its_neighbour():
+    xy, th, kw = reversal_case()
+    n = xy.shape[0]
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), **kw)
+    sim.step(1)
+    x1, _, _, st = sim.state()
+    assert st["reversals"] == 1
+    # the motion itself: straight lines of length 6 (no overlap after the move, so no correction)
+    np.testing.assert_allclose(x1 - xy, 6.0 * np.column_stack([np.cos(th), np.sin(th)]), atol=1e-12)
+    assert st["overlap_rounds_total"] == 0
+
+    # how discriminating the case is, from Qhull's triangulations (independent of the oracle)
+    def edges(p):
+        tris = QhullDelaunay(np.concatenate([p, oracle.frame(kw["L"], 1.0)])).simplices
+        return {(min(a, b), max(a, b)) for t in tris.tolist() for a, b in combinations(t, 2) if a < n and b < n}
+
+    def count(E, sign=1.0):
+        return sum(1 for i, j in E if sign * np.dot(xy[j] - xy[i], x1[j] - x1[i]) < 0)
+
+    assert count(edges(xy)) == 1 and count(edges(x1)) == 3 and count(edges(xy), -1.0) == 18
+
+
 def test_box_side_matches_paper_abp_example():
     vals = {r[0]: float(r[1]) for r in _rows("abp_box.txt")}
     L = synth.box_side(int(vals["N"]), vals["phi"], vals["sigma"] / 2)
@@ -424,6 +465,31 @@ def test_tangent_matches_central_differences():
     xp.step(5)
     xm.step(5)
     fd = (xp.state()[0] - xm.state()[0]) / (2 * h)
+    assert np.abs(jvp - fd).max() <= 1e-6 * np.abs(jvp).max()
+
+
+@pytest.mark.parametrize("law", [dict(kind="power", q=6.0), dict(kind="power", q=6.0, cutoff=2.5),
+                                 dict(kind="power", q=3.5), dict(kind="screened", A=1.0, lam=0.5),
+                                 dict(kind="screened", A=2.0, lam=0.8, cutoff=2.5)])
+def test_force_tangent_other_laws_match_central_differences(law):
+    # the slope term of the pair force for q != 2 and the screened law, against
+    # central differences of the oracle's brute-force forces (two species,
+    # non-reciprocal K, tangents in both the positions and K)
+    w = synth.make("C3", n=300)
+    sp = (np.arange(w.n) % 2).astype(np.int32)
+    K = np.array([[1.0, -0.3], [0.2, 0.7]])
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=(w.n, 2))
+    tK = rng.normal(size=(2, 2))
+    cut = law.get("cutoff", 0.0)
+    if cut > 0:   # central differences are only valid away from the cutoff switch
+        d = np.hypot(*(w.xy[:, None] - w.xy[None]).transpose(2, 0, 1))
+        assert np.abs(d - cut).min() > 1e-4
+    jvp = oracle.force_tangent(w.xy, sp, K, v, tK, **law)
+    h = 1e-6
+    fd = (oracle.forces(w.xy + h * v, sp, K + h * tK, **law) - oracle.forces(w.xy - h * v, sp, K - h * tK, **law))
+    fd /= 2 * h
+    assert np.abs(jvp).max() > 0
     assert np.abs(jvp - fd).max() <= 1e-6 * np.abs(jvp).max()
 
 
