@@ -47,6 +47,12 @@ enum bd_force_kind {
     BD_FORCE_SCREENED = 1   /* g(d) = A exp(-d / lambda) / d */
 };
 
+enum bd_overlap_method {
+    BD_OVERLAP_DELAUNAY = 0,  /* overlap rounds over the edges of the Delaunay triangulation (Sec. 4.4) */
+    BD_OVERLAP_VERLET = 1     /* overlap rounds over the neighbour lists, no triangulation (the paper's
+                                 short-range algorithm, Sec. 5); needs cutoff > 0 */
+};
+
 enum bd_precision {
     BD_PREC_FP64 = 0,       /* forces computed and summed in FP64 */
     BD_PREC_FP32 = 1        /* forces in FP32 from FP32 copies of the positions; everything else FP64 */
@@ -102,6 +108,17 @@ typedef struct bd_params {
                                     256 * force_per_lane particles i */
     int32_t force_launch;        /* with force_chunk > 0: 0 one workgroup per tile, 1 a resident grid taking
                                     the tiles from a queue (the autotuner's two launch forms) */
+    int32_t overlap_method;      /* bd_overlap_method.  BD_OVERLAP_VERLET finds overlapping pairs in the
+                                    neighbour lists (radius cutoff + skin); they hold every pair closer than
+                                    contact while no disk moved more than (cutoff + skin - 2 r_max) / 2 since
+                                    the build, and are rebuilt inside the step when one did.  No reversal
+                                    count and no triangulation (bd_get_triangulation fails) */
+    int32_t max_dt_halvings;     /* Sec. 4.3 edge reversal (a Delaunay edge whose vector reversed in a move):
+                                    0 counts it only; k in 1..12 discards the move and redoes the step as
+                                    two halves, each split again on a reversal, down to 2^-k of dt.  The
+                                    halves' noise is a Brownian bridge of the step's own draws (Philox,
+                                    keyed by step, disk, level and interval), so a trajectory stays a
+                                    function of the seed.  Delaunay overlap method only */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
@@ -120,7 +137,8 @@ typedef struct bd_stats {
     int64_t host_rebuilds;          /* repairs that fell back to a host triangulation */
     int64_t verlet_rebuilds;        /* neighbour-list rebuilds (cutoff > 0) */
     int64_t host_continued;         /* steps whose enqueued rounds ran out and the host finished */
-    int64_t reserved[2];
+    int64_t dt_halvings;            /* moves discarded after an edge reversal and redone as two halves */
+    int64_t reserved;
 } bd_stats;
 
 typedef struct bd_sim bd_sim;

@@ -67,6 +67,8 @@ def _load():
     lib.orc_overlap_round.argtypes = [ctypes.c_int, V, V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, V]
     lib.orc_overlap_round.restype = ctypes.c_int64
+    lib.orc_overlap_round_pairs.argtypes = lib.orc_overlap_round.argtypes
+    lib.orc_overlap_round_pairs.restype = ctypes.c_int64
     lib.orc_sim_new.argtypes = [ctypes.c_int, V, V, V, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -77,6 +79,15 @@ def _load():
     lib.orc_sim_step.restype = ctypes.c_int
     lib.orc_sim_last_rounds.argtypes = [V]
     lib.orc_sim_last_rounds.restype = ctypes.c_int
+    lib.orc_sim_set_overlap_method.argtypes = [V, ctypes.c_int]
+    lib.orc_sim_set_overlap_method.restype = None
+    lib.orc_sim_set_max_halvings.argtypes = [V, ctypes.c_int]
+    lib.orc_sim_set_max_halvings.restype = None
+    lib.orc_sim_dt_halvings.argtypes = [V]
+    lib.orc_sim_dt_halvings.restype = ctypes.c_int64
+    lib.orc_bridge.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, V, V, V, V, V, V]
+    lib.orc_bridge.restype = None
     lib.orc_sim_get.argtypes = [V, V, V, V, V]
     lib.orc_sim_get.restype = None
     lib.orc_sim_forces.argtypes = [V, V]
@@ -203,6 +214,20 @@ def force_tangent(xy, species, K, txy, tK=None, kind="power", q=2.0, A=1.0, lam=
     return out
 
 
+def bridge(W, Th, seed, step, level, index, h, D, Dr, clip=3.0):
+    """Noise increments of the two halves of interval (level, index) of a step (length h, increments W (n, 2)
+    and Th (n,)): the oracle's Brownian bridge.  Returns (WL, WR, ThL, ThR)."""
+    lib = _load()
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(-1, 2)
+    Th = np.ascontiguousarray(Th, dtype=np.float64)
+    n = W.shape[0]
+    WL, WR = np.zeros_like(W), np.zeros_like(W)
+    ThL, ThR = np.zeros_like(Th), np.zeros_like(Th)
+    lib.orc_bridge(n, ctypes.c_uint64(seed), int(step), int(level), int(index), float(h), float(D), float(Dr),
+                   float(clip), _p(W), _p(Th), _p(WL), _p(WR), _p(ThL), _p(ThR))
+    return WL, WR, ThL, ThR
+
+
 def wall(c: float, r: float, L: float) -> float:
     return _load().orc_wall(c, r, L)
 
@@ -219,8 +244,22 @@ def overlap_round(xy: np.ndarray, radii, L: float, f: float = 1.0, cap_frac: flo
     return out, int(cnt), int(hits[0])
 
 
+def overlap_round_pairs(xy: np.ndarray, radii, L: float, f: float = 1.0, cap_frac: float = 0.5,
+                        contact_tol: float = 1e-9):
+    """One Jacobi round over every overlapping pair (no triangulation); returns (new_xy, n_pairs, cap_hits)."""
+    lib = _load()
+    out = np.ascontiguousarray(xy, dtype=np.float64).copy()
+    rad = np.ascontiguousarray(radii, dtype=np.float64)
+    hits = np.zeros(1, dtype=np.int64)
+    cnt = lib.orc_overlap_round_pairs(out.shape[0], _p(out), _p(rad), L, f, cap_frac, contact_tol, _p(hits))
+    return out, int(cnt), int(hits[0])
+
+
 STAT_NAMES = ("steps", "overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "cap_hits",
               "reversals", "noise_clamps")
+# options of the GPU library that do not change what the step computes (force tiling, precision of the
+# pair sums): the oracle ignores them when it is built from the same workload with them
+GPU_ONLY = ("fp32", "force_chunk", "force_per_lane", "force_launch")
 
 
 class OracleSim:
@@ -228,7 +267,8 @@ class OracleSim:
 
     def __init__(self, xy, radii, species, theta, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0,
                  L=100.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0, step0=0, overlap_factor=1.0,
-                 cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9, max_overlap_rounds=10000):
+                 cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9, max_overlap_rounds=10000, overlap="delaunay",
+                 max_dt_halvings=0):
         lib = _load()
         self._lib = lib
         self.xy0 = np.ascontiguousarray(xy, dtype=np.float64)
@@ -244,14 +284,16 @@ class OracleSim:
                                   contact_tol, int(max_overlap_rounds))
         if not self._h:
             raise RuntimeError("oracle: initial triangulation failed")
+        lib.orc_sim_set_overlap_method(self._h, {"delaunay": 0, "verlet": 1}[overlap])
+        lib.orc_sim_set_max_halvings(self._h, int(max_dt_halvings))
 
     @classmethod
     def from_workload(cls, w, **over):
         kw = dict(K=w.K, kind=w.kind, q=w.q, A=w.A, lam=w.lam, cutoff=w.cutoff, L=w.L, D=w.D, dt=w.dt,
                   v0=w.v0, Dr=w.Dr, seed=w.seed, step0=w.step0, overlap_factor=w.overlap_factor,
                   cap_frac=w.cap_frac, noise_clip=w.noise_clip, contact_tol=w.contact_tol,
-                  max_overlap_rounds=w.max_overlap_rounds)
-        kw.update(over)
+                  max_overlap_rounds=w.max_overlap_rounds, overlap=w.overlap, max_dt_halvings=w.max_dt_halvings)
+        kw.update({k: v for k, v in over.items() if k not in GPU_ONLY})
         return cls(w.xy, w.radii, w.species, w.theta, **kw)
 
     def step(self, nsteps: int = 1) -> int:
@@ -269,7 +311,9 @@ class OracleSim:
         step = np.zeros(1, dtype=np.int64)
         st = np.zeros(7, dtype=np.int64)
         self._lib.orc_sim_get(self._h, _p(xy), _p(th), _p(step), _p(st))
-        return xy, th, int(step[0]), dict(zip(STAT_NAMES, (int(v) for v in st)))
+        stats = dict(zip(STAT_NAMES, (int(v) for v in st)))
+        stats["dt_halvings"] = int(self._lib.orc_sim_dt_halvings(self._h))
+        return xy, th, int(step[0]), stats
 
     def forces(self) -> np.ndarray:
         out = np.zeros((self.n, 2), dtype=np.float64)

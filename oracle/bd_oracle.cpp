@@ -365,7 +365,19 @@ struct ForceModel {
     std::vector<double> K;     // S*S row-major
     int kind = 0;              // 0 power, 1 screened
     double q = 2.0, A = 1.0, lam = 1.0, cutoff = 0.0;
+    double period = 0.0;       // > 0: periodic box of this side, separations by the minimum image (Sec. 2.1)
 };
+
+// Sec. 2.1 minimum-image convention: the separation component v of two
+// points of a periodic box of side L taken from the nearest image, in
+// [-L/2, L/2] (ties to even).
+inline double min_image(double v, double L) { return L > 0.0 ? v - L * std::nearbyint(v / L) : v; }
+
+// A coordinate of a periodic box of side L folded into [0, L).
+inline double wrap(double c, double L) {
+    double r = c - L * std::floor(c / L);
+    return r >= L ? r - L : r;
+}
 
 inline double pair_scale(const ForceModel &fm, double d) {
     // returns g(d)/d so that the force is scale * (r_i - r_j)
@@ -383,7 +395,8 @@ void forces_subset(const ForceModel &fm, int n, const double *xy, const int *sp,
         double fx = 0.0, fy = 0.0;
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
-            double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+            double dx = min_image(xy[2 * i] - xy[2 * j], fm.period);
+            double dy = min_image(xy[2 * i + 1] - xy[2 * j + 1], fm.period);
             double d = std::sqrt(dx * dx + dy * dy);
             if (fm.cutoff > 0.0 && d > fm.cutoff) continue;
             double k = fm.K[sp[i] * fm.S + sp[j]];
@@ -494,6 +507,7 @@ struct Stats {
     int64_t cap_hits = 0;
     int64_t reversals = 0;
     int64_t noise_clamps = 0;
+    int64_t dt_halvings = 0;   // moves discarded after an edge reversal and redone as two halves
 };
 
 // One Jacobi overlap round over the given edges, Sec. 2.3 and Sec. 4.4:
@@ -508,7 +522,8 @@ inline bool overlapping(double d, double contact, double tol) { return d < conta
 //   d[f (sigma - d) u / d] = f ((sigma/d - 1) I - (sigma/d) n n^T) du,  n = u/d,
 //   d[c D/|D|] = (c/|D|)(I - e e^T) dD,  e = D/|D|  (when the cap acts).
 int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, double cap_frac, double tol,
-                      const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits, double *txy = nullptr) {
+                      const std::vector<std::pair<int, int>> &edges, int64_t *cap_hits, double *txy = nullptr,
+                      bool periodic = false) {
     std::vector<double> disp(2 * (size_t)n, 0.0);
     std::vector<double> tdisp(txy ? 2 * (size_t)n : 0, 0.0);
     std::vector<char> touched(n, 0);
@@ -516,6 +531,10 @@ int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, 
     for (const auto &e : edges) {
         int i = e.first, j = e.second;
         double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+        if (periodic) {
+            dx = min_image(dx, L);
+            dy = min_image(dy, L);
+        }
         double d = std::sqrt(dx * dx + dy * dy);
         double contact = rad[i] + rad[j];
         if (!overlapping(d, contact, tol)) continue;
@@ -560,14 +579,64 @@ int64_t overlap_round(int n, double *xy, const double *rad, double L, double f, 
             txy[2 * i] = wall_slope(xy[2 * i] + ddx, rad[i], L) * (txy[2 * i] + tdx);
             txy[2 * i + 1] = wall_slope(xy[2 * i + 1] + ddy, rad[i], L) * (txy[2 * i + 1] + tdy);
         }
+        if (periodic) {
+            xy[2 * i] = wrap(xy[2 * i] + ddx, L);
+            xy[2 * i + 1] = wrap(xy[2 * i + 1] + ddy, L);
+            continue;
+        }
         xy[2 * i] = wall(xy[2 * i] + ddx, rad[i], L);
         xy[2 * i + 1] = wall(xy[2 * i + 1] + ddy, rad[i], L);
     }
     return count;
 }
 
+// Sec. 5 short-range variant of the overlap test: every pair of disks closer
+// than contact, by brute force over all pairs (the plain definition that the
+// library's neighbour lists reach faster); no triangulation is involved.
+void overlapping_pairs(int n, const double *xy, const double *rad, double tol, std::vector<std::pair<int, int>> &out,
+                       double period = 0.0) {
+    out.clear();
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double dx = min_image(xy[2 * i] - xy[2 * j], period);
+            double dy = min_image(xy[2 * i + 1] - xy[2 * j + 1], period);
+            if (overlapping(std::sqrt(dx * dx + dy * dy), rad[i] + rad[j], tol)) out.push_back({i, j});
+        }
+}
+
+// Noise of the two halves of interval (level, index) of step `step`, length h,
+// whose increments are W (2 per disk) and Th: a Brownian bridge.  Given the
+// increment W over h, the increment over the first half is W/2 plus an
+// independent normal of variance 2 D (h/2)(h/2)/h = D h / 2 per component; the
+// second half takes the rest.  The normals are Philox draws keyed by the step
+// and the particle like the step's own, on stream 2^31 + level' 2^24 + 2 index
+// (translation, clamped like the step's draws) and that + 1 (rotation, first
+// normal of the pair, not clamped), level' = level + 1.
+void bridge_noise(int n, uint64_t seed, int64_t step, int level, uint32_t index, double h, double D, double Dr,
+                  double clip, const double *W, const double *Th, double *WL, double *WR, double *ThL, double *ThR) {
+    const uint32_t key = 0x80000000u | ((uint32_t)(level + 1) << 24) | (index << 1);
+    const double at = std::sqrt(0.5 * D * h), ar = std::sqrt(0.5 * Dr * h);
+    for (int i = 0; i < n; ++i) {
+        double ex, ey, er, unused;
+        normal_pair(seed, step, (uint32_t)i, key, ex, ey);
+        normal_pair(seed, step, (uint32_t)i, key | 1u, er, unused);
+        ex = ex > clip ? clip : (ex < -clip ? -clip : ex);
+        ey = ey > clip ? clip : (ey < -clip ? -clip : ey);
+        WL[2 * i] = 0.5 * W[2 * i] + at * ex;
+        WL[2 * i + 1] = 0.5 * W[2 * i + 1] + at * ey;
+        WR[2 * i] = W[2 * i] - WL[2 * i];
+        WR[2 * i + 1] = W[2 * i + 1] - WL[2 * i + 1];
+        ThL[i] = 0.5 * Th[i] + ar * er;
+        ThR[i] = Th[i] - ThL[i];
+    }
+}
+
 struct Sim {
     int n = 0;
+    int overlap_method = 0;                    // 0: Delaunay edges (Sec. 4.4); 1: all pairs (Sec. 5 lists)
+    int max_halvings = 0;                      // 0: a reversal is only counted
+    bool periodic = false;                     // periodic box (Sec. 2.1) instead of hard walls
+    std::vector<int> torus_tris;               // periodic: triangles of the torus triangulation (3 ids each)
     std::vector<double> xy, rad, theta;
     std::vector<int> sp;
     ForceModel fm;
@@ -587,7 +656,46 @@ struct Sim {
     bool tan_on = false;
     std::vector<double> txy, tK, tforce;
 
+    // Periodic box: the Delaunay triangulation of the flat torus, from the
+    // Delaunay triangulation of the 3 x 3 periodic copies of the points.  A
+    // torus triangle appears there once per copy; the one kept is the copy
+    // whose vertex of smallest id lies in the central box.  Triangles near the
+    // outer border of the copies (where the copied triangulation is not the
+    // periodic one) are never kept, since every edge is far shorter than L.
+    // Every torus triangulation of n points has 2n triangles and 3n edges.
+    bool retriangulate_torus() {
+        pts.clear();
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox)
+                for (int i = 0; i < n; ++i) {
+                    pts.push_back(xy[2 * i] + ox * L);
+                    pts.push_back(xy[2 * i + 1] + oy * L);
+                }
+        if (!dt_now.build(pts.data(), 9 * n)) return false;
+        std::vector<int> all;
+        dt_now.finite_triangles(all);
+        torus_tris.clear();
+        for (size_t t = 0; t < all.size(); t += 3) {
+            int m = 0;
+            for (int k = 1; k < 3; ++k)
+                if (all[t + k] % n < all[t + m] % n) m = k;
+            if (all[t + m] / n != 4) continue;   // the central copy is number 4
+            for (int k = 0; k < 3; ++k) torus_tris.push_back(all[t + k] % n);
+        }
+        if ((int)torus_tris.size() != 6 * n) return false;
+        edges.clear();
+        for (size_t t = 0; t < torus_tris.size(); t += 3)
+            for (int k = 0; k < 3; ++k) {
+                int a = torus_tris[t + k], b = torus_tris[t + (k + 1) % 3];
+                edges.push_back({std::min(a, b), std::max(a, b)});
+            }
+        std::sort(edges.begin(), edges.end());
+        edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+        return (int)edges.size() == 3 * n;
+    }
+
     bool retriangulate() {
+        if (periodic) return retriangulate_torus();
         pts.assign(xy.begin(), xy.end());
         pts.insert(pts.end(), frame.begin(), frame.end());
         if (!dt_now.build(pts.data(), (int)(pts.size() / 2))) return false;
@@ -601,16 +709,14 @@ struct Sim {
 
     // One step, in the order of Algorithm 1 with the overlap loop of Sec. 4.4.
     // Returns 0, -3 (round cap exceeded) or -4 (triangulation failed).
+    // The translational noise of the step is W = sqrt(2 D dt) xi and the
+    // rotational one sqrt(2 Dr dt) n (xi clamped, n not); with
+    // max_halvings > 0 a move that reverses a Delaunay edge is discarded and
+    // the step is redone as two halves (Sec. 4.3), see substep().
     int advance() {
-        forces.assign(2 * (size_t)n, 0.0);
-        forces_subset(fm, n, xy.data(), sp.data(), nullptr, n, forces.data());
-        if (tan_on) {
-            tforce.assign(2 * (size_t)n, 0.0);
-            force_tangent(fm, n, xy.data(), sp.data(), txy.data(), tK.data(), tforce.data());
-        }
         const double amp = std::sqrt(2.0 * D * dt);
         const double amp_r = std::sqrt(2.0 * Dr * dt);
-        std::vector<double> nxy(2 * (size_t)n);
+        std::vector<double> W(2 * (size_t)n), Th(n);
         for (int i = 0; i < n; ++i) {
             double zx, zy, nr, unused;
             normal_pair(seed, step, (uint32_t)i, 0u, zx, zy);
@@ -619,55 +725,128 @@ struct Sim {
             if (zy > clip) { zy = clip; ++st.noise_clamps; }
             if (zy < -clip) { zy = -clip; ++st.noise_clamps; }
             normal_pair(seed, step, (uint32_t)i, 1u, nr, unused);
-            double th = theta[i];
-            double vx = forces[2 * i] + v0 * std::cos(th);
-            double vy = forces[2 * i + 1] + v0 * std::sin(th);
-            double x = xy[2 * i] + vx * dt + amp * zx;
-            double y = xy[2 * i + 1] + vy * dt + amp * zy;
-            nxy[2 * i] = wall(x, rad[i], L);
-            nxy[2 * i + 1] = wall(y, rad[i], L);
-            if (tan_on) {
-                txy[2 * i] = wall_slope(x, rad[i], L) * (txy[2 * i] + dt * tforce[2 * i]);
-                txy[2 * i + 1] = wall_slope(y, rad[i], L) * (txy[2 * i + 1] + dt * tforce[2 * i + 1]);
-            }
-            theta[i] = th + amp_r * nr;
+            W[2 * i] = amp * zx;
+            W[2 * i + 1] = amp * zy;
+            Th[i] = amp_r * nr;
         }
-        // Sec. 4.3: an edge whose vector reversed means the pair passed through
-        // each other; counted (the paper discards the step, not done here).
-        for (const auto &e : edges) {
-            int i = e.first, j = e.second;
-            double ox = xy[2 * j] - xy[2 * i], oy = xy[2 * j + 1] - xy[2 * i + 1];
-            double mx = nxy[2 * j] - nxy[2 * i], my = nxy[2 * j + 1] - nxy[2 * i + 1];
-            if (ox * mx + oy * my < 0.0) ++st.reversals;
-        }
-        xy.swap(nxy);
-        if (!retriangulate()) return -4;
         int rounds = 0;
-        for (;;) {
-            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, edges, &st.cap_hits,
-                                        tan_on ? txy.data() : nullptr);
-            if (cnt == 0) break;
-            ++rounds;
-            st.overlap_edges_total += cnt;
-            if (!retriangulate()) return -4;
-            if (rounds >= max_rounds) {
-                // still overlapping after the cap?
-                bool any = false;
-                for (const auto &e : edges) {
-                    int i = e.first, j = e.second;
-                    double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
-                    if (overlapping(std::sqrt(dx * dx + dy * dy), rad[i] + rad[j], tol)) { any = true; break; }
-                }
-                if (any) return -3;
-                break;
-            }
-        }
+        int rc = substep(0, 0, W, Th, dt, rounds);
+        if (rc != 0) return rc;
         last_rounds = rounds;
         st.overlap_rounds_total += rounds;
         if (rounds > st.overlap_rounds_max) st.overlap_rounds_max = rounds;
         ++st.steps;
         ++step;
         return 0;
+    }
+
+    void bridge(int level, uint32_t index, double h, const std::vector<double> &W, const std::vector<double> &Th,
+                std::vector<double> &WL, std::vector<double> &WR, std::vector<double> &ThL,
+                std::vector<double> &ThR) const {
+        WL.resize(2 * (size_t)n);
+        WR.resize(2 * (size_t)n);
+        ThL.resize(n);
+        ThR.resize(n);
+        bridge_noise(n, seed, step, level, index, h, D, Dr, clip, W.data(), Th.data(), WL.data(), WR.data(),
+                     ThL.data(), ThR.data());
+    }
+
+    // Interval (level, index) of the step: forces at the current positions,
+    // the Euler-Maruyama move over h with noise increments W, Th, walls, the
+    // reversal test on the Delaunay edges before the move (Sec. 4.3), then the
+    // triangulation of the new positions and the overlap rounds.  A move that
+    // reversed an edge is discarded and the interval redone as two halves
+    // while level < max_halvings.  rounds accumulates the overlap rounds.
+    int substep(int level, uint32_t index, const std::vector<double> &W, const std::vector<double> &Th, double h,
+                int &rounds) {
+        forces.assign(2 * (size_t)n, 0.0);
+        forces_subset(fm, n, xy.data(), sp.data(), nullptr, n, forces.data());
+        if (tan_on) {
+            tforce.assign(2 * (size_t)n, 0.0);
+            force_tangent(fm, n, xy.data(), sp.data(), txy.data(), tK.data(), tforce.data());
+        }
+        std::vector<double> nxy(2 * (size_t)n), nth(n), ntxy;
+        if (tan_on) ntxy = txy;
+        for (int i = 0; i < n; ++i) {
+            double th = theta[i];
+            double vx = forces[2 * i] + v0 * std::cos(th);
+            double vy = forces[2 * i + 1] + v0 * std::sin(th);
+            double x = xy[2 * i] + vx * h + W[2 * i];
+            double y = xy[2 * i + 1] + vy * h + W[2 * i + 1];
+            nxy[2 * i] = periodic ? wrap(x, L) : wall(x, rad[i], L);
+            nxy[2 * i + 1] = periodic ? wrap(y, L) : wall(y, rad[i], L);
+            if (tan_on) {
+                ntxy[2 * i] = wall_slope(x, rad[i], L) * (txy[2 * i] + h * tforce[2 * i]);
+                ntxy[2 * i + 1] = wall_slope(y, rad[i], L) * (txy[2 * i + 1] + h * tforce[2 * i + 1]);
+            }
+            nth[i] = th + Th[i];
+        }
+        if (overlap_method == 1) {
+            xy.swap(nxy);
+            theta.swap(nth);
+            if (tan_on) txy.swap(ntxy);
+            return pair_rounds(rounds);
+        }
+        // Sec. 4.3: an edge whose vector reversed means the pair passed through each other
+        int64_t rev = 0;
+        for (const auto &e : edges) {
+            int i = e.first, j = e.second;
+            const double P = periodic ? L : 0.0;
+            double ox = min_image(xy[2 * j] - xy[2 * i], P), oy = min_image(xy[2 * j + 1] - xy[2 * i + 1], P);
+            double mx = min_image(nxy[2 * j] - nxy[2 * i], P), my = min_image(nxy[2 * j + 1] - nxy[2 * i + 1], P);
+            if (ox * mx + oy * my < 0.0) ++rev;
+        }
+        st.reversals += rev;
+        if (rev > 0 && level < max_halvings) {
+            ++st.dt_halvings;
+            std::vector<double> WL, WR, ThL, ThR;
+            bridge(level, index, h, W, Th, WL, WR, ThL, ThR);
+            int rc = substep(level + 1, 2 * index, WL, ThL, 0.5 * h, rounds);
+            if (rc != 0) return rc;
+            return substep(level + 1, 2 * index + 1, WR, ThR, 0.5 * h, rounds);
+        }
+        xy.swap(nxy);
+        theta.swap(nth);
+        if (tan_on) txy.swap(ntxy);
+        if (!retriangulate()) return -4;
+        for (int done = 0;;) {
+            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, edges, &st.cap_hits,
+                                        tan_on ? txy.data() : nullptr, periodic);
+            if (cnt == 0) break;
+            ++done;
+            ++rounds;
+            st.overlap_edges_total += cnt;
+            if (!retriangulate()) return -4;
+            if (done >= max_rounds) {
+                // still overlapping after the cap?
+                bool any = false;
+                for (const auto &e : edges) {
+                    int i = e.first, j = e.second;
+                    const double P = periodic ? L : 0.0;
+                    double dx = min_image(xy[2 * i] - xy[2 * j], P), dy = min_image(xy[2 * i + 1] - xy[2 * j + 1], P);
+                    if (overlapping(std::sqrt(dx * dx + dy * dy), rad[i] + rad[j], tol)) { any = true; break; }
+                }
+                if (any) return -3;
+                break;
+            }
+        }
+        return 0;
+    }
+
+    // Overlap rounds of the short-range variant (Sec. 5): over every
+    // overlapping pair, no triangulation.
+    int pair_rounds(int &rounds) {
+        std::vector<std::pair<int, int>> pairs;
+        for (int done = 0;;) {
+            overlapping_pairs(n, xy.data(), rad.data(), tol, pairs, periodic ? L : 0.0);
+            if (pairs.empty()) return 0;
+            if (done >= max_rounds) return -3;
+            int64_t cnt = overlap_round(n, xy.data(), rad.data(), L, f, cap_frac, tol, pairs, &st.cap_hits,
+                                        tan_on ? txy.data() : nullptr, periodic);
+            ++done;
+            ++rounds;
+            st.overlap_edges_total += cnt;
+        }
     }
 };
 
@@ -717,14 +896,22 @@ int orc_delaunay(int n, const double *xy, int *tri_out, int cap) {
     return nt;
 }
 
-// Forces for the particles listed in idx (m of them; idx NULL = all n).
-void orc_forces(int n, const double *xy, const int *sp, int S, const double *K, int kind, double q, double A,
-                double lam, double cutoff, const int *idx, int m, double *out) {
+// Forces for the particles listed in idx (m of them; idx NULL = all n), in a
+// periodic box of side period (minimum-image separations; period 0: no box).
+void orc_forces_periodic(int n, const double *xy, const int *sp, int S, const double *K, int kind, double q, double A,
+                         double lam, double cutoff, double period, const int *idx, int m, double *out) {
     ForceModel fm;
+    fm.period = period;
     fm.S = S;
     fm.K.assign(K, K + S * S);
     fm.kind = kind; fm.q = q; fm.A = A; fm.lam = lam; fm.cutoff = cutoff;
     forces_subset(fm, n, xy, sp, idx, idx ? m : n, out);
+}
+
+// The same without a periodic box.
+void orc_forces(int n, const double *xy, const int *sp, int S, const double *K, int kind, double q, double A,
+                double lam, double cutoff, const int *idx, int m, double *out) {
+    orc_forces_periodic(n, xy, sp, S, K, kind, q, A, lam, cutoff, 0.0, idx, m, out);
 }
 
 // Tangent of the pair forces: d F / d(xy, K) applied to (txy, tK) (S*S, may be NULL).
@@ -749,6 +936,15 @@ int64_t orc_overlap_round(int n, double *xy, const double *rad, double L, double
     std::vector<std::pair<int, int>> e;
     d.finite_edges(e);
     return overlap_round(n, xy, rad, L, f, cap_frac, tol, e, cap_hits);
+}
+
+// One overlap round over every overlapping pair of xy (in place), the
+// short-range variant; returns the number of overlapping pairs.
+int64_t orc_overlap_round_pairs(int n, double *xy, const double *rad, double L, double f, double cap_frac, double tol,
+                                int64_t *cap_hits) {
+    std::vector<std::pair<int, int>> pairs;
+    overlapping_pairs(n, xy, rad, tol, pairs);
+    return overlap_round(n, xy, rad, L, f, cap_frac, tol, pairs, cap_hits);
 }
 
 // Frame points (2 doubles each) into out (room for cap points); returns m or -2.
@@ -796,6 +992,45 @@ int orc_sim_step(void *h, int64_t nsteps) {
 
 int orc_sim_last_rounds(void *h) { return ((Sim *)h)->last_rounds; }
 
+// 0: overlap rounds over Delaunay edges (default); 1: over all overlapping pairs, no triangulation.
+void orc_sim_set_overlap_method(void *h, int method) { ((Sim *)h)->overlap_method = method; }
+
+// Periodic box of side L (Sec. 2.1): minimum-image separations, positions
+// folded into [0, L), the torus triangulation, no walls and no frame.
+// Returns 0, or -4 if the torus triangulation fails.
+int orc_sim_set_periodic(void *h) {
+    Sim *s = (Sim *)h;
+    s->periodic = true;
+    s->fm.period = s->L;
+    s->frame.clear();
+    for (int i = 0; i < 2 * s->n; ++i) s->xy[i] = wrap(s->xy[i], s->L);
+    return s->retriangulate() ? 0 : -4;
+}
+
+// Torus triangulation of n points in [0, L)^2 (3 ids per triangle, CCW); returns the count or < 0.
+int orc_torus_delaunay(int n, const double *xy, double L, int *tri_out, int cap) {
+    Sim s;
+    s.n = n;
+    s.L = L;
+    s.periodic = true;
+    s.xy.assign(xy, xy + 2 * (size_t)n);
+    if (!s.retriangulate()) return -1;
+    int nt = (int)(s.torus_tris.size() / 3);
+    if (nt > cap) return -2;
+    std::memcpy(tri_out, s.torus_tris.data(), s.torus_tris.size() * sizeof(int));
+    return nt;
+}
+
+// Levels of halving of a move that reversed a Delaunay edge (0: only counted).
+void orc_sim_set_max_halvings(void *h, int levels) { ((Sim *)h)->max_halvings = levels; }
+
+int64_t orc_sim_dt_halvings(void *h) { return ((Sim *)h)->st.dt_halvings; }
+
+void orc_bridge(int n, uint64_t seed, int64_t step, int level, uint32_t index, double h, double D, double Dr,
+                double clip, const double *W, const double *Th, double *WL, double *WR, double *ThL, double *ThR) {
+    bridge_noise(n, seed, step, level, index, h, D, Dr, clip, W, Th, WL, WR, ThL, ThR);
+}
+
 void orc_sim_get(void *h, double *xy, double *theta, int64_t *step, int64_t *stats7) {
     Sim *s = (Sim *)h;
     if (xy) std::memcpy(xy, s->xy.data(), s->xy.size() * sizeof(double));
@@ -840,7 +1075,10 @@ int orc_sim_frame_count(void *h) { return (int)(((Sim *)h)->frame.size() / 2); }
 int orc_sim_triangles(void *h, int *tri_out, int cap) {
     Sim *s = (Sim *)h;
     std::vector<int> t;
-    s->dt_now.finite_triangles(t);
+    if (s->periodic)
+        t = s->torus_tris;
+    else
+        s->dt_now.finite_triangles(t);
     int nt = (int)(t.size() / 3);
     if (nt > cap) return -2;
     std::memcpy(tri_out, t.data(), t.size() * sizeof(int));

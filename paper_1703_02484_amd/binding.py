@@ -18,6 +18,8 @@ BD_FORCE_POWER = 0
 BD_FORCE_SCREENED = 1
 BD_PREC_FP64 = 0
 BD_PREC_FP32 = 1
+BD_OVERLAP_DELAUNAY = 0
+BD_OVERLAP_VERLET = 1
 
 EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_batch_init", "bd_batch_layout",
             "bd_get_force_config", "bd_step", "bd_forces", "bd_get_state", "bd_get_triangulation", "bd_get_frame",
@@ -41,7 +43,8 @@ class Params(ctypes.Structure):
                 ("max_overlap_rounds", ctypes.c_int32),
                 ("max_flip_rounds", ctypes.c_int32), ("force_precision", ctypes.c_int32),
                 ("force_chunk", ctypes.c_int32), ("force_per_lane", ctypes.c_int32),
-                ("force_launch", ctypes.c_int32)]
+                ("force_launch", ctypes.c_int32), ("overlap_method", ctypes.c_int32),
+                ("max_dt_halvings", ctypes.c_int32)]
 
 
 class ForceConfig(ctypes.Structure):
@@ -55,11 +58,11 @@ class ForceConfig(ctypes.Structure):
 
 STAT_NAMES = ("steps", "overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "cap_hits",
               "reversals", "noise_clamps", "flips_total", "inversion_flips", "flip_rounds_total", "kinetic_repairs",
-              "host_rebuilds", "verlet_rebuilds", "host_continued")
+              "host_rebuilds", "verlet_rebuilds", "host_continued", "dt_halvings")
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_int64) for name in STAT_NAMES] + [("reserved", ctypes.c_int64 * 2)]
+    _fields_ = [(name, ctypes.c_int64) for name in STAT_NAMES] + [("reserved", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name in STAT_NAMES}
@@ -180,7 +183,7 @@ def _ptr(a: np.ndarray) -> int:
 
 def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, step0, overlap_factor, cap_frac,
             noise_clip, contact_tol, max_overlap_rounds, max_flip_rounds, fp32, force_chunk, force_per_lane,
-            force_launch):
+            force_launch, overlap, max_dt_halvings):
     Km = np.ascontiguousarray(K, dtype=np.float64)
     fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
                      skin, _ptr(Km))
@@ -194,13 +197,15 @@ def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, st
     p.force_precision = BD_PREC_FP32 if fp32 else BD_PREC_FP64
     p.force_chunk = force_chunk
     p.force_per_lane, p.force_launch = force_per_lane, force_launch
+    p.overlap_method = {"delaunay": BD_OVERLAP_DELAUNAY, "verlet": BD_OVERLAP_VERLET}[overlap]
+    p.max_dt_halvings = max_dt_halvings
     return fp, p, Km
 
 
 _DEFAULTS = dict(kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, skin=0.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0,
                  step0=0, overlap_factor=1.0, cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9,
                  max_overlap_rounds=10000, max_flip_rounds=200, fp32=False, force_chunk=0, force_per_lane=0,
-                 force_launch=0)
+                 force_launch=0, overlap="delaunay", max_dt_halvings=0)
 
 
 class Sim:
@@ -260,7 +265,8 @@ class Sim:
         kw = dict(L=w.L, kind=w.kind, q=w.q, A=w.A, lam=w.lam, cutoff=w.cutoff, skin=w.skin, D=w.D, dt=w.dt,
                   v0=w.v0, Dr=w.Dr, seed=w.seed, step0=w.step0, overlap_factor=w.overlap_factor,
                   cap_frac=w.cap_frac, noise_clip=w.noise_clip, contact_tol=w.contact_tol,
-                  max_overlap_rounds=w.max_overlap_rounds, fp32=w.fp32_forces)
+                  max_overlap_rounds=w.max_overlap_rounds, fp32=w.fp32_forces, overlap=w.overlap,
+                  max_dt_halvings=w.max_dt_halvings)
         kw.update(over)
         return cls(w.xy, w.radii, w.species, w.theta, w.K, **kw)
 

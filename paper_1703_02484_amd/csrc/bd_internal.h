@@ -38,7 +38,9 @@ enum Ctl {
     K_VT_N = 16,       // triangles rewritten by flips since the last overlap detection (list length)
     K_TICKET = 17,     // workgroups finished in the current launch (last-workgroup checks; back to 0 after)
     K_NL_BUILT = 18,   // the neighbour lists were rebuilt on the device at the start of this step
-    K_CAND = 19,                     // [MAXR] flip candidates of round slot j
+    K_NL_STALE = 19,   // list overlap detection: a disk moved so far since the build that a pair may be missing
+    K_REV = 20,        // Delaunay edges reversed by this step's move, counted when a reversal halves the step
+    K_CAND = 21,                     // [MAXR] flip candidates of round slot j
     K_WL = K_CAND + MAXR,            // [MAXR] worklist length read by round slot j
     K_INVQ = K_WL + MAXR,            // [MAXR] evaluated quads holding an inverted triangle
     K_INV = K_INVQ + MAXR,           // [MAXREP] invalid triangles after repair j
@@ -51,7 +53,9 @@ enum HaltReason {
     HALT_INVALID = 2,
     HALT_TOPOLOGY = 3,
     HALT_OVERLAP_BUDGET = 4,
-    HALT_NL_CAPACITY = 5   // a rebuild inside a queued step found more neighbours than the lists hold
+    HALT_NL_CAPACITY = 5,  // a rebuild inside a queued step found more neighbours than the lists hold
+    HALT_NL_STALE = 6,     // list overlap detection: the lists may miss a pair (rebuild, then continue)
+    HALT_REVERSAL = 7      // the move reversed a Delaunay edge: the host redoes the step in halves
 };
 
 enum Acc {
@@ -241,6 +245,9 @@ struct Sim {
     int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_items = nullptr;
     double *xbuild = nullptr, *ybuild = nullptr;
     double2 *fsr = nullptr;          // short-range forces, caller order
+    int ovl_method = 0;              // 0: overlap rounds over Delaunay edges; 1: over the neighbour lists
+    double nl_margin = 0.0;          // lists hold every pair closer than contact while no disk moved farther
+                                     // than this since the build: (cutoff + skin - 2 r_max) / 2
     int *scan_bsum = nullptr;        // per-block totals of the cell-count scan
     // triangulation (half-edge SoA, ghosts included)
     int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
@@ -260,6 +267,7 @@ struct Sim {
     // repair fallback: topology snapshot and the move it must replay
     int *snap_v = nullptr, *snap_twin = nullptr, *snap_vh = nullptr;
     double *xa = nullptr, *ya = nullptr, *xb = nullptr, *yb = nullptr;
+    double *xs = nullptr, *ys = nullptr, *ths = nullptr;   // start of a step redone in halves (allocated on first use)
     int round_id = 0;                // flip-round stamp (absolute)
     int vround = 0;                  // overlap-round stamp (absolute)
     StepBase *dbase = nullptr;       // device copy of the bases below
@@ -269,7 +277,11 @@ struct Sim {
     bool use_graph = false;
     int batch_hint = kRing;          // graph steps queued per batch (adapts to the steps between stops)
     int tail_mode = -1;              // overlap rounds after the first detection: 0 launch per phase,
-                                     // 1 one workgroup, -1 chosen from the problem size
+                                     // 1 one workgroup, 2 the large first rounds launched per phase and the
+                                     // rest in one workgroup, -1 chosen from the problem size
+    int multi_em = 2;                // mode 2: flip rounds of the move's repair launched on many workgroups
+    int multi_ovl = 1;               // mode 2: the same for the repair after an overlap round
+    int ovl_phase = 1;               // mode 2: overlap rounds launched per phase before the one-workgroup tail
     struct StepGraph {
         hipGraphExec_t pre = nullptr, force = nullptr, post = nullptr;
         int r_used = 0, v_used = 0;
@@ -308,7 +320,8 @@ void launch_step_begin(Sim &s);                       // clear the control block
 void launch_step_end(Sim &s, int r_used, int v_used); // record the control block, advance or stop
 void launch_force(Sim &s);
 int force_max_grid(Sim &s, int per_lane);            // resident workgroups of the persistent launch
-void launch_em(Sim &s);
+// level > 0: sub-interval `index` of the 2^level halves of the step after edge reversals (Sec. 4.3)
+void launch_em(Sim &s, int level = 0, unsigned index = 0);
 void launch_reduce_forces(Sim &s);
 // short-range path (k_verlet.hip)
 int verlet_scan_blocks(int ncells);
@@ -316,8 +329,12 @@ void launch_verlet_build(Sim &s);
 void launch_verlet_build_requested(Sim &s);   // the same kernels, each doing nothing unless the step asks (graph mode)
 void launch_force_nl(Sim &s);
 void launch_skin_check(Sim &s);
+// overlap rounds over the neighbour lists (Sec. 5 short-range variant, no triangulation): round slot k
+void launch_ovl_nl_gather(Sim &s, int k);
+void launch_ovl_nl_apply(Sim &s, int k, bool final_check);
 // triangulation (slot: round slot in ctl; rep: repair slot)
-void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal);
+// reversal: 0 no test; 1 count reversed edges (Sec. 4.3); 2 count them and flag the step (K_REV) for halving
+void launch_flip_eval_full(Sim &s, int round, int slot, int reversal);
 void launch_flip_eval_list(Sim &s, int round, int slot);
 void launch_flip_apply(Sim &s, int round, int slot);
 void launch_flip_fix(Sim &s, int round, int slot);
@@ -355,8 +372,9 @@ struct TailPlan {
     double f, cap_frac, keep;
 };
 void launch_tail(Sim &s, const TailPlan &plan);
-// rounds [round0, round0 + rounds) of a repair whose first evaluation ran already, in one workgroup
-void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds);
+// rounds [round0, round0 + rounds) of a repair in one workgroup (first_evaluated: round0's evaluation ran
+// already, in a launch of many workgroups)
+void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds, bool first_evaluated = true);
 
 // adjoint sweep (k_adjoint.hip)
 void launch_adj_round(Sim &s, int first_entry, int count);     // one recorded overlap round, reversed
@@ -369,6 +387,9 @@ void launch_adj_dk_final(Sim &s);
 // or two coincide.
 uint64_t hilbert_index(uint32_t x, uint32_t y, int bits);
 int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_v, std::vector<int> &he_twin);
+// Delaunay triangulation of the flat torus [0, L)^2 (periodic box): 2n triangles over ids 0..n-1.
+int host_torus_delaunay(int n, const double *x, const double *y, double L, std::vector<int> &he_v,
+                        std::vector<int> &he_twin);
 
 // Fixed frame points closing the triangulation outside the walls of [0, L]^2.
 void frame_points(double L, double rmax, std::vector<double> &fx, std::vector<double> &fy);

@@ -56,6 +56,25 @@ BD_HD bool bd_in_closed_tri(double v1x, double v1y, double v2x, double v2y, doub
 
 enum { BD_NOFLIP = 0, BD_FLIP_LAWSON = 1, BD_FLIP_INVERSION = 2 };
 
+// Flip decision for a quad of four finite points: the edge a -> b shared by
+// the triangles (a, b, c) and (b, a, d).  With an inverted (or flat) triangle:
+// flip when one opposite vertex lies in the closed triangle formed by the edge
+// and the other opposite vertex (Sec. 4.3, evaluated for both orderings);
+// otherwise the Lawson flip when d is strictly inside the circumcircle of
+// (a, b, c) (Sec. 4.1).
+BD_HD int bd_flip_rule_quad(double ax, double ay, double bx, double by, double cx, double cy, double dx, double dy,
+                            bool allow_inversion, bool *inverted) {
+    const double o1 = bd_orient(ax, ay, bx, by, cx, cy);
+    const double o2 = bd_orient(bx, by, ax, ay, dx, dy);
+    if (o1 <= 0.0 || o2 <= 0.0) {
+        if (inverted) *inverted = true;
+        if (!allow_inversion) return BD_NOFLIP;
+        bool f = bd_in_closed_tri(ax, ay, bx, by, cx, cy, dx, dy) || bd_in_closed_tri(ax, ay, bx, by, dx, dy, cx, cy);
+        return f ? BD_FLIP_INVERSION : BD_NOFLIP;
+    }
+    return bd_incircle(ax, ay, bx, by, cx, cy, dx, dy) > 0.0 ? BD_FLIP_LAWSON : BD_NOFLIP;
+}
+
 // Flip decision for the edge a -> b shared by triangles (a, b, c) and
 // (b, a, d), any of a, b, c, d possibly an infinite vertex (ids >= inf; a
 // batch of independent triangulations has one infinite vertex each).
@@ -85,17 +104,7 @@ BD_HD int bd_flip_rule(int a, int b, int c, int d, int inf, const double *x, con
         if (inverted) *inverted = bad;
         return bad ? BD_FLIP_INVERSION : BD_NOFLIP;
     }
-    const double ax = x[a], ay = y[a], bx = x[b], by = y[b];
-    const double cx = x[c], cy = y[c], dx = x[d], dy = y[d];
-    const double o1 = bd_orient(ax, ay, bx, by, cx, cy);
-    const double o2 = bd_orient(bx, by, ax, ay, dx, dy);
-    if (o1 <= 0.0 || o2 <= 0.0) {
-        if (inverted) *inverted = true;
-        if (!allow_inversion) return BD_NOFLIP;
-        bool f = bd_in_closed_tri(ax, ay, bx, by, cx, cy, dx, dy) || bd_in_closed_tri(ax, ay, bx, by, dx, dy, cx, cy);
-        return f ? BD_FLIP_INVERSION : BD_NOFLIP;
-    }
-    return bd_incircle(ax, ay, bx, by, cx, cy, dx, dy) > 0.0 ? BD_FLIP_LAWSON : BD_NOFLIP;
+    return bd_flip_rule_quad(x[a], y[a], x[b], y[b], x[c], y[c], x[d], y[d], allow_inversion, inverted);
 }
 
 // Hard walls: reflect about the shifted wall [r, L - r], then clamp.
@@ -107,6 +116,20 @@ BD_HD double bd_wall(double c, double r, double L) {
     c = c < lo ? lo : c;
     c = c > hi ? hi : c;
     return c;
+}
+
+// Periodic box of side L (Sec. 2.1): a separation component from the nearest
+// image (minimum-image convention, ties to even), and a coordinate folded into
+// [0, L).
+BD_HD double bd_min_image(double v, double L) {
+#pragma clang fp contract(off)
+    return v - L * rint(v / L);
+}
+
+BD_HD double bd_wrap(double c, double L) {
+#pragma clang fp contract(off)
+    const double r = c - L * floor(c / L);
+    return r >= L ? r - L : r;
 }
 
 // Slope of bd_wall at c: -1 per reflection, 0 where the clamp acts.

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "bd_internal.h"
@@ -309,6 +310,81 @@ int host_delaunay(int n, const double *x, const double *y, std::vector<int> &he_
     he_v.swap(m.V);
     he_twin.swap(m.Tw);
     return 0;
+}
+
+// Delaunay triangulation of the flat torus [0, L)^2 (the periodic box of
+// Sec. 2.1, whose triangulation the paper builds with a periodic Delaunay
+// library) as half-edges over the ids 0..n-1, 2n triangles, no infinite
+// vertex.  The planar triangulation of the points and of their periodic
+// copies inside a band of width w around the box equals the periodic one
+// near the box; every torus triangle appears there once per copy, and the
+// copy kept is the one whose vertex of smallest id lies in the box itself.  A
+// kept triangle whose circumcircle leaves the band may be wrong (a copy
+// outside the band could lie inside it): the band is then widened.  Twins pair
+// the directed edges a -> b and b -> a, which are unique while every edge is
+// shorter than L / 2.  Returns 0, or -1 (degenerate input or a box too small
+// for its points).
+int host_torus_delaunay(int n, const double *x, const double *y, double L, std::vector<int> &he_v,
+                        std::vector<int> &he_twin) {
+    if (n < 3 || !(L > 0)) return -1;
+    double w = std::min(L, 6.0 * std::sqrt(L * L / n));
+    for (;;) {
+        std::vector<double> px, py;
+        std::vector<int> id, cp;   // original id and copy (ox + 1) + 3 (oy + 1); the box itself is copy 4
+        for (int oy = -1; oy <= 1; ++oy)
+            for (int ox = -1; ox <= 1; ++ox)
+                for (int i = 0; i < n; ++i) {
+                    const double X = x[i] + ox * L, Y = y[i] + oy * L;
+                    if (X < -w || X >= L + w || Y < -w || Y >= L + w) continue;
+                    px.push_back(X);
+                    py.push_back(Y);
+                    id.push_back(i);
+                    cp.push_back((ox + 1) + 3 * (oy + 1));
+                }
+        std::vector<int> V, Tw;
+        const int m = (int)px.size();
+        if (host_delaunay(m, px.data(), py.data(), V, Tw) != 0) return -1;
+        std::vector<int> tri;
+        bool narrow = false;
+        for (size_t t = 0; 3 * t < V.size(); ++t) {
+            const int a = V[3 * t], b = V[3 * t + 1], c = V[3 * t + 2];
+            if (a >= m || b >= m || c >= m) continue;   // ghost
+            int lo = a;
+            if (id[b] < id[lo]) lo = b;
+            if (id[c] < id[lo]) lo = c;
+            if (cp[lo] != 4) continue;
+            // circumcircle of the kept triangle inside the band
+            const double bx = px[b] - px[a], by = py[b] - py[a], cx = px[c] - px[a], cy = py[c] - py[a];
+            const double d = 2.0 * (bx * cy - by * cx);
+            const double b2 = bx * bx + by * by, c2 = cx * cx + cy * cy;
+            const double ux = (cy * b2 - by * c2) / d, uy = (bx * c2 - cx * b2) / d;
+            const double r = std::sqrt(ux * ux + uy * uy), ox = px[a] + ux, oy = py[a] + uy;
+            if (ox - r < -w || ox + r > L + w || oy - r < -w || oy + r > L + w) narrow = true;
+            tri.push_back(id[a]);
+            tri.push_back(id[b]);
+            tri.push_back(id[c]);
+        }
+        if (narrow && w < L) {
+            w = std::min(L, 2.0 * w);
+            continue;
+        }
+        if ((int)tri.size() != 6 * n) return -1;
+        he_v = tri;
+        he_twin.assign(tri.size(), -1);
+        std::unordered_map<uint64_t, int> dir;
+        dir.reserve(tri.size() * 2);
+        auto key = [](int a, int b) { return ((uint64_t)(uint32_t)a << 32) | (uint32_t)b; };
+        for (size_t h = 0; h < tri.size(); ++h) {
+            const int a = tri[h], b = tri[bd_next((int)h)];
+            if (!dir.emplace(key(a, b), (int)h).second) return -1;   // the same directed edge twice
+        }
+        for (size_t h = 0; h < tri.size(); ++h) {
+            auto it = dir.find(key(tri[bd_next((int)h)], tri[h]));
+            if (it == dir.end()) return -1;
+            he_twin[h] = it->second;
+        }
+        return 0;
+    }
 }
 
 }  // namespace bd

@@ -399,6 +399,9 @@ __device__ __forceinline__ void box_muller(uint4 w, double &z0, double &z1) {
 struct EmArgs {
     int n, S;
     double dt, amp, amp_r, v0, clip;
+    double D, Dr;          // for the bridge amplitudes of a sub-interval
+    int level;             // 0: the whole step; > 0: sub-interval `index` of 2^level after reversals (Sec. 4.3)
+    unsigned index;
 };
 
 // Fused Euler-Maruyama update: gather forces, draw noise (stream 0:
@@ -442,11 +445,33 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         if (zx < -a.clip) { zx = -a.clip; ++clamps; }
         if (zy > a.clip) { zy = a.clip; ++clamps; }
         if (zy < -a.clip) { zy = -a.clip; ++clamps; }
+        // noise increments of the step, then down the Brownian bridge to the sub-interval: the
+        // increment over the first half of an interval of length h with increment w is
+        // w/2 + sqrt(D h / 2) eta (eta keyed by the level of the halves and the parent's index,
+        // clamped like xi), the second half takes the rest
+        double wx = a.amp * zx, wy = a.amp * zy, wt = a.amp_r * nr;
+        double hsub = a.dt;
+        for (int lv = 1; lv <= a.level; ++lv) {
+            const unsigned par = a.index >> (a.level - lv + 1), side = (a.index >> (a.level - lv)) & 1u;
+            const unsigned skey = 0x80000000u | ((unsigned)lv << 24) | (par << 1);
+            double ex, ey, er;
+            box_muller(philox10(make_uint4(id, slo, shi, skey), key), ex, ey);
+            box_muller(philox10(make_uint4(id, slo, shi, skey | 1u), key), er, unused);
+            ex = ex > a.clip ? a.clip : (ex < -a.clip ? -a.clip : ex);
+            ey = ey > a.clip ? a.clip : (ey < -a.clip ? -a.clip : ey);
+            const double at = sqrt(0.5 * a.D * hsub), ar = sqrt(0.5 * a.Dr * hsub);
+            const double lx = 0.5 * wx + at * ex, ly = 0.5 * wy + at * ey, lt = 0.5 * wt + ar * er;
+            wx = side ? wx - lx : lx;
+            wy = side ? wy - ly : ly;
+            wt = side ? wt - lt : lt;
+            hsub = 0.5 * hsub;
+        }
+        if (a.level > 0) clamps = 0;   // the step's own draws were counted when it was first tried
         const double x0 = x[i], y0 = y[i], t0 = th[i], r = rad[i];
         const double vx = fx + a.v0 * cos(t0);
         const double vy = fy + a.v0 * sin(t0);
-        const double xn = x0 + vx * a.dt + a.amp * zx;
-        const double yn = y0 + vy * a.dt + a.amp * zy;
+        const double xn = x0 + vx * hsub + wx;
+        const double yn = y0 + vy * hsub + wy;
         xo[i] = x0;
         yo[i] = y0;
         tho[i] = t0;
@@ -456,7 +481,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
             wf[2 * (size_t)i] = bd_wall_slope(xn, r, ri.L);
             wf[2 * (size_t)i + 1] = bd_wall_slope(yn, r, ri.L);
         }
-        th[i] = t0 + a.amp_r * nr;
+        th[i] = t0 + wt;
     }
     // one atomic per wavefront (every lane is here)
     for (int off = 32; off > 0; off >>= 1) clamps += __shfl_xor(clamps, off);
@@ -635,7 +660,7 @@ int force_max_grid(Sim &s, int per_lane) {
     return cus * per_cu;
 }
 
-void launch_em(Sim &s) {
+void launch_em(Sim &s, int level, unsigned index) {
     EmArgs a;
     a.n = s.n;
     a.S = s.S;
@@ -644,6 +669,10 @@ void launch_em(Sim &s) {
     a.amp_r = std::sqrt(2.0 * s.p.Dr * s.p.dt);
     a.v0 = s.p.v0;
     a.clip = s.p.noise_clip;
+    a.D = s.p.D;
+    a.Dr = s.p.Dr;
+    a.level = level;
+    a.index = index;
     const int nb = blocks_for(s.n, 256);
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;

@@ -270,17 +270,22 @@ __device__ __forceinline__ bool adjacent(const Topo &t, int c, int d) {
 
 // Evaluates the canonical edge h (h < twin) and, if it must flip, registers
 // it as a candidate of round slot `slot` and claims its two triangles.
-__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, bool reversal) {
+__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, int reversal) {
     if (bad_he(t, tw)) return topo_err(t);
     const int t1 = h / 3, t2 = tw / 3;
     const int a = t.he_v[h], b = t.he_v[bd_next(h)], c = t.he_v[bd_prev(h)];
     const int d = t.he_v[bd_prev(tw)];
     if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c) || bad_v(t, d)) return topo_err(t);
-    if (reversal && a < t.n && b < t.n) {
+    if (reversal) {
         // Sec. 4.3: the pair passed through each other if the edge vector reversed
-        double ox = t.xo[b] - t.xo[a], oy = t.yo[b] - t.yo[a];
-        double mx = t.x[b] - t.x[a], my = t.y[b] - t.y[a];
-        wave_count64(&t.acc[A_REVERSALS], ox * mx + oy * my < 0.0);
+        bool rev = false;
+        if (a < t.n && b < t.n) {
+            const double ox = t.xo[b] - t.xo[a], oy = t.yo[b] - t.yo[a];
+            const double mx = t.x[b] - t.x[a], my = t.y[b] - t.y[a];
+            rev = ox * mx + oy * my < 0.0;
+        }
+        wave_count64(&t.acc[A_REVERSALS], rev);
+        if (reversal == 2) wave_count(&t.ctl[K_REV], rev);
     }
     bool inverted = false;
     const int rule = bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, &inverted);
@@ -306,7 +311,7 @@ __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
         for (int k = 0; k < 3; ++k) {
             int h = 3 * tri + k;
             int tw = t.he_twin[h];
-            if (h < tw) eval_edge(t, h, tw, round, slot, reversal != 0);
+            if (h < tw) eval_edge(t, h, tw, round, slot, reversal);
         }
     }
 }
@@ -332,7 +337,7 @@ __device__ __forceinline__ void flip_eval_list_body(const Topo &t, int round, in
             h = tw;
             tw = s;
         }
-        eval_edge(t, h, tw, round, slot, false);
+        eval_edge(t, h, tw, round, slot, 0);
     }
 }
 
@@ -527,6 +532,8 @@ __device__ __forceinline__ void repair_check_body(int *ctl, int rep, int last) {
     int reason = 0;
     if (ctl_read(ctl, K_TOPO) != 0)
         reason = HALT_TOPOLOGY;
+    else if (ctl_read(ctl, K_REV) != 0)   // only ever set by a move whose reversals halve the step
+        reason = HALT_REVERSAL;
     else if (ctl_read(ctl, K_CAND + last) != 0)
         reason = HALT_REPAIR_BUDGET;
     else if (ctl_read(ctl, K_INV + rep) != 0)
@@ -1079,10 +1086,13 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(Topo t, TailPlan p) {
 #undef TAIL_SYNC
 }
 
-// The flip rounds of the repair after the move, once its first evaluation
-// (every edge, many workgroups) has run: that round's apply and fix, then the
-// remaining rounds, in one workgroup.
-__global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0, int slot0, int rounds) {
+// Flip rounds [round0, round0 + rounds) of a repair in one workgroup, from
+// slot slot0 on.  first_evaluated: the first round's evaluation already ran in
+// a launch of many workgroups (the repair after the move scans every edge), so
+// it starts with that round's apply; otherwise with the evaluation of the
+// worklist in slot0.  The loop ends at the first round with nothing to do.
+__global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0, int slot0, int rounds,
+                                                              int first_evaluated) {
     const int i0 = threadIdx.x, stride = blockDim.x;
 #define TAIL_SYNC()                  \
     do {                             \
@@ -1095,7 +1105,7 @@ __global__ __launch_bounds__(kTailBlock) void k_repair_rounds(Topo t, int round0
         int slot = slot0 + r;
         if (slot >= MAXR) slot -= MAXR;
         const int round = round0 + r;
-        if (r > 0) {
+        if (r > 0 || !first_evaluated) {
             if (rounds_done(t, slot, false)) break;
             flip_eval_list_body(t, round, slot, i0, stride);
             TAIL_SYNC();
@@ -1169,11 +1179,11 @@ inline int list_grid(const Sim &s) {
 
 }  // namespace
 
-void launch_flip_eval_full(Sim &s, int round, int slot, bool reversal) {
+void launch_flip_eval_full(Sim &s, int round, int slot, int reversal) {
     round -= s.rbase;
     Topo t = topo_of(s);
     hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T, kScanGrid)), dim3(256), 0, s.stream, t, round, slot,
-                       reversal ? 1 : 0);
+                       reversal);
 }
 
 void launch_flip_eval_list(Sim &s, int round, int slot) {
@@ -1242,9 +1252,10 @@ void launch_tail(Sim &s, const TailPlan &plan) {
     hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailBlock), 0, s.stream, t, plan);
 }
 
-void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds) {
+void launch_repair_rounds(Sim &s, int round0, int slot0, int rounds, bool first_evaluated) {
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_repair_rounds, dim3(1), dim3(kTailBlock), 0, s.stream, t, round0 - s.rbase, slot0, rounds);
+    hipLaunchKernelGGL(k_repair_rounds, dim3(1), dim3(kTailBlock), 0, s.stream, t, round0 - s.rbase, slot0, rounds,
+                       first_evaluated ? 1 : 0);
 }
 
 void launch_snapshot(Sim &s) {

@@ -14,6 +14,8 @@
 // new lists (`req` points at the step's flag; null: always build).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bd_internal.h"
 #include "geom.h"
 
@@ -138,8 +140,12 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
     yb[i] = yi;
 }
 
-// Pair force over the list (FP64): F_i = sum_j K[s_i][s_j] g(d) (r_i - r_j)/d
-// for d <= r_cut, g(d) = A exp(-d/lam)/d (screened) or d^-q (power).
+// Pair force over the list: F_i = sum_j K[s_i][s_j] g(d) (r_i - r_j)/d for
+// d <= r_cut, g(d) = A exp(-d/lam)/d (screened) or d^-q (power).  The
+// separation, its length and the cutoff test are FP64 (positions stay FP64);
+// T is the precision of the law's arithmetic and of the sum (FP32 or FP64).  ONE_SPECIES: a single
+// species, so no neighbour's species is read.
+template <typename T, bool ONE_SPECIES>
 __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restrict__ x, const double *__restrict__ y,
                                                   const int *__restrict__ sp, const double *__restrict__ K, int S,
                                                   int kind, double q, double A, double lam, double rc,
@@ -150,24 +156,27 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || base->stop || ctl[K_HALT]) return;   // K_HALT: the lists of this step overflowed
     const double xi = x[i], yi = y[i];
-    const int si = sp[i];
+    const int si = ONE_SPECIES ? 0 : sp[i];
+    const T k0 = (T)K[0];
+    const T lamT = (T)lam, AT = (T)A, qT = (T)q;
     const int m = nl_cnt[i];
-    double fx = 0.0, fy = 0.0;
+    T fx = (T)0, fy = (T)0;
     for (int k = 0; k < m; ++k) {
         const int j = nl[(size_t)k * n + i];
-        const double dx = xi - x[j], dy = yi - y[j];
-        const double d = sqrt(dx * dx + dy * dy);
-        if (d > rc) continue;
-        double s;
+        const double ddx = xi - x[j], ddy = yi - y[j];
+        const double dd = sqrt(ddx * ddx + ddy * ddy);
+        if (dd > rc) continue;   // the cutoff decision in FP64 in both precisions
+        const T dx = (T)ddx, dy = (T)ddy, d = (T)dd;
+        T s;
         if (kind == BD_FORCE_SCREENED)
-            s = A * exp(-d / lam) / d / d;
+            s = AT * exp(-d / lamT) / d / d;
         else
-            s = pow(d, -q) / d;
-        s *= K[si * S + sp[j]];
+            s = pow(d, -qT) / d;
+        s *= ONE_SPECIES ? k0 : (T)K[si * S + sp[j]];
         fx += s * dx;
         fy += s * dy;
     }
-    f[i] = make_double2(fx, fy);
+    f[i] = make_double2((double)fx, (double)fy);
 }
 
 // Skin test at the end of a step: has any disk moved more than skin / 2 since
@@ -200,6 +209,124 @@ __global__ void k_nl_check(int *__restrict__ ctl, const StepBase *__restrict__ b
         ctl[K_REASON] = HALT_NL_CAPACITY;
         ctl[K_STAGE] = 0;
         ctl[K_HALT] = 1;
+    }
+}
+
+// ---------------------------------------------------------------- overlap rounds over the lists
+// The paper's short-range variant (Sec. 5) finds overlapping pairs through the
+// neighbour lists instead of a triangulation.  Round k, gather: every disk sums
+// its Jacobi displacement over the listed partners that overlap it (Sec. 2.3
+// displacement along the unit vector, factor f), truncates the sum to
+// cap_frac * r (Sec. 4.4) and applies the walls; a disk that moved is queued
+// with its new position.  Overlapping pairs are counted once (from the lower
+// id).  The lists contain every pair closer than contact only while no disk
+// has moved more than `margin` since the build; a disk beyond it raises
+// K_NL_STALE and the round is not applied (the host rebuilds the lists and
+// repeats the detection).  Apply: if the round found nothing the overlap loop
+// is done; otherwise the queued disks take their new positions (all at once,
+// after every gather has read the old ones).
+__global__ __launch_bounds__(256) void k_ovl_nl_gather(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                                       const double *__restrict__ rad, double L,
+                                                       const int *__restrict__ nl, const int *__restrict__ nl_cnt,
+                                                       const double *__restrict__ xb, const double *__restrict__ yb,
+                                                       double margin2, double f, double cap_frac, double keep,
+                                                       int *__restrict__ touched, double2 *__restrict__ newpos,
+                                                       int *__restrict__ ctl, unsigned long long *__restrict__ acc,
+                                                       int k) {
+#pragma clang fp contract(off)
+    if ((ctl[K_HALT] | ctl[K_DONE]) != 0) return;   // nothing in this launch writes them: uniform
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool moved = false, capped = false, stale = false;
+    int pairs = 0;
+    double nx = 0.0, ny = 0.0;
+    if (i < n) {
+        const double xi = x[i], yi = y[i], ri = rad[i];
+        const double ex = xi - xb[i], ey = yi - yb[i];
+        stale = ex * ex + ey * ey > margin2;
+        const int m = nl_cnt[i];
+        double sx = 0.0, sy = 0.0;
+        for (int q = 0; q < m; ++q) {
+            const int j = nl[(size_t)q * n + i];
+            const double dx = xi - x[j], dy = yi - y[j];
+            const double d = sqrt(dx * dx + dy * dy);
+            const double contact = ri + rad[j];
+            if (d < contact * keep) {
+                const double sc = f * (contact - d) / d;
+                sx += sc * dx;
+                sy += sc * dy;
+                moved = true;
+                if (i < j) ++pairs;
+            }
+        }
+        if (moved) {
+            const double len = sqrt(sx * sx + sy * sy);
+            const double cap = cap_frac * ri;
+            if (len > cap) {
+                const double sc = cap / len;
+                sx = sx * sc;
+                sy = sy * sc;
+                capped = true;
+            }
+            nx = bd_wall(xi + sx, ri, L);
+            ny = bd_wall(yi + sy, ri, L);
+        }
+    }
+    // every lane of the wavefront is here: one atomic per wavefront for each counter
+    const unsigned long long mm = __ballot(moved);
+    if (mm != 0) {
+        const int lane = __lane_id(), leader = __ffsll((unsigned long long)mm) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctl[K_TOUCH + k], __popcll(mm));
+        base = __shfl(base, leader);
+        if (moved) {
+            const int pos = base + __popcll(mm & ((1ull << lane) - 1ull));
+            touched[pos] = i;
+            newpos[pos] = make_double2(nx, ny);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) pairs += __shfl_xor(pairs, off);
+    if (__lane_id() == 0 && pairs) atomicAdd(&ctl[K_OVL + k], pairs);
+    const unsigned long long mc = __ballot(capped);
+    if (mc != 0 && __lane_id() == 0) atomicAdd(&acc[A_CAP_HITS], (unsigned long long)__popcll(mc));
+    if (__ballot(stale) != 0 && __lane_id() == 0) atomicOr(&ctl[K_NL_STALE], 1);
+}
+
+// final_check: the last budgeted round's detection; overlaps left halt the
+// step (the host continues the loop) instead of being applied.
+__global__ __launch_bounds__(256) void k_ovl_nl_apply(double *__restrict__ x, double *__restrict__ y,
+                                                      const int *__restrict__ touched,
+                                                      const double2 *__restrict__ newpos, int *__restrict__ ctl, int k,
+                                                      int final_check) {
+    if ((ctl[K_HALT] | ctl[K_DONE]) != 0) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // the counters below were written by the gather launch before this one: every thread reads the same
+    if (ctl[K_NL_STALE] != 0) {
+        if (lead) {
+            ctl[K_REASON] = HALT_NL_STALE;
+            ctl[K_STAGE] = k;
+            ctl[K_HALT] = 1;
+        }
+        return;
+    }
+    if (ctl[K_OVL + k] == 0) {
+        if (lead) ctl[K_DONE] = 1;
+        return;
+    }
+    if (final_check) {
+        if (lead) {
+            ctl[K_REASON] = HALT_OVERLAP_BUDGET;
+            ctl[K_STAGE] = k;
+            ctl[K_HALT] = 1;
+        }
+        return;
+    }
+    if (lead) ctl[K_OVL_ROUNDS] = k + 1;
+    const int cnt = ctl[K_TOUCH + k];
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < cnt; idx += gridDim.x * blockDim.x) {
+        const int v = touched[idx];
+        const double2 p = newpos[idx];
+        x[v] = p.x;
+        y[v] = p.y;
     }
 }
 
@@ -251,9 +378,32 @@ void launch_verlet_build_requested(Sim &s) {
 }
 
 void launch_force_nl(Sim &s) {
-    hipLaunchKernelGGL(k_force_nl, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, s.sp, s.Kd, s.S,
-                       s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff, s.nl, s.nl_cnt, s.fsr,
-                       (const StepBase *)s.dbase, (const int *)s.ctl);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
+                           (const double *)s.y, (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
+                           s.fp.A, s.fp.lambda, s.fp.cutoff, (const int *)s.nl, (const int *)s.nl_cnt, s.fsr,
+                           (const StepBase *)s.dbase, (const int *)s.ctl);
+    };
+    if (s.fp32)
+        s.S == 1 ? go(k_force_nl<float, true>) : go(k_force_nl<float, false>);
+    else
+        s.S == 1 ? go(k_force_nl<double, true>) : go(k_force_nl<double, false>);
+}
+
+void launch_ovl_nl_gather(Sim &s, int k) {
+    hipLaunchKernelGGL(k_ovl_nl_gather, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
+                       (const double *)s.y, (const double *)s.rad, s.L_h[0], (const int *)s.nl,
+                       (const int *)s.nl_cnt, (const double *)s.xbuild, (const double *)s.ybuild,
+                       s.nl_margin * s.nl_margin, s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol,
+                       s.touched + (size_t)(k & 1) * s.n, s.newpos, s.ctl, s.acc, k);
+}
+
+void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {
+    // the queued disks are usually a few percent of all: a grid for a tenth of them
+    const int g = std::max(1, std::min(blocks(s.n), blocks(s.n / 10 + 1)));
+    hipLaunchKernelGGL(k_ovl_nl_apply, dim3(g), dim3(256), 0, s.stream, s.x, s.y,
+                       (const int *)(s.touched + (size_t)(k & 1) * s.n), (const double2 *)s.newpos, s.ctl, k,
+                       final_check ? 1 : 0);
 }
 
 void launch_skin_check(Sim &s) {

@@ -229,6 +229,11 @@ struct Cursor {
 inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 
 bool tail_fused(const Sim &s);
+int tail_mode_of(const Sim &s);
+
+// Evaluation mode of the first flip round after a move: count reversed edges, and with halving
+// enabled also flag the step so that its repair check halts it.
+inline int rev_mode(const Sim &s) { return s.p.max_dt_halvings > 0 ? 2 : 1; }
 
 // ------------------------------------------------------------------ budgeted sequence
 // Enqueues one repair of `rounds` flip rounds with no host read-back: a
@@ -241,7 +246,7 @@ struct FusedDetect {
 };
 
 void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std::vector<int> *first_slots,
-                    int oround = -1, const FusedDetect *fd = nullptr) {
+                    int oround = -1, const FusedDetect *fd = nullptr, int multi = 1 << 30) {
     // The repair after the move keeps the triangulation of the step's start
     // positions: a later repair of the same step that fails replays the
     // whole move from there (the Delaunay triangulation of the end positions
@@ -254,7 +259,7 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
         // the first evaluation scans every edge; the rest of the rounds run in one workgroup
         const int r0 = ++s.round_id;
         const int slot0 = c.take_slot();
-        launch_flip_eval_full(s, r0, slot0, reversal);
+        launch_flip_eval_full(s, r0, slot0, reversal ? rev_mode(s) : 0);
         last = slot0;
         for (int j = 1; j < rounds; ++j) {
             ++s.round_id;
@@ -267,16 +272,27 @@ void enqueue_repair(Sim &s, Cursor &c, bool full, bool reversal, int rounds, std
             launch_validate(s, rep, last);
         return;
     }
-    for (int j = 0; j < rounds; ++j) {
+    // the first `multi` rounds (the long worklists) on many workgroups, the rest in one workgroup
+    // launch that stops at the first round with nothing to do
+    const int m = std::min(rounds, std::max(1, multi));
+    for (int j = 0; j < m; ++j) {
         const int r = ++s.round_id;
         const int slot = c.take_slot();
         if (j == 0 && full)
-            launch_flip_eval_full(s, r, slot, reversal);
+            launch_flip_eval_full(s, r, slot, reversal ? rev_mode(s) : 0);
         else
             launch_flip_eval_list(s, r, slot);
         launch_flip_apply(s, r, slot);
         launch_flip_fix(s, r, slot);
         last = slot;
+    }
+    if (m < rounds) {
+        const int r0 = s.round_id + 1, slot0 = c.slot;
+        for (int j = m; j < rounds; ++j) {
+            ++s.round_id;
+            last = c.take_slot();
+        }
+        launch_repair_rounds(s, r0, slot0, rounds - m, false);
     }
     if (fd && oround >= 0)
         launch_validate_detect_local(s, rep, oround, last, fd->stamp, fd->k, fd->check);
@@ -306,7 +322,7 @@ bool host_flip_rounds(Sim &s, Cursor &c, bool full, bool reversal, bool *snap) {
         zero_ctl(s, K_INVQ + slot);
         zero_ctl(s, K_WL + next_slot(slot));
         if (full)
-            launch_flip_eval_full(s, r, slot, reversal && it == 0);
+            launch_flip_eval_full(s, r, slot, reversal && it == 0 ? rev_mode(s) : 0);
         else
             launch_flip_eval_list(s, r, slot);
         read_ctl(s);
@@ -393,7 +409,7 @@ void rollback(Sim &s) {
     check(hipMemcpyAsync(s.th, s.tho, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback th");
     fill_int(s, s.ctl, N_CTL, 0);
     s.need_rebuild = true;
-    host_rebuild(s);
+    if (s.ovl_method == 0) host_rebuild(s);
 }
 
 void drop_graphs(Sim &s) {
@@ -490,6 +506,39 @@ int host_overlap_loop(Sim &s, Cursor &c, int &rounds) {
     }
 }
 
+// Host-driven overlap rounds of the list method (Sec. 5 variant) from round
+// index `rounds` on; a detection that finds the lists possibly incomplete
+// rebuilds them and is repeated.
+int host_overlap_loop_nl(Sim &s, Cursor &c, int &rounds) {
+    const int max_rounds = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
+    for (int stale = 0;;) {
+        const int k = c.take_oround();
+        zero_ctl(s, K_TOUCH + k);
+        zero_ctl(s, K_OVL + k);
+        zero_ctl(s, K_NL_STALE);
+        launch_ovl_nl_gather(s, k);
+        read_ctl(s);
+        if (s.hctl[K_NL_STALE] != 0) {
+            if (++stale > 1) {   // right after a rebuild every disk sits at its build position
+                s.last_error = "neighbour lists stale right after a rebuild";
+                return BD_ERR_DEVICE;
+            }
+            verlet_rebuild(s);
+            continue;
+        }
+        stale = 0;
+        const int npairs = s.hctl[K_OVL + k];
+        if (npairs == 0) return BD_OK;
+        if (rounds >= max_rounds) {
+            s.last_error = "overlap correction did not converge within max_overlap_rounds";
+            return BD_ERR_NO_CONVERGENCE;
+        }
+        ++rounds;
+        s.st.overlap_edges_total += npairs;
+        launch_ovl_nl_apply(s, k, false);
+    }
+}
+
 // Puts the step counter and the stamp bases of the coming step in device
 // memory (stream-ordered); later launches pass stamps relative to them.
 void write_base(Sim &s) {
@@ -519,38 +568,81 @@ int overlaps_budget(const Sim &s) {
     return nover;
 }
 
-// Whether the overlap rounds after the first detection run in one workgroup.
-bool tail_fused(const Sim &s) {
+// How the overlap rounds after the first detection are launched (bd_set_tail_mode).
+int tail_mode_of(const Sim &s) {
     // Library choice: one workgroup for handles of at most 32,768 disks.  Measured per step
     // with graph replay: 16,384 disks 10-21 % faster in one workgroup (the lists of the later
     // rounds hold tens of items and a launch costs more than a barrier); 65,536 disks 13 %
     // slower and 1M disks 15x slower (the phases are latency chains over thousands of items
     // that spread better over many CUs).
     constexpr int kTailMaxDisks = 32768;
-    return s.tail_mode == 1 || (s.tail_mode == -1 && s.n <= kTailMaxDisks);
+    if (s.tail_mode != -1) return s.tail_mode;
+    return s.n <= kTailMaxDisks ? 1 : 0;
 }
+
+// Whether the overlap rounds after the first detection run in one workgroup.
+bool tail_fused(const Sim &s) { return tail_mode_of(s) == 1; }
 
 // The budgeted part of a step after the update: repair rounds, then overlap
 // rounds each with its repair, the final overlap check, the skin test.
 void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<int> &rep_first) {
     const int nover = overlaps_budget(s);
-    if (!tail_fused(s) || nover > MAXTAIL || nover == 0) {
+    const int mode = tail_mode_of(s);
+    if (mode != 1 || nover > MAXTAIL || nover == 0) {
         // Each detection runs in the launch that validates the repair before it: the first one
         // scans every triangle (after the repair of the move), later ones the stars of the disks
         // the previous round moved and the diagonals flipped since; the launch's last workgroup
         // runs the repair's check, then the round's (and after the last budgeted round the final one).
+        // Mode 2: each repair launches its first rounds on many workgroups and the rest in one, and
+        // after the first ovl_phase overlap rounds the others run in one workgroup (k_tail).
+        const bool hybrid = mode == 2;
+        const int per_phase = hybrid ? std::min(nover, std::max(1, s.ovl_phase)) : nover;
         int k = c.take_oround();
         orounds.push_back(k);
         FusedDetect fd{k, ++s.vround, nover == 0 ? 2 : 1};
-        enqueue_repair(s, c, true, true, s.budget.em, &rep_first, -1, &fd);
-        for (int j = 0; j < nover; ++j) {
+        enqueue_repair(s, c, true, true, s.budget.em, &rep_first, -1, &fd, hybrid ? s.multi_em : 1 << 30);
+        for (int j = 0; j < per_phase; ++j) {
             launch_ovl_gather(s, k);
             launch_ovl_apply(s, k, s.round_id + 1, c.slot);
             const int knext = c.take_oround();
             orounds.push_back(knext);
             FusedDetect fn{knext, ++s.vround, j + 1 == nover ? 2 : 1};
-            enqueue_repair(s, c, false, false, s.budget.ovl[j], &rep_first, k, &fn);
+            enqueue_repair(s, c, false, false, s.budget.ovl[j], &rep_first, k, &fn,
+                           hybrid ? s.multi_ovl : 1 << 30);
             k = knext;
+        }
+        if (per_phase < nover) {
+            // the remaining rounds in one workgroup; the detection for the first of them (slot k)
+            // ran with the last repair's validation
+            TailPlan plan{};
+            plan.nover = nover - per_phase;
+            plan.f = s.p.overlap_factor;
+            plan.cap_frac = s.p.cap_frac;
+            plan.keep = 1.0 - s.p.contact_tol;
+            for (int jj = 0; jj < plan.nover; ++jj) {
+                if (jj > 0) {
+                    k = c.take_oround();
+                    orounds.push_back(k);
+                    plan.stamp[jj] = ++s.vround - s.vbase;
+                } else {
+                    plan.stamp[0] = 0;
+                }
+                plan.k[jj] = k;
+                plan.next_round[jj] = s.round_id + 1 - s.rbase;
+                plan.slot0[jj] = c.slot;
+                plan.rep[jj] = c.take_rep();
+                rep_first.push_back(c.slot);
+                plan.rounds[jj] = s.budget.ovl[per_phase + jj];
+                for (int r = 0; r < plan.rounds[jj]; ++r) {
+                    ++s.round_id;
+                    c.take_slot();
+                }
+            }
+            k = c.take_oround();
+            orounds.push_back(k);
+            plan.k[plan.nover] = k;
+            plan.stamp[plan.nover] = ++s.vround - s.vbase;
+            launch_tail(s, plan);
         }
         skin_check(s, false);
         return;
@@ -600,6 +692,20 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
     skin_check(s, false);
 }
 
+// The budgeted overlap rounds of the list method: gather and apply per round,
+// then a last detection that halts the step if overlaps remain; the skin test.
+void enqueue_rounds_nl(Sim &s, Cursor &c, std::vector<int> &orounds) {
+    const int cap = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
+    const int nover = std::min({s.budget.overlaps, cap, MAXO - 1});
+    for (int j = 0; j <= nover; ++j) {
+        const int k = c.take_oround();
+        orounds.push_back(k);
+        launch_ovl_nl_gather(s, k);
+        launch_ovl_nl_apply(s, k, j == nover);
+    }
+    skin_check(s, false);
+}
+
 hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
@@ -616,8 +722,8 @@ hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
 // [clear counters, cast] [force] [update, budgeted rounds, checks].  Stamps
 // inside are relative to the bases of the step being replayed.
 Sim::StepGraph &step_graph(Sim &s) {
-    const int nover = overlaps_budget(s);
-    std::vector<int> key = {s.budget.em, nover, tail_fused(s) ? 1 : 0};
+    const int nover = s.ovl_method == 1 ? s.budget.overlaps : overlaps_budget(s);
+    std::vector<int> key = {s.budget.em, nover, tail_mode_of(s), s.multi_em, s.multi_ovl, s.ovl_phase};
     for (int j = 0; j < nover; ++j) key.push_back(s.budget.ovl[j]);
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
@@ -648,7 +754,10 @@ Sim::StepGraph &step_graph(Sim &s) {
     Cursor c;
     g.post = capture(s, [&] {
         launch_em(s);
-        enqueue_rounds(s, c, g.orounds, g.rep_first);
+        if (s.ovl_method == 1)
+            enqueue_rounds_nl(s, c, g.orounds);
+        else
+            enqueue_rounds(s, c, g.orounds, g.rep_first);
         launch_step_end(s, s.round_id - r0, s.vround - v0);
     });
     g.r_used = s.round_id - r0;
@@ -687,6 +796,72 @@ struct StepPlan {
 
 int finish_step(Sim &s, const int *h_in, const StepPlan &plan);
 
+void copy_d(Sim &s, void *dst, const void *src, size_t bytes) {
+    check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s.stream), "device copy");
+}
+
+// Positions and angles back to those before the last move (kept by the update kernel) and the
+// triangulation back to its snapshot taken before that move's repair.
+void undo_move(Sim &s) {
+    const size_t dn = sizeof(double) * s.n;
+    copy_d(s, s.x, s.xo, dn);
+    copy_d(s, s.y, s.yo, dn);
+    copy_d(s, s.th, s.tho, dn);
+    copy_d(s, s.he_v, s.snap_v, sizeof(int) * s.H);
+    copy_d(s, s.he_twin, s.snap_twin, sizeof(int) * s.H);
+    copy_d(s, s.vert_he, s.snap_vh, sizeof(int) * (s.nv + s.R));
+}
+
+// Interval (level, index) of a step whose move reversed a Delaunay edge
+// (Sec. 4.3: discard the move and repeat with a smaller time step), run from
+// the host: forces at the current positions, the move over dt / 2^level with
+// the Brownian-bridge noise of this interval, the repair (its first round
+// counts reversed edges), then the overlap loop.  A move that reverses an
+// edge again is undone and split while level < max_dt_halvings.
+int halved_interval(Sim &s, Cursor &c, int level, unsigned index, int &rounds) {
+    if (s.use_nl) skin_check(s, true);   // the lists must hold at this interval's positions
+    compute_forces(s);
+    launch_em(s, level, index);
+    launch_snapshot(s);
+    zero_ctl(s, K_REV);
+    int rc = host_repair(s, c, true, true, MoveFrom::Previous, 0);
+    if (rc != BD_OK) return rc;
+    read_ctl(s);
+    if (s.hctl[K_REV] != 0 && level < s.p.max_dt_halvings) {
+        ++s.st.dt_halvings;
+        undo_move(s);
+        rc = halved_interval(s, c, level + 1, 2 * index, rounds);
+        if (rc != BD_OK) return rc;
+        return halved_interval(s, c, level + 1, 2 * index + 1, rounds);
+    }
+    return host_overlap_loop(s, c, rounds);
+}
+
+// A step halted because its move reversed a Delaunay edge: undo the move and
+// redo the step as two halves.  On error the state returns to the step's start.
+int redo_step_in_halves(Sim &s, Cursor &c, int &rounds) {
+    write_base(s);   // clears a graph batch's stop flag, which would keep the update and force kernels idle
+    undo_move(s);
+    const size_t dn = sizeof(double) * s.n;
+    if (!s.xs) {
+        s.xs = dalloc<double>(s.n);
+        s.ys = dalloc<double>(s.n);
+        s.ths = dalloc<double>(s.n);
+    }
+    copy_d(s, s.xs, s.x, dn);
+    copy_d(s, s.ys, s.y, dn);
+    copy_d(s, s.ths, s.th, dn);
+    ++s.st.dt_halvings;
+    int rc = halved_interval(s, c, 1, 0, rounds);
+    if (rc == BD_OK) rc = halved_interval(s, c, 1, 1, rounds);
+    if (rc != BD_OK) {   // leave the rollback the step's start in xo, yo, tho
+        copy_d(s, s.xo, s.xs, dn);
+        copy_d(s, s.yo, s.ys, dn);
+        copy_d(s, s.tho, s.ths, dn);
+    }
+    return rc;
+}
+
 // One step of Algorithm 1 launched kernel by kernel: the whole step is
 // enqueued as a budgeted sequence (force, update, repair rounds, overlap
 // rounds each with its repair) and the control block is read back once; if a
@@ -712,8 +887,13 @@ int one_step(Sim &s) {
     }
     launch_em(s);
     plan.b = s.budget;
-    plan.overlaps = overlaps_budget(s);
-    enqueue_rounds(s, plan.c, plan.orounds, plan.rep_first);
+    if (s.ovl_method == 1) {
+        plan.overlaps = s.budget.overlaps;
+        enqueue_rounds_nl(s, plan.c, plan.orounds);
+    } else {
+        plan.overlaps = overlaps_budget(s);
+        enqueue_rounds(s, plan.c, plan.orounds, plan.rep_first);
+    }
     read_ctl(s);
     return finish_step(s, s.hctl, plan);
 }
@@ -752,7 +932,7 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
         check(hipStreamSynchronize(s.stream), "sync");
         StepPlan plan;
         plan.b = s.budget;
-        plan.overlaps = overlaps_budget(s);
+        plan.overlaps = s.ovl_method == 1 ? s.budget.overlaps : overlaps_budget(s);
         plan.c.slot = g.c_slot;
         plan.c.rep = g.c_rep;
         plan.c.oround = g.c_oround;
@@ -789,7 +969,11 @@ int run_graph_steps(Sim &s, int64_t nsteps) {
 // Host side of a step whose budgeted part has run: bookkeeping, the
 // continuation of a halted step, budget adaptation.  h_in is the step's
 // control block as read back.
+// finish_step for the list method: no repairs, only overlap rounds.
+int finish_step_nl(Sim &s, const int *h_in, const StepPlan &plan);
+
 int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
+    if (s.ovl_method == 1) return finish_step_nl(s, h_in, plan);
     const std::vector<int> hv(h_in, h_in + N_CTL);
     const int *h = hv.data();
     const Cursor &c = plan.c;
@@ -821,7 +1005,15 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
         hc.slot = c.slot;
         hc.rep = c.rep;
         hc.oround = c.oround;
-        if (reason == HALT_REPAIR_BUDGET || reason == HALT_INVALID) {
+        if (reason == HALT_REVERSAL) {
+            rc = redo_step_in_halves(s, hc, rounds);
+            if (rc != BD_OK) {
+                rollback(s);
+                s.need_rebuild = true;
+                return rc;
+            }
+            skin_check(s, true);
+        } else if (reason == HALT_REPAIR_BUDGET || reason == HALT_INVALID) {
             // repair slot `stage`: 0 is the repair after the update, j >= 1 the one after overlap round j-1
             // a failure replays the step's whole move from the copy taken before its first repair
             if (reason == HALT_REPAIR_BUDGET) {
@@ -832,13 +1024,15 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
                 rc = kinetic_replay(s, hc, MoveFrom::Previous, 0);
             }
         }
-        if (rc == BD_OK) rc = host_overlap_loop(s, hc, rounds);
-        if (rc != BD_OK) {
-            rollback(s);
-            s.need_rebuild = true;
-            return rc;
+        if (reason != HALT_REVERSAL) {
+            if (rc == BD_OK) rc = host_overlap_loop(s, hc, rounds);
+            if (rc != BD_OK) {
+                rollback(s);
+                s.need_rebuild = true;
+                return rc;
+            }
+            skin_check(s, true);   // positions moved after the budgeted sequence's test
         }
-        skin_check(s, true);   // positions moved after the budgeted sequence's test
     }
     // adapt the budgets to the rounds this step needed: grow at once when a
     // budget ran out, shrink by one when it was larger than needed
@@ -886,6 +1080,48 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     }
     s.budget.overlaps = std::max(s.budget.overlaps, plan.overlaps);
     adapt(s.budget.overlaps, rounds, s.slack_over, MAXO / 2);   // contact-factor runs need ~20 rounds
+    s.st.overlap_rounds_total += rounds;
+    if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
+    ++s.st.steps;
+    ++s.step;
+    return BD_OK;
+}
+
+int finish_step_nl(Sim &s, const int *h_in, const StepPlan &plan) {
+    const std::vector<int> hv(h_in, h_in + N_CTL);
+    const int *h = hv.data();
+    s.need_rebuild = h[K_NL_REBUILD] != 0;
+    if (h[K_NL_BUILT]) ++s.st.verlet_rebuilds;
+    int rounds = h[K_OVL_ROUNDS];
+    for (int j = 0; j < rounds; ++j) s.st.overlap_edges_total += h[K_OVL + plan.orounds[j]];
+    if (h[K_HALT]) {
+        // overlaps left after the budgeted rounds, or lists that may miss a pair: the host continues
+        ++s.st.host_continued;
+        fill_int(s, s.ctl + K_HALT, 1, 0);
+        fill_int(s, s.ctl + K_DONE, 1, 0);
+        Cursor hc = plan.c;
+        if (h[K_REASON] == HALT_NL_STALE) verlet_rebuild(s);
+        int rc = host_overlap_loop_nl(s, hc, rounds);
+        if (rc != BD_OK) {
+            rollback(s);
+            return rc;
+        }
+        skin_check(s, true);   // positions moved after the budgeted sequence's test
+    }
+    constexpr int kShrinkAfter = 64;
+    int &budget = s.budget.overlaps;
+    budget = plan.b.overlaps;
+    if (rounds >= budget) {
+        budget = std::min(MAXO / 2, rounds + 1);
+        s.slack_over = 0;
+    } else if (rounds + 1 < budget) {
+        if (++s.slack_over >= kShrinkAfter) {
+            budget = std::max(2, budget - 1);
+            s.slack_over = 0;
+        }
+    } else {
+        s.slack_over = 0;
+    }
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
@@ -1265,7 +1501,7 @@ void free_all(Sim &s) {
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
                     s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
                     s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
-                    s.xbuild, s.ybuild, s.fsr, s.scan_bsum, s.stiles};
+                    s.xbuild, s.ybuild, s.fsr, s.scan_bsum, s.stiles, s.xs, s.ys, s.ths};
     for (void *p : ptrs)
         dfree(p);
     drop_graphs(s);
@@ -1308,6 +1544,14 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
     if (p->force_chunk != 0 && (p->force_chunk < -3 || (p->force_chunk > 0 && p->force_chunk < 64) ||
                                 p->force_chunk > 65536))
         return err = "force_chunk must be 0, -1, -2, -3 or in [64, 65536]", BD_ERR_INVALID_ARG;
+    if (p->overlap_method != BD_OVERLAP_DELAUNAY && p->overlap_method != BD_OVERLAP_VERLET)
+        return err = "unknown overlap method", BD_ERR_INVALID_ARG;
+    if (p->overlap_method == BD_OVERLAP_VERLET && !(fp->cutoff > 0))
+        return err = "the list overlap method needs short-range forces (cutoff > 0)", BD_ERR_INVALID_ARG;
+    if (p->max_dt_halvings < 0 || p->max_dt_halvings > 12)
+        return err = "max_dt_halvings must be in [0, 12]", BD_ERR_INVALID_ARG;
+    if (p->max_dt_halvings > 0 && p->overlap_method != BD_OVERLAP_DELAUNAY)
+        return err = "halving on edge reversal needs the Delaunay overlap method", BD_ERR_INVALID_ARG;
     if (p->force_per_lane != 0 && p->force_per_lane != 2 && p->force_per_lane != 4)
         return err = "force_per_lane must be 0, 2 or 4", BD_ERR_INVALID_ARG;
     if (p->force_launch != 0 && p->force_launch != 1) return err = "force_launch must be 0 or 1", BD_ERR_INVALID_ARG;
@@ -1454,6 +1698,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.fp32 = p->force_precision == BD_PREC_FP32;
     s.kind_fast = (fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)) ? 1 : 0;
     s.use_nl = fp->cutoff > 0;
+    s.ovl_method = p->overlap_method;
     check(hipGetDevice(&s.device), "hipGetDevice");
     check(hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking), "stream");
     s.stream = s.own_stream;
@@ -1598,12 +1843,22 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
 
     setup_force(s);
 
-    std::vector<int> hv, ht;
-    if (host_dt_all(s, hx.data(), hy.data(), hv, ht) != 0) {
-        s.last_error = "initial Delaunay triangulation failed (coincident positions)";
-        return BD_ERR_TRIANGULATION;
+    if (s.ovl_method == 0) {   // the list method keeps no triangulation
+        std::vector<int> hv, ht;
+        if (host_dt_all(s, hx.data(), hy.data(), hv, ht) != 0) {
+            s.last_error = "initial Delaunay triangulation failed (coincident positions)";
+            return BD_ERR_TRIANGULATION;
+        }
+        upload_topology(s, hv, ht);
+    } else {
+        double rmax = 0.0;
+        for (int i = 0; i < n; ++i) rmax = std::max(rmax, radii[i]);
+        s.nl_margin = 0.5 * (fp->cutoff + fp->skin - 2.0 * rmax);
+        if (!(s.nl_margin > 0.0)) {
+            s.last_error = "the list overlap method needs cutoff + skin larger than the largest contact distance";
+            return BD_ERR_INVALID_ARG;
+        }
     }
-    upload_topology(s, hv, ht);
     if (s.use_nl) verlet_rebuild(s);
     return BD_OK;
 }
@@ -1704,6 +1959,10 @@ void adj_free(Sim &s) {
 int adjoint_begin(Sim &s, int64_t nsteps, int every) {
     if (!s.kind_fast || s.use_nl) {
         s.last_error = "the adjoint covers the all-pairs inverse-square force only";
+        return BD_ERR_INVALID_ARG;
+    }
+    if (s.p.max_dt_halvings > 0) {
+        s.last_error = "the adjoint does not cover steps halved after an edge reversal";
         return BD_ERR_INVALID_ARG;
     }
     adj_free(s);
@@ -2089,6 +2348,10 @@ int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *
 int bd_get_triangulation(const bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out) {
     if (!sim || !tri_out || !ntri_out) return BD_ERR_INVALID_ARG;
     Sim &s = const_cast<bd_sim *>(sim)->s;
+    if (s.ovl_method != 0) {
+        s.last_error = "the list overlap method keeps no triangulation";
+        return BD_ERR_INVALID_ARG;
+    }
     return bd::guarded(s, [&] {
         std::vector<int> hv(s.H);
         bd::check(hipMemcpyAsync(hv.data(), s.he_v, sizeof(int) * s.H, hipMemcpyDeviceToHost, s.stream), "he_v");
@@ -2159,13 +2422,17 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         bd::check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "y");
         bd::fill_int(s, s.ctl, bd::N_CTL, 0);
         s.need_rebuild = true;
+        if (s.ovl_method != 0) {   // no triangulation to repair
+            bd::check(hipStreamSynchronize(s.stream), "sync");
+            return (int)BD_OK;
+        }
         bd::Cursor c;
         return bd::host_repair(s, c, true, false, bd::MoveFrom::Previous, 0);
     });
 }
 
 int bd_set_tail_mode(bd_sim *sim, int mode) {
-    if (!sim || mode < -1 || mode > 1) return BD_ERR_INVALID_ARG;
+    if (!sim || mode < -1 || mode > 2) return BD_ERR_INVALID_ARG;
     Sim &s = sim->s;
     return bd::guarded(s, [&] {
         bd::check(hipStreamSynchronize(s.stream), "sync");

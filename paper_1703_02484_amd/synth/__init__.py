@@ -103,6 +103,8 @@ class Workload:
     max_overlap_rounds: int = 10000
     steps: int = 100
     fp32_forces: bool = False
+    overlap: str = "delaunay"      # overlap test over Delaunay edges, or "verlet": over the neighbour lists
+    max_dt_halvings: int = 0       # halvings of a step whose move reversed a Delaunay edge (0: count only)
     extra: dict = field(default_factory=dict)
 
     @property

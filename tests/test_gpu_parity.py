@@ -319,7 +319,7 @@ def test_round_cap_reports_no_convergence_and_rolls_back():
 @pytest.mark.parametrize("n", [50, 3000])
 def test_forces_verlet_screened(n):
     w = synth.make("C3", n=n)
-    g = binding.Sim.from_workload(w)
+    g = binding.Sim.from_workload(w, fp32=False)
     fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=w.cutoff)
     fg = g.forces()
     assert np.abs(fg - fo).max() <= 1e-12 * max(_force_scale(fo), 1e-300)
@@ -336,7 +336,7 @@ def test_forces_verlet_power_two_species():
 
 
 def test_trajectory_c3_verlet_reduced():
-    worst, st = _run_parity(synth.make("C3", n=6000), 60, 1e-9)
+    worst, st = _run_parity(synth.make("C3", n=6000), 60, 1e-9, gpu_over=dict(fp32=False))
     assert st["verlet_rebuilds"] >= 2
 
 
@@ -344,12 +344,12 @@ def test_full_size_c3_verlet():
     # the short-range workload at full size (N = 1,048,576): sampled forces
     # against the oracle, then 2 steps and the properties of the result
     w = synth.make("C3")
-    g = binding.Sim.from_workload(w)
+    g = binding.Sim.from_workload(w)   # FP32 list force, as the workload asks
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(w.n, 256, replace=False))
     fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=w.cutoff, idx=idx)
     fg = g.forces()
-    assert np.abs(fg[idx] - fo).max() <= 1e-12 * _force_scale(fo)
+    assert np.abs(fg[idx] - fo).max() <= 1e-4 * _force_scale(fo)
     g.step(2)
     x, th, step, st = g.state()
     assert step == 2 and np.all(x >= 1.0) and np.all(x <= w.L - 1.0)
@@ -362,7 +362,7 @@ def test_verlet_list_capacity_grows():
     # cutoff 7 + skin 1 at phi = 0.5: about 32 neighbours per disk, more than the
     # initial list capacity; the build grows the lists once and forces stay exact
     w = synth.make("C3", n=3000)
-    g = binding.Sim.from_workload(w, cutoff=7.0, skin=1.0)
+    g = binding.Sim.from_workload(w, cutoff=7.0, skin=1.0, fp32=False)
     fo = oracle.forces(w.xy, w.species, w.K, kind="screened", A=w.A, lam=w.lam, cutoff=7.0)
     fg = g.forces()
     assert np.abs(fg - fo).max() <= 1e-12 * _force_scale(fo)

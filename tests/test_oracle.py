@@ -586,3 +586,117 @@ def test_tangent_wall_reflection_negates():
     x1 = o.state()[0]
     assert x1[0, 0] == pytest.approx(1.01, abs=1e-9)
     assert o.tangent()[0] == pytest.approx(np.array([-0.3, -0.7]), abs=1e-15)
+
+
+# ------------------------------------------------------------------ Sec. 4.3 halving (Brownian bridge)
+def test_bridge_halves_add_up_and_have_the_bridge_variance():
+    n = 200000
+    rng = np.random.default_rng(3)
+    W = rng.normal(size=(n, 2)) * 0.3
+    Th = rng.normal(size=n) * 0.2
+    D, Dr, h = 1.3, 0.7, 1e-2
+    WL, WR, ThL, ThR = oracle.bridge(W, Th, seed=5, step=11, level=0, index=0, h=h, D=D, Dr=Dr, clip=30.0)
+    # the two halves add up to the interval's increment (up to the rounding of one subtraction)
+    assert np.abs(WL + WR - W).max() <= 1e-15 * np.abs(W).max()
+    assert np.abs(ThL + ThR - Th).max() <= 1e-15 * np.abs(Th).max()
+    # first half = W/2 + N(0, D h / 2) per component, independent of W
+    e = (WL - 0.5 * W) / math.sqrt(0.5 * D * h)
+    r = (ThL - 0.5 * Th) / math.sqrt(0.5 * Dr * h)
+    for z in (e[:, 0], e[:, 1], r):
+        assert abs(z.mean()) < 0.01 and abs(z.var() - 1.0) < 0.01
+    assert abs(np.corrcoef(e[:, 0], W[:, 0])[0, 1]) < 0.01 and abs(np.corrcoef(e[:, 0], e[:, 1])[0, 1]) < 0.01
+    # without diffusion the halves are exact halves
+    WL0, WR0, ThL0, ThR0 = oracle.bridge(W, Th, 5, 11, 0, 0, h, 0.0, 0.0)
+    assert np.array_equal(WL0, 0.5 * W) and np.array_equal(WR0, W - 0.5 * W) and np.array_equal(ThL0, 0.5 * Th)
+    # the draws are keyed by the interval: another index or level gives other normals
+    WL1 = oracle.bridge(W, Th, 5, 11, 0, 1, h, D, Dr)[0]
+    WL2 = oracle.bridge(W, Th, 5, 11, 1, 0, h, D, Dr)[0]
+    assert not np.allclose(WL1, WL) and not np.allclose(WL2, WL)
+
+
+def _halving_sim(max_halvings, **extra):
+    xy, th, kw = reversal_case()
+    kw.update(extra)
+    n = xy.shape[0]
+    return oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), max_dt_halvings=max_halvings,
+                            **kw), xy, th, kw
+
+
+def test_halving_redoes_the_reversing_move_in_two_halves():
+    # the pinned reversal case (one edge reverses over the full step) with one halving level: the move
+    # is discarded and done as two moves of 3; without noise the bridge halves are exact, so the end
+    # positions are the same straight lines, and the reversals counted are those of the discarded move
+    # plus those of each half on the Delaunay edges of its own start (Qhull, independent of the oracle)
+    sim, xy, th, kw = _halving_sim(1)
+    sim.step(1)
+    x1, _, _, st = sim.state()
+    n = xy.shape[0]
+    np.testing.assert_allclose(x1 - xy, 6.0 * np.column_stack([np.cos(th), np.sin(th)]), atol=1e-12)
+    half = xy + 3.0 * np.column_stack([np.cos(th), np.sin(th)])
+
+    def revs(p0, p1):
+        tris = QhullDelaunay(np.concatenate([p0, oracle.frame(kw["L"], 1.0)])).simplices
+        E = {(min(a, b), max(a, b)) for t in tris.tolist() for a, b in combinations(t, 2) if a < n and b < n}
+        return sum(1 for i, j in E if np.dot(p0[j] - p0[i], p1[j] - p1[i]) < 0)
+
+    assert revs(xy, half) >= 1   # the halves still reverse, but level 1 is the deepest allowed
+    assert st["reversals"] == 1 + revs(xy, half) + revs(half, x1)
+    assert st["dt_halvings"] == 1
+    # with halving off the same step only counts
+    off, _, _, _ = _halving_sim(0)
+    off.step(1)
+    assert off.state()[3]["dt_halvings"] == 0 and off.state()[3]["reversals"] == 1
+
+
+def test_halving_changes_nothing_without_reversals():
+    w = synth.make("C1", n=400)
+    a = oracle.OracleSim.from_workload(w)
+    b = oracle.OracleSim.from_workload(w, max_dt_halvings=4)
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    assert b.state()[3]["dt_halvings"] == 0 and b.state()[3]["reversals"] == 0
+
+
+# ------------------------------------------------------------------ Sec. 5 short-range variant (all pairs)
+def test_pair_round_includes_overlapping_pairs_that_are_not_delaunay_edges():
+    # A-C overlap (d = 1.9) but D lies in the circumcircle of A, B, C, so A-C is no Delaunay edge
+    # (B-D is): the pair round corrects 6 overlapping pairs, the Delaunay round 5 (counts by a k-d tree)
+    from scipy.spatial import cKDTree
+
+    L = 40.0
+    xy = np.array([[0.0, 0.0], [0.95, 0.5], [1.9, 0.0], [0.8, -0.45]]) + 19.0
+    rad = np.ones(4)
+    assert len(cKDTree(xy).query_pairs(2.0)) == 6
+    tris = oracle.delaunay_with_frame(xy, L, 1.0)
+    edges = {tuple(sorted(e)) for t in tris.tolist() for e in combinations(t, 2)}
+    assert (0, 2) not in edges and (1, 3) in edges
+    xp, cp, _ = oracle.overlap_round_pairs(xy, rad, L)
+    xd, cd, _ = oracle.overlap_round(np.concatenate([xy]), rad, L)
+    assert cp == 6 and cd == 5 and np.abs(xp - xd).max() > 1e-3
+
+
+def test_pair_method_equals_delaunay_method_when_every_overlap_is_an_edge():
+    # dilute box: every overlapping pair is a Delaunay edge, and both methods visit the pairs in the
+    # same (i, j) order, so the trajectories agree bit for bit
+    w = synth.make("C1", n=400)
+    a = oracle.OracleSim.from_workload(w)
+    b = oracle.OracleSim.from_workload(w, overlap="verlet")
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    sa, sb = a.state()[3], b.state()[3]
+    assert sa["overlap_edges_total"] == sb["overlap_edges_total"] > 0
+    assert sb["reversals"] == 0
+
+
+def test_pair_method_leaves_no_overlap():
+    n = 400
+    L = synth.box_side(n, 0.55 * 0.9)
+    xy = synth.rsa(n, L, 1.0, seed=8)
+    sim = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0, dt=2e-3,
+                           seed=2, overlap="verlet")
+    for _ in range(10):
+        sim.step(1)
+        assert _bruteforce_min_gap(sim.state()[0]) == 0
+    assert sim.state()[3]["overlap_rounds_total"] > 0
