@@ -274,6 +274,29 @@ def test_full_size_c2_bench_configuration():
     assert st["host_rebuilds"] == 0
 
 
+def test_full_size_c2_bench_path_matches_oracle():
+    # the timed path itself at full size (N = 65,536): the force form the autotuner picks there (the symmetric
+    # form), graph replay with steps queued together, the default overlap-round launch form (one launch per
+    # phase above 32,768 disks); 3 steps against the oracle, element by element
+    w = synth.make("C2")
+    g = binding.Sim.from_workload(w)
+    cfg = g.force_config()
+    assert cfg["persistent"] == 2 and cfg["tuned"] in (1, 2), cfg
+    g.set_graph_mode(True)
+    g.step(3)
+    o = oracle.OracleSim.from_workload(w)
+    o.step(3)
+    xg, tg, sg, stg = g.state()
+    xo, to, so, sto = o.state()
+    assert sg == so == 3
+    assert rel_err(xg, xo) <= 1e-4
+    assert np.abs(tg - to).max() <= 1e-12     # angles do not depend on forces
+    assert tri_set(g.triangles()) == tri_set(o.triangles())
+    for k in ("overlap_rounds_total", "overlap_rounds_max", "overlap_edges_total", "reversals", "noise_clamps"):
+        assert stg[k] == sto[k], (k, stg[k], sto[k])
+    assert stg["overlap_rounds_total"] > 0 and stg["host_rebuilds"] == 0
+
+
 # ------------------------------------------------------------------ determinism, resume, errors
 def test_bitwise_run_to_run():
     w = synth.make("C2", n=3000)
