@@ -104,6 +104,14 @@ def _load():
     lib.orc_sim_frame_count.restype = ctypes.c_int
     lib.orc_sim_free.argtypes = [V]
     lib.orc_sim_free.restype = None
+    lib.orc_sim_set_periodic.argtypes = [V]
+    lib.orc_sim_set_periodic.restype = ctypes.c_int
+    lib.orc_forces_periodic.argtypes = [ctypes.c_int, V, V, ctypes.c_int, V, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, V,
+                                        ctypes.c_int, V]
+    lib.orc_forces_periodic.restype = None
+    lib.orc_torus_delaunay.argtypes = [ctypes.c_int, V, ctypes.c_double, V, ctypes.c_int]
+    lib.orc_torus_delaunay.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -181,23 +189,39 @@ def delaunay_with_frame(xy: np.ndarray, L: float, rmax: float) -> np.ndarray:
     return delaunay(pts)
 
 
-def forces(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, idx=None) -> np.ndarray:
+def forces(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, idx=None, period=0.0) -> np.ndarray:
+    """Pair forces by brute force over all pairs (Sec. 2.2); period > 0: periodic box of that side with
+    minimum-image separations (Sec. 2.1)."""
     lib = _load()
     xy = np.ascontiguousarray(xy, dtype=np.float64)
     sp = np.ascontiguousarray(species, dtype=np.int32)
     K = np.ascontiguousarray(K, dtype=np.float64)
     S = K.shape[0]
     n = xy.shape[0]
+    kd = 0 if kind == "power" else 1
     if idx is None:
         out = np.zeros((n, 2), dtype=np.float64)
-        lib.orc_forces(n, _p(xy), _p(sp), S, _p(K), 0 if kind == "power" else 1, q, A, lam, cutoff, None, n,
-                       _p(out))
+        lib.orc_forces_periodic(n, _p(xy), _p(sp), S, _p(K), kd, q, A, lam, cutoff, float(period), None, n,
+                                _p(out))
     else:
         ix = np.ascontiguousarray(idx, dtype=np.int32)
         out = np.zeros((ix.size, 2), dtype=np.float64)
-        lib.orc_forces(n, _p(xy), _p(sp), S, _p(K), 0 if kind == "power" else 1, q, A, lam, cutoff, _p(ix),
-                       int(ix.size), _p(out))
+        lib.orc_forces_periodic(n, _p(xy), _p(sp), S, _p(K), kd, q, A, lam, cutoff, float(period), _p(ix),
+                                int(ix.size), _p(out))
     return out
+
+
+def torus_delaunay(xy: np.ndarray, L: float) -> np.ndarray:
+    """Delaunay triangulation of the flat torus [0, L)^2 (periodic box, Sec. 2.1): 2n triangles of ids,
+    counter-clockwise in the frame of their nearest images."""
+    lib = _load()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    n = xy.shape[0]
+    out = np.zeros((2 * n + 4, 3), dtype=np.int32)
+    nt = lib.orc_torus_delaunay(n, _p(xy), float(L), _p(out), out.shape[0])
+    if nt < 0:
+        raise RuntimeError("oracle torus triangulation failed")
+    return out[:nt].copy()
 
 
 def force_tangent(xy, species, K, txy, tK=None, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0) -> np.ndarray:
@@ -268,7 +292,7 @@ class OracleSim:
     def __init__(self, xy, radii, species, theta, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0,
                  L=100.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0, step0=0, overlap_factor=1.0,
                  cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9, max_overlap_rounds=10000, overlap="delaunay",
-                 max_dt_halvings=0):
+                 max_dt_halvings=0, periodic=False):
         lib = _load()
         self._lib = lib
         self.xy0 = np.ascontiguousarray(xy, dtype=np.float64)
@@ -286,13 +310,17 @@ class OracleSim:
             raise RuntimeError("oracle: initial triangulation failed")
         lib.orc_sim_set_overlap_method(self._h, {"delaunay": 0, "verlet": 1}[overlap])
         lib.orc_sim_set_max_halvings(self._h, int(max_dt_halvings))
+        self.periodic = bool(periodic)
+        if self.periodic and lib.orc_sim_set_periodic(self._h) != 0:
+            raise RuntimeError("oracle: torus triangulation failed")
 
     @classmethod
     def from_workload(cls, w, **over):
         kw = dict(K=w.K, kind=w.kind, q=w.q, A=w.A, lam=w.lam, cutoff=w.cutoff, L=w.L, D=w.D, dt=w.dt,
                   v0=w.v0, Dr=w.Dr, seed=w.seed, step0=w.step0, overlap_factor=w.overlap_factor,
                   cap_frac=w.cap_frac, noise_clip=w.noise_clip, contact_tol=w.contact_tol,
-                  max_overlap_rounds=w.max_overlap_rounds, overlap=w.overlap, max_dt_halvings=w.max_dt_halvings)
+                  max_overlap_rounds=w.max_overlap_rounds, overlap=w.overlap, max_dt_halvings=w.max_dt_halvings,
+                  periodic=getattr(w, "periodic", False))
         kw.update({k: v for k, v in over.items() if k not in GPU_ONLY})
         return cls(w.xy, w.radii, w.species, w.theta, **kw)
 

@@ -50,6 +50,8 @@ def _load():
         lib.rsa_disks.restype = ctypes.c_int
         lib.rsa_disks.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.c_longlong, ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]
+        lib.rsa_disks_periodic.restype = ctypes.c_int
+        lib.rsa_disks_periodic.argtypes = lib.rsa_disks.argtypes
         _lib = lib
     return _lib
 
@@ -59,15 +61,18 @@ def box_side(n: int, phi: float, r: float = 1.0) -> float:
     return math.sqrt(n * math.pi * r * r / phi)
 
 
-def rsa(n: int, L: float, r: float = 1.0, seed: int = 0, max_attempts: Optional[int] = None) -> np.ndarray:
-    """Random sequential insertion of n disks of radius r into [0, L]^2; returns (n, 2) float64."""
+def rsa(n: int, L: float, r: float = 1.0, seed: int = 0, max_attempts: Optional[int] = None,
+        periodic: bool = False) -> np.ndarray:
+    """Random sequential insertion of n disks of radius r into [0, L]^2 (hard walls: centres in [r, L-r]^2;
+    periodic: centres in [0, L)^2, nearest-image separations); returns (n, 2) float64."""
     lib = _load()
     out = np.zeros((max(n, 0), 2), dtype=np.float64)
     if max_attempts is None:
         max_attempts = max(1000, 20000 * max(n, 1))
     att = ctypes.c_longlong(0)
-    rc = lib.rsa_disks(int(n), float(L), float(r), ctypes.c_uint64(seed & (2**64 - 1)), int(max_attempts),
-                       out.ctypes.data, ctypes.byref(att))
+    fn = lib.rsa_disks_periodic if periodic else lib.rsa_disks
+    rc = fn(int(n), float(L), float(r), ctypes.c_uint64(seed & (2**64 - 1)), int(max_attempts),
+            out.ctypes.data, ctypes.byref(att))
     if rc != 0:
         raise RuntimeError(f"rsa_disks failed rc={rc} (n={n}, L={L}, attempts={att.value})")
     return out
@@ -105,6 +110,7 @@ class Workload:
     fp32_forces: bool = False
     overlap: str = "delaunay"      # overlap test over Delaunay edges, or "verlet": over the neighbour lists
     max_dt_halvings: int = 0       # halvings of a step whose move reversed a Delaunay edge (0: count only)
+    periodic: bool = False         # periodic box [0, L)^2 instead of hard walls
     extra: dict = field(default_factory=dict)
 
     @property
@@ -117,14 +123,24 @@ def _thetas(n: int, seed: int) -> np.ndarray:
     return rng.uniform(0.0, 2.0 * math.pi, size=n)
 
 
-def make(name: str, n: Optional[int] = None, seed: int = 0, steps: Optional[int] = None) -> Workload:
+def make(name: str, n: Optional[int] = None, seed: int = 0, steps: Optional[int] = None,
+         periodic: bool = False) -> Workload:
     """Build workload ``name`` in {C1, C2, C3, C5} (optionally at a reduced n).
 
     C1  plain method, FP64: phi=0.30, S=1, K=1e-2, inverse-square law, all pairs.
     C2  FP32 forces: phi=0.40, S=2 (i mod 2), non-reciprocal K, self-propulsion v0=1, Dr=1.
     C3  short range: phi=0.50, S=1, K=1, screened law A=1, lam=0.5, cutoff 2.5, skin 0.5.
     C5  differentiation: phi=0.35, S=2, K=1e-2 everywhere, contact factor 1/2, 50 steps.
+
+    periodic: the same workload in a periodic box of the same side (the paper's own domain, Sec. 2.1):
+    positions placed with nearest-image separations in [0, L)^2, no walls.
     """
+    if periodic:
+        w = make(name, n, seed, steps)
+        w.xy = rsa(w.n, w.L, 1.0, seed, periodic=True)
+        w.periodic = True
+        w.name = w.name + "p"
+        return w
     r = 1.0
     if name == "C1":
         n = 1024 if n is None else n

@@ -83,3 +83,74 @@ int rsa_disks(int n, double L, double r, uint64_t seed, long long max_attempts,
     if (attempts_out) *attempts_out = attempts;
     return placed == n ? 0 : -2;
 }
+
+/*
+ * The same in a periodic box [0,L)^2: candidate centres are uniform in
+ * [0,L)^2 and separations are taken from the nearest periodic image.  Same
+ * return codes.
+ */
+int rsa_disks_periodic(int n, double L, double r, uint64_t seed, long long max_attempts,
+                       double *xy_out, long long *attempts_out) {
+    if (n < 0 || !(L > 2.0 * r) || !(r > 0.0) || xy_out == NULL) return -1;
+    long long nc = (long long)floor(L / (2.0 * r));
+    if (nc > 65536) nc = 65536;
+    const int brute = nc < 3;   /* fewer than 3 cells a side: test every placed disk */
+    if (nc < 1) nc = 1;
+    const double inv_cell = (double)nc / L;
+    int *head = (int *)malloc(sizeof(int) * (size_t)(nc * nc));
+    int *next = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    if (!head || !next) {
+        free(head);
+        free(next);
+        return -3;
+    }
+    for (long long c = 0; c < nc * nc; ++c) head[c] = -1;
+    uint64_t state = seed ^ 0x9A3D1C5B7ULL;
+    const double min_d2 = 4.0 * r * r;
+    long long attempts = 0;
+    int placed = 0;
+    while (placed < n) {
+        if (attempts >= max_attempts) break;
+        ++attempts;
+        double x = L * unit53(&state);
+        double y = L * unit53(&state);
+        long long cx = (long long)(x * inv_cell), cy = (long long)(y * inv_cell);
+        if (cx >= nc) cx = nc - 1;
+        if (cy >= nc) cy = nc - 1;
+        int ok = 1;
+        if (brute) {
+            for (int k = 0; k < placed && ok; ++k) {
+                double dx = x - xy_out[2 * k], dy = y - xy_out[2 * k + 1];
+                dx -= L * nearbyint(dx / L);
+                dy -= L * nearbyint(dy / L);
+                if (dx * dx + dy * dy < min_d2) ok = 0;
+            }
+        } else {
+            for (long long gy = cy - 1; gy <= cy + 1 && ok; ++gy) {
+                long long wy = (gy + nc) % nc;
+                for (long long gx = cx - 1; gx <= cx + 1 && ok; ++gx) {
+                    long long wx = (gx + nc) % nc;
+                    for (int k = head[wy * nc + wx]; k >= 0; k = next[k]) {
+                        double dx = x - xy_out[2 * k], dy = y - xy_out[2 * k + 1];
+                        dx -= L * nearbyint(dx / L);
+                        dy -= L * nearbyint(dy / L);
+                        if (dx * dx + dy * dy < min_d2) {
+                            ok = 0;
+                            break;
+                        }
+                    }
+                }
+            }
+        }
+        if (!ok) continue;
+        xy_out[2 * placed] = x;
+        xy_out[2 * placed + 1] = y;
+        next[placed] = head[cy * nc + cx];
+        head[cy * nc + cx] = placed;
+        ++placed;
+    }
+    free(head);
+    free(next);
+    if (attempts_out) *attempts_out = attempts;
+    return placed == n ? 0 : -2;
+}

@@ -700,3 +700,153 @@ def test_pair_method_leaves_no_overlap():
         sim.step(1)
         assert _bruteforce_min_gap(sim.state()[0]) == 0
     assert sim.state()[3]["overlap_rounds_total"] > 0
+
+
+# ------------------------------------------------------------------ periodic box (Sec. 2.1)
+def _min_image(v, L):
+    return v - L * np.rint(v / L)
+
+
+def test_periodic_two_particle_force_through_the_boundary():
+    # Sec. 2.1 minimum image: disks at x = 1 and x = L - 1 are 2 apart through the boundary, so the force on
+    # the first points in +x (away from the nearer image at x = -1) with magnitude K / d^2; without the box
+    # they are L - 2 apart and it points in -x
+    L, k = 40.0, 0.3
+    xy = np.array([[1.0, 7.0], [L - 1.0, 7.0]])
+    f = oracle.forces(xy, [0, 0], [[k]], period=L)
+    assert f[0, 0] == pytest.approx(k / 4.0, rel=1e-14) and f[0, 1] == 0.0
+    assert np.allclose(f[1], -f[0], rtol=0, atol=1e-18)
+    g = oracle.forces(xy, [0, 0], [[k]])
+    assert g[0, 0] == pytest.approx(-k / (L - 2.0) ** 2, rel=1e-14)
+    # diagonal through the corner: (0.5, 0.5) and (L - 0.5, L - 0.5) are sqrt(2) apart
+    xy = np.array([[0.5, 0.5], [L - 0.5, L - 0.5]])
+    f = oracle.forces(xy, [0, 0], [[k]], period=L)
+    assert f[0] == pytest.approx([k / 2.0 / math.sqrt(2.0)] * 2, rel=1e-13)
+
+
+def test_periodic_forces_are_translation_invariant():
+    # shifting every disk by the same vector (folded back into the box) leaves minimum-image forces unchanged
+    w = synth.make("C2", n=300, periodic=True)
+    f0 = oracle.forces(w.xy, w.species, w.K, period=w.L)
+    shifted = np.mod(w.xy + np.array([0.37 * w.L, 0.81 * w.L]), w.L)
+    f1 = oracle.forces(shifted, w.species, w.K, period=w.L)
+    assert np.abs(f1 - f0).max() <= 1e-11 * np.abs(f0).max()
+    # and equal brute force over the 3 x 3 images keeping the nearest one of each pair
+    n = w.n
+    ref = np.zeros((n, 2))
+    for i in range(n):
+        d = _min_image(w.xy[i] - w.xy, w.L)
+        r = np.hypot(d[:, 0], d[:, 1])
+        r[i] = np.inf
+        kk = w.K[w.species[i], w.species]
+        ref[i] = ((kk / r ** 3)[:, None] * d).sum(axis=0)
+    assert np.abs(ref - f0).max() <= 1e-12 * np.abs(f0).max()
+
+
+@pytest.mark.parametrize("n,phi,seed", [(30, 0.3, 1), (120, 0.5, 2), (150, 0.2, 3)])
+def test_torus_delaunay_empty_circumcircle_bruteforce(n, phi, seed):
+    # Euler on the torus: V - E + F = 0 with 3F = 2E, so 2n triangles and 3n edges; every triangle is
+    # counter-clockwise in the frame of the nearest images and no image of any disk lies inside its circumcircle
+    L = synth.box_side(n, phi)
+    xy = synth.rsa(n, L, 1.0, seed, periodic=True)
+    T = oracle.torus_delaunay(xy, L)
+    assert T.shape == (2 * n, 3)
+    edges = {tuple(sorted((t[k], t[(k + 1) % 3]))) for t in T for k in range(3)}
+    assert len(edges) == 3 * n
+    images = np.array([[ox, oy] for ox in (-1, 0, 1) for oy in (-1, 0, 1)]) * L
+    for a, b, c in T:
+        pa = xy[a]
+        pb = pa + _min_image(xy[b] - pa, L)
+        pc = pa + _min_image(xy[c] - pa, L)
+        assert oracle.orient2(pa, pb, pc) > 0
+        for j in range(n):
+            for off in images:
+                p = xy[j] + off
+                if np.min(np.hypot(*(np.array([pa, pb, pc]) - p).T)) < 1e-9:
+                    continue   # a vertex of the triangle itself
+                assert oracle.incircle(pa, pb, pc, p) <= 0.0
+
+
+@pytest.mark.parametrize("n,phi", [(500, 0.3), (3000, 0.5)])
+def test_torus_delaunay_matches_qhull_on_periodic_copies(n, phi):
+    # the planar Delaunay triangulation (Qhull) of the 3 x 3 periodic copies contains every torus triangle; the
+    # ones with a vertex in the central copy, mapped to ids, are exactly the torus triangulation
+    L = synth.box_side(n, phi)
+    xy = synth.rsa(n, L, 1.0, 7, periodic=True)
+    copies = np.concatenate([xy + np.array([ox, oy]) * L for oy in (-1, 0, 1) for ox in (-1, 0, 1)])
+    q = QhullDelaunay(copies).simplices
+    central = (q // n == 4).any(axis=1)
+    want = {tuple(sorted(t % n)) for t in q[central]}
+    got = {tuple(sorted(t)) for t in oracle.torus_delaunay(xy, L)}
+    assert got == want and len(got) == 2 * n
+
+
+def test_torus_delaunay_is_translation_invariant():
+    w = synth.make("C1", n=800, periodic=True)
+    t0 = {tuple(sorted(t)) for t in oracle.torus_delaunay(w.xy, w.L)}
+    shifted = np.mod(w.xy + np.array([0.5 * w.L + 0.123, 0.25 * w.L]), w.L)
+    t1 = {tuple(sorted(t)) for t in oracle.torus_delaunay(shifted, w.L)}
+    assert t0 == t1
+
+
+def _periodic_background(L, n, seed, keep_out, radius):
+    # disks of a periodic RSA at low density, minus those near the given points (the torus triangulation
+    # needs a point set dense enough that no Delaunay edge wraps around the box)
+    xy = synth.rsa(n, L, 1.0, seed, periodic=True)
+    far = np.ones(n, bool)
+    for p in keep_out:
+        d = _min_image(xy - np.asarray(p), L)
+        far &= np.hypot(d[:, 0], d[:, 1]) > radius
+    return xy[far]
+
+
+def test_periodic_pair_overlap_corrected_through_the_boundary():
+    # one overlapping pair across x = 0: with f = 1 (bounce) the separation becomes 2 sigma - d, measured
+    # through the boundary, and both disks stay in [0, L); the background disks do not move (D = 0, K = 0)
+    L = 30.0
+    pair = np.array([[0.4, 10.0], [L - 1.2, 10.0]])
+    xy = np.concatenate([pair, _periodic_background(L, 60, 5, pair, 5.0)])
+    n = xy.shape[0]
+    o = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), None, np.zeros((1, 1)), L=L, D=0.0, dt=1e-4,
+                         periodic=True)
+    o.step(1)
+    x = o.state()[0]
+    d = np.hypot(*_min_image(x[0] - x[1], L))
+    assert d == pytest.approx(2 * 2.0 - 1.6, abs=1e-12)
+    assert np.all((x >= 0.0) & (x < L))
+    assert np.array_equal(x[2:], xy[2:])
+    # the pair's midpoint (through the boundary) does not move
+    mid0 = xy[1] + 0.5 * _min_image(xy[0] - xy[1], L)
+    mid1 = x[1] + 0.5 * _min_image(x[0] - x[1], L)
+    assert np.abs(_min_image(mid1 - mid0, L)).max() <= 1e-12
+    assert o.state()[3]["overlap_rounds_total"] == 1
+
+
+def test_periodic_self_propulsion_wraps_around():
+    # D = 0, K = 0, Dr = 0, one director for all: rigid straight-line motion v0 t, folded back into [0, L)
+    L = 50.0
+    xy = np.concatenate([[[49.9, 3.0]], _periodic_background(L, 150, 6, [[49.9, 3.0]], 2.5)])
+    n = xy.shape[0]
+    th = np.full(n, 0.3)
+    o = oracle.OracleSim(xy, np.ones(n), np.zeros(n, np.int32), th, np.zeros((1, 1)), L=L, D=0.0, dt=1e-2, v0=5.0,
+                         periodic=True)
+    o.step(10)
+    x = o.state()[0]
+    want = np.mod(xy + 0.5 * np.array([math.cos(0.3), math.sin(0.3)]), L)
+    assert np.abs(_min_image(x - want, L)).max() <= 1e-12
+    assert x[0, 0] == pytest.approx(49.9 + 0.5 * math.cos(0.3) - L, abs=1e-12)
+    assert o.state()[3]["overlap_rounds_total"] == 0
+
+
+def test_periodic_steps_leave_no_overlap_and_torus_delaunay():
+    w = synth.make("C1", n=600, periodic=True)
+    o = oracle.OracleSim.from_workload(w, dt=2e-2)
+    o.step(8)
+    x, _, _, st = o.state()
+    assert st["overlap_rounds_total"] > 0
+    assert np.all((x >= 0.0) & (x < w.L))
+    d = _min_image(x[:, None, :] - x[None, :, :], w.L)
+    r = np.hypot(d[..., 0], d[..., 1])
+    np.fill_diagonal(r, np.inf)
+    assert r.min() >= 2.0 * (1 - 1e-9)
+    assert {tuple(sorted(t)) for t in o.triangles()} == {tuple(sorted(t)) for t in oracle.torus_delaunay(x, w.L)}
