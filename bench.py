@@ -234,6 +234,43 @@ def run_batched(steps, warmup, loop_steps):
     return out
 
 
+def run_ablation(steps):
+    """j-broadcast ablation of the all-pairs force on the default workload (N = 65,536, FP32): the same tiles
+    (chunks of 1024, 4 particles i per lane) with j as wave-uniform scalar loads or staged through LDS (the
+    shared-memory broadcast of the paper's n-body kernel, Sec. 6), and the symmetric form that turns j
+    around the wavefront by DPP.  Force launches timed with HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    from paper_1703_02484_amd import binding, synth
+
+    w = synth.make("C2")
+    pairs = w.n * (w.n - 1)
+    forms = {"scalar_loads": dict(force_chunk=1024, force_per_lane=4, force_launch=0),
+             "lds_staged": dict(force_chunk=1024, force_per_lane=4, force_launch=2),
+             "dpp_symmetric": dict(force_chunk=-1)}
+    out = {"workload": f"C2: N={w.n}, FP32 all-pairs inverse-square force", "steps": steps}
+    forces = {}
+    for name, pin in forms.items():
+        sim = binding.Sim.from_workload(w, **pin)
+        forces[name] = sim.forces()
+        sim.set_graph_mode(True)
+        sim.step(2)
+        sim.enable_kernel_timing(True)
+        sim.step(steps)
+        torch.cuda.synchronize()
+        ms, launches = sim.kernel_time()
+        avg = ms / max(launches, 1)
+        out[name] = {"force_ms": avg, "pair_interactions_per_s": pairs / (avg / 1e3),
+                     "tflops_12_flop_convention": FLOPS_PER_PAIR * pairs / (avg / 1e3) / 1e12,
+                     "force_config": sim.force_config()}
+        sim.close()
+    out["lds_vs_scalar_max_abs_force_diff"] = float(np.abs(forces["lds_staged"] - forces["scalar_loads"]).max())
+    out["lds_over_scalar_time"] = out["lds_staged"]["force_ms"] / out["scalar_loads"]["force_ms"]
+    out["scalar_over_dpp_time"] = out["scalar_loads"]["force_ms"] / out["dpp_symmetric"]["force_ms"]
+    return out
+
+
 def run_adjoint():
     """Gradient of the species-0 mean squared displacement after 50 steps (N = 16,384, FP64, contact factor 1/2)
     with respect to K and the initial positions: forward with checkpoints every 10 steps, then the adjoint sweep."""
@@ -323,7 +360,8 @@ def main():
     ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the secondary 256-system batched measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the secondary gradient measurement")
-    ap.add_argument("--only", choices=["short_range", "batched", "adjoint"], default=None,
+    ap.add_argument("--no-ablation", action="store_true", help="skip the j-broadcast ablation of the force")
+    ap.add_argument("--only", choices=["short_range", "batched", "adjoint", "ablation"], default=None,
                     help="run one secondary measurement alone and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (scale for HBM byte counters)")
@@ -355,7 +393,8 @@ def main():
     if args.only:
         fn = {"short_range": lambda: run_short_range(max(10, args.steps // 4), 20),
               "batched": lambda: run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100)),
-              "adjoint": run_adjoint}[args.only]
+              "adjoint": run_adjoint,
+              "ablation": lambda: run_ablation(max(5, args.steps // 20))}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     w = synth.make(args.workload, n=args.n)
@@ -444,6 +483,8 @@ def main():
         out["batched"] = run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100))
     if not args.no_adjoint and args.workload == "C2":
         out["adjoint"] = run_adjoint()
+    if not args.no_ablation and args.workload == "C2":
+        out["ablation"] = run_ablation(max(5, args.steps // 20))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

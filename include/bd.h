@@ -106,8 +106,11 @@ typedef struct bd_params {
                                     lane) / 512 (2 per lane) / 1024 (8 per lane, 2 wavefronts) */
     int32_t force_per_lane;      /* with force_chunk > 0: particles i per lane, 2 or 4 (0: 4); a tile holds
                                     256 * force_per_lane particles i */
-    int32_t force_launch;        /* with force_chunk > 0: 0 one workgroup per tile, 1 a resident grid taking
-                                    the tiles from a queue (the autotuner's two launch forms) */
+    int32_t force_launch;        /* with force_chunk > 0: 0 one workgroup per tile, j as wave-uniform scalar
+                                    loads; 1 a resident grid taking the tiles from a queue (the autotuner's
+                                    two launch forms); 2 one workgroup per tile with j staged through LDS
+                                    (the shared-memory broadcast of the paper's n-body kernel, Sec. 6;
+                                    inverse-square law without cutoff; same sums as 0, bitwise) */
     int32_t overlap_method;      /* bd_overlap_method.  BD_OVERLAP_VERLET finds overlapping pairs in the
                                     neighbour lists (radius cutoff + skin); they hold every pair closer than
                                     contact while no disk moved more than (cutoff + skin - 2 r_max) / 2 since
@@ -204,7 +207,8 @@ typedef struct bd_force_config {
     int32_t per_lane;     /* i per lane; a tile holds 256 * per_lane particles i */
     int32_t persistent;   /* launch form: 0 one workgroup per tile (i-block x chunk); 1 a fixed grid taking
                              those tiles from a queue; 2 symmetric: one workgroup per pair of chunks,
-                             each pair of disks evaluated once and both sums written */
+                             each pair of disks evaluated once and both sums written; 3 one workgroup
+                             per tile with j staged through LDS (force_launch 2) */
     int32_t tiles;        /* tiles per force evaluation */
     int32_t grid;         /* workgroups launched per force evaluation */
     int32_t tuned;        /* 1: chosen by timing, 2: taken from the tuning cache, 0: fixed rule */
@@ -223,6 +227,30 @@ int bd_step(bd_sim *sim, int64_t nsteps);
 
 /* Forces at the current positions in caller order, 2n doubles.  Does not advance time. */
 int bd_forces(bd_sim *sim, double *f_out);
+
+/*
+ * Pair forces of the Sec. 2.2 law for positions the caller holds in device
+ * memory, without a handle:
+ *   F_i = sum_{j != i} K[s_i][s_j] g(d_ij) (r_i - r_j) / d_ij
+ * with g and the cutoff from fp (fp->skin is ignored; all pairs are
+ * evaluated, no neighbour lists).
+ *   n          number of particles, >= 1
+ *   xy         device, 2n doubles, x and y interleaved (caller order)
+ *   species    device, n int32 in 0..fp->S-1 (not checked on the device)
+ *   fp         host; fp->K (S*S doubles, host) is copied before the call returns
+ *   precision  BD_PREC_FP64 or BD_PREC_FP32 (pair sums in FP32 from FP32
+ *              copies of the positions; the final sum over j splits in FP64)
+ *   f_out      device, 2n doubles (Fx, Fy interleaved), written
+ *   stream     hipStream_t of the current device to run on (NULL: the null stream)
+ * All device pointers belong to the current device.  The call allocates its
+ * working memory (the per-split sums, J * n * 16 bytes at most, J <= 64),
+ * runs on `stream`, synchronises it, frees the memory and returns.  Two
+ * distinct particles at the same position give non-finite forces.
+ * BD_ERR_INVALID_ARG for bad arguments, BD_ERR_OOM if the working memory
+ * cannot be allocated, BD_ERR_DEVICE if a launch fails.
+ */
+int bd_pair_forces_dev(int32_t n, const double *xy, const int32_t *species, const bd_force_params *fp,
+                       int32_t precision, double *f_out, void *stream);
 
 /*
  * Copies the state out: xy_out (2n doubles, may be NULL), theta_out (n

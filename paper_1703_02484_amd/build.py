@@ -24,7 +24,7 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
-SOURCES = ["k_particles.hip", "k_topology.hip", "k_verlet.hip", "k_adjoint.hip", "host_dt.cpp", "sim.cpp"]
+SOURCES = ["k_particles.hip", "k_topology.hip", "k_verlet.hip", "k_adjoint.hip", "k_pairforce.hip", "host_dt.cpp", "sim.cpp"]
 
 
 def _compile(src: str) -> str:

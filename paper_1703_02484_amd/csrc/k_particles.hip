@@ -174,6 +174,73 @@ __global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj
     force_tile<T, T2, P, FAST>(pj, tiles[blockIdx.x], part, law);
 }
 
+// LDS form (the shared-memory broadcast of the paper's n-body kernel, Sec. 6):
+// the workgroup stages the chunk's j positions in LDS, kLdsJ at a time, and
+// every lane reads the same j from there, instead of wave-uniform scalar
+// loads.  Same tiles, same j order and the same pair arithmetic as k_force,
+// so the partial sums are bitwise those of k_force (the self floor only
+// changes a pair with d^2 below 1e-20, i.e. i itself).
+constexpr int kLdsJ = 1024;
+
+template <typename T, typename T2, int P, bool SELF>
+__device__ __forceinline__ void pair_block_lds(const T2 *__restrict__ sj, int m, const T (&xi)[P], const T (&yi)[P],
+                                               T (&ax)[P], T (&ay)[P]) {
+#pragma unroll 8
+    for (int k = 0; k < m; ++k) {
+        const T2 q = sj[k];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            T dx = xi[p] - q.x;
+            T dy = yi[p] - q.y;
+            T d2 = dx * dx + dy * dy;
+            if (SELF) d2 = d2 > self_floor<T>() ? d2 : self_floor<T>();
+            T inv3 = inv_cube<T>(d2);
+            ax[p] += dx * inv3;
+            ay[p] += dy * inv3;
+        }
+    }
+}
+
+template <typename T, typename T2, int P>
+__global__ __launch_bounds__(kForceBlock) void k_force_lds(const T2 *__restrict__ pj, const Tile *__restrict__ tiles,
+                                                           T2 *__restrict__ part, const StepBase *__restrict__ base) {
+    __shared__ T2 sj[kLdsJ];
+    if (base->stop) return;
+    const Tile tl = tiles[blockIdx.x];
+    const int ib = tl.i0;
+    T xi[P], yi[P], ax[P], ay[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        int i = ib + k * kForceBlock + threadIdx.x;
+        T2 v = pj[i < tl.i1 ? i : tl.i1 - 1];
+        xi[k] = v.x;
+        yi[k] = v.y;
+        ax[k] = (T)0;
+        ay[k] = (T)0;
+    }
+    for (int jb = tl.js; jb < tl.je; jb += kLdsJ) {
+        const int m = min(kLdsJ, tl.je - jb);
+        __syncthreads();   // every lane is done with the previous block
+        for (int k = threadIdx.x; k < m; k += kForceBlock) sj[k] = pj[jb + k];
+        __syncthreads();
+        // a block that meets the workgroup's own particles floors d^2 (the self term adds 0)
+        if (jb < tl.i1 && jb + m > ib)
+            pair_block_lds<T, T2, P, true>(sj, m, xi, yi, ax, ay);
+        else
+            pair_block_lds<T, T2, P, false>(sj, m, xi, yi, ax, ay);
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        int i = ib + k * kForceBlock + threadIdx.x;
+        if (i < tl.i1) {
+            T2 v;
+            v.x = ax[k];
+            v.y = ay[k];
+            part[tl.pbase + i] = v;
+        }
+    }
+}
+
 // Persistent form: a grid sized to the resident workgroups takes tiles from
 // a queue (tile list longest first) until it is empty.  The queue counter is
 // zeroed before the launch; every workgroup leaves once the counter passes
@@ -570,7 +637,10 @@ namespace {
 
 template <typename T, typename T2, int P, bool FAST>
 void launch_force_t(Sim &s, const LawArgs &law) {
-    if (s.persistent) {
+    if (FAST && s.persistent == 3) {   // j staged through LDS (inverse-square law)
+        hipLaunchKernelGGL((k_force_lds<T, T2, P>), dim3(s.ntiles), dim3(kForceBlock), 0, s.stream,
+                           (const T2 *)s.pj, s.tiles, (T2 *)s.part, s.dbase);
+    } else if (s.persistent) {
         hipLaunchKernelGGL((k_force_queue<T, T2, P, FAST>), dim3(s.force_grid), dim3(kForceBlock), 0, s.stream,
                            (const T2 *)s.pj, s.tiles, s.ntiles, (T2 *)s.part, law, s.ctl + K_FQUEUE, s.dbase);
     } else {
@@ -633,7 +703,7 @@ void launch_force(Sim &s) {
         }
         return;
     }
-    if (s.persistent) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);
+    if (s.persistent == 1) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(64), 0, s.stream, s.ctl + K_FQUEUE);
     if (s.fp32) {
         if (s.per_lane == 2)
             launch_force_p<float, float2, 2>(s, law);

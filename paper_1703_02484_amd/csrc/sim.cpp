@@ -1234,9 +1234,9 @@ void upload_tiling(Sim &s, const Tiling &t, int chunk, int per_lane, int persist
     s.chunk_len = chunk;
     s.per_lane = per_lane;
     s.persistent = persistent;
-    s.force_grid = persistent == 2 ? s.nstiles
-                   : persistent   ? std::min(s.ntiles, force_max_grid(s, per_lane))
-                                  : s.ntiles;
+    s.force_grid = persistent == 2   ? s.nstiles
+                   : persistent == 1 ? std::min(s.ntiles, force_max_grid(s, per_lane))
+                                     : s.ntiles;
 }
 
 // Fixed rule: the smallest power-of-two chunk (>= 64) that keeps the launch
@@ -1371,7 +1371,7 @@ void setup_force(Sim &s) {
         const int pl = s.p.force_per_lane == 2 ? 2 : 4;
         Tiling t = make_tiling(s, s.p.force_chunk, pl);
         alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
-        upload_tiling(s, t, s.p.force_chunk, pl, s.p.force_launch == 1 ? 1 : 0);
+        upload_tiling(s, t, s.p.force_chunk, pl, s.p.force_launch == 1 ? 1 : s.p.force_launch == 2 ? 3 : 0);
         return;
     }
     if (s.p.force_chunk < 0) {   // the symmetric form, pinned: -1 chunks of 1024 (4 per lane), -2 of 512, -3 1024 (8)
@@ -1554,7 +1554,10 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
         return err = "halving on edge reversal needs the Delaunay overlap method", BD_ERR_INVALID_ARG;
     if (p->force_per_lane != 0 && p->force_per_lane != 2 && p->force_per_lane != 4)
         return err = "force_per_lane must be 0, 2 or 4", BD_ERR_INVALID_ARG;
-    if (p->force_launch != 0 && p->force_launch != 1) return err = "force_launch must be 0 or 1", BD_ERR_INVALID_ARG;
+    if (p->force_launch < 0 || p->force_launch > 2) return err = "force_launch must be 0, 1 or 2", BD_ERR_INVALID_ARG;
+    if (p->force_launch == 2 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
+        return err = "force_launch 2 (j staged in LDS) needs the inverse-square law without cutoff",
+               BD_ERR_INVALID_ARG;
     if (p->force_chunk < 0 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
         return err = "force_chunk < 0 (symmetric form) needs the inverse-square law without cutoff",
                BD_ERR_INVALID_ARG;

@@ -108,7 +108,7 @@ def test_rejects_too_few_disks():
 
 
 @pytest.mark.parametrize("kw", [dict(force_chunk=12), dict(force_chunk=512, force_per_lane=3),
-                                dict(force_chunk=512, force_launch=2), dict(force_chunk=-4)])
+                                dict(force_chunk=512, force_launch=3), dict(force_chunk=-4)])
 def test_rejects_bad_force_form(kw):
     with pytest.raises(binding.BDError) as e:
         _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], **kw)

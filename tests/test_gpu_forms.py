@@ -42,12 +42,33 @@ def test_pinned_force_form_matches_oracle(law, fp32, per_lane, launch, n):
     assert np.abs(g.forces() - fo).max() <= tol * _scale(fo)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("per_lane", [2, 4])
+@pytest.mark.parametrize("n", [1000, 4099])
+def test_lds_staged_form_matches_oracle_and_scalar_form(fp32, per_lane, n):
+    # j staged through LDS (the shared-memory broadcast of the paper's n-body kernel): same tiles and
+    # summation order as the scalar-load form, so the forces are bitwise equal to it
+    w = synth.make("C2", n=n)
+    g = binding.Sim.from_workload(w, fp32=fp32, force_chunk=512, force_per_lane=per_lane, force_launch=2)
+    assert g.force_config()["persistent"] == 3
+    h = binding.Sim.from_workload(w, fp32=fp32, force_chunk=512, force_per_lane=per_lane, force_launch=0)
+    fo = oracle.forces(w.xy, w.species, w.K)
+    fg = g.forces()
+    assert np.abs(fg - fo).max() <= (1e-4 if fp32 else 1e-12) * _scale(fo)
+    assert np.array_equal(fg, h.forces())
+    g.step(3)
+    h.step(3)
+    assert np.array_equal(g.state()[0], h.state()[0])
+
+
 def test_pinned_force_form_rejects_bad_values():
     w = synth.make("C1", n=100)
     with pytest.raises(binding.BDError):
         binding.Sim.from_workload(w, force_chunk=512, force_per_lane=3)
     with pytest.raises(binding.BDError):
-        binding.Sim.from_workload(w, force_chunk=512, force_launch=2)
+        binding.Sim.from_workload(w, force_chunk=512, force_launch=3)
+    with pytest.raises(binding.BDError):   # the LDS form is written for the inverse-square law only
+        binding.Sim.from_workload(w, force_chunk=512, force_launch=2, kind="power", q=6.0)
 
 
 def test_full_size_c2_bench_path_matches_oracle():
