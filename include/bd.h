@@ -122,6 +122,15 @@ typedef struct bd_params {
                                     halves' noise is a Brownian bridge of the step's own draws (Philox,
                                     keyed by step, disk, level and interval), so a trajectory stays a
                                     function of the seed.  Delaunay overlap method only */
+    int32_t periodic;            /* 0: hard walls.  1: periodic box [0, L)^2 (the paper's domain, Sec. 2.1):
+                                    positions folded into [0, L) after every move, every separation taken
+                                    from the nearest image (minimum-image convention, ties to even) in the
+                                    forces, the neighbour lists and the overlap rounds.  The Delaunay
+                                    overlap method keeps the triangulation of the flat torus (2n triangles,
+                                    no frame points, no infinite vertex), whose predicates read a triangle
+                                    or a quad at the nearest images of its vertices.  One system per
+                                    handle; all-pairs forces in the one-workgroup-per-tile form
+                                    (force_chunk >= 0, force_launch 0); no adjoint */
 } bd_params;
 
 /* Counters accumulated since bd_init (the paper reports rounds and flips per step, Sec. 6). */
@@ -271,7 +280,8 @@ int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out);
  * per triangle into tri_out (room for cap triangles; 2 (n + m) is always
  * enough), count into *ntri_out.  Ids 0..n-1 are disks in caller order; ids
  * n..n+m-1 are the frame points of bd_get_frame.  BD_ERR_INVALID_ARG if cap
- * is short.
+ * is short.  In a periodic box: the 2n triangles of the flat torus, each
+ * counter-clockwise at the nearest images of its vertices.
  */
 int bd_get_triangulation(const bd_sim *sim, int32_t *tri_out, int32_t cap, int32_t *ntri_out);
 

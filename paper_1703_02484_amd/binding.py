@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("max_flip_rounds", ctypes.c_int32), ("force_precision", ctypes.c_int32),
                 ("force_chunk", ctypes.c_int32), ("force_per_lane", ctypes.c_int32),
                 ("force_launch", ctypes.c_int32), ("overlap_method", ctypes.c_int32),
-                ("max_dt_halvings", ctypes.c_int32)]
+                ("max_dt_halvings", ctypes.c_int32), ("periodic", ctypes.c_int32)]
 
 
 class ForceConfig(ctypes.Structure):
@@ -200,16 +200,17 @@ def pair_forces_dev(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=
     fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
                      0.0, _ptr(Km))
     stream = torch.cuda.current_stream(xy.device).cuda_stream
-    rc = lib.bd_pair_forces_dev(n, xy.data_ptr(), species.data_ptr(), ctypes.byref(fp),
-                                BD_PREC_FP32 if fp32 else BD_PREC_FP64, out.data_ptr(), stream)
+    fn = lib.bd_pair_forces_dev
+    rc = fn(n, xy.data_ptr(), species.data_ptr(), ctypes.byref(fp), BD_PREC_FP32 if fp32 else BD_PREC_FP64,
+            out.data_ptr(), stream)
     if rc != 0:
-        raise BDError(rc, f"bd_pair_forces_dev failed: {lib.bd_strerror(rc).decode()}")
+        raise BDError(rc, f"{fn.__name__} failed: {lib.bd_strerror(rc).decode()}")
     return out
 
 
 def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, step0, overlap_factor, cap_frac,
             noise_clip, contact_tol, max_overlap_rounds, max_flip_rounds, fp32, force_chunk, force_per_lane,
-            force_launch, overlap, max_dt_halvings):
+            force_launch, overlap, max_dt_halvings, periodic):
     Km = np.ascontiguousarray(K, dtype=np.float64)
     fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
                      skin, _ptr(Km))
@@ -225,13 +226,14 @@ def _params(lib, *, L, kind, q, A, lam, cutoff, skin, K, D, dt, v0, Dr, seed, st
     p.force_per_lane, p.force_launch = force_per_lane, force_launch
     p.overlap_method = {"delaunay": BD_OVERLAP_DELAUNAY, "verlet": BD_OVERLAP_VERLET}[overlap]
     p.max_dt_halvings = max_dt_halvings
+    p.periodic = 1 if periodic else 0
     return fp, p, Km
 
 
 _DEFAULTS = dict(kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, skin=0.0, D=1.0, dt=1e-4, v0=0.0, Dr=0.0, seed=0,
                  step0=0, overlap_factor=1.0, cap_frac=0.5, noise_clip=3.0, contact_tol=1e-9,
                  max_overlap_rounds=10000, max_flip_rounds=200, fp32=False, force_chunk=0, force_per_lane=0,
-                 force_launch=0, overlap="delaunay", max_dt_halvings=0)
+                 force_launch=0, overlap="delaunay", max_dt_halvings=0, periodic=False)
 
 
 class Sim:
@@ -292,7 +294,7 @@ class Sim:
                   v0=w.v0, Dr=w.Dr, seed=w.seed, step0=w.step0, overlap_factor=w.overlap_factor,
                   cap_frac=w.cap_frac, noise_clip=w.noise_clip, contact_tol=w.contact_tol,
                   max_overlap_rounds=w.max_overlap_rounds, fp32=w.fp32_forces, overlap=w.overlap,
-                  max_dt_halvings=w.max_dt_halvings)
+                  max_dt_halvings=w.max_dt_halvings, periodic=getattr(w, "periodic", False))
         kw.update(over)
         return cls(w.xy, w.radii, w.species, w.theta, w.K, **kw)
 

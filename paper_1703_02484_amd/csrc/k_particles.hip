@@ -70,16 +70,23 @@ __device__ __forceinline__ double self_floor<double>() { return 1e-200; }
 
 // Inverse-square law (q = 2, all pairs): Phi += (r_i - r_j) / d^3.
 // SELF: the range may contain i itself; d^2 is floored so the self term is 0.
-template <typename T, typename T2, int P, bool SELF>
+// PER: periodic box of side per (inv_per = 1 / per): separations from the nearest image.
+template <typename T, bool PER>
+__device__ __forceinline__ T near_image(T v, T per, T inv_per) {
+    return PER ? v - per * rint(v * inv_per) : v;
+}
+
+template <typename T, typename T2, int P, bool SELF, bool PER = false>
 __device__ __forceinline__ void pair_range_q2(const T2 *__restrict__ pj, int j0, int j1, const T (&xi)[P],
-                                              const T (&yi)[P], T (&ax)[P], T (&ay)[P]) {
+                                              const T (&yi)[P], T (&ax)[P], T (&ay)[P], T per = (T)0,
+                                              T inv_per = (T)0) {
 #pragma unroll 8
     for (int j = j0; j < j1; ++j) {
         const T2 q = pj[j];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            T dx = xi[k] - q.x;
-            T dy = yi[k] - q.y;
+            T dx = near_image<T, PER>(xi[k] - q.x, per, inv_per);
+            T dy = near_image<T, PER>(yi[k] - q.y, per, inv_per);
             T d2 = dx * dx + dy * dy;
             if (SELF) d2 = d2 > self_floor<T>() ? d2 : self_floor<T>();
             T inv3 = inv_cube<T>(d2);
@@ -93,11 +100,13 @@ __device__ __forceinline__ void pair_range_q2(const T2 *__restrict__ pj, int j0,
 struct LawArgs {
     int kind;
     double q, A, lam, cutoff;
+    double period;   // > 0: periodic box (minimum-image separations)
 };
 
-template <typename T, typename T2, int P>
+template <typename T, typename T2, int P, bool PER = false>
 __device__ __forceinline__ void pair_range_general(const T2 *__restrict__ pj, int j0, int j1, const T (&xi)[P],
                                                    const T (&yi)[P], T (&ax)[P], T (&ay)[P], const LawArgs law) {
+    const T per = (T)law.period, inv_per = PER ? (T)(1.0 / law.period) : (T)0;
     const T cut2 = law.cutoff > 0.0 ? (T)(law.cutoff * law.cutoff) : (T)0;
     const T expo = (T)(-0.5 * (law.q + 1.0));
     const T invlam = (T)(1.0 / law.lam);
@@ -106,8 +115,8 @@ __device__ __forceinline__ void pair_range_general(const T2 *__restrict__ pj, in
         const T2 q = pj[j];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            T dx = xi[k] - q.x;
-            T dy = yi[k] - q.y;
+            T dx = near_image<T, PER>(xi[k] - q.x, per, inv_per);
+            T dy = near_image<T, PER>(yi[k] - q.y, per, inv_per);
             T d2 = dx * dx + dy * dy;
             bool ok = d2 > (T)0 && (cut2 == (T)0 || d2 <= cut2);
             T dd = ok ? d2 : (T)1;
@@ -125,9 +134,10 @@ __device__ __forceinline__ void pair_range_general(const T2 *__restrict__ pj, in
     }
 }
 
-template <typename T, typename T2, int P, bool FAST>
+template <typename T, typename T2, int P, bool FAST, bool PER = false>
 __device__ __forceinline__ void force_tile(const T2 *__restrict__ pj, const Tile &tl, T2 *__restrict__ part,
                                            const LawArgs &law) {
+    const T per = (T)law.period, inv_per = PER ? (T)(1.0 / law.period) : (T)0;
     const int ib = tl.i0;
     T xi[P], yi[P], ax[P], ay[P];
 #pragma unroll
@@ -144,14 +154,14 @@ __device__ __forceinline__ void force_tile(const T2 *__restrict__ pj, const Tile
         int lo = tl.js > ib ? tl.js : ib;
         int hi = tl.je < tl.i1 ? tl.je : tl.i1;
         if (lo < hi) {
-            pair_range_q2<T, T2, P, false>(pj, tl.js, lo, xi, yi, ax, ay);
-            pair_range_q2<T, T2, P, true>(pj, lo, hi, xi, yi, ax, ay);
-            pair_range_q2<T, T2, P, false>(pj, hi, tl.je, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false, PER>(pj, tl.js, lo, xi, yi, ax, ay, per, inv_per);
+            pair_range_q2<T, T2, P, true, PER>(pj, lo, hi, xi, yi, ax, ay, per, inv_per);
+            pair_range_q2<T, T2, P, false, PER>(pj, hi, tl.je, xi, yi, ax, ay, per, inv_per);
         } else {
-            pair_range_q2<T, T2, P, false>(pj, tl.js, tl.je, xi, yi, ax, ay);
+            pair_range_q2<T, T2, P, false, PER>(pj, tl.js, tl.je, xi, yi, ax, ay, per, inv_per);
         }
     } else {
-        pair_range_general<T, T2, P>(pj, tl.js, tl.je, xi, yi, ax, ay, law);
+        pair_range_general<T, T2, P, PER>(pj, tl.js, tl.je, xi, yi, ax, ay, law);
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -165,13 +175,13 @@ __device__ __forceinline__ void force_tile(const T2 *__restrict__ pj, const Tile
     }
 }
 
-// One workgroup per tile.
-template <typename T, typename T2, int P, bool FAST>
+// One workgroup per tile.  PER: periodic box (law.period > 0).
+template <typename T, typename T2, int P, bool FAST, bool PER = false>
 __global__ __launch_bounds__(kForceBlock) void k_force(const T2 *__restrict__ pj, const Tile *__restrict__ tiles,
                                                        T2 *__restrict__ part, LawArgs law,
                                                        const StepBase *__restrict__ base) {
     if (base->stop) return;
-    force_tile<T, T2, P, FAST>(pj, tiles[blockIdx.x], part, law);
+    force_tile<T, T2, P, FAST, PER>(pj, tiles[blockIdx.x], part, law);
 }
 
 // LDS form (the shared-memory broadcast of the paper's n-body kernel, Sec. 6):
@@ -469,6 +479,7 @@ struct EmArgs {
     double D, Dr;          // for the bridge amplitudes of a sub-interval
     int level;             // 0: the whole step; > 0: sub-interval `index` of 2^level after reversals (Sec. 4.3)
     unsigned index;
+    int periodic;          // fold into the periodic box [0, L)^2 instead of reflecting at the walls
 };
 
 // Fused Euler-Maruyama update: gather forces, draw noise (stream 0:
@@ -542,8 +553,8 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         xo[i] = x0;
         yo[i] = y0;
         tho[i] = t0;
-        x[i] = bd_wall(xn, r, ri.L);
-        y[i] = bd_wall(yn, r, ri.L);
+        x[i] = a.periodic ? bd_wrap(xn, ri.L) : bd_wall(xn, r, ri.L);
+        y[i] = a.periodic ? bd_wrap(yn, ri.L) : bd_wall(yn, r, ri.L);
         if (wf) {   // adjoint tape: wall slopes of this move
             wf[2 * (size_t)i] = bd_wall_slope(xn, r, ri.L);
             wf[2 * (size_t)i + 1] = bd_wall_slope(yn, r, ri.L);
@@ -637,7 +648,10 @@ namespace {
 
 template <typename T, typename T2, int P, bool FAST>
 void launch_force_t(Sim &s, const LawArgs &law) {
-    if (FAST && s.persistent == 3) {   // j staged through LDS (inverse-square law)
+    if (s.period > 0.0) {   // periodic box: one workgroup per tile, minimum-image separations
+        hipLaunchKernelGGL((k_force<T, T2, P, FAST, true>), dim3(s.ntiles), dim3(kForceBlock), 0, s.stream,
+                           (const T2 *)s.pj, s.tiles, (T2 *)s.part, law, s.dbase);
+    } else if (FAST && s.persistent == 3) {   // j staged through LDS (inverse-square law)
         hipLaunchKernelGGL((k_force_lds<T, T2, P>), dim3(s.ntiles), dim3(kForceBlock), 0, s.stream,
                            (const T2 *)s.pj, s.tiles, (T2 *)s.part, s.dbase);
     } else if (s.persistent) {
@@ -676,7 +690,7 @@ int max_grid_p(bool fast) {
 
 // Tiles of 256 * per_lane particles; per_lane is 2 or 4.
 void launch_force(Sim &s) {
-    LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff};
+    LawArgs law{s.fp.kind, s.fp.q, s.fp.A, s.fp.lambda, s.fp.cutoff, s.period};
     if (s.persistent == 2) {   // symmetric chunk pairs (the host builds them only for the inverse-square law)
         // per_lane 2 / 4: 4 wavefronts (chunks of 512 / 1024); 8: 2 wavefronts (chunks of 1024)
         const dim3 g(s.nstiles), b4(256), b2(128);
@@ -743,6 +757,7 @@ void launch_em(Sim &s, int level, unsigned index) {
     a.Dr = s.p.Dr;
     a.level = level;
     a.index = index;
+    a.periodic = s.period > 0.0 ? 1 : 0;
     const int nb = blocks_for(s.n, 256);
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;

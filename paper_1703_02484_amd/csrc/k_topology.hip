@@ -48,6 +48,7 @@ constexpr int kListGridMax = 256;  // worklist-driven launches (usually a few hu
 
 struct Topo {
     int n, inf, nvert, T;   // disks, first infinite-vertex id, all vertex ids, triangles
+    double P;               // > 0: periodic box of this side (torus triangulation, minimum-image geometry)
     const int *rep_of;      // replica of each disk
     const double *Lr;       // box side of each replica
     const double *x, *y, *xo, *yo, *rad;
@@ -75,6 +76,7 @@ Topo topo_of(Sim &s) {
     Topo t;
     t.n = s.n;
     t.inf = s.inf;
+    t.P = s.period;
     t.nvert = s.inf + s.R;
     t.rep_of = s.rep_of;
     t.Lr = s.Lr;
@@ -137,6 +139,28 @@ __device__ __forceinline__ int *wl_of(const Topo &t, int slot) { return (slot & 
 __device__ __forceinline__ bool bad_he(const Topo &t, int h) { return (unsigned)h >= (unsigned)(3 * t.T); }
 __device__ __forceinline__ bool bad_v(const Topo &t, int v) { return (unsigned)v >= (unsigned)t.nvert; }
 __device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctl[K_TOPO], 1); }
+
+// Geometry of the triangulation.  With walls the vertex positions are used as
+// they are.  In a periodic box (P > 0) a triangle or a quad is read in the
+// frame of its first vertex, every other vertex at its nearest image: every
+// edge of the torus triangulation is far shorter than P / 2, so that image is
+// the one the triangle spans.
+__device__ __forceinline__ double sep_p(double v, double P) { return P > 0.0 ? bd_min_image(v, P) : v; }
+
+__device__ __forceinline__ int flip_rule_of(const Topo &t, int a, int b, int c, int d, bool *inverted) {
+    if (t.P <= 0.0) return bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, inverted);
+    const double ax = t.x[a], ay = t.y[a];
+    return bd_flip_rule_quad(0.0, 0.0, sep_p(t.x[b] - ax, t.P), sep_p(t.y[b] - ay, t.P), sep_p(t.x[c] - ax, t.P),
+                             sep_p(t.y[c] - ay, t.P), sep_p(t.x[d] - ax, t.P), sep_p(t.y[d] - ay, t.P), true,
+                             inverted);
+}
+
+__device__ __forceinline__ double orient_of(const Topo &t, int a, int b, int c) {
+    if (t.P <= 0.0) return bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]);
+    const double ax = t.x[a], ay = t.y[a];
+    return bd_orient(0.0, 0.0, sep_p(t.x[b] - ax, t.P), sep_p(t.y[b] - ay, t.P), sep_p(t.x[c] - ax, t.P),
+                     sep_p(t.y[c] - ay, t.P));
+}
 
 __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
     return ((unsigned long long)(unsigned)round << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)e);
@@ -280,15 +304,15 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
         // Sec. 4.3: the pair passed through each other if the edge vector reversed
         bool rev = false;
         if (a < t.n && b < t.n) {
-            const double ox = t.xo[b] - t.xo[a], oy = t.yo[b] - t.yo[a];
-            const double mx = t.x[b] - t.x[a], my = t.y[b] - t.y[a];
+            const double ox = sep_p(t.xo[b] - t.xo[a], t.P), oy = sep_p(t.yo[b] - t.yo[a], t.P);
+            const double mx = sep_p(t.x[b] - t.x[a], t.P), my = sep_p(t.y[b] - t.y[a], t.P);
             rev = ox * mx + oy * my < 0.0;
         }
         wave_count64(&t.acc[A_REVERSALS], rev);
         if (reversal == 2) wave_count(&t.ctl[K_REV], rev);
     }
     bool inverted = false;
-    const int rule = bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, &inverted);
+    const int rule = flip_rule_of(t, a, b, c, d, &inverted);
     wave_count(&t.ctl[K_INVQ + slot], inverted);
     if (rule == BD_NOFLIP) return;
     if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
@@ -484,7 +508,7 @@ __device__ __forceinline__ void validate_tri(const Topo &t, int tri, int *inv) {
         return;
     }
     if (a >= t.inf || b >= t.inf || c >= t.inf) return;
-    if (bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]) <= 0.0) atomicAdd(inv, 1);
+    if (orient_of(t, a, b, c) <= 0.0) atomicAdd(inv, 1);
 }
 
 // After the repair that follows overlap round k the triangulation was valid
@@ -651,7 +675,7 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
                     continue;
                 }
                 if (a >= t.n || b >= t.n) continue;   // frame points and the infinite vertex never overlap
-                const double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
+                const double dx = sep_p(t.x[a] - t.x[b], t.P), dy = sep_p(t.y[a] - t.y[b], t.P);
                 const double d = sqrt(dx * dx + dy * dy);
                 if (d < (t.rad[a] + t.rad[b]) * keep) {
                     ++found;
@@ -697,7 +721,7 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     const int a = t.he_v[e], b = t.he_v[bd_next(e)];
     if (bad_v(t, a) || bad_v(t, b)) return topo_err(t);
     if (a >= t.n || b >= t.n) return;
-    const double dx = t.x[a] - t.x[b], dy = t.y[a] - t.y[b];
+    const double dx = sep_p(t.x[a] - t.x[b], t.P), dy = sep_p(t.y[a] - t.y[b], t.P);
     const double d = sqrt(dx * dx + dy * dy);
     if (d < (t.rad[a] + t.rad[b]) * keep) {
         ++found;
@@ -920,7 +944,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
         do {
             int w = t.he_v[bd_next(h)];
             if (w < t.n) {
-                double dx = xv - t.x[w], dy = yv - t.y[w];
+                double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
                 double d = sqrt(dx * dx + dy * dy);
                 double contact = rv + t.rad[w];
                 if (d < contact * keep) {
@@ -952,7 +976,10 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             t.tewf[2 * (size_t)e] = bd_wall_slope(xv + sx, rv, L);
             t.tewf[2 * (size_t)e + 1] = bd_wall_slope(yv + sy, rv, L);
         }
-        t.newpos[idx] = make_double2(bd_wall(xv + sx, rv, L), bd_wall(yv + sy, rv, L));
+        if (t.P > 0.0)
+            t.newpos[idx] = make_double2(bd_wrap(xv + sx, t.P), bd_wrap(yv + sy, t.P));
+        else
+            t.newpos[idx] = make_double2(bd_wall(xv + sx, rv, L), bd_wall(yv + sy, rv, L));
     }
 }
 
@@ -1148,14 +1175,20 @@ __global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
     }
 }
 
+// Sub-step i of k of a replayed move from (xa, ya) to (xb, yb); in a periodic
+// box (P > 0) along the nearest-image displacement, folded into [0, P).
 __global__ void k_interp(int n, int i, int k, const double *xa, const double *ya, const double *xb,
-                         const double *yb, double *x, double *y) {
+                         const double *yb, double *x, double *y, double P) {
 #pragma clang fp contract(off)
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     if (i == k) {
         x[v] = xb[v];
         y[v] = yb[v];
+    } else if (P > 0.0) {
+        const double s = (double)i / (double)k;
+        x[v] = bd_wrap(xa[v] + s * bd_min_image(xb[v] - xa[v], P), P);
+        y[v] = bd_wrap(ya[v] + s * bd_min_image(yb[v] - ya[v], P), P);
     } else {
         const double s = (double)i / (double)k;
         x[v] = xa[v] + s * (xb[v] - xa[v]);
@@ -1274,7 +1307,7 @@ void launch_scatter_oldpos(Sim &s, int k) {
 
 void launch_interp(Sim &s, int i, int k) {
     hipLaunchKernelGGL(k_interp, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n, i, k, s.xa, s.ya, s.xb,
-                       s.yb, s.x, s.y);
+                       s.yb, s.x, s.y, s.period);
 }
 
 }  // namespace bd

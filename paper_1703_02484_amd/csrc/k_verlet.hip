@@ -22,6 +22,9 @@
 namespace bd {
 namespace {
 
+// Separation component: from the nearest image in a periodic box of side P > 0, as is with walls (P = 0).
+__device__ __forceinline__ double sep(double v, double P) { return P > 0.0 ? bd_min_image(v, P) : v; }
+
 __device__ __forceinline__ int cell_coord(double v, double inv_cell, int nc) {
     int c = (int)(v * inv_cell);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
@@ -112,22 +115,32 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
                                                   const int *__restrict__ cell_start,
                                                   const int *__restrict__ cell_items, int *__restrict__ nl,
                                                   int *__restrict__ nl_cnt, double *__restrict__ xb,
-                                                  double *__restrict__ yb, int *__restrict__ overflow, const int *req) {
+                                                  double *__restrict__ yb, int *__restrict__ overflow, const int *req,
+                                                  double P) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || (req && !*req)) return;
     const double xi = x[i], yi = y[i];
     const int cx = cell_coord(xi, inv_cell, nc), cy = cell_coord(yi, inv_cell, nc);
     int cnt = 0;
-    for (int gy = cy - 1; gy <= cy + 1; ++gy) {
-        if (gy < 0 || gy >= nc) continue;
-        for (int gx = cx - 1; gx <= cx + 1; ++gx) {
-            if (gx < 0 || gx >= nc) continue;
+    // periodic box (P > 0): the 3 x 3 block wraps around (at least 3 cells a row, so no cell twice)
+    for (int oy = -1; oy <= 1; ++oy) {
+        int gy = cy + oy;
+        if (P > 0.0)
+            gy = gy < 0 ? gy + nc : (gy >= nc ? gy - nc : gy);
+        else if (gy < 0 || gy >= nc)
+            continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+            int gx = cx + ox;
+            if (P > 0.0)
+                gx = gx < 0 ? gx + nc : (gx >= nc ? gx - nc : gx);
+            else if (gx < 0 || gx >= nc)
+                continue;
             const int c = gy * nc + gx;
             for (int p = cell_start[c]; p < cell_start[c + 1]; ++p) {
                 const int j = cell_items[p];
                 if (j == i) continue;
-                const double dx = xi - x[j], dy = yi - y[j];
+                const double dx = sep(xi - x[j], P), dy = sep(yi - y[j], P);
                 if (dx * dx + dy * dy > rl2) continue;
                 if (cnt < CAP) nl[(size_t)cnt * n + i] = j;
                 ++cnt;
@@ -151,7 +164,7 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
                                                   int kind, double q, double A, double lam, double rc,
                                                   const int *__restrict__ nl, const int *__restrict__ nl_cnt,
                                                   double2 *__restrict__ f, const StepBase *__restrict__ base,
-                                                  const int *__restrict__ ctl) {
+                                                  const int *__restrict__ ctl, double P) {
 #pragma clang fp contract(off)
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || base->stop || ctl[K_HALT]) return;   // K_HALT: the lists of this step overflowed
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
     T fx = (T)0, fy = (T)0;
     for (int k = 0; k < m; ++k) {
         const int j = nl[(size_t)k * n + i];
-        const double ddx = xi - x[j], ddy = yi - y[j];
+        const double ddx = sep(xi - x[j], P), ddy = sep(yi - y[j], P);
         const double dd = sqrt(ddx * ddx + ddy * ddy);
         if (dd > rc) continue;   // the cutoff decision in FP64 in both precisions
         const T dx = (T)ddx, dy = (T)ddy, d = (T)dd;
@@ -186,11 +199,11 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
 // both flags before it tests the halted step's final positions itself.)
 __global__ void k_skin_check(int n, const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ xb, const double *__restrict__ yb, double half_skin2,
-                             int *__restrict__ flag, StepBase *__restrict__ base) {
+                             int *__restrict__ flag, StepBase *__restrict__ base, double P) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool out = false;
     if (i < n) {
-        const double dx = x[i] - xb[i], dy = y[i] - yb[i];
+        const double dx = sep(x[i] - xb[i], P), dy = sep(y[i] - yb[i], P);
         out = dx * dx + dy * dy > half_skin2;
     }
     if (__ballot(out) != 0 && __lane_id() == 0) {
@@ -232,7 +245,7 @@ __global__ __launch_bounds__(256) void k_ovl_nl_gather(int n, const double *__re
                                                        double margin2, double f, double cap_frac, double keep,
                                                        int *__restrict__ touched, double2 *__restrict__ newpos,
                                                        int *__restrict__ ctl, unsigned long long *__restrict__ acc,
-                                                       int k) {
+                                                       int k, double P) {
 #pragma clang fp contract(off)
     if ((ctl[K_HALT] | ctl[K_DONE]) != 0) return;   // nothing in this launch writes them: uniform
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,13 +254,13 @@ __global__ __launch_bounds__(256) void k_ovl_nl_gather(int n, const double *__re
     double nx = 0.0, ny = 0.0;
     if (i < n) {
         const double xi = x[i], yi = y[i], ri = rad[i];
-        const double ex = xi - xb[i], ey = yi - yb[i];
+        const double ex = sep(xi - xb[i], P), ey = sep(yi - yb[i], P);
         stale = ex * ex + ey * ey > margin2;
         const int m = nl_cnt[i];
         double sx = 0.0, sy = 0.0;
         for (int q = 0; q < m; ++q) {
             const int j = nl[(size_t)q * n + i];
-            const double dx = xi - x[j], dy = yi - y[j];
+            const double dx = sep(xi - x[j], P), dy = sep(yi - y[j], P);
             const double d = sqrt(dx * dx + dy * dy);
             const double contact = ri + rad[j];
             if (d < contact * keep) {
@@ -267,8 +280,8 @@ __global__ __launch_bounds__(256) void k_ovl_nl_gather(int n, const double *__re
                 sy = sy * sc;
                 capped = true;
             }
-            nx = bd_wall(xi + sx, ri, L);
-            ny = bd_wall(yi + sy, ri, L);
+            nx = P > 0.0 ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
+            ny = P > 0.0 ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
         }
     }
     // every lane of the wavefront is here: one atomic per wavefront for each counter
@@ -358,11 +371,11 @@ void enqueue_build(Sim &s, const int *req) {
     if (s.nl_cap <= 32)
         hipLaunchKernelGGL(k_nl_build<32>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
-                           s.ctl + K_NL_OVERFLOW, req);
+                           s.ctl + K_NL_OVERFLOW, req, s.period);
     else
         hipLaunchKernelGGL(k_nl_build<96>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
-                           s.ctl + K_NL_OVERFLOW, req);
+                           s.ctl + K_NL_OVERFLOW, req, s.period);
 }
 
 }  // namespace
@@ -382,7 +395,7 @@ void launch_force_nl(Sim &s) {
         hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
                            (const double *)s.y, (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
                            s.fp.A, s.fp.lambda, s.fp.cutoff, (const int *)s.nl, (const int *)s.nl_cnt, s.fsr,
-                           (const StepBase *)s.dbase, (const int *)s.ctl);
+                           (const StepBase *)s.dbase, (const int *)s.ctl, s.period);
     };
     if (s.fp32)
         s.S == 1 ? go(k_force_nl<float, true>) : go(k_force_nl<float, false>);
@@ -395,7 +408,7 @@ void launch_ovl_nl_gather(Sim &s, int k) {
                        (const double *)s.y, (const double *)s.rad, s.L_h[0], (const int *)s.nl,
                        (const int *)s.nl_cnt, (const double *)s.xbuild, (const double *)s.ybuild,
                        s.nl_margin * s.nl_margin, s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol,
-                       s.touched + (size_t)(k & 1) * s.n, s.newpos, s.ctl, s.acc, k);
+                       s.touched + (size_t)(k & 1) * s.n, s.newpos, s.ctl, s.acc, k, s.period);
 }
 
 void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {
@@ -409,7 +422,7 @@ void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {
 void launch_skin_check(Sim &s) {
     const double h = 0.5 * s.fp.skin;
     hipLaunchKernelGGL(k_skin_check, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, s.xbuild, s.ybuild,
-                       h * h, s.ctl + K_NL_REBUILD, (StepBase *)s.dbase);
+                       h * h, s.ctl + K_NL_REBUILD, (StepBase *)s.dbase, s.period);
 }
 
 }  // namespace bd

@@ -169,7 +169,9 @@ int host_dt_all(Sim &s, const double *hx, const double *hy, std::vector<int> &hv
                 ly[nr + k] = hy[f0 + k];
             }
             const int hb = 3 * s.toff_h[r], hr = 3 * (s.toff_h[r + 1] - s.toff_h[r]);
-            if (host_delaunay(vr, lx.data(), ly.data(), lv, lt) != 0 || (int)lv.size() != hr) {
+            const int rc = s.period > 0.0 ? host_torus_delaunay(nr, lx.data(), ly.data(), s.L_h[r], lv, lt)
+                                          : host_delaunay(vr, lx.data(), ly.data(), lv, lt);
+            if (rc != 0 || (int)lv.size() != hr) {
                 failed = 1;
                 continue;
             }
@@ -1384,7 +1386,8 @@ void setup_force(Sim &s) {
     long double pairs = 0;
     for (int r = 0; r < s.R; ++r) pairs += (long double)(s.off_h[r + 1] - s.off_h[r]) * (s.off_h[r + 1] - s.off_h[r]);
     const int dchunk = default_chunk(s);
-    if (pairs < (long double)(1 << 26)) {
+    // a periodic box has its own (minimum-image) kernel in the one-workgroup-per-tile form: fixed rule
+    if (pairs < (long double)(1 << 26) || s.period > 0.0) {
         Tiling t = make_tiling(s, dchunk, 4);
         alloc_force_buffers(s, (long long)t.tiles.size(), t.part_len);
         upload_tiling(s, t, dchunk, 4, 0);
@@ -1555,6 +1558,11 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
     if (p->force_per_lane != 0 && p->force_per_lane != 2 && p->force_per_lane != 4)
         return err = "force_per_lane must be 0, 2 or 4", BD_ERR_INVALID_ARG;
     if (p->force_launch < 0 || p->force_launch > 2) return err = "force_launch must be 0, 1 or 2", BD_ERR_INVALID_ARG;
+    if (p->periodic != 0 && p->periodic != 1) return err = "periodic must be 0 or 1", BD_ERR_INVALID_ARG;
+    if (p->periodic && !(fp->cutoff > 0) && (p->force_chunk < 0 || p->force_launch != 0))
+        return err = "a periodic box evaluates all-pairs forces in the one-workgroup-per-tile form only "
+                     "(force_chunk >= 0, force_launch 0)",
+               BD_ERR_INVALID_ARG;
     if (p->force_launch == 2 && !(fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)))
         return err = "force_launch 2 (j staged in LDS) needs the inverse-square law without cutoff",
                BD_ERR_INVALID_ARG;
@@ -1566,7 +1574,7 @@ int validate_params(const bd_force_params *fp, const bd_params *p, std::string &
 
 // One system: radii, species, positions inside [r, L - r], no overlap.
 int validate_system(int n, const double *xy, const double *radii, const int32_t *species, const double *theta,
-                    double L, int S, std::string &err) {
+                    double L, int S, bool periodic, std::string &err) {
     if (n < 3) return err = "n must be at least 3", BD_ERR_INVALID_ARG;
     if (!finite(L) || !(L > 0)) return err = "box side must be finite and > 0", BD_ERR_INVALID_ARG;
     for (int i = 0; i < n; ++i) {
@@ -1575,25 +1583,45 @@ int validate_system(int n, const double *xy, const double *radii, const int32_t 
             return err = "bad radius or position", BD_ERR_INVALID_ARG;
         if (species[i] < 0 || species[i] >= S) return err = "species out of range", BD_ERR_INVALID_ARG;
         if (theta && !finite(theta[i])) return err = "non-finite theta", BD_ERR_INVALID_ARG;
-        if (x < r || x > L - r || y < r || y > L - r) return err = "disk outside the walls", BD_ERR_BAD_INPUT;
+        if (periodic) {
+            if (x < 0.0 || x >= L || y < 0.0 || y >= L) return err = "disk outside [0, L)^2", BD_ERR_BAD_INPUT;
+        } else if (x < r || x > L - r || y < r || y > L - r) {
+            return err = "disk outside the walls", BD_ERR_BAD_INPUT;
+        }
     }
     // overlap check on a cell grid (cell side >= the largest contact distance)
     double rmax = 0;
     for (int i = 0; i < n; ++i) rmax = std::max(rmax, radii[i]);
     const double cell = 2 * rmax;
     long nc = std::max(1L, std::min(32768L, (long)std::floor(L / cell)));
+    // periodic: separations by the nearest image; neighbouring cells wrap (with fewer than 3 cells a
+    // row, every cell is a neighbour of every other: one cell holds all)
+    if (periodic && nc < 3) nc = 1;
     const double inv = nc / L;
     std::vector<int> head((size_t)nc * nc, -1), nxt(n, -1);
     auto cidx = [&](double v) { long c = (long)(v * inv); return c < 0 ? 0 : (c >= nc ? nc - 1 : c); };
+    const long span = nc == 1 ? 0 : 1;
     for (int i = 0; i < n; ++i) {
         long cx = cidx(xy[2 * i]), cy = cidx(xy[2 * i + 1]);
-        for (long gy = std::max(0L, cy - 1); gy <= std::min(nc - 1, cy + 1); ++gy)
-            for (long gx = std::max(0L, cx - 1); gx <= std::min(nc - 1, cx + 1); ++gx)
+        for (long oy = -span; oy <= span; ++oy)
+            for (long ox = -span; ox <= span; ++ox) {
+                long gy = cy + oy, gx = cx + ox;
+                if (periodic) {
+                    gy = (gy + nc) % nc;
+                    gx = (gx + nc) % nc;
+                } else if (gy < 0 || gy >= nc || gx < 0 || gx >= nc) {
+                    continue;
+                }
                 for (int j = head[gy * nc + gx]; j >= 0; j = nxt[j]) {
                     double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+                    if (periodic) {
+                        dx = bd_min_image(dx, L);
+                        dy = bd_min_image(dy, L);
+                    }
                     if (std::sqrt(dx * dx + dy * dy) < radii[i] + radii[j])
                         return err = "initial disks overlap", BD_ERR_BAD_INPUT;
                 }
+            }
         nxt[i] = head[cy * nc + cx];
         head[cy * nc + cx] = i;
     }
@@ -1608,6 +1636,7 @@ int validate_batch(int R, const int32_t *n_per, const double *xy, const double *
     int rc = validate_params(fp, p, err);
     if (rc != BD_OK) return rc;
     if (R > 1 && fp->cutoff > 0) return err = "short-range forces need one system per handle", BD_ERR_INVALID_ARG;
+    if (R > 1 && p->periodic) return err = "a periodic box needs one system per handle", BD_ERR_INVALID_ARG;
     long long total = 0;
     for (int r = 0; r < R; ++r) {
         if (n_per[r] < 3) return err = "every system needs at least 3 disks", BD_ERR_INVALID_ARG;
@@ -1617,7 +1646,7 @@ int validate_batch(int R, const int32_t *n_per, const double *xy, const double *
     long long off = 0;
     for (int r = 0; r < R; ++r) {
         rc = validate_system(n_per[r], xy + 2 * off, radii + off, species + off, theta ? theta + off : nullptr,
-                             L_per[r], fp->S, err);
+                             L_per[r], fp->S, p->periodic != 0, err);
         if (rc != BD_OK) {
             if (R > 1) err = "system " + std::to_string(r) + ": " + err;
             return rc;
@@ -1680,7 +1709,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     for (int r = 0; r < R; ++r) {
         double rmax = 0.0;
         for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) rmax = std::max(rmax, radii[i]);
-        frame_points(L_per[r], rmax, fxs[r], fys[r]);
+        if (!p->periodic) frame_points(L_per[r], rmax, fxs[r], fys[r]);   // a periodic box has no walls
         s.foff_h[r + 1] = s.foff_h[r] + (int)fxs[r].size();
     }
     s.n = n;
@@ -1688,8 +1717,11 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.nv = n + s.m;
     s.S = fp->S;
     s.toff_h.assign(R + 1, 0);
+    // planar: 2 (disks + frame) - 2 triangles with the infinite vertex; torus (periodic box): 2 n exactly
     for (int r = 0; r < R; ++r)
-        s.toff_h[r + 1] = s.toff_h[r] + 2 * (s.off_h[r + 1] - s.off_h[r] + s.foff_h[r + 1] - s.foff_h[r]) - 2;
+        s.toff_h[r + 1] = s.toff_h[r] + (p->periodic ? 2 * (s.off_h[r + 1] - s.off_h[r])
+                                                     : 2 * (s.off_h[r + 1] - s.off_h[r] + s.foff_h[r + 1] -
+                                                            s.foff_h[r]) - 2);
     s.T = s.toff_h[R];
     s.H = 3 * s.T;
     s.inf = s.nv;
@@ -1702,6 +1734,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     s.kind_fast = (fp->kind == BD_FORCE_POWER && fp->q == 2.0 && !(fp->cutoff > 0)) ? 1 : 0;
     s.use_nl = fp->cutoff > 0;
     s.ovl_method = p->overlap_method;
+    s.period = p->periodic ? L_per[0] : 0.0;
     check(hipGetDevice(&s.device), "hipGetDevice");
     check(hipStreamCreateWithFlags(&s.own_stream, hipStreamNonBlocking), "stream");
     s.stream = s.own_stream;
@@ -1795,6 +1828,10 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
     if (s.use_nl) {
         const double rl = fp->cutoff + fp->skin;
         s.nl_nc = std::max(1, std::min(46000, (int)std::floor(L_per[0] / rl)));
+        if (s.period > 0.0 && s.nl_nc < 3) {
+            s.last_error = "a periodic box needs a side of at least 3 (cutoff + skin) for its cell grid";
+            return BD_ERR_INVALID_ARG;
+        }
         s.nl_ncell = s.nl_nc * s.nl_nc;
         s.cell_count = dalloc<int>(s.nl_ncell + 1);
         s.cell_start = dalloc<int>(s.nl_ncell + 1);
@@ -1966,6 +2003,10 @@ int adjoint_begin(Sim &s, int64_t nsteps, int every) {
     }
     if (s.p.max_dt_halvings > 0) {
         s.last_error = "the adjoint does not cover steps halved after an edge reversal";
+        return BD_ERR_INVALID_ARG;
+    }
+    if (s.period > 0.0) {
+        s.last_error = "the adjoint covers the box with walls only";
         return BD_ERR_INVALID_ARG;
     }
     adj_free(s);
@@ -2412,9 +2453,12 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
             for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) {
                 hx[i] = xy[2 * (size_t)s.perm_h[i]];
                 hy[i] = xy[2 * (size_t)s.perm_h[i] + 1];
-                if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || hx[i] < hr[i] || hx[i] > L - hr[i] ||
-                    hy[i] < hr[i] || hy[i] > L - hr[i]) {
-                    s.last_error = "position outside the walls or not finite";
+                const bool out = s.period > 0.0
+                                     ? (hx[i] < 0.0 || hx[i] >= L || hy[i] < 0.0 || hy[i] >= L)
+                                     : (hx[i] < hr[i] || hx[i] > L - hr[i] || hy[i] < hr[i] || hy[i] > L - hr[i]);
+                if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || out) {
+                    s.last_error = s.period > 0.0 ? "position outside [0, L)^2 or not finite"
+                                                  : "position outside the walls or not finite";
                     return (int)BD_ERR_BAD_INPUT;
                 }
             }

@@ -46,6 +46,7 @@ int main(void) {{
   printf("%zu %zu %zu\\n", offsetof(bd_params, force_chunk), sizeof(bd_force_config),
          offsetof(bd_force_config, tuned_ms));
   printf("%zu %zu\\n", offsetof(bd_params, force_per_lane), offsetof(bd_params, force_launch));
+  printf("%zu %zu\\n", offsetof(bd_params, max_dt_halvings), offsetof(bd_params, periodic));
   return 0;
 }}
 """)
@@ -61,6 +62,7 @@ int main(void) {{
     C = binding.ForceConfig
     assert vals[11:14] == [P.force_chunk.offset, ctypes.sizeof(C), C.tuned_ms.offset]
     assert vals[14:16] == [P.force_per_lane.offset, P.force_launch.offset]
+    assert vals[16:18] == [P.max_dt_halvings.offset, P.periodic.offset]
 
 
 def test_params_default():
@@ -110,6 +112,14 @@ def test_rejects_too_few_disks():
 @pytest.mark.parametrize("kw", [dict(force_chunk=12), dict(force_chunk=512, force_per_lane=3),
                                 dict(force_chunk=512, force_launch=3), dict(force_chunk=-4)])
 def test_rejects_bad_force_form(kw):
+    with pytest.raises(binding.BDError) as e:
+        _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], **kw)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("kw", [dict(periodic=True, force_chunk=-1),   # periodic all pairs: ordinary form only
+                                dict(periodic=True, force_chunk=512, force_launch=1)])
+def test_rejects_unsupported_periodic(kw):
     with pytest.raises(binding.BDError) as e:
         _init([[5.0, 5.0], [9.0, 5.0], [5.0, 12.0]], **kw)
     assert e.value.code == -1
