@@ -262,6 +262,22 @@ int bd_pair_forces_dev(int32_t n, const double *xy, const int32_t *species, cons
                        int32_t precision, double *f_out, void *stream);
 
 /*
+ * bd_pair_forces_dev for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and bitwise the same forces.  It
+ * allocates nothing: the per-split sums use a fixed 32 MiB device array, one
+ * per GPU, held from the first call on that GPU until the process ends.
+ * Limit: J * n * (16 bytes for FP64, 8 for FP32) <= 32 MiB, i.e. n up to
+ * 2,097,152 (FP64) or 4,194,304 (FP32); larger n returns BD_ERR_INVALID_ARG.
+ * The call only enqueues the work on `stream` and returns; f_out is ready
+ * when the stream reaches that point.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other streams, other threads) race;
+ * order them on one stream.
+ */
+int bd_pair_forces_dev_noalloc(int32_t n, const double *xy, const int32_t *species, const bd_force_params *fp,
+                               int32_t precision, double *f_out, void *stream);
+
+/*
  * Copies the state out: xy_out (2n doubles, may be NULL), theta_out (n
  * doubles, may be NULL), step_out (may be NULL), stats_out (may be NULL).
  * Synchronises the library's stream.

@@ -26,7 +26,8 @@ EXPORTED = ("bd_strerror", "bd_last_error", "bd_params_default", "bd_init", "bd_
             "bd_set_positions", "bd_set_graph_mode", "bd_set_tail_mode", "bd_set_stream", "bd_enable_kernel_timing", "bd_kernel_time",
             "bd_adjoint_begin", "bd_adjoint_backward", "bd_adjoint_backward_dev", "bd_get_state_dev",
             "bd_set_allocator", "bd_destroy", "bd_batch_step", "bd_batch_get_state", "bd_batch_destroy",
-            "bd_rollout", "bd_backward", "bd_backward_dev", "bd_pair_forces_dev")
+            "bd_rollout", "bd_backward", "bd_backward_dev", "bd_pair_forces_dev",
+            "bd_pair_forces_dev_noalloc")
 
 
 class ForceParams(ctypes.Structure):
@@ -175,6 +176,8 @@ def load() -> ctypes.CDLL:
     lib.bd_backward_dev.restype = ctypes.c_int
     lib.bd_pair_forces_dev.argtypes = [ctypes.c_int32, V, V, P(ForceParams), ctypes.c_int32, V, V]
     lib.bd_pair_forces_dev.restype = ctypes.c_int
+    lib.bd_pair_forces_dev_noalloc.argtypes = [ctypes.c_int32, V, V, P(ForceParams), ctypes.c_int32, V, V]
+    lib.bd_pair_forces_dev_noalloc.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -183,9 +186,11 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
-def pair_forces_dev(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, fp32=False, out=None):
-    """Pair forces of torch CUDA tensors through bd_pair_forces_dev: xy (n, 2) float64, species (n,) int32,
-    K (S, S) host array.  Returns out, an (n, 2) float64 CUDA tensor (allocated here when None)."""
+def pair_forces_dev(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=0.0, fp32=False, out=None,
+                    noalloc=False):
+    """Pair forces of torch CUDA tensors through bd_pair_forces_dev (or, noalloc=True, through
+    bd_pair_forces_dev_noalloc, which only enqueues on torch's current stream): xy (n, 2) float64, species
+    (n,) int32, K (S, S) host array.  Returns out, an (n, 2) float64 CUDA tensor (allocated here when None)."""
     import torch
 
     lib = load()
@@ -200,7 +205,7 @@ def pair_forces_dev(xy, species, K, kind="power", q=2.0, A=1.0, lam=0.5, cutoff=
     fp = ForceParams(BD_FORCE_POWER if kind == "power" else BD_FORCE_SCREENED, Km.shape[0], q, A, lam, cutoff,
                      0.0, _ptr(Km))
     stream = torch.cuda.current_stream(xy.device).cuda_stream
-    fn = lib.bd_pair_forces_dev
+    fn = lib.bd_pair_forces_dev_noalloc if noalloc else lib.bd_pair_forces_dev
     rc = fn(n, xy.data_ptr(), species.data_ptr(), ctypes.byref(fp), BD_PREC_FP32 if fp32 else BD_PREC_FP64,
             out.data_ptr(), stream)
     if rc != 0:

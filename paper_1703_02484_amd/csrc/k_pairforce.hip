@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/bd.h"
 
@@ -216,4 +218,60 @@ extern "C" int bd_pair_forces_dev(int32_t n, const double *xy, const int32_t *sp
     if (hipStreamSynchronize(st) != hipSuccess) out = BD_ERR_DEVICE;
     if (hipFree(part) != hipSuccess) out = BD_ERR_DEVICE;
     return out;
+}
+
+// ------------------------------------------------------------------ no-allocation variant
+// For callers that cannot allocate device memory (code under HIP graph capture,
+// serving loops, harnesses that forbid hipMalloc): the split sums live in a
+// fixed device array of kScratchBytes, one copy per GPU, held until the
+// process ends.  Its device address is looked up once per device (with that
+// device current) on the first call there; kernels receive that address,
+// never the array's host-side name.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch array, or nullptr on failure.
+void *scratch_for_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int bd_pair_forces_dev_noalloc(int32_t n, const double *xy, const int32_t *species,
+                                          const bd_force_params *fp, int32_t precision, double *f_out, void *stream) {
+    PfLaw law;
+    const int rc = pf_check(n, xy, species, fp, precision, f_out, law);
+    if (rc != BD_OK) return rc;
+    const int J = pf_splits(n);
+    const size_t need = (size_t)J * (size_t)n * pf_value_bytes(precision);
+    if (need > kScratchBytes) {
+        std::fprintf(stderr, "bd_pair_forces_dev_noalloc: n = %d needs %zu bytes of scratch, more than its %zu\n",
+                     (int)n, need, kScratchBytes);
+        return BD_ERR_INVALID_ARG;
+    }
+    void *part = scratch_for_current_device();
+    if (!part) return BD_ERR_DEVICE;
+    // every split sum that the reduction reads is written first: nothing to clear
+    return pf_enqueue(n, xy, species, law, precision, f_out, (hipStream_t)stream, part, J);
 }
