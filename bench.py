@@ -315,6 +315,11 @@ def run_adjoint():
             "adjoint_flops_per_pair": 28, "overlap_rounds_forward": st["overlap_rounds_total"]}
 
 
+def _progress(msg):
+    """One line per finished or started part, on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def host_cpu():
     """Model name of the host CPU and the logical CPUs this process may use."""
     model = "unknown"
@@ -355,8 +360,9 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch kernel by kernel instead of replaying graphs")
-    ap.add_argument("--tail-mode", type=int, default=-1, choices=[-1, 0, 1],
-                    help="overlap rounds: 0 one launch per phase, 1 one workgroup, -1 automatic")
+    ap.add_argument("--tail-mode", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="overlap rounds: 0 one launch per phase, 1 one workgroup, 2 large phases launched and the "
+                         "rest in one workgroup, -1 automatic")
     ap.add_argument("--no-short-range", action="store_true", help="skip the secondary N=1M Verlet measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the secondary 256-system batched measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the secondary gradient measurement")
@@ -477,15 +483,21 @@ def main():
             "frac_of_nonpacked": achieved / PEAK_FP32_NONPACKED if w.fp32_forces else None,
         },
     }
+    _progress(f"main workload done: {ms_per_step:.3f} ms/step")
     if not args.no_short_range and args.workload == "C2":
+        _progress("short-range workload")
         out["short_range"] = run_short_range(max(10, args.steps // 4), 20)
     if not args.no_batched and args.workload == "C2":
+        _progress("batched workload")
         out["batched"] = run_batched(max(5, args.steps // 20), 2, max(2, args.steps // 100))
     if not args.no_adjoint and args.workload == "C2":
+        _progress("adjoint workload")
         out["adjoint"] = run_adjoint()
     if not args.no_ablation and args.workload == "C2":
+        _progress("force ablation")
         out["ablation"] = run_ablation(max(5, args.steps // 20))
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 

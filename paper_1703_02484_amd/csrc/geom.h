@@ -107,6 +107,26 @@ BD_HD int bd_flip_rule(int a, int b, int c, int d, int inf, const double *x, con
     return bd_flip_rule_quad(x[a], y[a], x[b], y[b], x[c], y[c], x[d], y[d], allow_inversion, inverted);
 }
 
+// bd_flip_rule with the four positions already loaded (an infinite vertex's
+// coordinates are never read).
+BD_HD int bd_flip_rule_xy(int a, int b, int c, int d, int inf, double ax, double ay, double bx, double by, double cx,
+                          double cy, double dx, double dy, bool allow_inversion, bool *inverted = nullptr) {
+    if (inverted) *inverted = false;
+    if (b >= inf) return bd_orient(dx, dy, ax, ay, cx, cy) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
+    if (a >= inf) return bd_orient(cx, cy, bx, by, dx, dy) < 0.0 ? BD_FLIP_INVERSION : BD_NOFLIP;
+    if (c >= inf) {
+        bool bad = bd_orient(bx, by, ax, ay, dx, dy) < 0.0;
+        if (inverted) *inverted = bad;
+        return bad ? BD_FLIP_INVERSION : BD_NOFLIP;
+    }
+    if (d >= inf) {
+        bool bad = bd_orient(ax, ay, bx, by, cx, cy) < 0.0;
+        if (inverted) *inverted = bad;
+        return bad ? BD_FLIP_INVERSION : BD_NOFLIP;
+    }
+    return bd_flip_rule_quad(ax, ay, bx, by, cx, cy, dx, dy, allow_inversion, inverted);
+}
+
 // Hard walls: reflect about the shifted wall [r, L - r], then clamp.
 BD_HD double bd_wall(double c, double r, double L) {
 #pragma clang fp contract(off)

@@ -473,6 +473,18 @@ __device__ __forceinline__ void box_muller(uint4 w, double &z0, double &z1) {
     z1 = rho * sin(ang);
 }
 
+// The first of the two normals of box_muller alone (same operations, same value).
+__device__ __forceinline__ double box_muller_first(uint4 w) {
+#pragma clang fp contract(off)
+    unsigned long long m1 = ((((unsigned long long)w.x) << 32) | w.y) >> 11;
+    unsigned long long m2 = ((((unsigned long long)w.z) << 32) | w.w) >> 11;
+    double u1 = ((double)m1 + 1.0) * 0x1.0p-53;
+    double u2 = (double)m2 * 0x1.0p-53;
+    double rho = sqrt(-2.0 * log(u1));
+    double ang = 2.0 * M_PI * u2;
+    return rho * cos(ang);
+}
+
 struct EmArgs {
     int n, S;
     double dt, amp, amp_r, v0, clip;
@@ -516,9 +528,12 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         const unsigned slo = (unsigned)step;
         const unsigned shi = (unsigned)(step >> 32);
         const uint2 key = make_uint2((unsigned)ri.seed, (unsigned)(ri.seed >> 32));
-        double zx, zy, nr, unused;
+        // without rotational diffusion (Dr = 0) the angle never changes and its draw is not needed;
+        // without self-propulsion (v0 = 0) the angle does not enter the move
+        const bool rot = a.Dr != 0.0;
+        double zx, zy;
         box_muller(philox10(make_uint4(id, slo, shi, 0u), key), zx, zy);
-        box_muller(philox10(make_uint4(id, slo, shi, 1u), key), nr, unused);
+        const double nr = rot ? box_muller_first(philox10(make_uint4(id, slo, shi, 1u), key)) : 0.0;
         if (zx > a.clip) { zx = a.clip; ++clamps; }
         if (zx < -a.clip) { zx = -a.clip; ++clamps; }
         if (zy > a.clip) { zy = a.clip; ++clamps; }
@@ -532,9 +547,9 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         for (int lv = 1; lv <= a.level; ++lv) {
             const unsigned par = a.index >> (a.level - lv + 1), side = (a.index >> (a.level - lv)) & 1u;
             const unsigned skey = 0x80000000u | ((unsigned)lv << 24) | (par << 1);
-            double ex, ey, er;
+            double ex, ey;
             box_muller(philox10(make_uint4(id, slo, shi, skey), key), ex, ey);
-            box_muller(philox10(make_uint4(id, slo, shi, skey | 1u), key), er, unused);
+            const double er = rot ? box_muller_first(philox10(make_uint4(id, slo, shi, skey | 1u), key)) : 0.0;
             ex = ex > a.clip ? a.clip : (ex < -a.clip ? -a.clip : ex);
             ey = ey > a.clip ? a.clip : (ey < -a.clip ? -a.clip : ey);
             const double at = sqrt(0.5 * a.D * hsub), ar = sqrt(0.5 * a.Dr * hsub);
@@ -545,21 +560,22 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
             hsub = 0.5 * hsub;
         }
         if (a.level > 0) clamps = 0;   // the step's own draws were counted when it was first tried
-        const double x0 = x[i], y0 = y[i], t0 = th[i], r = rad[i];
-        const double vx = fx + a.v0 * cos(t0);
-        const double vy = fy + a.v0 * sin(t0);
+        const bool angle = rot || a.v0 != 0.0;
+        const double x0 = x[i], y0 = y[i], t0 = angle ? th[i] : 0.0, r = rad[i];
+        const double vx = a.v0 != 0.0 ? fx + a.v0 * cos(t0) : fx;
+        const double vy = a.v0 != 0.0 ? fy + a.v0 * sin(t0) : fy;
         const double xn = x0 + vx * hsub + wx;
         const double yn = y0 + vy * hsub + wy;
         xo[i] = x0;
         yo[i] = y0;
-        tho[i] = t0;
+        if (rot) tho[i] = t0;
         x[i] = a.periodic ? bd_wrap(xn, ri.L) : bd_wall(xn, r, ri.L);
         y[i] = a.periodic ? bd_wrap(yn, ri.L) : bd_wall(yn, r, ri.L);
         if (wf) {   // adjoint tape: wall slopes of this move
             wf[2 * (size_t)i] = bd_wall_slope(xn, r, ri.L);
             wf[2 * (size_t)i + 1] = bd_wall_slope(yn, r, ri.L);
         }
-        th[i] = t0 + wt;
+        if (rot) th[i] = t0 + wt;
     }
     // one atomic per wavefront (every lane is here)
     for (int off = 32; off > 0; off >>= 1) clamps += __shfl_xor(clamps, off);

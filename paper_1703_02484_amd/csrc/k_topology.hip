@@ -292,11 +292,30 @@ __device__ __forceinline__ bool adjacent(const Topo &t, int c, int d) {
     return false;
 }
 
+// The flip decision `rule` for the canonical edge h (twin tw, opposite vertices
+// c and d): count an inverted quad; a flipping edge becomes a candidate of
+// round slot `slot` and claims its two triangles.
+__device__ __forceinline__ void register_flip(const Topo &t, int h, int tw, int c, int d, int rule, bool inverted,
+                                              int round, int slot) {
+    wave_count(&t.ctl[K_INVQ + slot], inverted);
+    if (rule == BD_NOFLIP) return;
+    if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
+        // blocked for now (c-d may disappear in this very round): look again next round
+        push_edge(t, h, round + 1, slot + 1 == MAXR ? 0 : slot + 1);
+        return;
+    }
+    const int t1 = h / 3, t2 = tw / 3;
+    const int pos = wave_reserve(&t.ctl[K_CAND + slot], true);
+    t.cand[pos] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
+    const unsigned long long key = claim_key(round, h);
+    atomicMax(&t.claim[t1], key);
+    atomicMax(&t.claim[t2], key);
+}
+
 // Evaluates the canonical edge h (h < twin) and, if it must flip, registers
 // it as a candidate of round slot `slot` and claims its two triangles.
 __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, int reversal) {
     if (bad_he(t, tw)) return topo_err(t);
-    const int t1 = h / 3, t2 = tw / 3;
     const int a = t.he_v[h], b = t.he_v[bd_next(h)], c = t.he_v[bd_prev(h)];
     const int d = t.he_v[bd_prev(tw)];
     if (bad_v(t, a) || bad_v(t, b) || bad_v(t, c) || bad_v(t, d)) return topo_err(t);
@@ -313,29 +332,83 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
     }
     bool inverted = false;
     const int rule = flip_rule_of(t, a, b, c, d, &inverted);
-    wave_count(&t.ctl[K_INVQ + slot], inverted);
-    if (rule == BD_NOFLIP) return;
-    if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
-        // blocked for now (c-d may disappear in this very round): look again next round
-        push_edge(t, h, round + 1, slot + 1 == MAXR ? 0 : slot + 1);
-        return;
-    }
-    const int pos = wave_reserve(&t.ctl[K_CAND + slot], true);
-    t.cand[pos] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
-    const unsigned long long key = claim_key(round, h);
-    atomicMax(&t.claim[t1], key);
-    atomicMax(&t.claim[t2], key);
+    register_flip(t, h, tw, c, d, rule, inverted, round, slot);
 }
 
+// Full evaluation after a move: one thread per triangle.  The triangle's three
+// vertices and their positions are read once for its canonical edges (h <
+// twin), and the far vertices of those edges are read together, so a thread
+// issues its loads in three dependent waves instead of one chain per edge.
+// The decisions are those of eval_edge.
 __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
     if (stopped(t.ctl)) return;
     round += t.base->rbase;
     for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
+        const int h0 = 3 * tri;
+        int v[3], tw[3], d[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            int h = 3 * tri + k;
-            int tw = t.he_twin[h];
-            if (h < tw) eval_edge(t, h, tw, round, slot, reversal);
+            v[k] = t.he_v[h0 + k];
+            tw[k] = t.he_twin[h0 + k];
+        }
+        bool own[3], ok = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            own[k] = h0 + k < tw[k];
+            if (own[k] && bad_he(t, tw[k])) own[k] = false, ok = false;
+            d[k] = own[k] ? t.he_v[bd_prev(tw[k])] : v[k];
+            if (bad_v(t, v[k]) || bad_v(t, d[k])) ok = false;
+        }
+        if (!ok) {
+            topo_err(t);
+            continue;
+        }
+        double px[3], py[3], qx[3], qy[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            px[k] = t.x[v[k]];
+            py[k] = t.y[v[k]];
+            qx[k] = t.x[d[k]];
+            qy[k] = t.y[d[k]];
+        }
+        if (reversal) {
+            double ox[3], oy[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ox[k] = t.xo[v[k]];
+                oy[k] = t.yo[v[k]];
+            }
+            // Sec. 4.3: the pair passed through each other if the edge vector reversed
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int k1 = k == 2 ? 0 : k + 1;
+                bool rev = false;
+                if (own[k] && v[k] < t.n && v[k1] < t.n) {
+                    const double rx = sep_p(ox[k1] - ox[k], t.P), ry = sep_p(oy[k1] - oy[k], t.P);
+                    const double mx = sep_p(px[k1] - px[k], t.P), my = sep_p(py[k1] - py[k], t.P);
+                    rev = rx * mx + ry * my < 0.0;
+                }
+                wave_count64(&t.acc[A_REVERSALS], rev);
+                if (reversal == 2) wave_count(&t.ctl[K_REV], rev);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!own[k]) continue;
+            const int k1 = k == 2 ? 0 : k + 1, k2 = k == 0 ? 2 : k - 1;
+            const int a = v[k], b = v[k1], c = v[k2];
+            bool inverted = false;
+            int rule;
+            if (t.P > 0.0) {
+                const double ax = px[k], ay = py[k];
+                rule = bd_flip_rule_quad(0.0, 0.0, sep_p(px[k1] - ax, t.P), sep_p(py[k1] - ay, t.P),
+                                         sep_p(px[k2] - ax, t.P), sep_p(py[k2] - ay, t.P), sep_p(qx[k] - ax, t.P),
+                                         sep_p(qy[k] - ay, t.P), true, &inverted);
+            } else {
+                rule = bd_flip_rule_xy(a, b, c, d[k], t.inf, px[k], py[k], px[k1], py[k1], px[k2], py[k2], qx[k],
+                                       qy[k], true, &inverted);
+            }
+            register_flip(t, h0 + k, tw[k], c, d[k], rule, inverted, round, slot);
         }
     }
 }
@@ -663,21 +736,45 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
     for (int t0 = blockIdx.x * kDetBlock; t0 < t.T; t0 += gridDim.x * kDetBlock) {   // same trip count for the workgroup
         const int tri = t0 + threadIdx.x;
         if (tri < t.T) {
-            if (vrep >= 0) validate_tri(t, tri, &inv);
+            // the triangle's vertices, positions and radii read once for its validation and its
+            // canonical edges
+            int v[3], tw[3];
+            double px[3], py[3], pr[3];
+            bool ok = true;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                v[e] = t.he_v[3 * tri + e];
+                tw[e] = t.he_twin[3 * tri + e];
+                if (bad_v(t, v[e])) ok = false;
+            }
+            if (!ok) topo_err(t);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const bool fin = ok && v[e] < t.inf;
+                px[e] = fin ? t.x[v[e]] : 0.0;
+                py[e] = fin ? t.y[v[e]] : 0.0;
+                pr[e] = fin ? t.rad[v[e]] : 0.0;
+            }
+            if (vrep >= 0) {   // as validate_tri
+                if (!ok) {
+                    atomicAdd(&inv, 1);
+                } else if (v[0] < t.inf && v[1] < t.inf && v[2] < t.inf) {
+                    const double o = t.P > 0.0 ? bd_orient(0.0, 0.0, sep_p(px[1] - px[0], t.P), sep_p(py[1] - py[0], t.P),
+                                                           sep_p(px[2] - px[0], t.P), sep_p(py[2] - py[0], t.P))
+                                               : bd_orient(px[0], py[0], px[1], py[1], px[2], py[2]);
+                    if (o <= 0.0) atomicAdd(&inv, 1);
+                }
+            }
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
                 const int h = 3 * tri + e;
-                const int tw = t.he_twin[h];
-                if (h > tw) continue;
-                const int a = t.he_v[h], b = t.he_v[bd_next(h)];
-                if (bad_v(t, a) || bad_v(t, b)) {
-                    topo_err(t);
-                    continue;
-                }
-                if (a >= t.n || b >= t.n) continue;   // frame points and the infinite vertex never overlap
-                const double dx = sep_p(t.x[a] - t.x[b], t.P), dy = sep_p(t.y[a] - t.y[b], t.P);
+                const int e1 = e == 2 ? 0 : e + 1;
+                if (!ok || h > tw[e]) continue;
+                const int a = v[e], b = v[e1];
+                if (a >= t.n || b >= t.n) continue;
+                const double dx = sep_p(px[e] - px[e1], t.P), dy = sep_p(py[e] - py[e1], t.P);
                 const double d = sqrt(dx * dx + dy * dy);
-                if (d < (t.rad[a] + t.rad[b]) * keep) {
+                if (d < (pr[e] + pr[e1]) * keep) {
                     ++found;
                     const bool fa = atomicExch(&t.vstamp[a], stamp) != stamp;
                     const bool fb = atomicExch(&t.vstamp[b], stamp) != stamp;
