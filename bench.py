@@ -34,9 +34,9 @@ PEAK_FP64_TFLOPS = 78.6
 # (FETCH_SIZE, WRITE_SIZE), each scaled by the same counter's reading for a plain
 # 1 GiB copy; valid only for the force kernel's source it was measured on (sha1 of
 # the force section of k_particles.hip, see force_source_sha1).
-MEASURED_TRAFFIC = {"sha1": "8870e362d2e8ecd5129e68e70c2f28629f2b9428", "workload": "C2", "n": 65536,
+MEASURED_TRAFFIC = {"sha1": "6bb720c9c1b32473e48c7b3a46cc513746b3524c", "workload": "C2", "n": 65536,
                     "force_config": {"chunk": 1024, "per_lane": 4, "persistent": 2},
-                    "bytes_per_launch": 38070172.9}
+                    "bytes_per_launch": 2.0 * 2205.0 * 1024 + 1.0 * 32768.0 * 1024}
 
 
 FORCE_KERNELS = {0: "k_force", 1: "k_force_queue", 2: "k_force_sym"}

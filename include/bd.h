@@ -340,9 +340,11 @@ int bd_set_graph_mode(bd_sim *sim, int enable);
  * How the overlap rounds of a step after its first detection are launched:
  * mode 0 one launch per phase (detection, gather, apply, each flip-round
  * phase, validation), mode 1 all of them in one workgroup separated by
- * barriers, -1 (default) the library's choice: one workgroup for handles of
- * at most 32,768 disks (measured faster on 16,384), else one launch per phase
- * (faster on 65,536 and more).  Results are identical.
+ * barriers, mode 2 the first flip rounds of each repair and the overlap
+ * rounds that recently queued many disks launched per phase and the rest in
+ * one workgroup, -1 (default) the library's choice: mode 1 for handles of at
+ * most 32,768 disks (measured faster on 16,384), else mode 2 (faster on
+ * 65,536 and on 1M).  Results are identical.
  */
 int bd_set_tail_mode(bd_sim *sim, int mode);
 

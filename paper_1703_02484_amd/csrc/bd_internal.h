@@ -65,8 +65,28 @@ enum Acc {
     A_NOISE_CLAMPS = 3,
     A_CAP_HITS = 4,
     A_OVL_EDGES = 5,
-    N_ACC = 8
+    // the noise clamps of the update (a few thousand per step on 1M disks) go to A_CLAMP_SLOTS
+    // counters on separate 128-byte lines, chosen by workgroup: updates of one address from every
+    // CU serialise; the host adds the slots
+    A_CLAMP_BASE = 16,
+    A_CLAMP_SLOTS = 64,
+    A_CLAMP_STRIDE = 16,
+    N_ACC = A_CLAMP_BASE + A_CLAMP_SLOTS * A_CLAMP_STRIDE
 };
+
+// Workgroups are dealt to the 8 XCDs of the device round-robin (XCD = block id mod
+// 8) and every XCD has its own L2.  This workgroup index gives the workgroups of
+// one XCD a contiguous range of the grid (a bijection of [0, gridDim.x)), so
+// neighbouring items -- triangles and disks that share vertices and neighbours
+// in the library's Hilbert order -- are read through one L2 instead of eight.
+#ifdef __HIPCC__
+__device__ __forceinline__ int xcd_block() {
+    constexpr int kXcd = 8;
+    const int b = (int)blockIdx.x, nb = (int)gridDim.x;
+    const int q = nb / kXcd, r = nb % kXcd, x = b % kXcd;
+    return x * q + (x < r ? x : r) + b / kXcd;
+}
+#endif
 
 // One workgroup of the all-pairs force: sorted i range [i0, i1) (at most
 // 256 * per_lane) against the sorted j range [js, je) of one species of the same
@@ -145,7 +165,7 @@ struct Checkpoint {
     int *he_v = nullptr, *he_twin = nullptr, *vert_he = nullptr;
     int64_t step = 0;
     bd_stats st{};
-    unsigned long long acc[8] = {};
+    unsigned long long acc[N_ACC] = {};
     Budgets budgets;
 };
 
@@ -283,6 +303,10 @@ struct Sim {
     int multi_em = 2;                // mode 2: flip rounds of the move's repair launched on many workgroups
     int multi_ovl = 1;               // mode 2: the same for the repair after an overlap round
     int ovl_phase = 1;               // mode 2: overlap rounds launched per phase before the one-workgroup tail
+                                     // (1 + the leading later rounds that recently queued many disks)
+    int touch_hi[MAXO] = {};         // most disks queued by overlap round j in the current window of steps
+    int touch_prev[MAXO] = {};       // the same over the previous window
+    int touch_steps = 0;             // steps in the current window
     struct StepGraph {
         hipGraphExec_t pre = nullptr, force = nullptr, post = nullptr;
         int r_used = 0, v_used = 0;

@@ -577,9 +577,15 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         }
         if (rot) th[i] = t0 + wt;
     }
-    // one atomic per wavefront (every lane is here)
+    // one atomic per workgroup (every thread is here), on the workgroup's clamp slot
+    __shared__ int wg_clamps;
+    if (threadIdx.x == 0) wg_clamps = 0;
     for (int off = 32; off > 0; off >>= 1) clamps += __shfl_xor(clamps, off);
-    if (__lane_id() == 0 && clamps) atomicAdd(&acc[A_NOISE_CLAMPS], (unsigned long long)clamps);
+    __syncthreads();
+    if (__lane_id() == 0 && clamps) atomicAdd(&wg_clamps, clamps);
+    __syncthreads();
+    if (threadIdx.x == 0 && wg_clamps)
+        atomicAdd(&acc[A_CLAMP_BASE + (blockIdx.x % A_CLAMP_SLOTS) * A_CLAMP_STRIDE], (unsigned long long)wg_clamps);
 }
 
 template <typename T2>
@@ -613,24 +619,21 @@ __global__ void k_step_begin(int *__restrict__ ctl, StepBase *__restrict__ base)
     }
 }
 
-// End of a queued step: record its control block in the ring (this kernel),
-// then either advance the step counter and the stamp bases, or stop the
-// batch when the step halted (the host finishes it) or the ring is full
-// (k_step_advance).
-__global__ void k_step_record(const int *__restrict__ ctl, const StepBase *__restrict__ base,
-                              int *__restrict__ ring) {
-    if (base->stop) return;
+// End of a queued step, one workgroup: record its control block in the ring,
+// then (after a barrier: every thread has read the step base) either advance
+// the step counter and the stamp bases, or stop the batch when the step halted
+// (the host finishes it) or the ring is full.
+__global__ void k_step_end(const int *__restrict__ ctl, StepBase *__restrict__ base, int *__restrict__ ring,
+                           int r_used, int v_used) {
+    if (base->stop) return;   // uniform: written by this kernel only after the barrier below
     const int idx = base->batch_idx;
     for (int i = threadIdx.x; i < N_CTL; i += blockDim.x) ring[(size_t)idx * N_CTL + i] = ctl[i];
-}
-
-__global__ void k_step_advance(const int *__restrict__ ctl, StepBase *__restrict__ base, int r_used, int v_used) {
-    if (threadIdx.x != 0 || base->stop) return;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     if (ctl[K_HALT]) {
         base->stop = 1;
         return;
     }
-    const int idx = base->batch_idx;
     base->step += 1;
     base->rbase += r_used;
     base->vbase += v_used;
@@ -645,9 +648,8 @@ void launch_step_begin(Sim &s) {
 }
 
 void launch_step_end(Sim &s, int r_used, int v_used) {
-    hipLaunchKernelGGL(k_step_record, dim3(1), dim3(256), 0, s.stream, (const int *)s.ctl,
-                       (const StepBase *)s.dbase, s.ring);
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s.stream, (const int *)s.ctl, s.dbase, r_used, v_used);
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s.stream, (const int *)s.ctl, s.dbase, s.ring, r_used,
+                       v_used);
 }
 
 void launch_cast(Sim &s) {

@@ -292,11 +292,23 @@ __device__ __forceinline__ bool adjacent(const Topo &t, int c, int d) {
     return false;
 }
 
+// Workgroup staging of flip candidates (LDS), for the full evaluation: lanes
+// take stage positions with one LDS atomic per wavefront; at the end the
+// workgroup reserves its candidates in the round's list with one atomic and
+// copies them out (same-address atomics from every CU serialise).  Candidates
+// beyond the stage's capacity go to the list directly.
+template <int CAP>
+struct CandStage {
+    int2 buf[CAP];
+    int cnt, base;
+};
+
 // The flip decision `rule` for the canonical edge h (twin tw, opposite vertices
 // c and d): count an inverted quad; a flipping edge becomes a candidate of
 // round slot `slot` and claims its two triangles.
+template <int CAP = 1>
 __device__ __forceinline__ void register_flip(const Topo &t, int h, int tw, int c, int d, int rule, bool inverted,
-                                              int round, int slot) {
+                                              int round, int slot, CandStage<CAP> *st = nullptr) {
     wave_count(&t.ctl[K_INVQ + slot], inverted);
     if (rule == BD_NOFLIP) return;
     if (c < t.inf ? adjacent(t, c, d) : adjacent(t, d, c)) {
@@ -305,8 +317,16 @@ __device__ __forceinline__ void register_flip(const Topo &t, int h, int tw, int 
         return;
     }
     const int t1 = h / 3, t2 = tw / 3;
-    const int pos = wave_reserve(&t.ctl[K_CAND + slot], true);
-    t.cand[pos] = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
+    const int2 cand = make_int2(h, t2 | (rule == BD_FLIP_INVERSION ? (int)0x80000000 : 0));
+    if (st) {
+        const int p = wave_reserve(&st->cnt, true);
+        if (p < CAP)
+            st->buf[p] = cand;
+        else
+            t.cand[atomicAdd(&t.ctl[K_CAND + slot], 1)] = cand;
+    } else {
+        t.cand[wave_reserve(&t.ctl[K_CAND + slot], true)] = cand;
+    }
     const unsigned long long key = claim_key(round, h);
     atomicMax(&t.claim[t1], key);
     atomicMax(&t.claim[t2], key);
@@ -314,7 +334,9 @@ __device__ __forceinline__ void register_flip(const Topo &t, int h, int tw, int 
 
 // Evaluates the canonical edge h (h < twin) and, if it must flip, registers
 // it as a candidate of round slot `slot` and claims its two triangles.
-__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, int reversal) {
+template <int CAP = 1>
+__device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int round, int slot, int reversal,
+                                          CandStage<CAP> *st = nullptr) {
     if (bad_he(t, tw)) return topo_err(t);
     const int a = t.he_v[h], b = t.he_v[bd_next(h)], c = t.he_v[bd_prev(h)];
     const int d = t.he_v[bd_prev(tw)];
@@ -332,7 +354,7 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
     }
     bool inverted = false;
     const int rule = flip_rule_of(t, a, b, c, d, &inverted);
-    register_flip(t, h, tw, c, d, rule, inverted, round, slot);
+    register_flip<CAP>(t, h, tw, c, d, rule, inverted, round, slot, st);
 }
 
 // Full evaluation after a move: one thread per triangle.  The triangle's three
@@ -340,10 +362,26 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
 // twin), and the far vertices of those edges are read together, so a thread
 // issues its loads in three dependent waves instead of one chain per edge.
 // The decisions are those of eval_edge.
-__global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
-    if (stopped(t.ctl)) return;
+constexpr int kEvalStage = 2048;
+
+// Every thread of the workgroup calls it once, at the end: the staged
+// candidates are reserved in the round's list with one atomic and copied out.
+template <int CAP>
+__device__ __forceinline__ void cand_flush(const Topo &t, int slot, CandStage<CAP> &st) {
+    __syncthreads();
+    const int n = st.cnt < CAP ? st.cnt : CAP;
+    if (threadIdx.x == 0 && n > 0) st.base = atomicAdd(&t.ctl[K_CAND + slot], n);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t.cand[st.base + i] = st.buf[i];
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
+    __shared__ CandStage<kEvalStage> st;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
+    if (threadIdx.x == 0) st.cnt = 0;
+    __syncthreads();
     round += t.base->rbase;
-    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
+    for (int tri = xcd_block() * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x) {
         const int h0 = 3 * tri;
         int v[3], tw[3], d[3];
 #pragma unroll
@@ -408,12 +446,15 @@ __global__ void k_flip_eval_full(Topo t, int round, int slot, int reversal) {
                 rule = bd_flip_rule_xy(a, b, c, d[k], t.inf, px[k], py[k], px[k1], py[k1], px[k2], py[k2], qx[k],
                                        qy[k], true, &inverted);
             }
-            register_flip(t, h0 + k, tw[k], c, d[k], rule, inverted, round, slot);
+            register_flip<kEvalStage>(t, h0 + k, tw[k], c, d[k], rule, inverted, round, slot, &st);
         }
     }
+    cand_flush(t, slot, st);
 }
 
-__device__ __forceinline__ void flip_eval_list_body(const Topo &t, int round, int slot, int i0, int stride) {
+template <int CAP = 1>
+__device__ __forceinline__ void flip_eval_list_body(const Topo &t, int round, int slot, int i0, int stride,
+                                                    CandStage<CAP> *st = nullptr) {
     if (stopped(t.ctl)) return;
     round += t.base->rbase;
     const int count = t.ctl[K_WL + slot];
@@ -434,12 +475,18 @@ __device__ __forceinline__ void flip_eval_list_body(const Topo &t, int round, in
             h = tw;
             tw = s;
         }
-        eval_edge(t, h, tw, round, slot, 0);
+        eval_edge<CAP>(t, h, tw, round, slot, 0, st);
     }
 }
 
 __global__ void k_flip_eval_list(Topo t, int round, int slot) {
-    flip_eval_list_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    __shared__ CandStage<kEvalStage> st;
+    if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
+    if (threadIdx.x == 0) st.cnt = 0;
+    __syncthreads();
+    flip_eval_list_body<kEvalStage>(t, round, slot, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x,
+                                    &st);
+    cand_flush(t, slot, st);
 }
 
 __device__ __forceinline__ void flip_apply_body(const Topo &t, int round, int slot, int i0, int stride) {
@@ -514,7 +561,7 @@ __device__ __forceinline__ void flip_apply_body(const Topo &t, int round, int sl
 }
 
 __global__ void k_flip_apply(Topo t, int round, int slot) {
-    flip_apply_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    flip_apply_body(t, round, slot, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 template <int CAP = 1>
@@ -566,7 +613,7 @@ __global__ void k_flip_fix(Topo t, int round, int slot) {
     __shared__ Stage<kFixStage> st;
     if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
     stage_init(st);
-    flip_fix_body(t, round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
+    flip_fix_body(t, round, slot, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
     const int nslot = slot + 1 == MAXR ? 0 : slot + 1;
     stage_flush(st, &t.ctl[K_WL + nslot], wl_of(t, nslot));
 }
@@ -659,7 +706,7 @@ __global__ __launch_bounds__(kScanBlock) void k_validate(Topo t, int rep, int la
     if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags: uniform
     if (threadIdx.x == 0) inv = 0;
     __syncthreads();
-    for (int tri = blockIdx.x * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x)
+    for (int tri = xcd_block() * blockDim.x + threadIdx.x; tri < t.T; tri += gridDim.x * blockDim.x)
         validate_tri(t, tri, &inv);
     const bool added = add_block_count(&t.ctl[K_INV + rep], &inv);
     if (last >= 0 && last_workgroup(t.ctl, added) && threadIdx.x == 0) repair_check_body(t.ctl, rep, last);
@@ -670,7 +717,7 @@ __global__ void k_validate_local(Topo t, int rep, int k, int last) {
     if (stopped(t.ctl)) return;
     if (threadIdx.x == 0) inv = 0;
     __syncthreads();
-    validate_local_body(t, &inv, k, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    validate_local_body(t, &inv, k, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
     const bool added = add_block_count(&t.ctl[K_INV + rep], &inv);
     if (last >= 0 && last_workgroup(t.ctl, added) && threadIdx.x == 0) repair_check_body(t.ctl, rep, last);
 }
@@ -679,8 +726,20 @@ __global__ void k_validate_local(Topo t, int rep, int k, int last) {
 // Detect: every Delaunay edge between two disks with d < (r_i + r_j)(1 - tol)
 // (Algorithm 2 test, Sec. 2.3 contact distance); both ends are queued once
 // per round.
-__device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, int k) {
+// Queues disk v for overlap round k once per stamp; with a workgroup stage the
+// position is taken in LDS (the stage is copied out at the end of the launch).
+template <int CAP = 1>
+__device__ __forceinline__ void mark_touched(const Topo &t, int v, int stamp, int k, Stage<CAP> *st = nullptr) {
     const bool fresh = atomicExch(&t.vstamp[v], stamp) != stamp;
+    if (st) {
+        const int pos = wave_reserve(&st->cnt, fresh);
+        if (!fresh) return;
+        if (pos < CAP)
+            st->buf[pos] = v;
+        else
+            touched_of(t, k)[atomicAdd(&t.ctl[K_TOUCH + k], 1)] = v;
+        return;
+    }
     const int pos = wave_reserve(&t.ctl[K_TOUCH + k], fresh);
     if (fresh) touched_of(t, k)[pos] = v;
 }
@@ -733,7 +792,7 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
     }
     __syncthreads();
     int found = 0;
-    for (int t0 = blockIdx.x * kDetBlock; t0 < t.T; t0 += gridDim.x * kDetBlock) {   // same trip count for the workgroup
+    for (int t0 = xcd_block() * kDetBlock; t0 < t.T; t0 += gridDim.x * kDetBlock) {   // same trip count for the workgroup
         const int tri = t0 + threadIdx.x;
         if (tri < t.T) {
             // the triangle's vertices, positions and radii read once for its validation and its
@@ -810,7 +869,9 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
 // that detection created it; every other edge was tested then and neither of
 // its disks has moved.  So only the stars of the disks moved by round kprev
 // and the flipped list are tested, each edge once (det_stamp).
-__device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, double keep, int k, int &found) {
+template <int CAP = 1>
+__device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, double keep, int k, int &found,
+                                            Stage<CAP> *st = nullptr) {
     const int tw = t.he_twin[h];
     if (bad_he(t, tw)) return topo_err(t);
     const int e = h < tw ? h : tw;
@@ -822,8 +883,8 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     const double d = sqrt(dx * dx + dy * dy);
     if (d < (t.rad[a] + t.rad[b]) * keep) {
         ++found;
-        mark_touched(t, a, stamp, k);
-        mark_touched(t, b, stamp, k);
+        mark_touched(t, a, stamp, k, st);
+        mark_touched(t, b, stamp, k, st);
     }
 }
 
@@ -876,8 +937,9 @@ __device__ __forceinline__ int ovl_detect_local_body(const Topo &t, int stamp, d
 // Body: inv is the repair's invalid-triangle counter, or a workgroup's share
 // of it in LDS; the stamp st is absolute.  Returns the overlapping edges this thread found (the caller adds them
 // to K_OVL + knew).
+template <int CAP = 1>
 __device__ __forceinline__ int validate_detect_local_body(const Topo &t, int *inv, int k, int st, double keep,
-                                                          int knew, int i0, int stride) {
+                                                          int knew, int i0, int stride, Stage<CAP> *stage = nullptr) {
 #pragma clang fp contract(off)
     const int nmoved = t.ctl[K_TOUCH + k];
     const int nvt = t.ctl[K_VT_N];
@@ -891,7 +953,7 @@ __device__ __forceinline__ int validate_detect_local_body(const Topo &t, int *in
                 topo_err(t);
                 continue;
             }
-            detect_edge(t, e, st, keep, knew, found);
+            detect_edge(t, e, st, keep, knew, found, stage);
             continue;
         }
         if (idx >= nmoved) {
@@ -912,7 +974,7 @@ __device__ __forceinline__ int validate_detect_local_body(const Topo &t, int *in
         int h = h0, guard = 0;
         do {
             validate_tri(t, h / 3, inv);
-            detect_edge(t, h, st, keep, knew, found);
+            detect_edge(t, h, st, keep, knew, found, stage);
             h = t.he_twin[bd_prev(h)];
             if (bad_he(t, h) || ++guard > 4096) {
                 atomicAdd(inv, 1);
@@ -924,17 +986,21 @@ __device__ __forceinline__ int validate_detect_local_body(const Topo &t, int *in
     return found;
 }
 
+constexpr int kTouchStage = 2048;
+
 __global__ void k_validate_detect_local(Topo t, int rep, int k, int last, int stamp, double keep, int knew,
                                         int check) {
     __shared__ int inv, nfound;
+    __shared__ Stage<kTouchStage> st;
     if (stopped(t.ctl)) return;   // nothing in this launch writes the stop flags before its last workgroup
     if (threadIdx.x == 0) {
         inv = 0;
         nfound = 0;
     }
-    __syncthreads();
+    stage_init(st);
     int found = validate_detect_local_body(t, &inv, k, stamp + t.base->vbase, keep, knew,
-                                           blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+                                           xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
+    stage_flush(st, &t.ctl[K_TOUCH + knew], touched_of(t, knew));
     for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
     if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
     const bool a1 = add_block_count(&t.ctl[K_INV + rep], &inv);
@@ -951,7 +1017,7 @@ __global__ void k_ovl_detect_local(Topo t, int stamp, double keep, int k, int kp
     if (stopped(t.ctl)) return;
     if (threadIdx.x == 0) nfound = 0;
     __syncthreads();
-    int found = ovl_detect_local_body(t, stamp, keep, k, kprev, blockIdx.x * blockDim.x + threadIdx.x,
+    int found = ovl_detect_local_body(t, stamp, keep, k, kprev, xcd_block() * blockDim.x + threadIdx.x,
                                       gridDim.x * blockDim.x);
     for (int off = 32; off > 0; off >>= 1) found += __shfl_xor(found, off);
     if (__lane_id() == 0 && found) atomicAdd(&nfound, found);
@@ -989,7 +1055,13 @@ __device__ __forceinline__ void final_check_body(int *ctl, int k) {
 // Gather: for a queued disk, sum the Jacobi displacement over its star
 // (Sec. 2.3 displacement along the unit vector, factor f), starting at the
 // neighbour of smallest id so the summation order is independent of flip
-// history; truncate the sum to cap_frac * r (Sec. 4.4); reflect at the walls.
+// history; truncate the sum to cap_frac * r (Sec. 4.4); reflect at the walls
+// (fold into the box when periodic).  The star is walked once: each
+// neighbour's contribution is kept in registers (stars of up to kStarCache
+// neighbours) and the sum is then folded in the canonical order with static
+// indices; a larger star is walked a second time in that order.
+constexpr int kStarCache = 10;
+
 __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, double cap_frac, double keep, int i0, int stride) {
 #pragma clang fp contract(off)
     if (stopped(t.ctl)) return;
@@ -1005,12 +1077,21 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             topo_err(t);
             continue;
         }
-        int best = h0, bestid = 0x7FFFFFFF;
+        // walk: neighbour ids and contributions (0 for a non-overlapping or non-disk neighbour)
+        int nid[kStarCache];
+        double cxs[kStarCache], cys[kStarCache];
+        int best = h0, bestid = 0x7FFFFFFF, bestpos = 0, deg = 0;
         int h = h0;
         int guard = 0;
         bool broken = false;
+#pragma unroll
+        for (int q = 0; q < kStarCache; ++q) {
+            nid[q] = -1;
+            cxs[q] = 0.0;
+            cys[q] = 0.0;
+        }
         do {
-            int w = t.he_v[bd_next(h)];
+            const int w = t.he_v[bd_next(h)];
             if (bad_v(t, w)) {
                 broken = true;
                 break;
@@ -1018,7 +1099,29 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             if (w < t.inf && w < bestid) {
                 bestid = w;
                 best = h;
+                bestpos = deg;
             }
+            if (deg < kStarCache && w < t.n) {
+                const double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
+                const double d = sqrt(dx * dx + dy * dy);
+                const double contact = rv + t.rad[w];
+                double cx = 0.0, cy = 0.0;
+                int id = -1;
+                if (d < contact * keep) {
+                    const double sc = f * (contact - d) / d;
+                    cx = sc * dx;
+                    cy = sc * dy;
+                    id = w;
+                }
+#pragma unroll
+                for (int q = 0; q < kStarCache; ++q)
+                    if (q == deg) {
+                        nid[q] = id;
+                        cxs[q] = cx;
+                        cys[q] = cy;
+                    }
+            }
+            ++deg;
             h = t.he_twin[bd_prev(h)];
             if (bad_he(t, h) || ++guard > 4096) {
                 broken = true;
@@ -1037,23 +1140,40 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
         if (rec && !room) atomicOr(&t.ctl[K_TAPE_OVF], 1);
         int na = 0;
         double sx = 0.0, sy = 0.0;
-        h = best;
-        do {
-            int w = t.he_v[bd_next(h)];
-            if (w < t.n) {
-                double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
-                double d = sqrt(dx * dx + dy * dy);
-                double contact = rv + t.rad[w];
-                if (d < contact * keep) {
-                    double s = f * (contact - d) / d;
-                    sx += s * dx;
-                    sy += s * dy;
-                    if (room && na < MAXACT) t.tenb[(size_t)e * MAXACT + na] = w;
-                    ++na;
+        if (deg <= kStarCache) {
+            // canonical order: positions bestpos .. deg-1, then 0 .. bestpos-1
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                for (int q = 0; q < kStarCache; ++q) {
+                    const bool in = pass == 0 ? (q >= bestpos && q < deg) : (q < bestpos);
+                    if (in && nid[q] >= 0) {
+                        sx += cxs[q];
+                        sy += cys[q];
+                        if (room && na < MAXACT) t.tenb[(size_t)e * MAXACT + na] = nid[q];
+                        ++na;
+                    }
                 }
             }
-            h = t.he_twin[bd_prev(h)];
-        } while (h != best);
+        } else {
+            h = best;
+            do {
+                int w = t.he_v[bd_next(h)];
+                if (w < t.n) {
+                    double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
+                    double d = sqrt(dx * dx + dy * dy);
+                    double contact = rv + t.rad[w];
+                    if (d < contact * keep) {
+                        double sc = f * (contact - d) / d;
+                        sx += sc * dx;
+                        sy += sc * dy;
+                        if (room && na < MAXACT) t.tenb[(size_t)e * MAXACT + na] = w;
+                        ++na;
+                    }
+                }
+                h = t.he_twin[bd_prev(h)];
+            } while (h != best);
+        }
         if (room) {
             if (na > MAXACT) atomicOr(&t.ctl[K_TAPE_OVF], 2);
             t.tev[e] = v;
@@ -1081,7 +1201,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
 }
 
 __global__ void k_ovl_gather(Topo t, int k, double f, double cap_frac, double keep) {
-    ovl_gather_body(t, k, f, cap_frac, keep, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+    ovl_gather_body(t, k, f, cap_frac, keep, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // Apply: write the new positions (keeping the old ones for a replay) and queue
@@ -1141,7 +1261,7 @@ __global__ void k_ovl_apply(Topo t, int k, int next_round, int slot) {
     __shared__ Stage<kApplyStage> st;
     if (stopped(t.ctl)) return;
     stage_init(st);
-    ovl_apply_body(t, k, next_round, slot, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
+    ovl_apply_body(t, k, next_round, slot, xcd_block() * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, &st);
     stage_flush(st, &t.ctl[K_WL + slot], wl_of(t, slot));
 }
 
@@ -1312,8 +1432,8 @@ inline int list_grid(const Sim &s) {
 void launch_flip_eval_full(Sim &s, int round, int slot, int reversal) {
     round -= s.rbase;
     Topo t = topo_of(s);
-    hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for(s.T, kScanGrid)), dim3(256), 0, s.stream, t, round, slot,
-                       reversal);
+    hipLaunchKernelGGL(k_flip_eval_full, dim3(grid_for((s.T + 3) / 4)), dim3(kScanBlock), 0, s.stream, t, round,
+                       slot, reversal);
 }
 
 void launch_flip_eval_list(Sim &s, int round, int slot) {

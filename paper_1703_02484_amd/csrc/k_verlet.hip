@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
                                                   double *__restrict__ yb, int *__restrict__ overflow, const int *req,
                                                   double P) {
 #pragma clang fp contract(off)
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n || (req && !*req)) return;
     const double xi = x[i], yi = y[i];
     const int cx = cell_coord(xi, inv_cell, nc), cy = cell_coord(yi, inv_cell, nc);
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
                                                   double2 *__restrict__ f, const StepBase *__restrict__ base,
                                                   const int *__restrict__ ctl, double P) {
 #pragma clang fp contract(off)
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block() * blockDim.x + threadIdx.x;
     if (i >= n || base->stop || ctl[K_HALT]) return;   // K_HALT: the lists of this step overflowed
     const double xi = x[i], yi = y[i];
     const int si = ONE_SPECIES ? 0 : sp[i];
@@ -238,70 +238,114 @@ __global__ void k_nl_check(int *__restrict__ ctl, const StepBase *__restrict__ b
 // repeats the detection).  Apply: if the round found nothing the overlap loop
 // is done; otherwise the queued disks take their new positions (all at once,
 // after every gather has read the old ones).
-__global__ __launch_bounds__(256) void k_ovl_nl_gather(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                       const double *__restrict__ rad, double L,
-                                                       const int *__restrict__ nl, const int *__restrict__ nl_cnt,
-                                                       const double *__restrict__ xb, const double *__restrict__ yb,
-                                                       double margin2, double f, double cap_frac, double keep,
-                                                       int *__restrict__ touched, double2 *__restrict__ newpos,
-                                                       int *__restrict__ ctl, unsigned long long *__restrict__ acc,
-                                                       int k, double P) {
+// Workgroups of 1024 threads, at most kNlGatherGrid of them, each disk once
+// (grid-stride): the disks a workgroup queues are staged in LDS with their
+// new positions and reserved on the shared counter once per workgroup, and the
+// pair, cap and stale counts are added once per workgroup (updates of one
+// address from every CU serialise).
+constexpr int kNlGatherBlock = 1024;
+constexpr int kNlGatherGrid = 512;
+constexpr int kNlStage = 2048;
+
+__global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
+    int n, const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ rad, double L,
+    const int *__restrict__ nl, const int *__restrict__ nl_cnt, const double *__restrict__ xb,
+    const double *__restrict__ yb, double margin2, double f, double cap_frac, double keep, int *__restrict__ touched,
+    double2 *__restrict__ newpos, int *__restrict__ ctl, unsigned long long *__restrict__ acc, int k, double P) {
 #pragma clang fp contract(off)
+    __shared__ int s_id[kNlStage];
+    __shared__ double2 s_pos[kNlStage];
+    __shared__ int s_cnt, s_base, s_pairs, s_caps, s_stale;
     if ((ctl[K_HALT] | ctl[K_DONE]) != 0) return;   // nothing in this launch writes them: uniform
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool moved = false, capped = false, stale = false;
-    int pairs = 0;
-    double nx = 0.0, ny = 0.0;
-    if (i < n) {
-        const double xi = x[i], yi = y[i], ri = rad[i];
-        const double ex = sep(xi - xb[i], P), ey = sep(yi - yb[i], P);
-        stale = ex * ex + ey * ey > margin2;
-        const int m = nl_cnt[i];
-        double sx = 0.0, sy = 0.0;
-        for (int q = 0; q < m; ++q) {
-            const int j = nl[(size_t)q * n + i];
-            const double dx = sep(xi - x[j], P), dy = sep(yi - y[j], P);
-            const double d = sqrt(dx * dx + dy * dy);
-            const double contact = ri + rad[j];
-            if (d < contact * keep) {
-                const double sc = f * (contact - d) / d;
-                sx += sc * dx;
-                sy += sc * dy;
-                moved = true;
-                if (i < j) ++pairs;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_pairs = 0;
+        s_caps = 0;
+        s_stale = 0;
+    }
+    __syncthreads();
+    int pairs = 0, caps = 0;
+    bool stale_any = false;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = xcd_block() * blockDim.x; i0 < n; i0 += stride) {   // same trip count in the workgroup
+        const int i = i0 + (int)threadIdx.x;
+        bool moved = false;
+        double nx = 0.0, ny = 0.0;
+        if (i < n) {
+            const double xi = x[i], yi = y[i], ri = rad[i];
+            const double ex = sep(xi - xb[i], P), ey = sep(yi - yb[i], P);
+            stale_any |= ex * ex + ey * ey > margin2;
+            const int m = nl_cnt[i];
+            double sx = 0.0, sy = 0.0;
+            for (int q = 0; q < m; ++q) {
+                const int j = nl[(size_t)q * n + i];
+                const double dx = sep(xi - x[j], P), dy = sep(yi - y[j], P);
+                const double d = sqrt(dx * dx + dy * dy);
+                const double contact = ri + rad[j];
+                if (d < contact * keep) {
+                    const double sc = f * (contact - d) / d;
+                    sx += sc * dx;
+                    sy += sc * dy;
+                    moved = true;
+                    if (i < j) ++pairs;
+                }
+            }
+            if (moved) {
+                const double len = sqrt(sx * sx + sy * sy);
+                const double cap = cap_frac * ri;
+                if (len > cap) {
+                    const double sc = cap / len;
+                    sx = sx * sc;
+                    sy = sy * sc;
+                    ++caps;
+                }
+                nx = P > 0.0 ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
+                ny = P > 0.0 ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
             }
         }
-        if (moved) {
-            const double len = sqrt(sx * sx + sy * sy);
-            const double cap = cap_frac * ri;
-            if (len > cap) {
-                const double sc = cap / len;
-                sx = sx * sc;
-                sy = sy * sc;
-                capped = true;
+        // stage the queued disk (one LDS atomic per wavefront; every lane is here)
+        const unsigned long long mm = __ballot(moved);
+        if (mm != 0) {
+            const int lane = __lane_id(), leader = __ffsll((unsigned long long)mm) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&s_cnt, __popcll(mm));
+            base = __shfl(base, leader);
+            if (moved) {
+                const int pos = base + __popcll(mm & ((1ull << lane) - 1ull));
+                if (pos < kNlStage) {
+                    s_id[pos] = i;
+                    s_pos[pos] = make_double2(nx, ny);
+                } else {
+                    const int g = atomicAdd(&ctl[K_TOUCH + k], 1);
+                    touched[g] = i;
+                    newpos[g] = make_double2(nx, ny);
+                }
             }
-            nx = P > 0.0 ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
-            ny = P > 0.0 ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
         }
     }
-    // every lane of the wavefront is here: one atomic per wavefront for each counter
-    const unsigned long long mm = __ballot(moved);
-    if (mm != 0) {
-        const int lane = __lane_id(), leader = __ffsll((unsigned long long)mm) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&ctl[K_TOUCH + k], __popcll(mm));
-        base = __shfl(base, leader);
-        if (moved) {
-            const int pos = base + __popcll(mm & ((1ull << lane) - 1ull));
-            touched[pos] = i;
-            newpos[pos] = make_double2(nx, ny);
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+        pairs += __shfl_xor(pairs, off);
+        caps += __shfl_xor(caps, off);
     }
-    for (int off = 32; off > 0; off >>= 1) pairs += __shfl_xor(pairs, off);
-    if (__lane_id() == 0 && pairs) atomicAdd(&ctl[K_OVL + k], pairs);
-    const unsigned long long mc = __ballot(capped);
-    if (mc != 0 && __lane_id() == 0) atomicAdd(&acc[A_CAP_HITS], (unsigned long long)__popcll(mc));
-    if (__ballot(stale) != 0 && __lane_id() == 0) atomicOr(&ctl[K_NL_STALE], 1);
+    const bool stale_w = __ballot(stale_any) != 0;
+    if (__lane_id() == 0) {
+        if (pairs) atomicAdd(&s_pairs, pairs);
+        if (caps) atomicAdd(&s_caps, caps);
+        if (stale_w) s_stale = 1;
+    }
+    __syncthreads();
+    const int cnt = s_cnt < kNlStage ? s_cnt : kNlStage;
+    if (threadIdx.x == 0) {
+        if (cnt > 0) s_base = atomicAdd(&ctl[K_TOUCH + k], cnt);
+        if (s_pairs) atomicAdd(&ctl[K_OVL + k], s_pairs);
+        if (s_caps) atomicAdd(&acc[A_CAP_HITS], (unsigned long long)s_caps);
+        if (s_stale) atomicOr(&ctl[K_NL_STALE], 1);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        touched[s_base + q] = s_id[q];
+        newpos[s_base + q] = s_pos[q];
+    }
 }
 
 // final_check: the last budgeted round's detection; overlaps left halt the
@@ -404,7 +448,8 @@ void launch_force_nl(Sim &s) {
 }
 
 void launch_ovl_nl_gather(Sim &s, int k) {
-    hipLaunchKernelGGL(k_ovl_nl_gather, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
+    const int g = std::max(1, std::min(kNlGatherGrid, (s.n + kNlGatherBlock - 1) / kNlGatherBlock));
+    hipLaunchKernelGGL(k_ovl_nl_gather, dim3(g), dim3(kNlGatherBlock), 0, s.stream, s.n, (const double *)s.x,
                        (const double *)s.y, (const double *)s.rad, s.L_h[0], (const int *)s.nl,
                        (const int *)s.nl_cnt, (const double *)s.xbuild, (const double *)s.ybuild,
                        s.nl_margin * s.nl_margin, s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol,

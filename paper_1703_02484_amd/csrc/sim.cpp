@@ -232,6 +232,7 @@ inline int next_slot(int slot) { return slot + 1 == MAXR ? 0 : slot + 1; }
 
 bool tail_fused(const Sim &s);
 int tail_mode_of(const Sim &s);
+void update_ovl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int rounds);
 
 // Evaluation mode of the first flip round after a move: count reversed edges, and with halving
 // enabled also flag the step so that its repair check halts it.
@@ -461,10 +462,11 @@ void compute_forces(Sim &s) {
     });
 }
 
-// Skin test for the next step's lists (short-range path only).
+// Skin test for the next step's lists (short-range path only).  Inside an
+// enqueued step (read_back false) the flag is still clear from the step's start.
 void skin_check(Sim &s, bool read_back) {
     if (!s.use_nl) return;
-    zero_ctl(s, K_NL_REBUILD);
+    if (read_back) zero_ctl(s, K_NL_REBUILD);
     launch_skin_check(s);
     if (read_back) {
         read_ctl(s);
@@ -572,14 +574,34 @@ int overlaps_budget(const Sim &s) {
 
 // How the overlap rounds after the first detection are launched (bd_set_tail_mode).
 int tail_mode_of(const Sim &s) {
-    // Library choice: one workgroup for handles of at most 32,768 disks.  Measured per step
-    // with graph replay: 16,384 disks 10-21 % faster in one workgroup (the lists of the later
-    // rounds hold tens of items and a launch costs more than a barrier); 65,536 disks 13 %
-    // slower and 1M disks 15x slower (the phases are latency chains over thousands of items
-    // that spread better over many CUs).
+    // Library choice: one workgroup for handles of at most 32,768 disks, measured per step with
+    // graph replay on 16,384 disks 10-21 % faster than launching every phase (the lists of the
+    // later rounds hold tens of items and a launch costs more than a barrier).  Larger handles:
+    // the first rounds of each repair and the overlap rounds that queue many disks launched
+    // per phase, the rest in one workgroup (mode 2), measured 0.99 vs 1.11 ms per step on
+    // 65,536 disks and 0.73 vs 0.84 ms on 1M (all in one workgroup: 1.25 ms and 13.6 ms; the
+    // large phases are latency chains over thousands of items that spread better over many CUs).
     constexpr int kTailMaxDisks = 32768;
     if (s.tail_mode != -1) return s.tail_mode;
-    return s.n <= kTailMaxDisks ? 1 : 0;
+    return s.n <= kTailMaxDisks ? 1 : 2;
+}
+
+// Mode 2: overlap rounds launched per phase before the one-workgroup tail.  Round 0 always is;
+// a later round j is too while its detection recently queued more than kTailItems disks (about
+// what the tail's workgroup of 1024 threads takes in one pass of each phase), counted over the
+// current and the previous window of kTouchWindow steps.
+void update_ovl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int rounds) {
+    constexpr int kTailItems = 512, kTouchWindow = 64;
+    for (int j = 0; j < rounds && j < (int)orounds.size() && j < MAXO; ++j)
+        s.touch_hi[j] = std::max(s.touch_hi[j], h[K_TOUCH + orounds[j]]);
+    if (++s.touch_steps >= kTouchWindow) {
+        std::copy(s.touch_hi, s.touch_hi + MAXO, s.touch_prev);
+        std::fill(s.touch_hi, s.touch_hi + MAXO, 0);
+        s.touch_steps = 0;
+    }
+    int phase = 1;
+    while (phase < MAXO && std::max(s.touch_hi[phase], s.touch_prev[phase]) > kTailItems) ++phase;
+    s.ovl_phase = phase;
 }
 
 // Whether the overlap rounds after the first detection run in one workgroup.
@@ -1082,6 +1104,7 @@ int finish_step(Sim &s, const int *h_in, const StepPlan &plan) {
     }
     s.budget.overlaps = std::max(s.budget.overlaps, plan.overlaps);
     adapt(s.budget.overlaps, rounds, s.slack_over, MAXO / 2);   // contact-factor runs need ~20 rounds
+    update_ovl_phase(s, h, plan.orounds, std::min(rounds, plan.overlaps));
     s.st.overlap_rounds_total += rounds;
     if (rounds > s.st.overlap_rounds_max) s.st.overlap_rounds_max = rounds;
     ++s.st.steps;
@@ -2382,6 +2405,8 @@ int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *
             st.inversion_flips = (int64_t)s.hacc[bd::A_INV_FLIPS];
             st.reversals = (int64_t)s.hacc[bd::A_REVERSALS];
             st.noise_clamps = (int64_t)s.hacc[bd::A_NOISE_CLAMPS];
+            for (int j = 0; j < bd::A_CLAMP_SLOTS; ++j)
+                st.noise_clamps += (int64_t)s.hacc[bd::A_CLAMP_BASE + j * bd::A_CLAMP_STRIDE];
             st.cap_hits = (int64_t)s.hacc[bd::A_CAP_HITS];
             *stats_out = st;
         }

@@ -137,15 +137,17 @@ def test_tail_mode_with_more_rounds_than_one_workgroup_takes(graph):
     # outgrows what one workgroup runs and the step falls back to launches per
     # phase while the repair after the move still runs in one workgroup
     w = synth.make("C5", n=2048)
-    a, b = binding.Sim.from_workload(w), binding.Sim.from_workload(w)
+    a, b, c = binding.Sim.from_workload(w), binding.Sim.from_workload(w), binding.Sim.from_workload(w)
     a.set_tail_mode(0)
     b.set_tail_mode(1)
-    a.set_graph_mode(graph)
-    b.set_graph_mode(graph)
+    c.set_tail_mode(2)
+    for h in (a, b, c):
+        h.set_graph_mode(graph)
     for _ in range(4):
-        a.step(2)
-        b.step(2)
+        for h in (a, b, c):
+            h.step(2)
         _same(a, b)
+        _same(a, c)
     assert b.state()[3]["overlap_rounds_max"] > 8
 
 
@@ -159,22 +161,25 @@ def test_tail_in_one_workgroup_equals_launch_per_phase(graph):
     xy = synth.rsa(n, L, 1.0, seed=12)
     mk = lambda: binding.Sim(xy, np.ones(n), np.zeros(n, np.int32), None, np.array([[0.0]]), L=L, D=1.0,
                              dt=2e-2, seed=6)
-    a, b = mk(), mk()
+    a, b, c = mk(), mk(), mk()
     a.set_tail_mode(0)
     b.set_tail_mode(1)
-    a.set_graph_mode(graph)
-    b.set_graph_mode(graph)
+    c.set_tail_mode(2)
+    for h in (a, b, c):
+        h.set_graph_mode(graph)
     for _ in range(10):
-        a.step(1)
-        b.step(1)
+        for h in (a, b, c):
+            h.step(1)
         _same(a, b)
+        _same(a, c)
     assert b.state()[3]["overlap_rounds_max"] >= 3
     w = synth.make("C2", n=3000)
-    a, b = binding.Sim.from_workload(w), binding.Sim.from_workload(w)
+    a, b, c = binding.Sim.from_workload(w), binding.Sim.from_workload(w), binding.Sim.from_workload(w)
     a.set_tail_mode(0)
     b.set_tail_mode(1)
-    a.set_graph_mode(graph)
-    b.set_graph_mode(graph)
-    a.step(25)
-    b.step(25)
+    c.set_tail_mode(2)
+    for h in (a, b, c):
+        h.set_graph_mode(graph)
+        h.step(25)
     _same(a, b)
+    _same(a, c)

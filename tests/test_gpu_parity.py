@@ -186,14 +186,14 @@ def test_trajectory_c2_fp32_reduced_100_steps():
     assert st["flips_total"] > 0
 
 
-@pytest.mark.parametrize("tail_mode", [0, 1])
+@pytest.mark.parametrize("tail_mode", [0, 1, 2])
 def test_trajectory_c1_fp64_100_steps_graph(tail_mode):
     # graph replay (the benchmark's mode) against the oracle directly, both overlap-round launch forms
     worst, st = _run_parity(synth.make("C1"), 100, 1e-9, graph=True, tail_mode=tail_mode)
     assert st["overlap_rounds_total"] > 0
 
 
-@pytest.mark.parametrize("tail_mode", [0, 1])
+@pytest.mark.parametrize("tail_mode", [0, 1, 2])
 def test_trajectory_c2_fp32_reduced_100_steps_graph(tail_mode):
     worst, st = _run_parity(synth.make("C2", n=4096), 100, 1e-4, graph=True, tail_mode=tail_mode)
     assert st["flips_total"] > 0
