@@ -80,6 +80,30 @@ def measured_traffic(workload, n, fcfg):
     return m["bytes_per_launch"]
 
 
+# HBM bytes per dispatch of the short-range step's full passes (N = 1,048,576, the C3 workload) from two
+# rocprofv3 --pmc passes (FETCH_SIZE x 2, WRITE_SIZE x 1, calibrated on a plain copy), beside the algorithmic
+# bytes; valid for the kernel sources they were counted on (sha1 of the three kernel files, see
+# c3_source_sha1).  MB = 1e6 bytes.
+C3_TRAFFIC = {"sha1": "479242510626de905355ea7b83cf7339ef0ea30d", "kernels": {
+    "k_flip_eval_full": {"measured_MB": 102.7, "algorithmic_MB": 84.1},
+    "k_ovl_detect": {"measured_MB": 83.5, "algorithmic_MB": 75.7},
+    "k_em": {"measured_MB": 84.2, "algorithmic_MB": 83.9},
+    "k_force_nl": {"measured_MB": 62.1, "algorithmic_MB": 54.5},
+    "k_skin_check": {"measured_MB": 33.6, "algorithmic_MB": 33.6},
+    "k_snapshot": {"measured_MB": 109.6, "algorithmic_MB": 109.6}}}
+
+
+def c3_source_sha1():
+    """sha1 of the kernel sources of the short-range step's full passes."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in ("k_topology.hip", "k_verlet.hip", "k_particles.hip"):
+        with open(os.path.join(ROOT, "paper_1703_02484_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _short_range_once(w, steps, warmup, overlap):
     import torch
 
@@ -136,6 +160,7 @@ def run_short_range(steps, warmup):
             "flips_per_step": d["flips_total"] / steps, "verlet_rebuilds": d["verlet_rebuilds"],
             "kinetic_repairs": d["kinetic_repairs"], "host_rebuilds": d["host_rebuilds"],
             "host_continued_steps": d["host_continued"]}
+    out["traffic_per_dispatch"] = C3_TRAFFIC["kernels"] if C3_TRAFFIC["sha1"] == c3_source_sha1() else None
     # headline of this secondary line: the library's default (Delaunay overlap correction)
     out.update({k: out["delaunay"][k] for k in ("value", "unit", "steps", "warmup", "ms_per_step")})
     return out
