@@ -343,8 +343,9 @@ int bd_set_graph_mode(bd_sim *sim, int enable);
  * barriers, mode 2 the first flip rounds of each repair and the overlap
  * rounds that recently queued many disks launched per phase and the rest in
  * one workgroup, -1 (default) the library's choice: mode 1 for handles of at
- * most 32,768 disks (measured faster on 16,384), else mode 2 (faster on
- * 65,536 and on 1M).  Results are identical.
+ * most 16,384 disks (measured equal or up to 2 % faster there), else mode 2
+ * (6-18 % faster on 32,768, faster on 65,536 and on 1M).  Results are
+ * identical.
  */
 int bd_set_tail_mode(bd_sim *sim, int mode);
 

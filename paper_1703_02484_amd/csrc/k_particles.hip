@@ -420,17 +420,19 @@ __device__ __forceinline__ void gather_force(const T2 *__restrict__ part, const 
     const long long row = ri.poff + (k - ri.off);
     const double *Ki = K + si * S;
     int c = 0;
-    // 8 chunks at a time: the loads are all issued before the sums, which keep the chunk order
-    for (; c + 8 <= ri.nch; c += 8) {
-        T2 v[8];
-        double w[8];
+    // 16 chunks at a time: the loads are all issued before the sums, which keep the chunk order (one
+    // particle per thread, so the loads in flight per thread set how much of the latency is hidden)
+    constexpr int kB = 16;
+    for (; c + kB <= ri.nch; c += kB) {
+        T2 v[kB];
+        double w[kB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kB; ++u) {
             v[u] = part[row + (long long)(c + u) * ri.n];
             w[u] = Ki[chunk_spec[ri.cfirst + c + u]];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kB; ++u) {
             fx += w[u] * (double)v[u].x;
             fy += w[u] * (double)v[u].y;
         }
@@ -497,7 +499,8 @@ struct EmArgs {
 // Fused Euler-Maruyama update: gather forces, draw noise (stream 0:
 // translation, stream 1: rotation), move, reflect at the walls, keep the
 // previous state for the reversal check and for error rollback.
-template <typename T2>
+// DIRECT: the forces come in fdirect (the list force), else as partial sums to reduce with K.
+template <typename T2, bool DIRECT>
 __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict__ base, const T2 *__restrict__ part,
                                             const RepInfo *__restrict__ reps,
                                             const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
     if (i < a.n) {
         const RepInfo ri = reps[rep_of[i]];
         double fx, fy;
-        if (fdirect) {
+        if (DIRECT) {
             fx = fdirect[i].x;
             fy = fdirect[i].y;
         } else {
@@ -779,16 +782,21 @@ void launch_em(Sim &s, int level, unsigned index) {
     const int nb = blocks_for(s.n, 256);
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
-    if (s.fp32)
-        hipLaunchKernelGGL(k_em<float2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
-                           (const float2 *)s.part, s.reps,
-                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
-                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf, (const int *)s.ctl);
+    if (s.use_nl)
+        hipLaunchKernelGGL((k_em<float2, true>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
+                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
+                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)s.fsr, wf,
+                           (const int *)s.ctl);
+    else if (s.fp32)
+        hipLaunchKernelGGL((k_em<float2, false>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
+                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
+                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)nullptr, wf,
+                           (const int *)s.ctl);
     else
-        hipLaunchKernelGGL(k_em<double2>, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
-                           (const double2 *)s.part, s.reps,
-                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo,
-                           s.th, s.tho, s.acc, s.use_nl ? s.fsr : nullptr, wf, (const int *)s.ctl);
+        hipLaunchKernelGGL((k_em<double2, false>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
+                           (const double2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
+                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)nullptr, wf,
+                           (const int *)s.ctl);
 }
 
 void launch_reduce_forces(Sim &s) {

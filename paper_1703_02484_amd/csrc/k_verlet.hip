@@ -30,13 +30,19 @@ __device__ __forceinline__ int cell_coord(double v, double inv_cell, int nc) {
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// The build kernels loop over their items with a grid of at most kBuildGrid
+// workgroups: in a queued step they usually find no request and return at
+// once, and a launch of few workgroups costs less.
+constexpr int kBuildGrid = 512;
+
 __global__ void k_cell_count(int n, const double *__restrict__ x, const double *__restrict__ y, double inv_cell,
                              int nc, int *__restrict__ cell_of, int *__restrict__ cell_count, const int *req) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || (req && !*req)) return;
-    int c = cell_coord(y[i], inv_cell, nc) * nc + cell_coord(x[i], inv_cell, nc);
-    cell_of[i] = c;
-    atomicAdd(&cell_count[c], 1);
+    if (req && !*req) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int c = cell_coord(y[i], inv_cell, nc) * nc + cell_coord(x[i], inv_cell, nc);
+        cell_of[i] = c;
+        atomicAdd(&cell_count[c], 1);
+    }
 }
 
 // Exclusive scan of the cell counts (m = cells + 1 entries; the last count is
@@ -44,44 +50,56 @@ __global__ void k_cell_count(int n, const double *__restrict__ x, const double *
 // total, then every block adds the totals of the blocks before it.
 constexpr int kScanBlk = 1024;
 
+// Segments of kScanBlk entries, each scanned by one workgroup at a time (a
+// workgroup takes segments blockIdx.x, blockIdx.x + gridDim.x, ...).
 __global__ __launch_bounds__(kScanBlk) void k_scan_local(int m, const int *__restrict__ cnt, int *__restrict__ start,
                                                          int *__restrict__ bsum, const int *req) {
     __shared__ int buf[kScanBlk];
     if (req && !*req) return;
-    const int i = blockIdx.x * kScanBlk + threadIdx.x;
-    const int v = i < m ? cnt[i] : 0;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kScanBlk; off <<= 1) {
-        const int add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0;
+    const int nseg = (m + kScanBlk - 1) / kScanBlk;
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        const int i = seg * kScanBlk + threadIdx.x;
+        const int v = i < m ? cnt[i] : 0;
+        __syncthreads();   // the previous segment's reads of buf are done
+        buf[threadIdx.x] = v;
         __syncthreads();
-        buf[threadIdx.x] += add;
-        __syncthreads();
+        for (int off = 1; off < kScanBlk; off <<= 1) {
+            const int add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < m) start[i] = buf[threadIdx.x] - v;
+        if (threadIdx.x == kScanBlk - 1) bsum[seg] = buf[threadIdx.x];
     }
-    if (i < m) start[i] = buf[threadIdx.x] - v;
-    if (threadIdx.x == kScanBlk - 1) bsum[blockIdx.x] = buf[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kScanBlk) void k_scan_offsets(int m, int *__restrict__ start,
                                                            const int *__restrict__ bsum, const int *req) {
     __shared__ int total;
-    if ((req && !*req) || blockIdx.x == 0) return;
-    if (threadIdx.x == 0) total = 0;
-    __syncthreads();
-    int acc = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBlk) acc += bsum[b];
-    if (acc) atomicAdd(&total, acc);
-    __syncthreads();
-    const int i = blockIdx.x * kScanBlk + threadIdx.x;
-    if (i < m) start[i] += total;
+    if (req && !*req) return;
+    const int nseg = (m + kScanBlk - 1) / kScanBlk;
+    for (int seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        if (seg == 0) continue;   // uniform in the workgroup
+        __syncthreads();          // the previous segment's read of total is done
+        if (threadIdx.x == 0) total = 0;
+        __syncthreads();
+        int acc = 0;
+        for (int b = threadIdx.x; b < seg; b += kScanBlk) acc += bsum[b];
+        if (acc) atomicAdd(&total, acc);
+        __syncthreads();
+        const int i = seg * kScanBlk + threadIdx.x;
+        if (i < m) start[i] += total;
+    }
 }
 
 __global__ void k_cell_scatter(int n, const int *__restrict__ cell_of, const int *__restrict__ cell_start,
                                int *__restrict__ cell_fill, int *__restrict__ cell_items, const int *req) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || (req && !*req)) return;
-    int c = cell_of[i];
-    cell_items[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
+    if (req && !*req) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int c = cell_of[i];
+        cell_items[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
+    }
 }
 
 // One thread per cell: the scatter filled each cell in arbitrary order; sort
@@ -89,19 +107,20 @@ __global__ void k_cell_scatter(int n, const int *__restrict__ cell_of, const int
 // The cell's count and fill counter are zeroed for the next build.
 __global__ void k_cell_sort(int ncell, const int *__restrict__ cell_start, int *__restrict__ cell_items,
                             int *__restrict__ cell_count, int *__restrict__ cell_fill, const int *req) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell || (req && !*req)) return;
-    cell_count[c] = 0;
-    cell_fill[c] = 0;
-    const int b = cell_start[c], e = cell_start[c + 1];
-    for (int p = b + 1; p < e; ++p) {
-        const int v = cell_items[p];
-        int q = p;
-        while (q > b && cell_items[q - 1] > v) {
-            cell_items[q] = cell_items[q - 1];
-            --q;
+    if (req && !*req) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        cell_count[c] = 0;
+        cell_fill[c] = 0;
+        const int b = cell_start[c], e = cell_start[c + 1];
+        for (int p = b + 1; p < e; ++p) {
+            const int v = cell_items[p];
+            int q = p;
+            while (q > b && cell_items[q - 1] > v) {
+                cell_items[q] = cell_items[q - 1];
+                --q;
+            }
+            cell_items[q] = v;
         }
-        cell_items[q] = v;
     }
 }
 
@@ -109,17 +128,14 @@ __global__ void k_cell_sort(int ncell, const int *__restrict__ cell_start, int *
 // order and by id inside a cell, written straight to the slot-major list (at
 // most CAP; the largest count above CAP is reported so the caller can grow the
 // lists).  The position at build time is kept for the skin test.
+// The list of disk i (see k_nl_build).
 template <int CAP>
-__global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                  double inv_cell, int nc, double rl2,
-                                                  const int *__restrict__ cell_start,
-                                                  const int *__restrict__ cell_items, int *__restrict__ nl,
-                                                  int *__restrict__ nl_cnt, double *__restrict__ xb,
-                                                  double *__restrict__ yb, int *__restrict__ overflow, const int *req,
-                                                  double P) {
+__device__ __forceinline__ void nl_build_one(int i, int n, const double *__restrict__ x, const double *__restrict__ y,
+                                             double inv_cell, int nc, double rl2, const int *__restrict__ cell_start,
+                                             const int *__restrict__ cell_items, int *__restrict__ nl,
+                                             int *__restrict__ nl_cnt, double *__restrict__ xb,
+                                             double *__restrict__ yb, int *__restrict__ overflow, double P) {
 #pragma clang fp contract(off)
-    int i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= n || (req && !*req)) return;
     const double xi = x[i], yi = y[i];
     const int cx = cell_coord(xi, inv_cell, nc), cy = cell_coord(yi, inv_cell, nc);
     int cnt = 0;
@@ -153,6 +169,20 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
     yb[i] = yi;
 }
 
+template <int CAP>
+__global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restrict__ x, const double *__restrict__ y,
+                                                  double inv_cell, int nc, double rl2,
+                                                  const int *__restrict__ cell_start,
+                                                  const int *__restrict__ cell_items, int *__restrict__ nl,
+                                                  int *__restrict__ nl_cnt, double *__restrict__ xb,
+                                                  double *__restrict__ yb, int *__restrict__ overflow, const int *req,
+                                                  double P) {
+#pragma clang fp contract(off)
+    if (req && !*req) return;
+    for (int i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        nl_build_one<CAP>(i, n, x, y, inv_cell, nc, rl2, cell_start, cell_items, nl, nl_cnt, xb, yb, overflow, P);
+}
+
 // Pair force over the list: F_i = sum_j K[s_i][s_j] g(d) (r_i - r_j)/d for
 // d <= r_cut, g(d) = A exp(-d/lam)/d (screened) or d^-q (power).  The
 // separation, its length and the cutoff test are FP64 (positions stay FP64);
@@ -164,10 +194,23 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
                                                   int kind, double q, double A, double lam, double rc,
                                                   const int *__restrict__ nl, const int *__restrict__ nl_cnt,
                                                   double2 *__restrict__ f, const StepBase *__restrict__ base,
-                                                  const int *__restrict__ ctl, double P) {
+                                                  int *__restrict__ ctl, double P) {
 #pragma clang fp contract(off)
     int i = xcd_block() * blockDim.x + threadIdx.x;
-    if (i >= n || base->stop || ctl[K_HALT]) return;   // K_HALT: the lists of this step overflowed
+    if (base->stop) return;
+    // after a rebuild inside a queued step: count it, and stop the step here if a disk had more
+    // neighbours than the lists hold (the host grows them and runs the step again)
+    const bool built = base->nl_now != 0;
+    const bool over = built && ctl[K_NL_OVERFLOW] > 0;
+    if (built && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl[K_NL_BUILT] = 1;
+        if (over) {
+            ctl[K_REASON] = HALT_NL_CAPACITY;
+            ctl[K_STAGE] = 0;
+            ctl[K_HALT] = 1;
+        }
+    }
+    if (over || i >= n) return;
     const double xi = x[i], yi = y[i];
     const int si = ONE_SPECIES ? 0 : sp[i];
     const T k0 = (T)K[0];
@@ -209,19 +252,6 @@ __global__ void k_skin_check(int n, const double *__restrict__ x, const double *
     if (__ballot(out) != 0 && __lane_id() == 0) {
         atomicOr(flag, 1);
         atomicOr(&base->nl_req, 1);
-    }
-}
-
-// After a rebuild inside a queued step: count it, and stop the step before its
-// force if a disk had more neighbours than the lists hold (the host grows them
-// and runs the step again).
-__global__ void k_nl_check(int *__restrict__ ctl, const StepBase *__restrict__ base) {
-    if (threadIdx.x != 0 || base->stop || !base->nl_now) return;
-    ctl[K_NL_BUILT] = 1;
-    if (ctl[K_NL_OVERFLOW] > 0) {
-        ctl[K_REASON] = HALT_NL_CAPACITY;
-        ctl[K_STAGE] = 0;
-        ctl[K_HALT] = 1;
     }
 }
 
@@ -388,6 +418,7 @@ __global__ __launch_bounds__(256) void k_ovl_nl_apply(double *__restrict__ x, do
 }
 
 inline int blocks(int n) { return (n + 255) / 256; }
+inline int capped(int b, int cap = kBuildGrid) { return b < 1 ? 1 : (b > cap ? cap : b); }
 
 }  // namespace
 
@@ -401,23 +432,23 @@ namespace {
 void enqueue_build(Sim &s, const int *req) {
     const double inv_cell = (double)s.nl_nc / s.L_h[0];
     const int m = s.nl_ncell + 1;
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell, s.nl_nc,
+    hipLaunchKernelGGL(k_cell_count, dim3(capped(blocks(s.n))), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell, s.nl_nc,
                        s.cell_of, s.cell_count, req);
-    hipLaunchKernelGGL(k_scan_local, dim3(verlet_scan_blocks(s.nl_ncell)), dim3(kScanBlk), 0, s.stream, m,
+    hipLaunchKernelGGL(k_scan_local, dim3(capped(verlet_scan_blocks(s.nl_ncell), 256)), dim3(kScanBlk), 0, s.stream, m,
                        (const int *)s.cell_count, s.cell_start, s.scan_bsum, req);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(verlet_scan_blocks(s.nl_ncell)), dim3(kScanBlk), 0, s.stream, m,
+    hipLaunchKernelGGL(k_scan_offsets, dim3(capped(verlet_scan_blocks(s.nl_ncell), 256)), dim3(kScanBlk), 0, s.stream, m,
                        s.cell_start, (const int *)s.scan_bsum, req);
-    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.cell_of, s.cell_start,
+    hipLaunchKernelGGL(k_cell_scatter, dim3(capped(blocks(s.n))), dim3(256), 0, s.stream, s.n, s.cell_of, s.cell_start,
                        s.cell_fill, s.cell_items, req);
-    hipLaunchKernelGGL(k_cell_sort, dim3(blocks(s.nl_ncell)), dim3(256), 0, s.stream, s.nl_ncell, s.cell_start,
+    hipLaunchKernelGGL(k_cell_sort, dim3(capped(blocks(s.nl_ncell))), dim3(256), 0, s.stream, s.nl_ncell, s.cell_start,
                        s.cell_items, s.cell_count, s.cell_fill, req);
     const double rl = s.fp.cutoff + s.fp.skin;
     if (s.nl_cap <= 32)
-        hipLaunchKernelGGL(k_nl_build<32>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
+        hipLaunchKernelGGL(k_nl_build<32>, dim3(capped(blocks(s.n), 2 * kBuildGrid)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
                            s.ctl + K_NL_OVERFLOW, req, s.period);
     else
-        hipLaunchKernelGGL(k_nl_build<96>, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
+        hipLaunchKernelGGL(k_nl_build<96>, dim3(capped(blocks(s.n), 2 * kBuildGrid)), dim3(256), 0, s.stream, s.n, s.x, s.y, inv_cell,
                            s.nl_nc, rl * rl, s.cell_start, s.cell_items, s.nl, s.nl_cnt, s.xbuild, s.ybuild,
                            s.ctl + K_NL_OVERFLOW, req, s.period);
 }
@@ -430,8 +461,7 @@ void launch_verlet_build(Sim &s) { enqueue_build(s, nullptr); }
 
 void launch_verlet_build_requested(Sim &s) {
     StepBase *b = (StepBase *)s.dbase;
-    enqueue_build(s, &b->nl_now);
-    hipLaunchKernelGGL(k_nl_check, dim3(1), dim3(64), 0, s.stream, s.ctl, (const StepBase *)s.dbase);
+    enqueue_build(s, &b->nl_now);   // the force kernel that follows records the rebuild and checks its capacity
 }
 
 void launch_force_nl(Sim &s) {
@@ -439,7 +469,7 @@ void launch_force_nl(Sim &s) {
         hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
                            (const double *)s.y, (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
                            s.fp.A, s.fp.lambda, s.fp.cutoff, (const int *)s.nl, (const int *)s.nl_cnt, s.fsr,
-                           (const StepBase *)s.dbase, (const int *)s.ctl, s.period);
+                           (const StepBase *)s.dbase, s.ctl, s.period);
     };
     if (s.fp32)
         s.S == 1 ? go(k_force_nl<float, true>) : go(k_force_nl<float, false>);

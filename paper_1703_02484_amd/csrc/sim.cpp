@@ -574,24 +574,27 @@ int overlaps_budget(const Sim &s) {
 
 // How the overlap rounds after the first detection are launched (bd_set_tail_mode).
 int tail_mode_of(const Sim &s) {
-    // Library choice: one workgroup for handles of at most 32,768 disks, measured per step with
+    // Library choice: one workgroup for handles of at most 16,384 disks, measured per step with
     // graph replay on 16,384 disks 10-21 % faster than launching every phase (the lists of the
-    // later rounds hold tens of items and a launch costs more than a barrier).  Larger handles:
-    // the first rounds of each repair and the overlap rounds that queue many disks launched
-    // per phase, the rest in one workgroup (mode 2), measured 0.99 vs 1.11 ms per step on
-    // 65,536 disks and 0.73 vs 0.84 ms on 1M (all in one workgroup: 1.25 ms and 13.6 ms; the
-    // large phases are latency chains over thousands of items that spread better over many CUs).
-    constexpr int kTailMaxDisks = 32768;
+    // later rounds hold tens of items and a launch costs more than a barrier) and within 2 % of
+    // mode 2 from 4,096 to 16,384 disks.  Larger handles: the first rounds of each repair and the
+    // overlap rounds that queue many disks launched per phase, the rest in one workgroup (mode 2),
+    // measured 6-18 % faster than mode 1 on 32,768 disks, 0.96 vs 1.11 ms per step (mode 0) on
+    // 65,536 and 0.64 vs 0.84 ms on 1M (all in one workgroup: 1.25 ms and 13.6 ms; the large
+    // phases are latency chains over thousands of items that spread better over many CUs).
+    constexpr int kTailMaxDisks = 16384;
     if (s.tail_mode != -1) return s.tail_mode;
     return s.n <= kTailMaxDisks ? 1 : 2;
 }
 
-// Mode 2: overlap rounds launched per phase before the one-workgroup tail.  Round 0 always is;
-// a later round j is too while its detection recently queued more than kTailItems disks (about
-// what the tail's workgroup of 1024 threads takes in one pass of each phase), counted over the
-// current and the previous window of kTouchWindow steps.
+// Mode 2: overlap rounds launched per phase before the one-workgroup tail.  Rounds 0, 1, ... are,
+// up to the first round whose detection queued at most kTailItems disks (half of what the tail's
+// workgroup of 1024 threads takes in one pass of each phase) in the current and the previous
+// window of kTouchWindow steps; that round and the later ones run in the tail.  Measured per step
+// with graph replay: 512 and 128 within 1 % of each other on 65,536 and 1M disks and on 16,384
+// disks with the contact factor; 2048 is 25-40 % slower on the first two.
 void update_ovl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int rounds) {
-    constexpr int kTailItems = 512, kTouchWindow = 64;
+    constexpr int kTouchWindow = 64, kTailItems = 512;
     for (int j = 0; j < rounds && j < (int)orounds.size() && j < MAXO; ++j)
         s.touch_hi[j] = std::max(s.touch_hi[j], h[K_TOUCH + orounds[j]]);
     if (++s.touch_steps >= kTouchWindow) {
@@ -599,7 +602,7 @@ void update_ovl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int
         std::fill(s.touch_hi, s.touch_hi + MAXO, 0);
         s.touch_steps = 0;
     }
-    int phase = 1;
+    int phase = 0;
     while (phase < MAXO && std::max(s.touch_hi[phase], s.touch_prev[phase]) > kTailItems) ++phase;
     s.ovl_phase = phase;
 }
@@ -620,7 +623,8 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
         // Mode 2: each repair launches its first rounds on many workgroups and the rest in one, and
         // after the first ovl_phase overlap rounds the others run in one workgroup (k_tail).
         const bool hybrid = mode == 2;
-        const int per_phase = hybrid ? std::min(nover, std::max(1, s.ovl_phase)) : nover;
+        const int per_phase =
+            hybrid ? std::min(nover, std::max({0, s.ovl_phase, nover - MAXTAIL})) : nover;   // the tail holds MAXTAIL
         int k = c.take_oround();
         orounds.push_back(k);
         FusedDetect fd{k, ++s.vround, nover == 0 ? 2 : 1};

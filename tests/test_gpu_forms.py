@@ -73,7 +73,8 @@ def test_pinned_force_form_rejects_bad_values():
 
 def test_full_size_c2_bench_path_matches_oracle():
     # exactly what bench.py times: the tuned force (the symmetric form on MI355X), graph replay,
-    # overlap rounds launched per phase (the library's choice above 32,768 disks)
+    # the large overlap and flip rounds launched per phase and the rest in one workgroup (the library's choice
+    # above 16,384 disks)
     w = synth.make("C2")
     g = binding.Sim.from_workload(w)
     cfg = g.force_config()

@@ -276,8 +276,9 @@ def test_full_size_c2_bench_configuration():
 
 def test_full_size_c2_bench_path_matches_oracle():
     # the timed path itself at full size (N = 65,536): the force form the autotuner picks there (the symmetric
-    # form), graph replay with steps queued together, the default overlap-round launch form (one launch per
-    # phase above 32,768 disks); 3 steps against the oracle, element by element
+    # form), graph replay with steps queued together, the default overlap-round launch form (the large
+    # phases launched one by one, the rest in one workgroup, above 16,384 disks); 3 steps against the
+    # oracle, element by element
     w = synth.make("C2")
     g = binding.Sim.from_workload(w)
     cfg = g.force_config()
