@@ -24,11 +24,18 @@ namespace {
 
 // Separation component: from the nearest image in a periodic box of side P > 0, as is with walls (P = 0).
 __device__ __forceinline__ double sep(double v, double P) { return P > 0.0 ? bd_min_image(v, P) : v; }
+// The same with the box kind fixed at compile time: the list passes are instantiated for each kind, so
+// the minimum image (an FP64 division) is absent from the wall-box kernels instead of selected per pair.
+template <bool PER>
+__device__ __forceinline__ double sep_k(double v, double P) { return PER ? bd_min_image(v, P) : v; }
 
 __device__ __forceinline__ int cell_coord(double v, double inv_cell, int nc) {
     int c = (int)(v * inv_cell);
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
+
+// List passes (force, overlap gather): neighbours whose loads are issued together.
+constexpr int kNlBatch = 2;
 
 // The build kernels loop over their items with a grid of at most kBuildGrid
 // workgroups: in a queued step they usually find no request and return at
@@ -188,7 +195,7 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
 // separation, its length and the cutoff test are FP64 (positions stay FP64);
 // T is the precision of the law's arithmetic and of the sum (FP32 or FP64).  ONE_SPECIES: a single
 // species, so no neighbour's species is read.
-template <typename T, bool ONE_SPECIES>
+template <typename T, bool ONE_SPECIES, bool PER>
 __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restrict__ x, const double *__restrict__ y,
                                                   const int *__restrict__ sp, const double *__restrict__ K, int S,
                                                   int kind, double q, double A, double lam, double rc,
@@ -217,20 +224,36 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
     const T lamT = (T)lam, AT = (T)A, qT = (T)q;
     const int m = nl_cnt[i];
     T fx = (T)0, fy = (T)0;
-    for (int k = 0; k < m; ++k) {
-        const int j = nl[(size_t)k * n + i];
-        const double ddx = sep(xi - x[j], P), ddy = sep(yi - y[j], P);
-        const double dd = sqrt(ddx * ddx + ddy * ddy);
-        if (dd > rc) continue;   // the cutoff decision in FP64 in both precisions
-        const T dx = (T)ddx, dy = (T)ddy, d = (T)dd;
-        T s;
-        if (kind == BD_FORCE_SCREENED)
-            s = AT * exp(-d / lamT) / d / d;
-        else
-            s = pow(d, -qT) / d;
-        s *= ONE_SPECIES ? k0 : (T)K[si * S + sp[j]];
-        fx += s * dx;
-        fy += s * dy;
+    // kNlBatch neighbours at a time: their ids, then their positions, are all loaded before the sums,
+    // which keep the list order (slots past the count read disk i itself and are not summed)
+    for (int k = 0; k < m; k += kNlBatch) {
+        int jb[kNlBatch];
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) jb[u] = k + u < m ? nl[(size_t)(k + u) * n + i] : i;
+        double xj[kNlBatch], yj[kNlBatch];
+        int sj[kNlBatch];
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) {
+            xj[u] = x[jb[u]];
+            yj[u] = y[jb[u]];
+            sj[u] = ONE_SPECIES ? 0 : sp[jb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) {
+            if (k + u >= m) break;
+            const double ddx = sep_k<PER>(xi - xj[u], P), ddy = sep_k<PER>(yi - yj[u], P);
+            const double dd = sqrt(ddx * ddx + ddy * ddy);
+            if (dd > rc) continue;   // the cutoff decision in FP64 in both precisions
+            const T dx = (T)ddx, dy = (T)ddy, d = (T)dd;
+            T s;
+            if (kind == BD_FORCE_SCREENED)
+                s = AT * exp(-d / lamT) / d / d;
+            else
+                s = pow(d, -qT) / d;
+            s *= ONE_SPECIES ? k0 : (T)K[si * S + sj[u]];
+            fx += s * dx;
+            fy += s * dy;
+        }
     }
     f[i] = make_double2((double)fx, (double)fy);
 }
@@ -277,6 +300,7 @@ constexpr int kNlGatherBlock = 1024;
 constexpr int kNlGatherGrid = 512;
 constexpr int kNlStage = 2048;
 
+template <bool PER>
 __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
     int n, const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ rad, double L,
     const int *__restrict__ nl, const int *__restrict__ nl_cnt, const double *__restrict__ xb,
@@ -303,21 +327,34 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
         double nx = 0.0, ny = 0.0;
         if (i < n) {
             const double xi = x[i], yi = y[i], ri = rad[i];
-            const double ex = sep(xi - xb[i], P), ey = sep(yi - yb[i], P);
+            const double ex = sep_k<PER>(xi - xb[i], P), ey = sep_k<PER>(yi - yb[i], P);
             stale_any |= ex * ex + ey * ey > margin2;
             const int m = nl_cnt[i];
             double sx = 0.0, sy = 0.0;
-            for (int q = 0; q < m; ++q) {
-                const int j = nl[(size_t)q * n + i];
-                const double dx = sep(xi - x[j], P), dy = sep(yi - y[j], P);
-                const double d = sqrt(dx * dx + dy * dy);
-                const double contact = ri + rad[j];
-                if (d < contact * keep) {
-                    const double sc = f * (contact - d) / d;
-                    sx += sc * dx;
-                    sy += sc * dy;
-                    moved = true;
-                    if (i < j) ++pairs;
+            for (int q = 0; q < m; q += kNlBatch) {   // batched loads as in k_force_nl, sums in list order
+                int jb[kNlBatch];
+#pragma unroll
+                for (int u = 0; u < kNlBatch; ++u) jb[u] = q + u < m ? nl[(size_t)(q + u) * n + i] : i;
+                double xj[kNlBatch], yj[kNlBatch], rj[kNlBatch];
+#pragma unroll
+                for (int u = 0; u < kNlBatch; ++u) {
+                    xj[u] = x[jb[u]];
+                    yj[u] = y[jb[u]];
+                    rj[u] = rad[jb[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < kNlBatch; ++u) {
+                    if (q + u >= m) break;
+                    const double dx = sep_k<PER>(xi - xj[u], P), dy = sep_k<PER>(yi - yj[u], P);
+                    const double d = sqrt(dx * dx + dy * dy);
+                    const double contact = ri + rj[u];
+                    if (d < contact * keep) {
+                        const double sc = f * (contact - d) / d;
+                        sx += sc * dx;
+                        sy += sc * dy;
+                        moved = true;
+                        if (i < jb[u]) ++pairs;
+                    }
                 }
             }
             if (moved) {
@@ -329,8 +366,8 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
                     sy = sy * sc;
                     ++caps;
                 }
-                nx = P > 0.0 ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
-                ny = P > 0.0 ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
+                nx = PER ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
+                ny = PER ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
             }
         }
         // stage the queued disk (one LDS atomic per wavefront; every lane is here)
@@ -465,6 +502,7 @@ void launch_verlet_build_requested(Sim &s) {
 }
 
 void launch_force_nl(Sim &s) {
+    const bool per = s.period > 0.0;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
                            (const double *)s.y, (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
@@ -472,18 +510,21 @@ void launch_force_nl(Sim &s) {
                            (const StepBase *)s.dbase, s.ctl, s.period);
     };
     if (s.fp32)
-        s.S == 1 ? go(k_force_nl<float, true>) : go(k_force_nl<float, false>);
+        per ? (s.S == 1 ? go(k_force_nl<float, true, true>) : go(k_force_nl<float, false, true>))
+            : (s.S == 1 ? go(k_force_nl<float, true, false>) : go(k_force_nl<float, false, false>));
     else
-        s.S == 1 ? go(k_force_nl<double, true>) : go(k_force_nl<double, false>);
+        per ? (s.S == 1 ? go(k_force_nl<double, true, true>) : go(k_force_nl<double, false, true>))
+            : (s.S == 1 ? go(k_force_nl<double, true, false>) : go(k_force_nl<double, false, false>));
 }
 
 void launch_ovl_nl_gather(Sim &s, int k) {
     const int g = std::max(1, std::min(kNlGatherGrid, (s.n + kNlGatherBlock - 1) / kNlGatherBlock));
-    hipLaunchKernelGGL(k_ovl_nl_gather, dim3(g), dim3(kNlGatherBlock), 0, s.stream, s.n, (const double *)s.x,
-                       (const double *)s.y, (const double *)s.rad, s.L_h[0], (const int *)s.nl,
-                       (const int *)s.nl_cnt, (const double *)s.xbuild, (const double *)s.ybuild,
-                       s.nl_margin * s.nl_margin, s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol,
-                       s.touched + (size_t)(k & 1) * s.n, s.newpos, s.ctl, s.acc, k, s.period);
+    hipLaunchKernelGGL(s.period > 0.0 ? k_ovl_nl_gather<true> : k_ovl_nl_gather<false>, dim3(g),
+                       dim3(kNlGatherBlock), 0, s.stream, s.n, (const double *)s.x, (const double *)s.y,
+                       (const double *)s.rad, s.L_h[0], (const int *)s.nl, (const int *)s.nl_cnt,
+                       (const double *)s.xbuild, (const double *)s.ybuild, s.nl_margin * s.nl_margin,
+                       s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol, s.touched + (size_t)(k & 1) * s.n,
+                       s.newpos, s.ctl, s.acc, k, s.period);
 }
 
 void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {
