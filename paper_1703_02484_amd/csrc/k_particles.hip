@@ -500,7 +500,9 @@ struct EmArgs {
 // translation, stream 1: rotation), move, reflect at the walls, keep the
 // previous state for the reversal check and for error rollback.
 // DIRECT: the forces come in fdirect (the list force), else as partial sums to reduce with K.
-template <typename T2, bool DIRECT>
+// BRIDGE: a sub-interval of a halved step (level > 0); the bridge draws hold about twice the registers
+// of the rest, so the whole steps (level 0) run an instance without them at twice the waves per SIMD.
+template <typename T2, bool DIRECT, bool BRIDGE>
 __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict__ base, const T2 *__restrict__ part,
                                             const RepInfo *__restrict__ reps,
                                             const int *__restrict__ rep_of, const int *__restrict__ chunk_spec,
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         // clamped like xi), the second half takes the rest
         double wx = a.amp * zx, wy = a.amp * zy, wt = a.amp_r * nr;
         double hsub = a.dt;
-        for (int lv = 1; lv <= a.level; ++lv) {
+        for (int lv = 1; BRIDGE && lv <= a.level; ++lv) {
             const unsigned par = a.index >> (a.level - lv + 1), side = (a.index >> (a.level - lv)) & 1u;
             const unsigned skey = 0x80000000u | ((unsigned)lv << 24) | (par << 1);
             double ex, ey;
@@ -782,21 +784,20 @@ void launch_em(Sim &s, int level, unsigned index) {
     const int nb = blocks_for(s.n, 256);
     const Tape &tp = s.adj.tape;
     signed char *wf = tp.on ? tp.emwf + (size_t)tp.step_idx * 2 * s.n : nullptr;
+    const bool bridge = level > 0;
+    auto go = [&](auto kern, auto part, const double2 *fdirect) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, part, s.reps,
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th,
+                           s.tho, s.acc, fdirect, wf, (const int *)s.ctl);
+    };
+    const float2 *p32 = (const float2 *)s.part;
+    const double2 *p64 = (const double2 *)s.part, *none = nullptr, *fsr = (const double2 *)s.fsr;
     if (s.use_nl)
-        hipLaunchKernelGGL((k_em<float2, true>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
-                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
-                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)s.fsr, wf,
-                           (const int *)s.ctl);
+        bridge ? go(k_em<float2, true, true>, p32, fsr) : go(k_em<float2, true, false>, p32, fsr);
     else if (s.fp32)
-        hipLaunchKernelGGL((k_em<float2, false>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
-                           (const float2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
-                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)nullptr, wf,
-                           (const int *)s.ctl);
+        bridge ? go(k_em<float2, false, true>, p32, none) : go(k_em<float2, false, false>, p32, none);
     else
-        hipLaunchKernelGGL((k_em<double2, false>), dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase,
-                           (const double2 *)s.part, s.reps, s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp,
-                           s.rad, s.x, s.y, s.xo, s.yo, s.th, s.tho, s.acc, (const double2 *)nullptr, wf,
-                           (const int *)s.ctl);
+        bridge ? go(k_em<double2, false, true>, p64, none) : go(k_em<double2, false, false>, p64, none);
 }
 
 void launch_reduce_forces(Sim &s) {
