@@ -267,6 +267,7 @@ struct Sim {
     double2 *fsr = nullptr;          // short-range forces, caller order
     int ovl_method = 0;              // 0: overlap rounds over Delaunay edges; 1: over the neighbour lists
     double period = 0.0;             // > 0: periodic box of this side (minimum-image separations), else walls
+    double rad_uni = 0.0;            // > 0: every disk has this radius
     double nl_margin = 0.0;          // lists hold every pair closer than contact while no disk moved farther
                                      // than this since the build: (cutoff + skin - 2 r_max) / 2
     int *scan_bsum = nullptr;        // per-block totals of the cell-count scan

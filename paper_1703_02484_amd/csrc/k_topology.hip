@@ -49,6 +49,7 @@ constexpr int kListGridMax = 256;  // worklist-driven launches (usually a few hu
 struct Topo {
     int n, inf, nvert, T;   // disks, first infinite-vertex id, all vertex ids, triangles
     double P;               // > 0: periodic box of this side (torus triangulation, minimum-image geometry)
+    double ru;              // > 0: every disk has this radius (a contact distance is 2 ru, radii are not loaded)
     const int *rep_of;      // replica of each disk
     const double *Lr;       // box side of each replica
     const double *x, *y, *xo, *yo, *rad;
@@ -77,6 +78,7 @@ Topo topo_of(Sim &s) {
     t.n = s.n;
     t.inf = s.inf;
     t.P = s.period;
+    t.ru = s.rad_uni;
     t.nvert = s.inf + s.R;
     t.rep_of = s.rep_of;
     t.Lr = s.Lr;
@@ -815,7 +817,7 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
                 const bool fin = ok && v[e] < t.inf;
                 px[e] = fin ? t.x[v[e]] : 0.0;
                 py[e] = fin ? t.y[v[e]] : 0.0;
-                pr[e] = fin ? t.rad[v[e]] : 0.0;
+                pr[e] = fin ? (t.ru > 0.0 ? t.ru : t.rad[v[e]]) : 0.0;
             }
             if (vrep >= 0) {   // as validate_tri
                 if (!ok) {
@@ -884,7 +886,7 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     if (a >= t.n || b >= t.n) return;
     const double dx = sep_p(t.x[a] - t.x[b], t.P), dy = sep_p(t.y[a] - t.y[b], t.P);
     const double d = sqrt(dx * dx + dy * dy);
-    if (d < (t.rad[a] + t.rad[b]) * keep) {
+    if (d < (t.ru > 0.0 ? t.ru + t.ru : t.rad[a] + t.rad[b]) * keep) {
         ++found;
         mark_touched(t, a, stamp, k, st);
         mark_touched(t, b, stamp, k, st);
@@ -1072,7 +1074,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
     const int *touched = touched_of(t, k);
     for (int idx = i0; idx < ntouched; idx += stride) {
         const int v = touched[idx];
-        const double xv = t.x[v], yv = t.y[v], rv = t.rad[v];
+        const double xv = t.x[v], yv = t.y[v], rv = t.ru > 0.0 ? t.ru : t.rad[v];
         const double L = t.Lr[t.rep_of[v]];
         t.newpos[idx] = make_double2(xv, yv);
         const int h0 = t.vert_he[v];
@@ -1107,7 +1109,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             if (deg < kStarCache && w < t.n) {
                 const double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
                 const double d = sqrt(dx * dx + dy * dy);
-                const double contact = rv + t.rad[w];
+                const double contact = rv + (t.ru > 0.0 ? t.ru : t.rad[w]);
                 double cx = 0.0, cy = 0.0;
                 int id = -1;
                 if (d < contact * keep) {
@@ -1165,7 +1167,7 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
                 if (w < t.n) {
                     double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
                     double d = sqrt(dx * dx + dy * dy);
-                    double contact = rv + t.rad[w];
+                    double contact = rv + (t.ru > 0.0 ? t.ru : t.rad[w]);
                     if (d < contact * keep) {
                         double sc = f * (contact - d) / d;
                         sx += sc * dx;

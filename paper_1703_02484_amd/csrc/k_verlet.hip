@@ -300,7 +300,9 @@ constexpr int kNlGatherBlock = 1024;
 constexpr int kNlGatherGrid = 512;
 constexpr int kNlStage = 2048;
 
-template <bool PER>
+// UNI: every disk has the same radius (the contact distance is then 2 r_i, the same value rad[i] + rad[j]
+// gives), so the neighbours' radii are not loaded.
+template <bool PER, bool UNI>
 __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
     int n, const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ rad, double L,
     const int *__restrict__ nl, const int *__restrict__ nl_cnt, const double *__restrict__ xb,
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
                 for (int u = 0; u < kNlBatch; ++u) {
                     xj[u] = x[jb[u]];
                     yj[u] = y[jb[u]];
-                    rj[u] = rad[jb[u]];
+                    rj[u] = UNI ? ri : rad[jb[u]];
                 }
 #pragma unroll
                 for (int u = 0; u < kNlBatch; ++u) {
@@ -519,7 +521,10 @@ void launch_force_nl(Sim &s) {
 
 void launch_ovl_nl_gather(Sim &s, int k) {
     const int g = std::max(1, std::min(kNlGatherGrid, (s.n + kNlGatherBlock - 1) / kNlGatherBlock));
-    hipLaunchKernelGGL(s.period > 0.0 ? k_ovl_nl_gather<true> : k_ovl_nl_gather<false>, dim3(g),
+    const bool per = s.period > 0.0, uni = s.rad_uni > 0.0;
+    hipLaunchKernelGGL(per ? (uni ? k_ovl_nl_gather<true, true> : k_ovl_nl_gather<true, false>)
+                           : (uni ? k_ovl_nl_gather<false, true> : k_ovl_nl_gather<false, false>),
+                       dim3(g),
                        dim3(kNlGatherBlock), 0, s.stream, s.n, (const double *)s.x, (const double *)s.y,
                        (const double *)s.rad, s.L_h[0], (const int *)s.nl, (const int *)s.nl_cnt,
                        (const double *)s.xbuild, (const double *)s.ybuild, s.nl_margin * s.nl_margin,

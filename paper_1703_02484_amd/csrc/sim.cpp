@@ -1776,6 +1776,9 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
         hrad[i] = radii[i];
         if (theta) hth[i] = theta[i];
     }
+    s.rad_uni = n > 0 ? radii[0] : 0.0;
+    for (int i = 1; i < n && s.rad_uni > 0.0; ++i)
+        if (radii[i] != radii[0]) s.rad_uni = 0.0;
     for (int r = 0; r < R; ++r) {
         for (int i = s.off_h[r]; i < s.off_h[r + 1]; ++i) hrep[i] = r;
         for (int k = 0; k < (int)fxs[r].size(); ++k) {
