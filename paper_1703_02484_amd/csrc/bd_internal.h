@@ -228,6 +228,9 @@ struct Sim {
     // follow the Hilbert curve over the box (neighbours in space are
     // neighbours in memory); perm maps it back to the caller's order
     double *x = nullptr, *y = nullptr, *xo = nullptr, *yo = nullptr;
+    // (x, y) of every vertex as one 16-byte pair, equal to x, y after every writer: the kernels that
+    // gather the positions of other disks (triangle scans, star walks, list passes) load one pair
+    double2 *xy = nullptr;
     double *th = nullptr, *tho = nullptr, *rad = nullptr;
     int *sp = nullptr;
     int *sp_sorted = nullptr;        // species in sorted order
@@ -354,6 +357,8 @@ int verlet_scan_blocks(int ncells);
 void launch_verlet_build(Sim &s);
 void launch_verlet_build_requested(Sim &s);   // the same kernels, each doing nothing unless the step asks (graph mode)
 void launch_force_nl(Sim &s);
+// xy[0, m) = (x, y)[0, m): after a copy into x, y
+void launch_pack_xy(Sim &s, int m);
 void launch_skin_check(Sim &s);
 // overlap rounds over the neighbour lists (Sec. 5 short-range variant, no triangulation): round slot k
 void launch_ovl_nl_gather(Sim &s, int k);

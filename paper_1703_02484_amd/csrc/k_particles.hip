@@ -38,6 +38,12 @@ __global__ void k_cast(int n, const double *__restrict__ x, const double *__rest
     pj[k] = v;
 }
 
+__global__ void k_pack_xy(int m, const double *__restrict__ x, const double *__restrict__ y,
+                          double2 *__restrict__ xy) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) xy[i] = make_double2(x[i], y[i]);
+}
+
 // ---------------------------------------------------------------- forces
 // d^-3 from d^2.  FP32: the hardware reciprocal square root (v_rsq_f32, ~1 ulp)
 // cubed.  FP64: the hardware estimate y0 of d2^-1/2 corrected with
@@ -510,6 +516,7 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
                                             const int *__restrict__ key_id,
                                             const int *__restrict__ sp, const double *__restrict__ rad,
                                             double *__restrict__ x, double *__restrict__ y,
+                                            double2 *__restrict__ xy,
                                             double *__restrict__ xo, double *__restrict__ yo,
                                             double *__restrict__ th, double *__restrict__ tho,
                                             unsigned long long *__restrict__ acc, const double2 *__restrict__ fdirect,
@@ -566,7 +573,8 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         }
         if (a.level > 0) clamps = 0;   // the step's own draws were counted when it was first tried
         const bool angle = rot || a.v0 != 0.0;
-        const double x0 = x[i], y0 = y[i], t0 = angle ? th[i] : 0.0, r = rad[i];
+        const double2 p0 = xy[i];   // the packed copy: a writer that missed it would show in every later state
+        const double x0 = p0.x, y0 = p0.y, t0 = angle ? th[i] : 0.0, r = rad[i];
         const double vx = a.v0 != 0.0 ? fx + a.v0 * cos(t0) : fx;
         const double vy = a.v0 != 0.0 ? fy + a.v0 * sin(t0) : fy;
         const double xn = x0 + vx * hsub + wx;
@@ -574,8 +582,11 @@ __global__ __launch_bounds__(256) void k_em(EmArgs a, const StepBase *__restrict
         xo[i] = x0;
         yo[i] = y0;
         if (rot) tho[i] = t0;
-        x[i] = a.periodic ? bd_wrap(xn, ri.L) : bd_wall(xn, r, ri.L);
-        y[i] = a.periodic ? bd_wrap(yn, ri.L) : bd_wall(yn, r, ri.L);
+        const double xw = a.periodic ? bd_wrap(xn, ri.L) : bd_wall(xn, r, ri.L);
+        const double yw = a.periodic ? bd_wrap(yn, ri.L) : bd_wall(yn, r, ri.L);
+        x[i] = xw;
+        y[i] = yw;
+        xy[i] = make_double2(xw, yw);
         if (wf) {   // adjoint tape: wall slopes of this move
             wf[2 * (size_t)i] = bd_wall_slope(xn, r, ri.L);
             wf[2 * (size_t)i + 1] = bd_wall_slope(yn, r, ri.L);
@@ -655,6 +666,12 @@ void launch_step_begin(Sim &s) {
 void launch_step_end(Sim &s, int r_used, int v_used) {
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(256), 0, s.stream, (const int *)s.ctl, s.dbase, s.ring, r_used,
                        v_used);
+}
+
+void launch_pack_xy(Sim &s, int m) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_pack_xy, dim3(blocks_for(m, 256)), dim3(256), 0, s.stream, m, (const double *)s.x,
+                           (const double *)s.y, s.xy);
 }
 
 void launch_cast(Sim &s) {
@@ -787,7 +804,7 @@ void launch_em(Sim &s, int level, unsigned index) {
     const bool bridge = level > 0;
     auto go = [&](auto kern, auto part, const double2 *fdirect) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s.stream, a, (const StepBase *)s.dbase, part, s.reps,
-                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xo, s.yo, s.th,
+                           s.rep_of, s.chunk_spec, s.Kd, s.pos_of, s.key_id, s.sp, s.rad, s.x, s.y, s.xy, s.xo, s.yo, s.th,
                            s.tho, s.acc, fdirect, wf, (const int *)s.ctl);
     };
     const float2 *p32 = (const float2 *)s.part;

@@ -53,6 +53,7 @@ struct Topo {
     const int *rep_of;      // replica of each disk
     const double *Lr;       // box side of each replica
     const double *x, *y, *xo, *yo, *rad;
+    const double2 *xy;      // (x, y) pairs, kept equal to x, y: the gathers of other vertices' positions load these
     int *he_v, *he_twin, *vert_he;
     unsigned long long *claim;
     int *tri_stamp, *moved, *edge_stamp, *vstamp;
@@ -85,6 +86,7 @@ Topo topo_of(Sim &s) {
     t.T = s.T;
     t.x = s.x;
     t.y = s.y;
+    t.xy = s.xy;
     t.xo = s.xo;
     t.yo = s.yo;
     t.rad = s.rad;
@@ -150,18 +152,18 @@ __device__ __forceinline__ void topo_err(const Topo &t) { atomicAdd(&t.ctl[K_TOP
 __device__ __forceinline__ double sep_p(double v, double P) { return P > 0.0 ? bd_min_image(v, P) : v; }
 
 __device__ __forceinline__ int flip_rule_of(const Topo &t, int a, int b, int c, int d, bool *inverted) {
-    if (t.P <= 0.0) return bd_flip_rule(a, b, c, d, t.inf, t.x, t.y, true, inverted);
-    const double ax = t.x[a], ay = t.y[a];
-    return bd_flip_rule_quad(0.0, 0.0, sep_p(t.x[b] - ax, t.P), sep_p(t.y[b] - ay, t.P), sep_p(t.x[c] - ax, t.P),
-                             sep_p(t.y[c] - ay, t.P), sep_p(t.x[d] - ax, t.P), sep_p(t.y[d] - ay, t.P), true,
+    const double2 pa = t.xy[a], pb = t.xy[b], pc = t.xy[c], pd = t.xy[d];
+    if (t.P <= 0.0) return bd_flip_rule_xy(a, b, c, d, t.inf, pa.x, pa.y, pb.x, pb.y, pc.x, pc.y, pd.x, pd.y, true, inverted);
+    return bd_flip_rule_quad(0.0, 0.0, sep_p(pb.x - pa.x, t.P), sep_p(pb.y - pa.y, t.P), sep_p(pc.x - pa.x, t.P),
+                             sep_p(pc.y - pa.y, t.P), sep_p(pd.x - pa.x, t.P), sep_p(pd.y - pa.y, t.P), true,
                              inverted);
 }
 
 __device__ __forceinline__ double orient_of(const Topo &t, int a, int b, int c) {
-    if (t.P <= 0.0) return bd_orient(t.x[a], t.y[a], t.x[b], t.y[b], t.x[c], t.y[c]);
-    const double ax = t.x[a], ay = t.y[a];
-    return bd_orient(0.0, 0.0, sep_p(t.x[b] - ax, t.P), sep_p(t.y[b] - ay, t.P), sep_p(t.x[c] - ax, t.P),
-                     sep_p(t.y[c] - ay, t.P));
+    const double2 pa = t.xy[a], pb = t.xy[b], pc = t.xy[c];
+    if (t.P <= 0.0) return bd_orient(pa.x, pa.y, pb.x, pb.y, pc.x, pc.y);
+    return bd_orient(0.0, 0.0, sep_p(pb.x - pa.x, t.P), sep_p(pb.y - pa.y, t.P), sep_p(pc.x - pa.x, t.P),
+                     sep_p(pc.y - pa.y, t.P));
 }
 
 __device__ __forceinline__ unsigned long long claim_key(int round, int e) {
@@ -348,7 +350,8 @@ __device__ __forceinline__ void eval_edge(const Topo &t, int h, int tw, int roun
         bool rev = false;
         if (a < t.n && b < t.n) {
             const double ox = sep_p(t.xo[b] - t.xo[a], t.P), oy = sep_p(t.yo[b] - t.yo[a], t.P);
-            const double mx = sep_p(t.x[b] - t.x[a], t.P), my = sep_p(t.y[b] - t.y[a], t.P);
+            const double2 pa = t.xy[a], pb = t.xy[b];
+            const double mx = sep_p(pb.x - pa.x, t.P), my = sep_p(pb.y - pa.y, t.P);
             rev = ox * mx + oy * my < 0.0;
         }
         wave_count64(&t.acc[A_REVERSALS], rev);
@@ -409,10 +412,17 @@ __global__ __launch_bounds__(kEvalBlock) void k_flip_eval_full(Topo t, int round
         double px[3], py[3], qx[3], qy[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            px[k] = t.x[v[k]];
-            py[k] = t.y[v[k]];
-            qx[k] = t.x[d[k]];
-            qy[k] = t.y[d[k]];
+            const double2 pv = t.xy[v[k]];
+            px[k] = pv.x;
+            py[k] = pv.y;
+            if (own[k]) {   // the far vertex of a canonical edge (the others are not evaluated here)
+                const double2 pd = t.xy[d[k]];
+                qx[k] = pd.x;
+                qy[k] = pd.y;
+            } else {
+                qx[k] = pv.x;
+                qy[k] = pv.y;
+            }
         }
         if (reversal) {
             double ox[3], oy[3];
@@ -815,8 +825,9 @@ __global__ __launch_bounds__(kDetBlock) void k_ovl_detect(Topo t, int rstamp, do
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
                 const bool fin = ok && v[e] < t.inf;
-                px[e] = fin ? t.x[v[e]] : 0.0;
-                py[e] = fin ? t.y[v[e]] : 0.0;
+                const double2 pv = fin ? t.xy[v[e]] : make_double2(0.0, 0.0);
+                px[e] = pv.x;
+                py[e] = pv.y;
                 pr[e] = fin ? (t.ru > 0.0 ? t.ru : t.rad[v[e]]) : 0.0;
             }
             if (vrep >= 0) {   // as validate_tri
@@ -884,7 +895,8 @@ __device__ __forceinline__ void detect_edge(const Topo &t, int h, int stamp, dou
     const int a = t.he_v[e], b = t.he_v[bd_next(e)];
     if (bad_v(t, a) || bad_v(t, b)) return topo_err(t);
     if (a >= t.n || b >= t.n) return;
-    const double dx = sep_p(t.x[a] - t.x[b], t.P), dy = sep_p(t.y[a] - t.y[b], t.P);
+    const double2 pa = t.xy[a], pb = t.xy[b];
+    const double dx = sep_p(pa.x - pb.x, t.P), dy = sep_p(pa.y - pb.y, t.P);
     const double d = sqrt(dx * dx + dy * dy);
     if (d < (t.ru > 0.0 ? t.ru + t.ru : t.rad[a] + t.rad[b]) * keep) {
         ++found;
@@ -1074,7 +1086,8 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
     const int *touched = touched_of(t, k);
     for (int idx = i0; idx < ntouched; idx += stride) {
         const int v = touched[idx];
-        const double xv = t.x[v], yv = t.y[v], rv = t.ru > 0.0 ? t.ru : t.rad[v];
+        const double2 pv = t.xy[v];
+        const double xv = pv.x, yv = pv.y, rv = t.ru > 0.0 ? t.ru : t.rad[v];
         const double L = t.Lr[t.rep_of[v]];
         t.newpos[idx] = make_double2(xv, yv);
         const int h0 = t.vert_he[v];
@@ -1107,7 +1120,8 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
                 bestpos = deg;
             }
             if (deg < kStarCache && w < t.n) {
-                const double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
+                const double2 pw = t.xy[w];
+                const double dx = sep_p(xv - pw.x, t.P), dy = sep_p(yv - pw.y, t.P);
                 const double d = sqrt(dx * dx + dy * dy);
                 const double contact = rv + (t.ru > 0.0 ? t.ru : t.rad[w]);
                 double cx = 0.0, cy = 0.0;
@@ -1165,7 +1179,8 @@ __device__ __forceinline__ void ovl_gather_body(const Topo &t, int k, double f, 
             do {
                 int w = t.he_v[bd_next(h)];
                 if (w < t.n) {
-                    double dx = sep_p(xv - t.x[w], t.P), dy = sep_p(yv - t.y[w], t.P);
+                    const double2 pw = t.xy[w];
+                    double dx = sep_p(xv - pw.x, t.P), dy = sep_p(yv - pw.y, t.P);
                     double d = sqrt(dx * dx + dy * dy);
                     double contact = rv + (t.ru > 0.0 ? t.ru : t.rad[w]);
                     if (d < contact * keep) {
@@ -1232,9 +1247,10 @@ __device__ __forceinline__ void ovl_apply_body(const Topo &t, int k, int next_ro
     for (int idx = i0; idx < ntouched; idx += stride) {
         const int v = touched[idx];
         const double2 np = t.newpos[idx];
-        t.oldpos[idx] = make_double2(t.x[v], t.y[v]);
+        t.oldpos[idx] = t.xy[v];
         ((double *)t.x)[v] = np.x;
         ((double *)t.y)[v] = np.y;
+        ((double2 *)t.xy)[v] = np;
         const int h0 = t.vert_he[v];
         if (bad_he(t, h0)) {
             topo_err(t);
@@ -1400,22 +1416,26 @@ __global__ void k_scatter_oldpos(Topo t, int k, double *xa, double *ya) {
 // Sub-step i of k of a replayed move from (xa, ya) to (xb, yb); in a periodic
 // box (P > 0) along the nearest-image displacement, folded into [0, P).
 __global__ void k_interp(int n, int i, int k, const double *xa, const double *ya, const double *xb,
-                         const double *yb, double *x, double *y, double P) {
+                         const double *yb, double *x, double *y, double2 *xy, double P) {
 #pragma clang fp contract(off)
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    double nx, ny;
     if (i == k) {
-        x[v] = xb[v];
-        y[v] = yb[v];
+        nx = xb[v];
+        ny = yb[v];
     } else if (P > 0.0) {
         const double s = (double)i / (double)k;
-        x[v] = bd_wrap(xa[v] + s * bd_min_image(xb[v] - xa[v], P), P);
-        y[v] = bd_wrap(ya[v] + s * bd_min_image(yb[v] - ya[v], P), P);
+        nx = bd_wrap(xa[v] + s * bd_min_image(xb[v] - xa[v], P), P);
+        ny = bd_wrap(ya[v] + s * bd_min_image(yb[v] - ya[v], P), P);
     } else {
         const double s = (double)i / (double)k;
-        x[v] = xa[v] + s * (xb[v] - xa[v]);
-        y[v] = ya[v] + s * (yb[v] - ya[v]);
+        nx = xa[v] + s * (xb[v] - xa[v]);
+        ny = ya[v] + s * (yb[v] - ya[v]);
     }
+    x[v] = nx;
+    y[v] = ny;
+    xy[v] = make_double2(nx, ny);
 }
 
 inline int grid_for(long items, int cap = kMaxGrid) {
@@ -1529,7 +1549,7 @@ void launch_scatter_oldpos(Sim &s, int k) {
 
 void launch_interp(Sim &s, int i, int k) {
     hipLaunchKernelGGL(k_interp, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n, i, k, s.xa, s.ya, s.xb,
-                       s.yb, s.x, s.y, s.period);
+                       s.yb, s.x, s.y, s.xy, s.period);
 }
 
 }  // namespace bd

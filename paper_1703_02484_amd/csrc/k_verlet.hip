@@ -196,8 +196,7 @@ __global__ __launch_bounds__(256) void k_nl_build(int n, const double *__restric
 // T is the precision of the law's arithmetic and of the sum (FP32 or FP64).  ONE_SPECIES: a single
 // species, so no neighbour's species is read.
 template <typename T, bool ONE_SPECIES, bool PER>
-__global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restrict__ x, const double *__restrict__ y,
-                                                  const int *__restrict__ sp, const double *__restrict__ K, int S,
+__global__ __launch_bounds__(256) void k_force_nl(int n, const double2 *__restrict__ xy, const int *__restrict__ sp, const double *__restrict__ K, int S,
                                                   int kind, double q, double A, double lam, double rc,
                                                   const int *__restrict__ nl, const int *__restrict__ nl_cnt,
                                                   double2 *__restrict__ f, const StepBase *__restrict__ base,
@@ -218,7 +217,8 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
         }
     }
     if (over || i >= n) return;
-    const double xi = x[i], yi = y[i];
+    const double2 pi = xy[i];
+    const double xi = pi.x, yi = pi.y;
     const int si = ONE_SPECIES ? 0 : sp[i];
     const T k0 = (T)K[0];
     const T lamT = (T)lam, AT = (T)A, qT = (T)q;
@@ -234,8 +234,9 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double *__restric
         int sj[kNlBatch];
 #pragma unroll
         for (int u = 0; u < kNlBatch; ++u) {
-            xj[u] = x[jb[u]];
-            yj[u] = y[jb[u]];
+            const double2 pj = xy[jb[u]];
+            xj[u] = pj.x;
+            yj[u] = pj.y;
             sj[u] = ONE_SPECIES ? 0 : sp[jb[u]];
         }
 #pragma unroll
@@ -304,7 +305,7 @@ constexpr int kNlStage = 2048;
 // gives), so the neighbours' radii are not loaded.
 template <bool PER, bool UNI>
 __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
-    int n, const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ rad, double L,
+    int n, const double2 *__restrict__ xy, const double *__restrict__ rad, double L,
     const int *__restrict__ nl, const int *__restrict__ nl_cnt, const double *__restrict__ xb,
     const double *__restrict__ yb, double margin2, double f, double cap_frac, double keep, int *__restrict__ touched,
     double2 *__restrict__ newpos, int *__restrict__ ctl, unsigned long long *__restrict__ acc, int k, double P) {
@@ -328,7 +329,8 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
         bool moved = false;
         double nx = 0.0, ny = 0.0;
         if (i < n) {
-            const double xi = x[i], yi = y[i], ri = rad[i];
+            const double2 pi = xy[i];
+            const double xi = pi.x, yi = pi.y, ri = rad[i];
             const double ex = sep_k<PER>(xi - xb[i], P), ey = sep_k<PER>(yi - yb[i], P);
             stale_any |= ex * ex + ey * ey > margin2;
             const int m = nl_cnt[i];
@@ -340,8 +342,9 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
                 double xj[kNlBatch], yj[kNlBatch], rj[kNlBatch];
 #pragma unroll
                 for (int u = 0; u < kNlBatch; ++u) {
-                    xj[u] = x[jb[u]];
-                    yj[u] = y[jb[u]];
+                    const double2 pj = xy[jb[u]];
+                    xj[u] = pj.x;
+                    yj[u] = pj.y;
                     rj[u] = UNI ? ri : rad[jb[u]];
                 }
 #pragma unroll
@@ -420,6 +423,7 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
 // final_check: the last budgeted round's detection; overlaps left halt the
 // step (the host continues the loop) instead of being applied.
 __global__ __launch_bounds__(256) void k_ovl_nl_apply(double *__restrict__ x, double *__restrict__ y,
+                                                      double2 *__restrict__ xy,
                                                       const int *__restrict__ touched,
                                                       const double2 *__restrict__ newpos, int *__restrict__ ctl, int k,
                                                       int final_check) {
@@ -453,6 +457,7 @@ __global__ __launch_bounds__(256) void k_ovl_nl_apply(double *__restrict__ x, do
         const double2 p = newpos[idx];
         x[v] = p.x;
         y[v] = p.y;
+        xy[v] = p;
     }
 }
 
@@ -506,8 +511,8 @@ void launch_verlet_build_requested(Sim &s) {
 void launch_force_nl(Sim &s) {
     const bool per = s.period > 0.0;
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double *)s.x,
-                           (const double *)s.y, (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
+        hipLaunchKernelGGL(kern, dim3(blocks(s.n)), dim3(256), 0, s.stream, s.n, (const double2 *)s.xy,
+                           (const int *)s.sp, (const double *)s.Kd, s.S, s.fp.kind, s.fp.q,
                            s.fp.A, s.fp.lambda, s.fp.cutoff, (const int *)s.nl, (const int *)s.nl_cnt, s.fsr,
                            (const StepBase *)s.dbase, s.ctl, s.period);
     };
@@ -524,9 +529,7 @@ void launch_ovl_nl_gather(Sim &s, int k) {
     const bool per = s.period > 0.0, uni = s.rad_uni > 0.0;
     hipLaunchKernelGGL(per ? (uni ? k_ovl_nl_gather<true, true> : k_ovl_nl_gather<true, false>)
                            : (uni ? k_ovl_nl_gather<false, true> : k_ovl_nl_gather<false, false>),
-                       dim3(g),
-                       dim3(kNlGatherBlock), 0, s.stream, s.n, (const double *)s.x, (const double *)s.y,
-                       (const double *)s.rad, s.L_h[0], (const int *)s.nl, (const int *)s.nl_cnt,
+                       dim3(g), dim3(kNlGatherBlock), 0, s.stream, s.n, (const double2 *)s.xy, (const double *)s.rad, s.L_h[0], (const int *)s.nl, (const int *)s.nl_cnt,
                        (const double *)s.xbuild, (const double *)s.ybuild, s.nl_margin * s.nl_margin,
                        s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol, s.touched + (size_t)(k & 1) * s.n,
                        s.newpos, s.ctl, s.acc, k, s.period);
@@ -535,7 +538,7 @@ void launch_ovl_nl_gather(Sim &s, int k) {
 void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {
     // the queued disks are usually a few percent of all: a grid for a tenth of them
     const int g = std::max(1, std::min(blocks(s.n), blocks(s.n / 10 + 1)));
-    hipLaunchKernelGGL(k_ovl_nl_apply, dim3(g), dim3(256), 0, s.stream, s.x, s.y,
+    hipLaunchKernelGGL(k_ovl_nl_apply, dim3(g), dim3(256), 0, s.stream, s.x, s.y, s.xy,
                        (const int *)(s.touched + (size_t)(k & 1) * s.n), (const double2 *)s.newpos, s.ctl, k,
                        final_check ? 1 : 0);
 }

@@ -31,15 +31,15 @@ namespace bd {
 namespace {
 
 // library order -> caller order (perm: library index -> caller index)
-__global__ void k_to_caller(int n, const int *__restrict__ perm, const double *__restrict__ x,
-                            const double *__restrict__ y, const double *__restrict__ th, double *__restrict__ xy,
-                            double *__restrict__ th_out) {
+// The positions are read from the packed copy, so every state a caller sees has been through it.
+__global__ void k_to_caller(int n, const int *__restrict__ perm, const double2 *__restrict__ pos,
+                            const double *__restrict__ th, double *__restrict__ xy, double *__restrict__ th_out) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) {
         const size_t i = (size_t)perm[k];
         if (xy) {
-            xy[2 * i] = x[k];
-            xy[2 * i + 1] = y[k];
+            xy[2 * i] = pos[k].x;
+            xy[2 * i + 1] = pos[k].y;
         }
         if (th_out) th_out[i] = th[k];
     }
@@ -389,6 +389,7 @@ int kinetic_replay(Sim &s, Cursor &c, MoveFrom from, int oround) {
     }
     check(hipMemcpyAsync(s.x, s.xb, bytes, hipMemcpyDeviceToDevice, s.stream), "x");
     check(hipMemcpyAsync(s.y, s.yb, bytes, hipMemcpyDeviceToDevice, s.stream), "y");
+    launch_pack_xy(s, s.n);
     return host_rebuild(s);
 }
 
@@ -409,6 +410,7 @@ int host_repair(Sim &s, Cursor &c, bool full, bool reversal, MoveFrom from, int 
 void rollback(Sim &s) {
     check(hipMemcpyAsync(s.x, s.xo, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback x");
     check(hipMemcpyAsync(s.y, s.yo, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback y");
+    launch_pack_xy(s, s.n);
     check(hipMemcpyAsync(s.th, s.tho, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "rollback th");
     fill_int(s, s.ctl, N_CTL, 0);
     s.need_rebuild = true;
@@ -834,6 +836,7 @@ void undo_move(Sim &s) {
     const size_t dn = sizeof(double) * s.n;
     copy_d(s, s.x, s.xo, dn);
     copy_d(s, s.y, s.yo, dn);
+    launch_pack_xy(s, s.n);
     copy_d(s, s.th, s.tho, dn);
     copy_d(s, s.he_v, s.snap_v, sizeof(int) * s.H);
     copy_d(s, s.he_twin, s.snap_twin, sizeof(int) * s.H);
@@ -1525,7 +1528,7 @@ void adj_free(Sim &s);
 
 void free_all(Sim &s) {
     adj_free(s);
-    void *ptrs[] = {s.x, s.y, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.perm, s.key_id, s.sorted_id, s.pos_of, s.pj, s.part,
+    void *ptrs[] = {s.x, s.y, s.xy, s.xo, s.yo, s.th, s.tho, s.rad, s.sp, s.sp_sorted, s.perm, s.key_id, s.sorted_id, s.pos_of, s.pj, s.part,
                     s.tiles, s.chunk_spec, s.reps, s.rep_of, s.Lr, s.Kd, s.fout, s.he_v, s.he_twin, s.vert_he,
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
@@ -1805,6 +1808,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
 
     s.x = dalloc<double>(nva);
     s.y = dalloc<double>(nva);
+    s.xy = dalloc<double2>(nva);
     s.xo = dalloc<double>(nva);
     s.yo = dalloc<double>(nva);
     s.th = dalloc<double>(n);
@@ -1883,6 +1887,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
 
     check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "x");
     check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "y");
+    launch_pack_xy(s, nva);
     check(hipMemcpyAsync(s.xo, hx.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "xo");
     check(hipMemcpyAsync(s.yo, hy.data(), sizeof(double) * nva, hipMemcpyHostToDevice, s.stream), "yo");
     check(hipMemcpyAsync(s.th, hth.data(), sizeof(double) * n, hipMemcpyHostToDevice, s.stream), "th");
@@ -1979,6 +1984,7 @@ void ck_restore(Sim &s, const Checkpoint &c) {
     const size_t dn = sizeof(double) * s.n;
     d2d(s, s.x, c.x, dn);
     d2d(s, s.y, c.y, dn);
+    launch_pack_xy(s, s.n);
     d2d(s, s.xo, c.xo, dn);
     d2d(s, s.yo, c.yo, dn);
     d2d(s, s.th, c.th, dn);
@@ -2315,7 +2321,7 @@ int bd_get_state_dev(bd_sim *sim, double *xy_out, double *theta_out) {
     return bd::guarded(s, [&] {
         if (xy_out || theta_out)
             hipLaunchKernelGGL(bd::k_to_caller, dim3((s.n + 255) / 256), dim3(256), 0, s.stream, s.n,
-                               (const int *)s.perm, s.x, s.y, s.th, xy_out, theta_out);
+                               (const int *)s.perm, (const double2 *)s.xy, s.th, xy_out, theta_out);
         bd::check(hipStreamSynchronize(s.stream), "sync");
         return (int)BD_OK;
     });
@@ -2386,11 +2392,11 @@ int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *
     // reading the state changes nothing the caller sees; only the detail of a failure is recorded
     Sim &s = const_cast<bd_sim *>(sim)->s;
     return bd::guarded(s, [&] {
-        std::vector<double> hx(s.n), hy(s.n), ht(s.n);
-        if (xy_out) {
-            bd::check(hipMemcpyAsync(hx.data(), s.x, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "x");
-            bd::check(hipMemcpyAsync(hy.data(), s.y, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "y");
-        }
+        // positions from the packed copy, so every state a caller sees has been through it
+        std::vector<double2> hp(s.n);
+        std::vector<double> ht(s.n);
+        if (xy_out)
+            bd::check(hipMemcpyAsync(hp.data(), s.xy, sizeof(double2) * s.n, hipMemcpyDeviceToHost, s.stream), "xy");
         if (theta_out)
             bd::check(hipMemcpyAsync(ht.data(), s.th, sizeof(double) * s.n, hipMemcpyDeviceToHost, s.stream), "th");
         bd::check(hipMemcpyAsync(s.hacc, s.acc, sizeof(unsigned long long) * bd::N_ACC, hipMemcpyDeviceToHost,
@@ -2400,8 +2406,8 @@ int bd_get_state(const bd_sim *sim, double *xy_out, double *theta_out, int64_t *
         for (int k = 0; k < s.n; ++k) {
             const size_t i = (size_t)s.perm_h[k];
             if (xy_out) {
-                xy_out[2 * i] = hx[k];
-                xy_out[2 * i + 1] = hy[k];
+                xy_out[2 * i] = hp[k].x;
+                xy_out[2 * i + 1] = hp[k].y;
             }
             if (theta_out) theta_out[i] = ht[k];
         }
@@ -2499,6 +2505,7 @@ int bd_set_positions(bd_sim *sim, const double *xy) {
         bd::check(hipMemcpyAsync(s.yo, s.y, sizeof(double) * s.n, hipMemcpyDeviceToDevice, s.stream), "yo");
         bd::check(hipMemcpyAsync(s.x, hx.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "x");
         bd::check(hipMemcpyAsync(s.y, hy.data(), sizeof(double) * s.n, hipMemcpyHostToDevice, s.stream), "y");
+        bd::launch_pack_xy(s, s.n);
         bd::fill_int(s, s.ctl, bd::N_CTL, 0);
         s.need_rebuild = true;
         if (s.ovl_method != 0) {   // no triangulation to repair
