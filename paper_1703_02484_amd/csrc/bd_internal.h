@@ -346,6 +346,7 @@ struct Sim {
 // ---- kernel launchers (k_*.hip) ------------------------------------------
 void launch_cast(Sim &s);
 void launch_step_begin(Sim &s);                       // clear the control block unless the batch stopped
+void launch_step_begin_cast(Sim &s);                  // both of the above in one launch (all-pairs path)
 void launch_step_end(Sim &s, int r_used, int v_used); // record the control block, advance or stop
 void launch_force(Sim &s);
 int force_max_grid(Sim &s, int per_lane);            // resident workgroups of the persistent launch

@@ -623,7 +623,7 @@ __global__ void k_zero_one(int *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-__global__ void k_step_begin(int *__restrict__ ctl, StepBase *__restrict__ base) {
+__device__ __forceinline__ void step_begin_body(int *__restrict__ ctl, StepBase *__restrict__ base) {
     if (base->stop) {   // keep the halted step's control block for the host; no list rebuild
         if (threadIdx.x == 0) base->nl_now = 0;
         return;
@@ -633,6 +633,25 @@ __global__ void k_step_begin(int *__restrict__ ctl, StepBase *__restrict__ base)
         base->nl_now = base->nl_req;
         base->nl_req = 0;
     }
+}
+
+__global__ void k_step_begin(int *__restrict__ ctl, StepBase *__restrict__ base) { step_begin_body(ctl, base); }
+
+// The step's start and the cast in one launch (all-pairs path): workgroup 0 also clears the control
+// block.  Nothing in the cast reads what the clear writes (the control block, the list flags), and
+// the stop flag both read is not written here.
+template <typename T2>
+__global__ void k_step_begin_cast(int *__restrict__ ctl, StepBase *__restrict__ base, int n,
+                                  const double *__restrict__ x, const double *__restrict__ y,
+                                  const int *__restrict__ sorted_id, T2 *__restrict__ pj) {
+    if (blockIdx.x == 0) step_begin_body(ctl, base);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || base->stop) return;
+    const int i = sorted_id[k];
+    T2 v;
+    v.x = x[i];
+    v.y = y[i];
+    pj[k] = v;
 }
 
 // End of a queued step, one workgroup: record its control block in the ring,
@@ -672,6 +691,16 @@ void launch_pack_xy(Sim &s, int m) {
     if (m > 0)
         hipLaunchKernelGGL(k_pack_xy, dim3(blocks_for(m, 256)), dim3(256), 0, s.stream, m, (const double *)s.x,
                            (const double *)s.y, s.xy);
+}
+
+void launch_step_begin_cast(Sim &s) {
+    const int nb = blocks_for(s.n, 256);
+    if (s.fp32)
+        hipLaunchKernelGGL(k_step_begin_cast<float2>, dim3(nb), dim3(256), 0, s.stream, s.ctl, s.dbase, s.n,
+                           (const double *)s.x, (const double *)s.y, (const int *)s.sorted_id, (float2 *)s.pj);
+    else
+        hipLaunchKernelGGL(k_step_begin_cast<double2>, dim3(nb), dim3(256), 0, s.stream, s.ctl, s.dbase, s.n,
+                           (const double *)s.x, (const double *)s.y, (const int *)s.sorted_id, (double2 *)s.pj);
 }
 
 void launch_cast(Sim &s) {

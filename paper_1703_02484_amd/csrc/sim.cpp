@@ -771,9 +771,12 @@ Sim::StepGraph &step_graph(Sim &s) {
     s.rbase = r0;
     s.vbase = v0;
     g.pre = capture(s, [&] {
-        launch_step_begin(s);
-        if (!s.use_nl) launch_cast(s);
-        if (s.use_nl) launch_verlet_build_requested(s);
+        if (s.use_nl) {
+            launch_step_begin(s);
+            launch_verlet_build_requested(s);
+        } else {
+            launch_step_begin_cast(s);
+        }
     });
     g.force = capture(s, [&] {
         if (s.use_nl)
