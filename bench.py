@@ -84,11 +84,11 @@ def measured_traffic(workload, n, fcfg):
 # rocprofv3 --pmc passes (FETCH_SIZE x 2, WRITE_SIZE x 1, calibrated on a plain copy), beside the algorithmic
 # bytes; valid for the kernel sources they were counted on (sha1 of the three kernel files, see
 # c3_source_sha1).  MB = 1e6 bytes.
-C3_TRAFFIC = {"sha1": "479242510626de905355ea7b83cf7339ef0ea30d", "kernels": {
-    "k_flip_eval_full": {"measured_MB": 102.7, "algorithmic_MB": 84.1},
-    "k_ovl_detect": {"measured_MB": 83.5, "algorithmic_MB": 75.7},
-    "k_em": {"measured_MB": 84.2, "algorithmic_MB": 83.9},
-    "k_force_nl": {"measured_MB": 62.1, "algorithmic_MB": 54.5},
+C3_TRAFFIC = {"sha1": "11b87fa54dbb5779ec608e69560330ba239a30a6", "kernels": {
+    "k_flip_eval_full": {"measured_MB": 100.2, "algorithmic_MB": 84.1},
+    "k_ovl_detect": {"measured_MB": 72.0, "algorithmic_MB": 67.4},
+    "k_em": {"measured_MB": 101.0, "algorithmic_MB": 100.7},
+    "k_force_nl": {"measured_MB": 61.9, "algorithmic_MB": 54.5},
     "k_skin_check": {"measured_MB": 33.6, "algorithmic_MB": 33.6},
     "k_snapshot": {"measured_MB": 109.6, "algorithmic_MB": 109.6}}}
 
@@ -143,13 +143,13 @@ def run_short_range(steps, warmup):
         gbs = bytes_per_disk * w.n / avg_s / 1e9
         rounds = d["overlap_rounds_total"] / steps
         if overlap == "delaunay":
-            # algorithmic bytes per disk: update 64, force, one repair scan 64, first overlap detection 64,
-            # per overlap round gather + apply 84, list rebuild amortised 10
-            step_bytes = w.n * (64 + bytes_per_disk + 64 + 64 + 84 * rounds + 10)
+            # algorithmic bytes per disk: update 96 (it also writes the (x, y) pairs), force, one repair scan
+            # 64, first overlap detection 64, per overlap round gather + apply 84, list rebuild amortised 10
+            step_bytes = w.n * (96 + bytes_per_disk + 64 + 64 + 84 * rounds + 10)
         else:
-            # update 64, force, per detection (rounds + 1) a full list pass 40, per round apply 16 per moved
+            # update 96, force, per detection (rounds + 1) a full list pass 40, per round apply 16 per moved
             # disk (counted as the full pass's share), list rebuild amortised 10
-            step_bytes = w.n * (64 + bytes_per_disk + 40 * (rounds + 1) + 10)
+            step_bytes = w.n * (96 + bytes_per_disk + 40 * (rounds + 1) + 10)
         step_gbs = step_bytes * steps / elapsed / 1e9
         out[overlap] = {
             "value": w.n * steps / elapsed, "unit": "particle-steps/s", "steps": steps, "warmup": warmup,

@@ -222,6 +222,8 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double2 *__restri
     const int si = ONE_SPECIES ? 0 : sp[i];
     const T k0 = (T)K[0];
     const T lamT = (T)lam, AT = (T)A, qT = (T)q;
+    constexpr bool F32 = sizeof(T) == 4;
+    const T inv_lam = (T)(1.0 / lam);   // FP32: one reciprocal of the separation per pair instead of three divisions
     const int m = nl_cnt[i];
     T fx = (T)0, fy = (T)0;
     // kNlBatch neighbours at a time: their ids, then their positions, are all loaded before the sums,
@@ -247,9 +249,14 @@ __global__ __launch_bounds__(256) void k_force_nl(int n, const double2 *__restri
             if (dd > rc) continue;   // the cutoff decision in FP64 in both precisions
             const T dx = (T)ddx, dy = (T)ddy, d = (T)dd;
             T s;
-            if (kind == BD_FORCE_SCREENED)
-                s = AT * exp(-d / lamT) / d / d;
-            else
+            if (kind == BD_FORCE_SCREENED) {
+                if (F32) {
+                    const T r = (T)1 / d;
+                    s = AT * exp(-d * inv_lam) * (r * r);
+                } else {
+                    s = AT * exp(-d / lamT) / d / d;
+                }
+            } else
                 s = pow(d, -qT) / d;
             s *= ONE_SPECIES ? k0 : (T)K[si * S + sj[u]];
             fx += s * dx;
