@@ -265,6 +265,8 @@ struct Sim {
     bool need_rebuild = true;
     int nl_cap = 32, nl_nc = 1, nl_ncell = 1;
     int *nl = nullptr, *nl_cnt = nullptr;
+    int *nl_cand = nullptr;          // disks of a one-workgroup list round
+    int nl_phase = 1;                // list overlap rounds launched as full passes before the one-workgroup rest
     int *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_items = nullptr;
     double *xbuild = nullptr, *ybuild = nullptr;
     double2 *fsr = nullptr;          // short-range forces, caller order
@@ -364,6 +366,16 @@ void launch_skin_check(Sim &s);
 // overlap rounds over the neighbour lists (Sec. 5 short-range variant, no triangulation): round slot k
 void launch_ovl_nl_gather(Sim &s, int k);
 void launch_ovl_nl_apply(Sim &s, int k, bool final_check);
+// the later overlap rounds over the lists in one workgroup, each over the disks the round before moved and
+// their listed neighbours
+struct NlTailPlan {
+    int nr;          // rounds in the launch
+    int k[MAXO];     // their round slots
+    int kprev;       // slot of the round before the first
+    int stamp0;      // stamp of the first round's marks (relative; one per round)
+    int final_last;  // the last round is the budget's last (overlaps left halt the step)
+};
+void launch_nl_tail(Sim &s, const NlTailPlan &p);
 // triangulation (slot: round slot in ctl; rep: repair slot)
 // reversal: 0 no test; 1 count reversed edges (Sec. 4.3); 2 count them and flag the step (K_REV) for halving
 void launch_flip_eval_full(Sim &s, int round, int slot, int reversal);

@@ -310,13 +310,83 @@ constexpr int kNlStage = 2048;
 
 // UNI: every disk has the same radius (the contact distance is then 2 r_i, the same value rad[i] + rad[j]
 // gives), so the neighbours' radii are not loaded.
+// The arguments of the overlap rounds over the lists.
+struct NlArgs {
+    int n;
+    const double2 *xy;
+    const double *rad;
+    double L;
+    const int *nl, *nl_cnt;
+    const double *xb, *yb;
+    double margin2, f, cap_frac, keep, P;
+};
+
+// Round k's gather for disk i: the sum over its listed neighbours closer than
+// contact (in list order), truncated to cap_frac * r_i, walls or wrap; moved
+// when it has an overlapping neighbour.  Counts the overlapping pairs it owns
+// (the lower id), cap hits, and whether the disk is beyond the list margin.
 template <bool PER, bool UNI>
-__global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
-    int n, const double2 *__restrict__ xy, const double *__restrict__ rad, double L,
-    const int *__restrict__ nl, const int *__restrict__ nl_cnt, const double *__restrict__ xb,
-    const double *__restrict__ yb, double margin2, double f, double cap_frac, double keep, int *__restrict__ touched,
-    double2 *__restrict__ newpos, int *__restrict__ ctl, unsigned long long *__restrict__ acc, int k, double P) {
+__device__ __forceinline__ void nl_gather_disk(const NlArgs &a, int i, bool &moved, double &nx, double &ny,
+                                               int &pairs, int &caps, bool &stale_any) {
 #pragma clang fp contract(off)
+    const int n = a.n;
+    const double2 *__restrict__ xy = a.xy;
+    const double *__restrict__ rad = a.rad;
+    const int *__restrict__ nl = a.nl;
+    const double P = a.P, keep = a.keep, f = a.f;
+    const double2 pi = xy[i];
+    const double xi = pi.x, yi = pi.y, ri = rad[i];
+    const double ex = sep_k<PER>(xi - a.xb[i], P), ey = sep_k<PER>(yi - a.yb[i], P);
+    stale_any |= ex * ex + ey * ey > a.margin2;
+    const int m = a.nl_cnt[i];
+    double sx = 0.0, sy = 0.0;
+    for (int q = 0; q < m; q += kNlBatch) {   // batched loads as in k_force_nl, sums in list order
+        int jb[kNlBatch];
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) jb[u] = q + u < m ? nl[(size_t)(q + u) * n + i] : i;
+        double xj[kNlBatch], yj[kNlBatch], rj[kNlBatch];
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) {
+            const double2 pj = xy[jb[u]];
+            xj[u] = pj.x;
+            yj[u] = pj.y;
+            rj[u] = UNI ? ri : rad[jb[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kNlBatch; ++u) {
+            if (q + u >= m) break;
+            const double dx = sep_k<PER>(xi - xj[u], P), dy = sep_k<PER>(yi - yj[u], P);
+            const double d = sqrt(dx * dx + dy * dy);
+            const double contact = ri + rj[u];
+            if (d < contact * keep) {
+                const double sc = f * (contact - d) / d;
+                sx += sc * dx;
+                sy += sc * dy;
+                moved = true;
+                if (i < jb[u]) ++pairs;
+            }
+        }
+    }
+    if (moved) {
+        const double len = sqrt(sx * sx + sy * sy);
+        const double cap = a.cap_frac * ri;
+        if (len > cap) {
+            const double sc = cap / len;
+            sx = sx * sc;
+            sy = sy * sc;
+            ++caps;
+        }
+        nx = PER ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, a.L);
+        ny = PER ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, a.L);
+    }
+}
+
+template <bool PER, bool UNI>
+__global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(NlArgs a, int *__restrict__ touched,
+                                                                  double2 *__restrict__ newpos, int *__restrict__ ctl,
+                                                                  unsigned long long *__restrict__ acc, int k) {
+#pragma clang fp contract(off)
+    const int n = a.n;
     __shared__ int s_id[kNlStage];
     __shared__ double2 s_pos[kNlStage];
     __shared__ int s_cnt, s_base, s_pairs, s_caps, s_stale;
@@ -335,53 +405,7 @@ __global__ __launch_bounds__(kNlGatherBlock) void k_ovl_nl_gather(
         const int i = i0 + (int)threadIdx.x;
         bool moved = false;
         double nx = 0.0, ny = 0.0;
-        if (i < n) {
-            const double2 pi = xy[i];
-            const double xi = pi.x, yi = pi.y, ri = rad[i];
-            const double ex = sep_k<PER>(xi - xb[i], P), ey = sep_k<PER>(yi - yb[i], P);
-            stale_any |= ex * ex + ey * ey > margin2;
-            const int m = nl_cnt[i];
-            double sx = 0.0, sy = 0.0;
-            for (int q = 0; q < m; q += kNlBatch) {   // batched loads as in k_force_nl, sums in list order
-                int jb[kNlBatch];
-#pragma unroll
-                for (int u = 0; u < kNlBatch; ++u) jb[u] = q + u < m ? nl[(size_t)(q + u) * n + i] : i;
-                double xj[kNlBatch], yj[kNlBatch], rj[kNlBatch];
-#pragma unroll
-                for (int u = 0; u < kNlBatch; ++u) {
-                    const double2 pj = xy[jb[u]];
-                    xj[u] = pj.x;
-                    yj[u] = pj.y;
-                    rj[u] = UNI ? ri : rad[jb[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < kNlBatch; ++u) {
-                    if (q + u >= m) break;
-                    const double dx = sep_k<PER>(xi - xj[u], P), dy = sep_k<PER>(yi - yj[u], P);
-                    const double d = sqrt(dx * dx + dy * dy);
-                    const double contact = ri + rj[u];
-                    if (d < contact * keep) {
-                        const double sc = f * (contact - d) / d;
-                        sx += sc * dx;
-                        sy += sc * dy;
-                        moved = true;
-                        if (i < jb[u]) ++pairs;
-                    }
-                }
-            }
-            if (moved) {
-                const double len = sqrt(sx * sx + sy * sy);
-                const double cap = cap_frac * ri;
-                if (len > cap) {
-                    const double sc = cap / len;
-                    sx = sx * sc;
-                    sy = sy * sc;
-                    ++caps;
-                }
-                nx = PER ? bd_wrap(xi + sx, P) : bd_wall(xi + sx, ri, L);
-                ny = PER ? bd_wrap(yi + sy, P) : bd_wall(yi + sy, ri, L);
-            }
-        }
+        if (i < n) nl_gather_disk<PER, UNI>(a, i, moved, nx, ny, pairs, caps, stale_any);
         // stage the queued disk (one LDS atomic per wavefront; every lane is here)
         const unsigned long long mm = __ballot(moved);
         if (mm != 0) {
@@ -468,8 +492,142 @@ __global__ __launch_bounds__(256) void k_ovl_nl_apply(double *__restrict__ x, do
     }
 }
 
+// The later overlap rounds over the lists in one workgroup.  After a round,
+// only a disk that moved in it, or a listed neighbour of one, can overlap
+// another (a pair whose disks both stayed keeps its distance, and every disk
+// that had an overlapping neighbour moved): round r gathers over exactly those
+// disks (each once, marked with the round's stamp), with the arithmetic of the
+// full pass, so it moves the same disks to the same places and counts the same
+// pairs; the margin test of a disk that did not move since its last test would
+// give the same answer.  Each round ends as k_ovl_nl_apply does (lists stale:
+// halt; no overlap: done; the budget's last round with overlaps left: halt;
+// else the queued disks take their positions), phases separated by barriers.
+constexpr int kNlTailBlock = 1024;
+
+__device__ __forceinline__ bool nl_stopped(const int *ctl) {
+    return (__hip_atomic_load(ctl + K_HALT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+            __hip_atomic_load(ctl + K_DONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0;
+}
+
+// (xyw is the array a.xy reads: the gathers and the position writes of a round are separated by barriers.)
+template <bool PER, bool UNI>
+__global__ __launch_bounds__(kNlTailBlock) void k_nl_tail(NlArgs a, NlTailPlan p, double *x, double *y, double2 *xyw,
+                                                          int *touched, double2 *newpos, int *mark, int *cand,
+                                                          int *ctl, unsigned long long *acc,
+                                                          const StepBase *__restrict__ base) {
+    __shared__ int s_nc, s_cnt, s_pairs, s_caps, s_stale, s_go;
+    const int tid = threadIdx.x, n = a.n;
+    // the decisions every thread follows are taken by thread 0 and read from LDS after a barrier
+    if (tid == 0) s_go = nl_stopped(ctl) ? 0 : 1;
+    __syncthreads();
+    if (!s_go) return;
+    int kprev = p.kprev;
+    for (int r = 0; r < p.nr; ++r) {
+        const int k = p.k[r];
+        const int stamp = p.stamp0 + r + base->vbase;
+        if (tid == 0) {
+            s_nc = 0;
+            s_cnt = 0;
+            s_pairs = 0;
+            s_caps = 0;
+            s_stale = 0;
+        }
+        __syncthreads();
+        // the disks of this round: those the previous round moved and their listed neighbours
+        const int nprev = ctl[K_TOUCH + kprev];
+        const int *prev = touched + (size_t)(kprev & 1) * n;
+        for (int idx = tid; idx < nprev; idx += kNlTailBlock) {
+            const int v = prev[idx];
+            if ((unsigned)v >= (unsigned)n) continue;
+            if (atomicExch(&mark[v], stamp) != stamp) cand[atomicAdd(&s_nc, 1)] = v;
+            const int m = a.nl_cnt[v];
+            for (int q = 0; q < m; ++q) {
+                const int w = a.nl[(size_t)q * n + v];
+                if (atomicExch(&mark[w], stamp) != stamp) cand[atomicAdd(&s_nc, 1)] = w;
+            }
+        }
+        __syncthreads();
+        const int nc = s_nc;
+        int *cur = touched + (size_t)(k & 1) * n;
+        int pairs = 0, caps = 0;
+        bool stale = false;
+        for (int c = tid; c < nc; c += kNlTailBlock) {
+            const int i = cand[c];
+            bool moved = false;
+            double nx = 0.0, ny = 0.0;
+            nl_gather_disk<PER, UNI>(a, i, moved, nx, ny, pairs, caps, stale);
+            if (moved) {
+                const int g = atomicAdd(&s_cnt, 1);
+                cur[g] = i;
+                newpos[g] = make_double2(nx, ny);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            pairs += __shfl_xor(pairs, off);
+            caps += __shfl_xor(caps, off);
+        }
+        const bool stale_w = __ballot(stale) != 0;
+        if (__lane_id() == 0) {
+            if (pairs) atomicAdd(&s_pairs, pairs);
+            if (caps) atomicAdd(&s_caps, caps);
+            if (stale_w) s_stale = 1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            ctl[K_TOUCH + k] = s_cnt;
+            ctl[K_OVL + k] += s_pairs;
+            if (s_caps) atomicAdd(&acc[A_CAP_HITS], (unsigned long long)s_caps);
+            if (s_stale) {
+                ctl[K_NL_STALE] = 1;
+                ctl[K_REASON] = HALT_NL_STALE;
+                ctl[K_STAGE] = k;
+                ctl[K_HALT] = 1;
+            } else if (s_pairs == 0) {
+                ctl[K_DONE] = 1;
+            } else if (p.final_last && r + 1 == p.nr) {
+                ctl[K_REASON] = HALT_OVERLAP_BUDGET;
+                ctl[K_STAGE] = k;
+                ctl[K_HALT] = 1;
+            } else {
+                ctl[K_OVL_ROUNDS] = k + 1;
+            }
+            s_go = ctl[K_HALT] == 0 && ctl[K_DONE] == 0;
+        }
+        __syncthreads();
+        if (!s_go) return;
+        const int cnt = s_cnt;
+        for (int idx = tid; idx < cnt; idx += kNlTailBlock) {
+            const int v = cur[idx];
+            const double2 np = newpos[idx];
+            x[v] = np.x;
+            y[v] = np.y;
+            xyw[v] = np;
+        }
+        __syncthreads();
+        kprev = k;
+    }
+}
+
 inline int blocks(int n) { return (n + 255) / 256; }
 inline int capped(int b, int cap = kBuildGrid) { return b < 1 ? 1 : (b > cap ? cap : b); }
+
+NlArgs nl_args(const Sim &s) {
+    NlArgs a;
+    a.n = s.n;
+    a.xy = s.xy;
+    a.rad = s.rad;
+    a.L = s.L_h[0];
+    a.nl = s.nl;
+    a.nl_cnt = s.nl_cnt;
+    a.xb = s.xbuild;
+    a.yb = s.ybuild;
+    a.margin2 = s.nl_margin * s.nl_margin;
+    a.f = s.p.overlap_factor;
+    a.cap_frac = s.p.cap_frac;
+    a.keep = 1.0 - s.p.contact_tol;
+    a.P = s.period;
+    return a;
+}
 
 }  // namespace
 
@@ -536,10 +694,16 @@ void launch_ovl_nl_gather(Sim &s, int k) {
     const bool per = s.period > 0.0, uni = s.rad_uni > 0.0;
     hipLaunchKernelGGL(per ? (uni ? k_ovl_nl_gather<true, true> : k_ovl_nl_gather<true, false>)
                            : (uni ? k_ovl_nl_gather<false, true> : k_ovl_nl_gather<false, false>),
-                       dim3(g), dim3(kNlGatherBlock), 0, s.stream, s.n, (const double2 *)s.xy, (const double *)s.rad, s.L_h[0], (const int *)s.nl, (const int *)s.nl_cnt,
-                       (const double *)s.xbuild, (const double *)s.ybuild, s.nl_margin * s.nl_margin,
-                       s.p.overlap_factor, s.p.cap_frac, 1.0 - s.p.contact_tol, s.touched + (size_t)(k & 1) * s.n,
-                       s.newpos, s.ctl, s.acc, k, s.period);
+                       dim3(g), dim3(kNlGatherBlock), 0, s.stream, nl_args(s), s.touched + (size_t)(k & 1) * s.n,
+                       s.newpos, s.ctl, s.acc, k);
+}
+
+void launch_nl_tail(Sim &s, const NlTailPlan &p) {
+    const bool per = s.period > 0.0, uni = s.rad_uni > 0.0;
+    hipLaunchKernelGGL(per ? (uni ? k_nl_tail<true, true> : k_nl_tail<true, false>)
+                           : (uni ? k_nl_tail<false, true> : k_nl_tail<false, false>),
+                       dim3(1), dim3(kNlTailBlock), 0, s.stream, nl_args(s), p, s.x, s.y, s.xy, s.touched, s.newpos,
+                       s.vstamp, s.nl_cand, s.ctl, s.acc, (const StepBase *)s.dbase);
 }
 
 void launch_ovl_nl_apply(Sim &s, int k, bool final_check) {

@@ -727,13 +727,46 @@ void enqueue_rounds(Sim &s, Cursor &c, std::vector<int> &orounds, std::vector<in
 void enqueue_rounds_nl(Sim &s, Cursor &c, std::vector<int> &orounds) {
     const int cap = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
     const int nover = std::min({s.budget.overlaps, cap, MAXO - 1});
-    for (int j = 0; j <= nover; ++j) {
+    // rounds 0 .. nfull-1 as full passes over every disk (round 0 after the move always), the rest in one
+    // workgroup over the disks near those the round before moved
+    const int nfull = std::min(nover + 1, std::max(1, s.nl_phase));
+    for (int j = 0; j < nfull; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);
         launch_ovl_nl_gather(s, k);
         launch_ovl_nl_apply(s, k, j == nover);
     }
+    if (nfull <= nover) {
+        NlTailPlan p{};
+        p.nr = nover + 1 - nfull;
+        p.kprev = orounds.back();
+        for (int r = 0; r < p.nr; ++r) {
+            p.k[r] = c.take_oround();
+            orounds.push_back(p.k[r]);
+        }
+        p.stamp0 = s.vround + 1 - s.vbase;
+        s.vround += p.nr;
+        p.final_last = 1;
+        launch_nl_tail(s, p);
+    }
     skin_check(s, false);
+}
+
+// List overlap rounds launched as full passes: round j >= 1 joins the one-workgroup rest once the round
+// before it recently moved at most kNlTailItems disks (over the current and the previous window of
+// kTouchWindow steps); its disks are then those and their listed neighbours, a few times as many.
+void update_nl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int rounds) {
+    constexpr int kTouchWindow = 64, kNlTailItems = 512;
+    for (int j = 0; j < rounds && j < (int)orounds.size() && j < MAXO; ++j)
+        s.touch_hi[j] = std::max(s.touch_hi[j], h[K_TOUCH + orounds[j]]);
+    if (++s.touch_steps >= kTouchWindow) {
+        std::copy(s.touch_hi, s.touch_hi + MAXO, s.touch_prev);
+        std::fill(s.touch_hi, s.touch_hi + MAXO, 0);
+        s.touch_steps = 0;
+    }
+    int phase = 1;
+    while (phase < MAXO && std::max(s.touch_hi[phase - 1], s.touch_prev[phase - 1]) > kNlTailItems) ++phase;
+    s.nl_phase = phase;
 }
 
 hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
@@ -753,7 +786,7 @@ hipGraphExec_t capture(Sim &s, const std::function<void()> &enqueue) {
 // inside are relative to the bases of the step being replayed.
 Sim::StepGraph &step_graph(Sim &s) {
     const int nover = s.ovl_method == 1 ? s.budget.overlaps : overlaps_budget(s);
-    std::vector<int> key = {s.budget.em, nover, tail_mode_of(s), s.multi_em, s.multi_ovl, s.ovl_phase};
+    std::vector<int> key = {s.budget.em, nover, tail_mode_of(s), s.multi_em, s.multi_ovl, s.ovl_phase, s.nl_phase};
     for (int j = 0; j < nover; ++j) key.push_back(s.budget.ovl[j]);
     for (auto &e : s.graphs)
         if (e.first == key) return e.second;
@@ -1129,6 +1162,7 @@ int finish_step_nl(Sim &s, const int *h_in, const StepPlan &plan) {
     if (h[K_NL_BUILT]) ++s.st.verlet_rebuilds;
     int rounds = h[K_OVL_ROUNDS];
     for (int j = 0; j < rounds; ++j) s.st.overlap_edges_total += h[K_OVL + plan.orounds[j]];
+    update_nl_phase(s, h, plan.orounds, rounds);
     if (h[K_HALT]) {
         // overlaps left after the budgeted rounds, or lists that may miss a pair: the host continues
         ++s.st.host_continued;
@@ -1536,7 +1570,7 @@ void free_all(Sim &s) {
                     s.claim, s.tri_stamp, s.moved, s.edge_stamp, s.vstamp, s.wl[0], s.wl[1], s.cand, s.cand_won,
                     s.touched, s.det_stamp, s.fl_stamp, s.fl, s.vt_stamp, s.vt, s.newpos, s.oldpos, s.snap_v, s.snap_twin,
                     s.snap_vh, s.xa, s.ya, s.xb, s.yb, s.ctl,
-                    s.acc, s.nl, s.nl_cnt, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
+                    s.acc, s.nl, s.nl_cnt, s.nl_cand, s.cell_of, s.cell_count, s.cell_start, s.cell_fill, s.cell_items,
                     s.xbuild, s.ybuild, s.fsr, s.scan_bsum, s.stiles, s.xs, s.ys, s.ths};
     for (void *p : ptrs)
         dfree(p);
@@ -1877,6 +1911,7 @@ int init_impl(Sim &s, int R, const int32_t *n_per, const double *xy, const doubl
         s.cell_items = dalloc<int>(n);
         s.nl = dalloc<int>((size_t)s.nl_cap * n);
         s.nl_cnt = dalloc<int>(n);
+        s.nl_cand = dalloc<int>(n);
         s.xbuild = dalloc<double>(n);
         s.ybuild = dalloc<double>(n);
         s.fsr = dalloc<double2>(n);
