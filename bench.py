@@ -84,7 +84,7 @@ def measured_traffic(workload, n, fcfg):
 # rocprofv3 --pmc passes (FETCH_SIZE x 2, WRITE_SIZE x 1, calibrated on a plain copy), beside the algorithmic
 # bytes; valid for the kernel sources they were counted on (sha1 of the three kernel files, see
 # c3_source_sha1).  MB = 1e6 bytes.
-C3_TRAFFIC = {"sha1": "11b87fa54dbb5779ec608e69560330ba239a30a6", "kernels": {
+C3_TRAFFIC = {"sha1": "a3d772a99d6da0544405237dc6d1be9af153ea52", "kernels": {
     "k_flip_eval_full": {"measured_MB": 100.2, "algorithmic_MB": 84.1},
     "k_ovl_detect": {"measured_MB": 72.0, "algorithmic_MB": 67.4},
     "k_em": {"measured_MB": 101.0, "algorithmic_MB": 100.7},
