@@ -344,8 +344,12 @@ int bd_set_graph_mode(bd_sim *sim, int enable);
  * rounds that recently queued many disks launched per phase and the rest in
  * one workgroup, -1 (default) the library's choice: mode 1 for handles of at
  * most 16,384 disks (measured equal or up to 2 % faster there), else mode 2
- * (6-18 % faster on 32,768, faster on 65,536 and on 1M).  Results are
- * identical.
+ * (6-18 % faster on 32,768, faster on 65,536 and on 1M).  With overlap
+ * rounds over the neighbour lists (Sec. 5): mode 0 every round a launch over
+ * all disks, mode 1 every round after the first in one workgroup over the
+ * disks near those the round before moved, mode 2 the rounds after one that
+ * recently moved more than 512 disks launched over all disks, the rest in one
+ * workgroup.  Results are identical.
  */
 int bd_set_tail_mode(bd_sim *sim, int mode);
 

@@ -728,8 +728,12 @@ void enqueue_rounds_nl(Sim &s, Cursor &c, std::vector<int> &orounds) {
     const int cap = s.p.max_overlap_rounds > 0 ? s.p.max_overlap_rounds : 10000;
     const int nover = std::min({s.budget.overlaps, cap, MAXO - 1});
     // rounds 0 .. nfull-1 as full passes over every disk (round 0 after the move always), the rest in one
-    // workgroup over the disks near those the round before moved
-    const int nfull = std::min(nover + 1, std::max(1, s.nl_phase));
+    // workgroup over the disks near those the round before moved: launch form 0 every round as a full
+    // pass, 1 every round after the first in one workgroup, 2 the rounds that recently moved many disks
+    // as full passes (same results in every form)
+    const int mode = tail_mode_of(s);
+    const int phase = mode == 0 ? nover + 1 : (mode == 1 ? 1 : s.nl_phase);
+    const int nfull = std::min(nover + 1, std::max(1, phase));
     for (int j = 0; j < nfull; ++j) {
         const int k = c.take_oround();
         orounds.push_back(k);

@@ -84,6 +84,44 @@ def test_verlet_overlap_rebuilds_stale_lists_inside_a_step():
     assert st["host_continued"] > 0 and st["verlet_rebuilds"] > 10 and st["overlap_rounds_max"] >= 2
 
 
+def _list_run(w, steps, mode, graph=True, **over):
+    g = binding.Sim.from_workload(w, overlap="verlet", **over)
+    g.set_tail_mode(mode)
+    g.set_graph_mode(graph)
+    g.step(steps)
+    x, th, step, st = g.state()
+    g.close()
+    return x, st
+
+
+def test_verlet_overlap_launch_forms_agree_with_the_oracle():
+    # the later list rounds as launches over every disk (form 0), in one workgroup over the disks near
+    # those the round before moved (form 1), or the library's mix (form 2): the same positions bit for
+    # bit, and the oracle's
+    w = synth.make("C3", n=6000)
+    runs = {m: _list_run(w, 30, m, fp32=False) for m in (0, 1, 2)}
+    o = oracle.OracleSim.from_workload(w, overlap="verlet", fp32=False)
+    o.step(30)
+    xo = o.state()[0]
+    for m, (x, st) in runs.items():
+        assert np.array_equal(x, runs[0][0]), m
+        assert st["overlap_edges_total"] == runs[0][1]["overlap_edges_total"], m
+        assert st["overlap_rounds_total"] > 0
+        assert rel_err(x, xo) <= 1e-9, m
+
+
+def test_verlet_overlap_launch_forms_agree_at_200k():
+    # large enough that the library's form launches the first rounds over all disks and runs the rest
+    # in one workgroup (it picks the split from the previous steps' rounds)
+    w = synth.make("C3", n=200000)
+    x0, st0 = _list_run(w, 12, 0)
+    x2, st2 = _list_run(w, 12, 2)
+    assert np.array_equal(x0, x2)
+    assert st0["overlap_edges_total"] == st2["overlap_edges_total"]
+    assert st0["overlap_rounds_max"] >= 3 and st0["host_continued"] == st2["host_continued"]
+    assert count_overlaps(x2) == 0
+
+
 def test_verlet_overlap_has_no_triangulation():
     w = synth.make("C3", n=500)
     g = binding.Sim.from_workload(w, overlap="verlet")
