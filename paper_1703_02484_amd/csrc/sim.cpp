@@ -759,6 +759,9 @@ void enqueue_rounds_nl(Sim &s, Cursor &c, std::vector<int> &orounds) {
 // List overlap rounds launched as full passes: round j >= 1 joins the one-workgroup rest once the round
 // before it recently moved at most kNlTailItems disks (over the current and the previous window of
 // kTouchWindow steps); its disks are then those and their listed neighbours, a few times as many.
+// (The window is the one update_ovl_phase keeps: a handle runs one overlap method.)  Limits of 128 to 1024
+// measured within 1 % on 1M disks; 2048 and above let rounds that moved thousands of disks into the one
+// workgroup, which then takes longer than a pass over every disk.
 void update_nl_phase(Sim &s, const int *h, const std::vector<int> &orounds, int rounds) {
     constexpr int kTouchWindow = 64, kNlTailItems = 512;
     for (int j = 0; j < rounds && j < (int)orounds.size() && j < MAXO; ++j)
